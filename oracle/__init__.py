@@ -1,0 +1,202 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It shares no code with the GPU path: it loads
+``liboracle.so`` built from ``les_oracle.cpp`` (see ``build.py``), which
+implements the residual and Runge-Kutta step of the paper's Sec. 3-4 with the
+readings listed at the top of that file.
+
+Array conventions (numpy, float64, C-contiguous):
+  * padded box arrays have shape (nfields, nk+4, nj+4, ni+4): two ghost layers
+    per side, i fastest; interior index 0..n-1 sits at n+2;
+  * coordinates xyz: (3, ...); metrics: (10, ...) = xi_x/J .. zeta_z/J, J;
+  * state Q: (5, ...) = rho, rho u, rho v, rho w, e;
+  * source f: (5, nk, nj) on the plane i = i_f.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class OrcDims(ctypes.Structure):
+    _fields_ = [("ni", ctypes.c_int), ("nj", ctypes.c_int), ("nk", ctypes.c_int),
+                ("bc", ctypes.c_int * 3)]
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("Pr", ctypes.c_double), ("Pr_sgs", ctypes.c_double),
+                ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("S_suth", ctypes.c_double),
+                ("R_gas", ctypes.c_double), ("sgs", ctypes.c_int), ("Cs", ctypes.c_double),
+                ("k2", ctypes.c_double), ("k4", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("cfl", ctypes.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_box_nodes.restype = ctypes.c_size_t
+    lib.orc_box_nodes.argtypes = [ctypes.POINTER(OrcDims)]
+    lib.orc_metrics.restype = None
+    lib.orc_metrics.argtypes = [ctypes.POINTER(OrcDims), _dp, _dp]
+    lib.orc_fill_ghosts.restype = None
+    lib.orc_fill_ghosts.argtypes = [ctypes.POINTER(OrcDims), _dp, ctypes.c_int]
+    lib.orc_residual.restype = None
+    lib.orc_residual.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp,
+                                 ctypes.c_int, _dp]
+    lib.orc_residual_tangent.restype = None
+    lib.orc_residual_tangent.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp,
+                                         _dp, _dp, ctypes.c_int, _dp, _dp]
+    lib.orc_cfl_dt.restype = ctypes.c_double
+    lib.orc_cfl_dt.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
+    lib.orc_rk_step.restype = ctypes.c_double
+    lib.orc_rk_step.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, ctypes.c_double,
+                                _dp, ctypes.c_int, _dp, _dp]
+    lib.orc_objective_rollout.restype = ctypes.c_double
+    lib.orc_objective_rollout.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp,
+                                          _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_double, _dp]
+    lib.orc_objective.restype = ctypes.c_double
+    lib.orc_objective.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double]
+    lib.orc_rk_scalar.restype = None
+    lib.orc_rk_scalar.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp]
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def dims(ni, nj, nk, bc=(0, 0, 0)) -> OrcDims:
+    d = OrcDims()
+    d.ni, d.nj, d.nk = int(ni), int(nj), int(nk)
+    for i in range(3):
+        d.bc[i] = int(bc[i])
+    return d
+
+
+_PARAM_KEYS = ["gamma", "Pr", "Pr_sgs", "mu_ref", "T_ref", "S_suth", "R_gas", "sgs", "Cs", "k2", "k4",
+               "alpha", "cfl"]
+
+
+def params(p: dict) -> OrcParams:
+    o = OrcParams()
+    for k in _PARAM_KEYS:
+        setattr(o, k, int(p[k]) if k == "sgs" else float(p[k]))
+    return o
+
+
+def _dims_of(case):
+    return dims(case["ni"], case["nj"], case["nk"], case["bc"])
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def metrics(case) -> np.ndarray:
+    """Metrics (10, nk+4, nj+4, ni+4) from the coordinates case['xyz'];
+    defined on nodes with all indices in [-1, n], NaN elsewhere."""
+    lib = _load()
+    xyz = _c(case["xyz"])
+    m = np.empty((10,) + xyz.shape[1:], dtype=np.float64)
+    lib.orc_metrics(ctypes.byref(_dims_of(case)), _ptr(xyz), _ptr(m))
+    return m
+
+
+def fill_ghosts(case, a: np.ndarray) -> np.ndarray:
+    lib = _load()
+    a = _c(a).copy()
+    lib.orc_fill_ghosts(ctypes.byref(_dims_of(case)), _ptr(a), a.shape[0])
+    return a
+
+
+def residual(case, m, Q, prm=None, f=None, i_f=-1) -> np.ndarray:
+    """R(Q) on the padded box (zeros in the ghost layers)."""
+    lib = _load()
+    prm = case["params"] if prm is None else prm
+    Q = _c(Q)
+    R = np.zeros_like(Q)
+    fa = None if f is None else _c(f)
+    lib.orc_residual(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q), _ptr(fa),
+                     int(i_f), _ptr(R))
+    return R
+
+
+def residual_tangent(case, m, Q, dQ, prm=None, f=None, df=None, i_f=-1):
+    """(R, dR) with dR the exact directional derivative of R along (dQ, df)."""
+    lib = _load()
+    prm = case["params"] if prm is None else prm
+    Q = _c(Q)
+    R = np.zeros_like(Q)
+    dR = np.zeros_like(Q)
+    lib.orc_residual_tangent(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q),
+                             _ptr(None if dQ is None else _c(dQ)), _ptr(None if f is None else _c(f)),
+                             _ptr(None if df is None else _c(df)), int(i_f), _ptr(R), _ptr(dR))
+    return R, dR
+
+
+def cfl_dt(case, m, Q, prm=None) -> float:
+    lib = _load()
+    prm = case["params"] if prm is None else prm
+    return lib.orc_cfl_dt(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(_c(Q)))
+
+
+def rk_step(case, m, Q, dt=0.0, prm=None, f=None, i_f=-1, want_stages=False):
+    """One RK step from Q (not modified).  Returns (Q_next, dt, norms[10], stages|None)."""
+    lib = _load()
+    prm = case["params"] if prm is None else prm
+    Qn = _c(Q).copy()
+    norms = np.zeros(10, dtype=np.float64)
+    stages = np.zeros((5,) + Qn.shape, dtype=np.float64) if want_stages else None
+    dt_used = lib.orc_rk_step(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Qn),
+                              float(dt), _ptr(None if f is None else _c(f)), int(i_f), _ptr(norms), _ptr(stages))
+    return Qn, dt_used, norms, stages
+
+
+def objective_rollout(case, m, Q0, f, df, i_f, i_p, p_inf, nsteps, dt, dQ0=None):
+    """(J, dJ): objective of the forcing workload and its exact directional
+    derivative along (dQ0, df) computed with dual numbers."""
+    lib = _load()
+    prm = case["params"]
+    Q = _c(Q0).copy()
+    dJ = ctypes.c_double(0.0)
+    J = lib.orc_objective_rollout(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q),
+                                  _ptr(None if dQ0 is None else _c(dQ0)), _ptr(_c(f)),
+                                  _ptr(None if df is None else _c(df)), int(i_f), int(i_p), float(p_inf),
+                                  int(nsteps), float(dt), ctypes.byref(dJ))
+    return J, dJ.value
+
+
+def objective(case, m, Q0, f, i_f, i_p, p_inf, nsteps, dt):
+    lib = _load()
+    Q = _c(Q0).copy()
+    return lib.orc_objective(ctypes.byref(_dims_of(case)), ctypes.byref(params(case["params"])), _ptr(_c(m)),
+                             _ptr(Q), _ptr(_c(f)), int(i_f), int(i_p), float(p_inf), int(nsteps), float(dt))
+
+
+def rk_scalar(lam: complex, dt: float, y0: complex = 1.0) -> complex:
+    """The RK driver applied to y' = lam*y for one step."""
+    lib = _load()
+    yr = ctypes.c_double(float(np.real(y0)))
+    yi = ctypes.c_double(float(np.imag(y0)))
+    lib.orc_rk_scalar(float(np.real(lam)), float(np.imag(lam)), float(dt), ctypes.byref(yr), ctypes.byref(yi))
+    return complex(yr.value, yi.value)

@@ -1,0 +1,683 @@
+// les_oracle.cpp -- plain, slow FP64 CPU oracle of the LES residual and the
+// five-stage Runge-Kutta step.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+// call this file; only the tests, the smoke check and the CPU-baseline leg of
+// the benchmark do.  It shares no source with the GPU path.
+//
+// What it computes (paper: "Strong Scaling of Numerical Solver for Supersonic
+// Jet Flow Configurations", arXiv 2003.08746):
+//   * Sec. 3, Eq. (1)-(15): filtered compressible Navier-Stokes written as
+//     dQ/dt = -RHS with Q = [rho, rho u_i, e]; e = p/(gamma-1) + rho u_i u_i/2
+//     (Eq. 2); p = rho R T (Eq. 7); Sutherland viscosity (Eq. 6); Fourier heat
+//     flux with kappa = mu Cp / Pr (Eq. 3-4) and kappa_sgs = mu_sgs Cp/Pr_sgs
+//     (Eq. 5); stress tau_ij = 2(mu+mu_sgs)(S_ij - S_kk delta_ij/3) (Eq. 9-10).
+//   * Sec. 3 (end) and Sec. 4: centred finite differences in general
+//     curvilinear coordinates, Turkel-Vatsa anisotropic scalar artificial
+//     dissipation, Jameson's explicit 5-stage 2nd-order Runge-Kutta scheme.
+//   * Sec. 4, Alg. 2: each stage re-evaluates inviscid flux, artificial
+//     dissipation, viscous flux and the RHS at every point, then updates the
+//     conserved vector with coefficient alpha_l; boundary (ghost) values and
+//     the viscosity are refreshed between stages; two ghost layers (Sec. 4,
+//     Fig. 3) because the dissipation uses a five-point stencil.
+//
+// The paper defers the discrete details to other works, so the following
+// readings are fixed here (each one marked where it is used):
+//   R1  strong-conservation form on a stationary grid, index spacing 1, the
+//       state is Q itself and R = J * sum_d d/dxi_d (contravariant flux).
+//   R2  metrics by the conservative (Thomas-Lombard) form with the same
+//       central difference, J from the central-difference determinant; in a
+//       periodic direction the ghost-layer metrics are copies of the interior
+//       metrics at the wrapped index.
+//   R3  node gradients by central differences + chain rule; node fluxes;
+//       face flux = average of the two node fluxes.
+//   R4  heat flux enters the energy flux as +(kappa+kappa_sgs) dT/dx_j
+//       (physical Fourier conduction; the printed sign is inconsistent).
+//   R5  Sutherland: mu = mu_ref (T/T_ref)^(3/2) (1+S)/(T/T_ref+S), S=S1/T_ref.
+//   R6  static Smagorinsky eddy viscosity mu_sgs = rho (Cs D)^2 |S|,
+//       |S| = sqrt(2 S_ij S_ij), D = (1/J)^(1/3), sigma_kk = 0.
+//   R7  Turkel-Vatsa: pressure sensor nu = |p+ - 2p + p-|/(p+ + 2p + p-);
+//       eps2 = k2 max(nu_i, nu_i+1); eps4 = max(0, k4 - eps2);
+//       lambda_d = |U~_d| + c |grad d / J|;
+//       Lambda_d = lambda_d [1 + sum_{e!=d} (lambda_e/lambda_d)^alpha];
+//       face Lambda = mean of the node values; D = Lambda (eps2 dQ - eps4 d3Q).
+//   R8  RK coefficients alpha = (1/4, 1/6, 3/8, 1/2, 1); the full residual is
+//       re-evaluated at every stage.
+//   R9  CFL time step: dt = cfl * min 1/(sum_d lam^_d + 2 nu_v sum_d |grad d|^2),
+//       lam^_d = |U_d| + c |grad d| with physical metrics,
+//       nu_v = max(4/3, gamma/Pr) mu/rho; one global min per step from Q^n.
+//   R10 ghost nodes: a node that is a ghost in a Dirichlet direction keeps its
+//       given (frozen) value; every other ghost node takes the value of the
+//       node whose periodic indices are wrapped into the interior.
+//   R11 non-smooth derivatives (dual numbers): d|x|/dx = sign(x), 0 at 0;
+//       max(a, b) follows a when a >= b.
+//   R12 an optional constant source f on the plane i = i_f: dQ/dt = -R + f.
+//
+// Data layout (all arrays): padded box [nk+4][nj+4][ni+4], i fastest, two
+// ghost layers per side; interior index 0..n-1 is stored at n+2.  Multi-field
+// arrays are [field][box].
+//
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -fPIC -shared.
+// OpenMP only splits loops whose iterations are independent (pointwise work);
+// every reduction is a serial loop.
+
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+// ---------------------------------------------------------------------------
+// Scalar types: double, and a forward-mode dual number for exact tangents.
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual() : v(0.0), d(0.0) {}
+  Dual(double a) : v(a), d(0.0) {}
+  Dual(double a, double b) : v(a), d(b) {}
+};
+static inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+static inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+static inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+static inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+static inline Dual operator/(Dual a, Dual b) {
+  return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+static inline Dual operator+(Dual a, double b) { return Dual(a.v + b, a.d); }
+static inline Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+static inline Dual operator-(Dual a, double b) { return Dual(a.v - b, a.d); }
+static inline Dual operator-(double a, Dual b) { return Dual(a - b.v, -b.d); }
+static inline Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+static inline Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+static inline Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
+static inline Dual operator/(double a, Dual b) { return Dual(a / b.v, -a * b.d / (b.v * b.v)); }
+
+static inline double val(double a) { return a; }
+static inline double val(const Dual& a) { return a.v; }
+
+static inline double s_sqrt(double a) { return std::sqrt(a); }
+static inline Dual s_sqrt(Dual a) {
+  double s = std::sqrt(a.v);
+  return Dual(s, a.d / (2.0 * s));
+}
+static inline double s_pow(double a, double e) { return std::pow(a, e); }
+static inline Dual s_pow(Dual a, double e) {
+  return Dual(std::pow(a.v, e), e * std::pow(a.v, e - 1.0) * a.d);
+}
+// R11: d|x|/dx = sign(x), and 0 at x = 0.
+static inline double s_abs(double a) { return std::fabs(a); }
+static inline Dual s_abs(Dual a) {
+  if (a.v > 0.0) return a;
+  if (a.v < 0.0) return -a;
+  return Dual(0.0, 0.0);
+}
+// R11: max(a, b) follows a when a >= b.
+static inline double s_max(double a, double b) { return a >= b ? a : b; }
+static inline Dual s_max(Dual a, Dual b) { return a.v >= b.v ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Problem description (mirrored by the Python wrapper with ctypes).
+// ---------------------------------------------------------------------------
+extern "C" {
+typedef struct {
+  int ni, nj, nk;  // interior points per direction
+  int bc[3];       // per direction i, j, k: 0 = periodic, 1 = frozen Dirichlet ghosts
+} orc_dims;
+
+typedef struct {
+  double gamma;   // ratio of specific heats
+  double Pr;      // molecular Prandtl number (Eq. 4)
+  double Pr_sgs;  // SGS Prandtl number (Eq. 5)
+  double mu_ref;  // Sutherland reference viscosity at T_ref (Eq. 6)
+  double T_ref;   // Sutherland reference temperature (nondimensional)
+  double S_suth;  // S1 / T_ref (Eq. 6, reading R5)
+  double R_gas;   // gas constant (Eq. 7-8)
+  int sgs;        // 0: mu_sgs = 0 (the paper's runs), 1: static Smagorinsky (R6)
+  double Cs;      // Smagorinsky constant
+  double k2, k4, alpha;  // Turkel-Vatsa constants (R7)
+  double cfl;     // CFL number (R9)
+} orc_params;
+}
+
+namespace {
+
+const int G = 2;  // ghost layers per side
+
+struct Box {
+  int ni, nj, nk, bc[3];
+  int pi, pj, pk;  // padded extents
+  size_t N;        // padded node count
+  explicit Box(const orc_dims& d) {
+    ni = d.ni; nj = d.nj; nk = d.nk;
+    bc[0] = d.bc[0]; bc[1] = d.bc[1]; bc[2] = d.bc[2];
+    pi = ni + 2 * G; pj = nj + 2 * G; pk = nk + 2 * G;
+    N = (size_t)pi * pj * pk;
+  }
+  // index of node (i, j, k) with interior range 0..n-1 and ghosts -2, -1, n, n+1
+  size_t at(int i, int j, int k) const {
+    return ((size_t)(k + G) * pj + (size_t)(j + G)) * pi + (size_t)(i + G);
+  }
+  int n(int d) const { return d == 0 ? ni : (d == 1 ? nj : nk); }
+};
+
+// offset of the unit step in direction d
+static inline void step(int d, int& di, int& dj, int& dk) {
+  di = (d == 0); dj = (d == 1); dk = (d == 2);
+}
+
+// ---------------------------------------------------------------------------
+// R10: ghost fill.
+// ---------------------------------------------------------------------------
+template <class S>
+void fill_ghosts(const Box& b, S* a, int nfields) {
+  for (int f = 0; f < nfields; ++f) {
+    S* q = a + (size_t)f * b.N;
+    for (int k = -G; k < b.nk + G; ++k)
+      for (int j = -G; j < b.nj + G; ++j)
+        for (int i = -G; i < b.ni + G; ++i) {
+          int idx[3] = {i, j, k};
+          bool ghost = false, dirichlet = false;
+          int w[3];
+          for (int d = 0; d < 3; ++d) {
+            int n = b.n(d);
+            bool g = idx[d] < 0 || idx[d] >= n;
+            if (g) {
+              ghost = true;
+              if (b.bc[d] == 1) dirichlet = true;
+            }
+            w[d] = ((idx[d] % n) + n) % n;
+          }
+          if (!ghost || dirichlet) continue;
+          q[b.at(i, j, k)] = q[b.at(w[0], w[1], w[2])];
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// R2: metrics.  m[0..8] = xi_x/J, xi_y/J, xi_z/J, eta_x/J, ..., zeta_z/J;
+// m[9] = J.  Defined on every node with all indices in [-1, n]; NaN elsewhere.
+// ---------------------------------------------------------------------------
+void metrics(const Box& b, const double* xyz, double* m) {
+  const double* X[3] = {xyz, xyz + b.N, xyz + 2 * b.N};
+  const double nan = std::nan("");
+  for (int c = 0; c < 10; ++c)
+    for (size_t n = 0; n < b.N; ++n) m[(size_t)c * b.N + n] = nan;
+
+  // first derivatives of the coordinates, dX[c][d] = delta_d x_c, on [-2+1, n+1-1]
+  // along d and on the full padded range in the other directions.
+  std::vector<double> dX(9 * b.N, nan);
+  for (int c = 0; c < 3; ++c)
+    for (int d = 0; d < 3; ++d) {
+      int di, dj, dk;
+      step(d, di, dj, dk);
+      double* out = &dX[(size_t)(3 * c + d) * b.N];
+      for (int k = -G; k < b.nk + G; ++k)
+        for (int j = -G; j < b.nj + G; ++j)
+          for (int i = -G; i < b.ni + G; ++i) {
+            int id[3] = {i, j, k};
+            if (id[d] - 1 < -G || id[d] + 1 >= b.n(d) + G) continue;
+            out[b.at(i, j, k)] =
+                0.5 * (X[c][b.at(i + di, j + dj, k + dk)] - X[c][b.at(i - di, j - dj, k - dk)]);
+          }
+    }
+  auto dx = [&](int c, int d, int i, int j, int k) { return dX[(size_t)(3 * c + d) * b.N + b.at(i, j, k)]; };
+
+  // Conservative form: the metric row of direction a (cyclic a, b=a+1, c=a+2)
+  // component x_l (with cyclic l, l+1, l+2 as x, y, z):
+  //   (a_{x_l}) / J = delta_c[(delta_b y_{l+1}) y_{l+2}] - delta_b[(delta_c y_{l+1}) y_{l+2}]
+  // e.g. xi_x/J = delta_zeta[(delta_eta y) z] - delta_eta[(delta_zeta y) z].
+  for (int a = 0; a < 3; ++a) {
+    int bd = (a + 1) % 3, cd = (a + 2) % 3;
+    int bi, bj, bk, ci, cj, ck;
+    step(bd, bi, bj, bk);
+    step(cd, ci, cj, ck);
+    for (int l = 0; l < 3; ++l) {
+      int l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+      double* out = m + (size_t)(3 * a + l) * b.N;
+      for (int k = -1; k <= b.nk; ++k)
+        for (int j = -1; j <= b.nj; ++j)
+          for (int i = -1; i <= b.ni; ++i) {
+            // delta_c [ (delta_b x_l1) x_l2 ]
+            double t1 = 0.5 * (dx(l1, bd, i + ci, j + cj, k + ck) * X[l2][b.at(i + ci, j + cj, k + ck)] -
+                               dx(l1, bd, i - ci, j - cj, k - ck) * X[l2][b.at(i - ci, j - cj, k - ck)]);
+            // delta_b [ (delta_c x_l1) x_l2 ]
+            double t2 = 0.5 * (dx(l1, cd, i + bi, j + bj, k + bk) * X[l2][b.at(i + bi, j + bj, k + bk)] -
+                               dx(l1, cd, i - bi, j - bj, k - bk) * X[l2][b.at(i - bi, j - bj, k - bk)]);
+            out[b.at(i, j, k)] = t1 - t2;
+          }
+    }
+  }
+  // 1/J = det d(x,y,z)/d(xi,eta,zeta) with central differences; J = 1/(1/J).
+  double* Jout = m + (size_t)9 * b.N;
+  for (int k = -1; k <= b.nk; ++k)
+    for (int j = -1; j <= b.nj; ++j)
+      for (int i = -1; i <= b.ni; ++i) {
+        double a11 = dx(0, 0, i, j, k), a12 = dx(0, 1, i, j, k), a13 = dx(0, 2, i, j, k);
+        double a21 = dx(1, 0, i, j, k), a22 = dx(1, 1, i, j, k), a23 = dx(1, 2, i, j, k);
+        double a31 = dx(2, 0, i, j, k), a32 = dx(2, 1, i, j, k), a33 = dx(2, 2, i, j, k);
+        double vol = a11 * (a22 * a33 - a23 * a32) - a12 * (a21 * a33 - a23 * a31) + a13 * (a21 * a32 - a22 * a31);
+        Jout[b.at(i, j, k)] = 1.0 / vol;
+      }
+  // R2: periodic directions take wrapped interior metrics in their ghost layer.
+  for (int c = 0; c < 10; ++c) {
+    double* q = m + (size_t)c * b.N;
+    for (int k = -1; k <= b.nk; ++k)
+      for (int j = -1; j <= b.nj; ++j)
+        for (int i = -1; i <= b.ni; ++i) {
+          int id[3] = {i, j, k}, w[3];
+          bool any = false;
+          for (int d = 0; d < 3; ++d) {
+            int n = b.n(d);
+            w[d] = id[d];
+            if (b.bc[d] == 0 && (id[d] < 0 || id[d] >= n)) {
+              w[d] = ((id[d] % n) + n) % n;
+              any = true;
+            }
+          }
+          if (any) q[b.at(i, j, k)] = q[b.at(w[0], w[1], w[2])];
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual R(Q) at interior nodes (R1-R7, R12).  Q must have its ghosts
+// filled.  Everything is computed on the box B1 = [-1, n]^3 with separate
+// arrays for every intermediate.
+// ---------------------------------------------------------------------------
+template <class S>
+void residual(const Box& b, const orc_params& P, const double* m, const S* Q, const S* f, int i_f, S* R) {
+  const size_t N = b.N;
+  const double g = P.gamma;
+  const double Cp = g * P.R_gas / (g - 1.0);
+  const S* Qv[5] = {Q, Q + N, Q + 2 * N, Q + 3 * N, Q + 4 * N};
+  const double* M[10];
+  for (int c = 0; c < 10; ++c) M[c] = m + (size_t)c * N;
+
+  // --- node primitives on the full padded box (Eq. 2, 6, 7) ---
+  std::vector<S> rho(N), u(N), v(N), w(N), p(N), T(N), c(N), mu(N);
+#pragma omp parallel for
+  for (int k = -G; k < b.nk + G; ++k)
+    for (int j = -G; j < b.nj + G; ++j)
+      for (int i = -G; i < b.ni + G; ++i) {
+        size_t n = b.at(i, j, k);
+        rho[n] = Qv[0][n];
+        u[n] = Qv[1][n] / rho[n];
+        v[n] = Qv[2][n] / rho[n];
+        w[n] = Qv[3][n] / rho[n];
+        p[n] = (g - 1.0) * (Qv[4][n] - 0.5 * rho[n] * (u[n] * u[n] + v[n] * v[n] + w[n] * w[n]));
+        T[n] = p[n] / (rho[n] * P.R_gas);
+        c[n] = s_sqrt(g * p[n] / rho[n]);
+        S th = T[n] / P.T_ref;
+        mu[n] = P.mu_ref * s_pow(th, 1.5) * (1.0 + P.S_suth) / (th + P.S_suth);
+      }
+
+  // --- node gradients of u, v, w, T on B1 (R3): grad[q][x] ---
+  // q = 0..3 for u, v, w, T;  x = 0..2 for d/dx, d/dy, d/dz.
+  std::vector<S> grad(12 * N);
+  const std::vector<S>* phi[4] = {&u, &v, &w, &T};
+#pragma omp parallel for
+  for (int k = -1; k <= b.nk; ++k)
+    for (int j = -1; j <= b.nj; ++j)
+      for (int i = -1; i <= b.ni; ++i) {
+        size_t n = b.at(i, j, k);
+        double Jn = M[9][n];
+        for (int q = 0; q < 4; ++q) {
+          const std::vector<S>& F = *phi[q];
+          S dxi = 0.5 * (F[b.at(i + 1, j, k)] - F[b.at(i - 1, j, k)]);
+          S deta = 0.5 * (F[b.at(i, j + 1, k)] - F[b.at(i, j - 1, k)]);
+          S dzeta = 0.5 * (F[b.at(i, j, k + 1)] - F[b.at(i, j, k - 1)]);
+          for (int x = 0; x < 3; ++x)
+            grad[(size_t)(3 * q + x) * N + n] = Jn * (M[0 + x][n] * dxi + M[3 + x][n] * deta + M[6 + x][n] * dzeta);
+        }
+      }
+
+  // --- stress, SGS viscosity and the energy-flux vector Theta on B1 ---
+  // tau[3*a+b] (symmetric), Theta[x] = u_i tau_ix + (kappa + kappa_sgs) dT/dx
+  std::vector<S> tau(9 * N), Theta(3 * N);
+#pragma omp parallel for
+  for (int k = -1; k <= b.nk; ++k)
+    for (int j = -1; j <= b.nj; ++j)
+      for (int i = -1; i <= b.ni; ++i) {
+        size_t n = b.at(i, j, k);
+        S du[3][3];  // du[a][x] = d u_a / d x
+        for (int a = 0; a < 3; ++a)
+          for (int x = 0; x < 3; ++x) du[a][x] = grad[(size_t)(3 * a + x) * N + n];
+        S Sij[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int x = 0; x < 3; ++x) Sij[a][x] = 0.5 * (du[a][x] + du[x][a]);
+        S Skk = Sij[0][0] + Sij[1][1] + Sij[2][2];
+        S mu_sgs = 0.0;
+        if (P.sgs) {
+          S SS = 0.0;
+          for (int a = 0; a < 3; ++a)
+            for (int x = 0; x < 3; ++x) SS = SS + Sij[a][x] * Sij[a][x];
+          S Smag = s_sqrt(2.0 * SS);
+          double Delta = std::cbrt(1.0 / M[9][n]);
+          mu_sgs = rho[n] * (P.Cs * Delta) * (P.Cs * Delta) * Smag;
+        }
+        S mut = mu[n] + mu_sgs;
+        for (int a = 0; a < 3; ++a)
+          for (int x = 0; x < 3; ++x)
+            tau[(size_t)(3 * a + x) * N + n] = 2.0 * mut * (Sij[a][x] - (a == x ? Skk / 3.0 : S(0.0)));
+        S kap = mu[n] * Cp / P.Pr + mu_sgs * Cp / P.Pr_sgs;
+        S uu[3] = {u[n], v[n], w[n]};
+        for (int x = 0; x < 3; ++x) {
+          S t = 0.0;
+          for (int a = 0; a < 3; ++a) t = t + uu[a] * tau[(size_t)(3 * a + x) * N + n];
+          Theta[(size_t)x * N + n] = t + kap * grad[(size_t)(9 + x) * N + n];  // R4
+        }
+      }
+
+  // --- node fluxes H_d = E^_d - Ev^_d on B1, d = xi, eta, zeta (Eq. 15) ---
+  std::vector<S> H(15 * N);
+#pragma omp parallel for
+  for (int k = -1; k <= b.nk; ++k)
+    for (int j = -1; j <= b.nj; ++j)
+      for (int i = -1; i <= b.ni; ++i) {
+        size_t n = b.at(i, j, k);
+        for (int d = 0; d < 3; ++d) {
+          double mx = M[3 * d][n], my = M[3 * d + 1][n], mz = M[3 * d + 2][n];
+          S U = mx * u[n] + my * v[n] + mz * w[n];
+          S E[5];
+          E[0] = rho[n] * U;
+          E[1] = rho[n] * u[n] * U + mx * p[n];
+          E[2] = rho[n] * v[n] * U + my * p[n];
+          E[3] = rho[n] * w[n] * U + mz * p[n];
+          E[4] = (Qv[4][n] + p[n]) * U;
+          S Ev[5];
+          Ev[0] = 0.0;
+          for (int a = 0; a < 3; ++a)
+            Ev[1 + a] = mx * tau[(size_t)(3 * a + 0) * N + n] + my * tau[(size_t)(3 * a + 1) * N + n] +
+                        mz * tau[(size_t)(3 * a + 2) * N + n];
+          Ev[4] = mx * Theta[n] + my * Theta[N + n] + mz * Theta[2 * N + n];
+          for (int q = 0; q < 5; ++q) H[(size_t)(5 * d + q) * N + n] = E[q] - Ev[q];
+        }
+      }
+
+  // --- spectral radii, anisotropic scaling and pressure sensor on B1 (R7) ---
+  std::vector<S> lam(3 * N), Lam(3 * N), nu(3 * N);
+#pragma omp parallel for
+  for (int k = -1; k <= b.nk; ++k)
+    for (int j = -1; j <= b.nj; ++j)
+      for (int i = -1; i <= b.ni; ++i) {
+        size_t n = b.at(i, j, k);
+        for (int d = 0; d < 3; ++d) {
+          double mx = M[3 * d][n], my = M[3 * d + 1][n], mz = M[3 * d + 2][n];
+          S U = mx * u[n] + my * v[n] + mz * w[n];
+          lam[(size_t)d * N + n] = s_abs(U) + c[n] * std::sqrt(mx * mx + my * my + mz * mz);
+        }
+      }
+#pragma omp parallel for
+  for (int k = -1; k <= b.nk; ++k)
+    for (int j = -1; j <= b.nj; ++j)
+      for (int i = -1; i <= b.ni; ++i) {
+        size_t n = b.at(i, j, k);
+        for (int d = 0; d < 3; ++d) {
+          S ld = lam[(size_t)d * N + n];
+          S le = lam[(size_t)((d + 1) % 3) * N + n];
+          S lf = lam[(size_t)((d + 2) % 3) * N + n];
+          Lam[(size_t)d * N + n] = ld * (1.0 + s_pow(le / ld, P.alpha) + s_pow(lf / ld, P.alpha));
+          int di, dj, dk;
+          step(d, di, dj, dk);
+          S pp = p[b.at(i + di, j + dj, k + dk)], pm = p[b.at(i - di, j - dj, k - dk)];
+          nu[(size_t)d * N + n] = s_abs(pp - 2.0 * p[n] + pm) / (pp + 2.0 * p[n] + pm);
+        }
+      }
+
+  // --- face fluxes F = (H_a + H_b)/2 - D, stored at the lower node a ---
+  // faces exist for a = -1..n-1 along d, interior in the other directions.
+  std::vector<S> F(15 * N);
+  for (int d = 0; d < 3; ++d) {
+    int di, dj, dk;
+    step(d, di, dj, dk);
+#pragma omp parallel for
+    for (int k = -1; k < b.nk; ++k)
+      for (int j = -1; j < b.nj; ++j)
+        for (int i = -1; i < b.ni; ++i) {
+          int id[3] = {i, j, k};
+          bool ok = true;
+          for (int e = 0; e < 3; ++e)
+            if (e != d && id[e] < 0) ok = false;
+          if (!ok) continue;
+          size_t a = b.at(i, j, k);
+          size_t bb = b.at(i + di, j + dj, k + dk);
+          size_t am = b.at(i - di, j - dj, k - dk);
+          size_t bp = b.at(i + 2 * di, j + 2 * dj, k + 2 * dk);
+          S eps2 = P.k2 * s_max(nu[(size_t)d * N + a], nu[(size_t)d * N + bb]);
+          S eps4 = s_max(S(0.0), P.k4 - eps2);
+          S Lf = 0.5 * (Lam[(size_t)d * N + a] + Lam[(size_t)d * N + bb]);
+          for (int q = 0; q < 5; ++q) {
+            S d1 = Qv[q][bb] - Qv[q][a];
+            S d3 = Qv[q][bp] - 3.0 * Qv[q][bb] + 3.0 * Qv[q][a] - Qv[q][am];
+            S D = Lf * (eps2 * d1 - eps4 * d3);
+            F[(size_t)(5 * d + q) * N + a] = 0.5 * (H[(size_t)(5 * d + q) * N + a] + H[(size_t)(5 * d + q) * N + bb]) - D;
+          }
+        }
+  }
+
+  // --- residual at interior nodes (R1, R12) ---
+  for (size_t n = 0; n < 5 * N; ++n) R[n] = 0.0;
+#pragma omp parallel for
+  for (int k = 0; k < b.nk; ++k)
+    for (int j = 0; j < b.nj; ++j)
+      for (int i = 0; i < b.ni; ++i) {
+        size_t n = b.at(i, j, k);
+        for (int q = 0; q < 5; ++q) {
+          S s = 0.0;
+          s = s + (F[(size_t)(0 + q) * N + n] - F[(size_t)(0 + q) * N + b.at(i - 1, j, k)]);
+          s = s + (F[(size_t)(5 + q) * N + n] - F[(size_t)(5 + q) * N + b.at(i, j - 1, k)]);
+          s = s + (F[(size_t)(10 + q) * N + n] - F[(size_t)(10 + q) * N + b.at(i, j, k - 1)]);
+          S r = M[9][n] * s;
+          if (f && i == i_f) r = r - f[((size_t)q * b.nk + k) * b.nj + j];
+          R[(size_t)q * N + n] = r;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// R9: CFL time step from the interior of Q (no ghosts needed).
+// ---------------------------------------------------------------------------
+double cfl_dt(const Box& b, const orc_params& P, const double* m, const double* Q) {
+  const size_t N = b.N;
+  const double g = P.gamma;
+  double best = INFINITY;
+  for (int k = 0; k < b.nk; ++k)
+    for (int j = 0; j < b.nj; ++j)
+      for (int i = 0; i < b.ni; ++i) {
+        size_t n = b.at(i, j, k);
+        double rho = Q[n], u = Q[N + n] / rho, v = Q[2 * N + n] / rho, w = Q[3 * N + n] / rho;
+        double p = (g - 1.0) * (Q[4 * N + n] - 0.5 * rho * (u * u + v * v + w * w));
+        double T = p / (rho * P.R_gas);
+        double c = std::sqrt(g * p / rho);
+        double th = T / P.T_ref;
+        double mu = P.mu_ref * std::pow(th, 1.5) * (1.0 + P.S_suth) / (th + P.S_suth);
+        double nuv = std::max(4.0 / 3.0, g / P.Pr) * mu / rho;
+        double J = m[9 * N + n];
+        double lam = 0.0, g2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          double gx = J * m[(3 * d) * N + n], gy = J * m[(3 * d + 1) * N + n], gz = J * m[(3 * d + 2) * N + n];
+          double U = gx * u + gy * v + gz * w;
+          double gg = gx * gx + gy * gy + gz * gz;
+          lam += std::fabs(U) + c * std::sqrt(gg);
+          g2 += gg;
+        }
+        double loc = 1.0 / (lam + 2.0 * nuv * g2);
+        if (loc < best) best = loc;
+      }
+  return P.cfl * best;
+}
+
+const double RK_ALPHA[5] = {0.25, 1.0 / 6.0, 0.375, 0.5, 1.0};
+
+// ---------------------------------------------------------------------------
+// One RK step (R8).  Q: padded [5][N], in/out (interior = Q^{n+1} on return;
+// ghosts = the filled ghosts of Q^n).  stages (optional): [5][5][N] receives
+// the stage inputs Q^(0..4) with their ghosts filled.  norms (optional):
+// L2 (RMS) then Linf of R(Q^n) per variable.
+// ---------------------------------------------------------------------------
+template <class S>
+void rk_step(const Box& b, const orc_params& P, const double* m, S* Q, double dt, const S* f, int i_f,
+             double* norms, S* stages) {
+  const size_t N = b.N;
+  fill_ghosts(b, Q, 5);
+  std::vector<S> Q0(Q, Q + 5 * N), cur(Q, Q + 5 * N), R(5 * N);
+  for (int l = 0; l < 5; ++l) {
+    fill_ghosts(b, cur.data(), 5);
+    if (stages) std::copy(cur.begin(), cur.end(), stages + (size_t)l * 5 * N);
+    residual(b, P, m, cur.data(), f, i_f, R.data());
+    if (l == 0 && norms) {
+      size_t cnt = (size_t)b.ni * b.nj * b.nk;
+      for (int q = 0; q < 5; ++q) {
+        double s2 = 0.0, mx = 0.0;
+        for (int k = 0; k < b.nk; ++k)
+          for (int j = 0; j < b.nj; ++j)
+            for (int i = 0; i < b.ni; ++i) {
+              double r = val(R[(size_t)q * N + b.at(i, j, k)]);
+              s2 += r * r;
+              if (std::fabs(r) > mx || std::isnan(r)) mx = std::isnan(r) ? r : std::fabs(r);
+            }
+        norms[q] = std::sqrt(s2 / (double)cnt);
+        norms[5 + q] = mx;
+      }
+    }
+    std::vector<S> nxt(Q0);
+#pragma omp parallel for
+    for (int k = 0; k < b.nk; ++k)
+      for (int j = 0; j < b.nj; ++j)
+        for (int i = 0; i < b.ni; ++i) {
+          size_t n = b.at(i, j, k);
+          for (int q = 0; q < 5; ++q)
+            nxt[(size_t)q * N + n] = Q0[(size_t)q * N + n] - (RK_ALPHA[l] * dt) * R[(size_t)q * N + n];
+        }
+    cur.swap(nxt);
+  }
+  for (int k = 0; k < b.nk; ++k)
+    for (int j = 0; j < b.nj; ++j)
+      for (int i = 0; i < b.ni; ++i) {
+        size_t n = b.at(i, j, k);
+        for (int q = 0; q < 5; ++q) Q[(size_t)q * N + n] = cur[(size_t)q * N + n];
+      }
+}
+
+template <class S>
+S probe_pressure_sq(const Box& b, const orc_params& P, const S* Q, int i_p, double p_inf) {
+  const size_t N = b.N;
+  const double g = P.gamma;
+  S acc = 0.0;
+  for (int k = 0; k < b.nk; ++k)
+    for (int j = 0; j < b.nj; ++j) {
+      size_t n = b.at(i_p, j, k);
+      S rho = Q[n], u = Q[N + n] / rho, v = Q[2 * N + n] / rho, w = Q[3 * N + n] / rho;
+      S p = (g - 1.0) * (Q[4 * N + n] - 0.5 * rho * (u * u + v * v + w * w));
+      S dp = p - p_inf;
+      acc = acc + dp * dp;
+    }
+  return acc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C API
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t orc_box_nodes(const orc_dims* d) { return Box(*d).N; }
+
+void orc_metrics(const orc_dims* d, const double* xyz, double* m) { metrics(Box(*d), xyz, m); }
+
+void orc_fill_ghosts(const orc_dims* d, double* a, int nfields) { fill_ghosts(Box(*d), a, nfields); }
+
+// R of a state (ghosts of a copy are filled first).  f: [5][nk][nj] or NULL.
+void orc_residual(const orc_dims* d, const orc_params* P, const double* m, const double* Q, const double* f, int i_f,
+                  double* R) {
+  Box b(*d);
+  std::vector<double> q(Q, Q + 5 * b.N);
+  fill_ghosts(b, q.data(), 5);
+  residual(b, *P, m, q.data(), f, i_f, R);
+}
+
+// Tangent of the residual: dR = (dR/dQ) dQ + (dR/df) df (ghosts of copies filled).
+void orc_residual_tangent(const orc_dims* d, const orc_params* P, const double* m, const double* Q, const double* dQ,
+                          const double* f, const double* df, int i_f, double* R, double* dR) {
+  Box b(*d);
+  std::vector<Dual> q(5 * b.N), r(5 * b.N);
+  for (size_t n = 0; n < 5 * b.N; ++n) q[n] = Dual(Q[n], dQ ? dQ[n] : 0.0);
+  fill_ghosts(b, q.data(), 5);
+  std::vector<Dual> fd;
+  if (f) {
+    size_t nf = (size_t)5 * b.nk * b.nj;
+    fd.resize(nf);
+    for (size_t n = 0; n < nf; ++n) fd[n] = Dual(f[n], df ? df[n] : 0.0);
+  }
+  residual(b, *P, m, q.data(), f ? fd.data() : nullptr, i_f, r.data());
+  for (size_t n = 0; n < 5 * b.N; ++n) {
+    R[n] = r[n].v;
+    dR[n] = r[n].d;
+  }
+}
+
+double orc_cfl_dt(const orc_dims* d, const orc_params* P, const double* m, const double* Q) {
+  return cfl_dt(Box(*d), *P, m, Q);
+}
+
+// One RK step.  dt <= 0 selects the CFL time step from Q^n.  Returns the dt used.
+double orc_rk_step(const orc_dims* d, const orc_params* P, const double* m, double* Q, double dt, const double* f,
+                   int i_f, double* norms, double* stages) {
+  Box b(*d);
+  if (!(dt > 0.0)) dt = cfl_dt(b, *P, m, Q);
+  rk_step(b, *P, m, Q, dt, f, i_f, norms, stages);
+  return dt;
+}
+
+// Objective of the differentiation workload: run nsteps RK steps at fixed dt
+// from Q0 with source f on plane i_f, and return
+//   J = sum_{n=1..nsteps} dt * sum_{j,k} (p(Q^n)_{i_p,j,k} - p_inf)^2
+// together with its directional derivative along (dQ0, df) in *dJ.
+// Q0 is overwritten with Q^nsteps.
+double orc_objective_rollout(const orc_dims* d, const orc_params* P, const double* m, double* Q0, const double* dQ0,
+                             const double* f, const double* df, int i_f, int i_p, double p_inf, int nsteps, double dt,
+                             double* dJ) {
+  Box b(*d);
+  std::vector<Dual> q(5 * b.N);
+  for (size_t n = 0; n < 5 * b.N; ++n) q[n] = Dual(Q0[n], dQ0 ? dQ0[n] : 0.0);
+  size_t nf = (size_t)5 * b.nk * b.nj;
+  std::vector<Dual> fd(nf);
+  for (size_t n = 0; n < nf; ++n) fd[n] = Dual(f ? f[n] : 0.0, df ? df[n] : 0.0);
+  Dual J = 0.0;
+  for (int s = 0; s < nsteps; ++s) {
+    rk_step(b, *P, m, q.data(), dt, fd.data(), i_f, nullptr, (Dual*)nullptr);
+    J = J + dt * probe_pressure_sq(b, *P, q.data(), i_p, p_inf);
+  }
+  for (size_t n = 0; n < 5 * b.N; ++n) Q0[n] = q[n].v;
+  if (dJ) *dJ = J.d;
+  return J.v;
+}
+
+// Plain-double objective (same definition) for finite differences.
+double orc_objective(const orc_dims* d, const orc_params* P, const double* m, double* Q0, const double* f, int i_f,
+                     int i_p, double p_inf, int nsteps, double dt) {
+  Box b(*d);
+  double J = 0.0;
+  for (int s = 0; s < nsteps; ++s) {
+    rk_step(b, *P, m, Q0, dt, f, i_f, nullptr, (double*)nullptr);
+    J += dt * probe_pressure_sq(b, *P, Q0, i_p, p_inf);
+  }
+  return J;
+}
+
+// Test hook for the scalar rules R11 and the RK driver on y' = lambda y
+// (complex lambda), used to check the amplification polynomial.
+void orc_rk_scalar(double lr, double li, double dt, double* yr, double* yi) {
+  double y0r = *yr, y0i = *yi, cr = y0r, ci = y0i;
+  for (int l = 0; l < 5; ++l) {
+    // R(y) = -lambda y  (dy/dt = -R)
+    double Rr = -(lr * cr - li * ci), Ri = -(lr * ci + li * cr);
+    cr = y0r - RK_ALPHA[l] * dt * Rr;
+    ci = y0i - RK_ALPHA[l] * dt * Ri;
+  }
+  *yr = cr;
+  *yi = ci;
+}
+
+}  // extern "C"

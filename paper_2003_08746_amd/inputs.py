@@ -1,0 +1,207 @@
+"""Seeded synthetic inputs: grids, flow parameters and initial states.
+
+This module builds inputs only.  It holds none of the method's arithmetic
+(no metrics, fluxes, dissipation, residual or time stepping); the one physical
+relation it uses is the ideal-gas total energy e = p/(gamma-1) + rho|u|^2/2
+(paper Eq. 2) to turn an analytic primitive field into the conserved input
+state.  Both the oracle tests and the GPU path consume these arrays.
+
+Every array is float64 on the padded box (nfields, nk+4, nj+4, ni+4): two
+ghost layers per side, i fastest; interior index 0..n-1 is stored at n+2.
+Coordinates are given on every node of the padded box; in a periodic
+direction the ghost coordinates are the period-shifted images (the analytic
+mappings below are periodic up to a translation, so evaluating them at the
+ghost indices gives exactly that).
+
+Workloads (nondimensional, acoustic scaling rho_inf = T_inf = c_inf = 1,
+R = 1/gamma, p_inf = 1/gamma):
+  * ``tgv_case``: Taylor-Green vortex, Mach 0.1, Re 1600, unit Cartesian
+    metrics, periodic in all three directions.
+  * ``jet_case``: one GPU's share of the paper's jet (Sec. 5.1): perfectly
+    expanded Mach 1.4 jet, PR = TR = 1, Re_D = 1.57e6, on a stretched,
+    smoothly wavy curvilinear grid (tanh clustering across the shear layers),
+    periodic in i (axial) and k (spanwise), frozen far-field ghosts in j.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def flow_params(**over) -> dict:
+    """Default flow/scheme parameters (jet values); keyword overrides."""
+    p = dict(
+        gamma=GAMMA,
+        Pr=0.72,               # paper Eq. 4
+        Pr_sgs=0.9,            # paper Eq. 5 (static closure)
+        mu_ref=1.4 / 1.57e6,   # rho_j U_j D / Re_D with U_j = M_j c_inf = 1.4, D = 1
+        T_ref=1.0,
+        S_suth=110.4 / 288.15, # Sutherland S1 = 110.4 K over a 288.15 K reference
+        R_gas=1.0 / GAMMA,
+        sgs=1,
+        Cs=0.17,
+        k2=0.25,
+        k4=1.0 / 64.0,
+        alpha=0.5,
+        cfl=0.5,
+    )
+    p.update(over)
+    return p
+
+
+def padded_indices(n: int) -> np.ndarray:
+    """Index values -2 .. n+1 of one padded axis."""
+    return np.arange(-2, n + 2, dtype=np.float64)
+
+
+def cons_from_prim(rho, u, v, w, p, gamma=GAMMA) -> np.ndarray:
+    """Conserved input state [rho, rho u, rho v, rho w, e] (Eq. 2)."""
+    e = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.ascontiguousarray(np.stack([rho, rho * u, rho * v, rho * w, e]), dtype=np.float64)
+
+
+def _mesh(ni, nj, nk):
+    I = padded_indices(ni)[None, None, :]
+    J = padded_indices(nj)[None, :, None]
+    K = padded_indices(nk)[:, None, None]
+    return I, J, K
+
+
+# ---------------------------------------------------------------------------
+# Taylor-Green vortex on the unit Cartesian box
+# ---------------------------------------------------------------------------
+def tgv_case(n: int = 32, mach: float = 0.1, re: float = 1600.0, sgs: int = 1) -> dict:
+    I, J, K = _mesh(n, n, n)
+    shape = (n + 4, n + 4, n + 4)
+    x = np.broadcast_to(I, shape)
+    y = np.broadcast_to(J, shape)
+    z = np.broadcast_to(K, shape)
+    xyz = np.ascontiguousarray(np.stack([x, y, z]), dtype=np.float64)
+    L = n / (2.0 * math.pi)
+    V0 = mach  # c0 = 1
+    rho0, p0 = 1.0, 1.0 / GAMMA
+    u = V0 * np.sin(x / L) * np.cos(y / L) * np.cos(z / L)
+    v = -V0 * np.cos(x / L) * np.sin(y / L) * np.cos(z / L)
+    w = np.zeros(shape)
+    p = p0 + rho0 * V0 * V0 / 16.0 * (np.cos(2 * x / L) + np.cos(2 * y / L)) * (np.cos(2 * z / L) + 2.0)
+    rho = p / (flow_params()["R_gas"] * 1.0)  # uniform T0 = 1
+    Q = cons_from_prim(rho, u, v, w, p)
+    prm = flow_params(mu_ref=rho0 * V0 * L / re, sgs=sgs)
+    return dict(name=f"tgv{n}", ni=n, nj=n, nk=n, bc=(0, 0, 0), xyz=xyz, Q=Q, params=prm,
+                p_inf=p0, period=(float(n), float(n), float(n)))
+
+
+# ---------------------------------------------------------------------------
+# Jet shard grid: tanh clustering in j plus a smooth wavy mapping.
+# ---------------------------------------------------------------------------
+def _logcosh(x):
+    return np.logaddexp(x, -x) - math.log(2.0)
+
+
+def _cluster(t, a=0.8, w=0.05, tR=0.55):
+    """Integral of 1 - (a/2)[tanh((t+tR)/w) - tanh((t-tR)/w)]: spacing is
+    (1-a) times the outer spacing for |t| < tR."""
+    return t - a * (w / 2.0) * (_logcosh((t + tR) / w) - _logcosh((t - tR) / w))
+
+
+def jet_grid(ni, nj, nk, Lx=7.5, Ly=10.0, Lz=2.5, m=2, amp=0.2) -> np.ndarray:
+    """Coordinates (3, nk+4, nj+4, ni+4) of the curvilinear jet shard."""
+    I, J, K = _mesh(ni, nj, nk)
+    t = -1.0 + 2.0 * J / (nj - 1)
+    Y1 = _cluster(np.array([1.0]))[0]
+    Y = (Ly / 2.0) * _cluster(t) / Y1
+    tin = -1.0 + 2.0 * np.arange(nj) / (nj - 1)
+    dY = np.diff((Ly / 2.0) * _cluster(tin) / Y1).min()
+    W = np.sin(2 * math.pi * m * I / ni) * np.sin(2 * math.pi * m * K / nk) * np.cos(math.pi * t)
+    shape = (nk + 4, nj + 4, ni + 4)
+    x = np.broadcast_to(Lx * I / ni + amp * (Lx / ni) * W, shape)
+    y = np.broadcast_to(Y + amp * dY * W, shape)
+    z = np.broadcast_to(Lz * K / nk + amp * (Lz / nk) * W, shape)
+    return np.ascontiguousarray(np.stack([x, y, z]), dtype=np.float64)
+
+
+def jet_state(xyz: np.ndarray, ni, nj, nk, seed=0, mach=1.4, R=0.5, theta=0.05, pert=0.01) -> np.ndarray:
+    """Perfectly expanded jet: tanh double shear layer in y, Crocco-Busemann
+    temperature (TR = 1), uniform p = p_inf, seeded velocity perturbations on
+    the interior (uniform in [-1, 1], times a shear-layer envelope)."""
+    y = xyz[1]
+    Uj = mach
+    u = 0.5 * Uj * (np.tanh((R + y) / (2 * theta)) + np.tanh((R - y) / (2 * theta)))
+    s = u / Uj
+    T = 1.0 + 0.5 * (GAMMA - 1.0) * mach * mach * s * (1.0 - s)
+    p = np.full_like(u, 1.0 / GAMMA)
+    rho = p / ((1.0 / GAMMA) * T)
+    env = 4.0 * s * (1.0 - s)
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(-1.0, 1.0, size=(3, nk, nj, ni))
+    vel = [u.copy(), np.zeros_like(u), np.zeros_like(u)]
+    inner = (slice(2, nk + 2), slice(2, nj + 2), slice(2, ni + 2))
+    for c in range(3):
+        vel[c][inner] += pert * Uj * r[c] * env[inner]
+    return cons_from_prim(rho, vel[0], vel[1], vel[2], p)
+
+
+def jet_case(ni=256, nj=128, nk=128, seed=0, **kw) -> dict:
+    scale = dict(Lx=7.5 * ni / 256, Ly=10.0, Lz=2.5 * nk / 128)
+    scale.update({k: kw.pop(k) for k in list(kw) if k in ("Lx", "Ly", "Lz")})
+    xyz = jet_grid(ni, nj, nk, **scale)
+    Q = jet_state(xyz, ni, nj, nk, seed=seed)
+    prm = flow_params(**kw)
+    return dict(name=f"jet{ni}x{nj}x{nk}", ni=ni, nj=nj, nk=nk, bc=(0, 1, 0), xyz=xyz, Q=Q, params=prm,
+                p_inf=1.0 / GAMMA, period=(scale["Lx"], None, scale["Lz"]))
+
+
+# ---------------------------------------------------------------------------
+# Generic test grids and states
+# ---------------------------------------------------------------------------
+def wavy_grid(ni, nj, nk, L=(1.0, 1.0, 1.0), amp=0.15, m=1) -> np.ndarray:
+    """A box periodic in all three directions (periods L) with a smooth wavy
+    interior mapping; every metric term is non-trivial."""
+    I, J, K = _mesh(ni, nj, nk)
+    a, b, c = 2 * math.pi * m * I / ni, 2 * math.pi * m * J / nj, 2 * math.pi * m * K / nk
+    W1 = np.sin(a) * np.sin(b) * np.sin(c)
+    W2 = np.sin(a + 0.3) * np.cos(b) * np.sin(2 * c)
+    W3 = np.cos(a) * np.sin(2 * b + 0.1) * np.sin(c)
+    shape = (nk + 4, nj + 4, ni + 4)
+    x = np.broadcast_to(L[0] * (I / ni + amp / ni * (W1 + 0.5 * W2)), shape)
+    y = np.broadcast_to(L[1] * (J / nj + amp / nj * (W2 + 0.5 * W3)), shape)
+    z = np.broadcast_to(L[2] * (K / nk + amp / nk * (W3 + 0.5 * W1)), shape)
+    return np.ascontiguousarray(np.stack([x, y, z]), dtype=np.float64)
+
+
+def uniform_state(shape3, rho=1.0, vel=(0.8, 0.6, 0.7), p=1.0 / GAMMA) -> np.ndarray:
+    one = np.ones(shape3)
+    return cons_from_prim(rho * one, vel[0] * one, vel[1] * one, vel[2] * one, p * one)
+
+
+def smooth_state(ni, nj, nk, seed=0, amp=0.05, base_vel=(0.3, -0.2, 0.1), modes=3) -> np.ndarray:
+    """A random smooth periodic state: base flow plus a few seeded Fourier
+    modes in index space (periodic in every direction)."""
+    rng = np.random.default_rng(seed)
+    I, J, K = _mesh(ni, nj, nk)
+    shape = (nk + 4, nj + 4, ni + 4)
+    fields = []
+    base = [1.0, base_vel[0], base_vel[1], base_vel[2], 1.0 / GAMMA]
+    for q in range(5):
+        f = np.full(shape, base[q])
+        for _ in range(modes):
+            ka, kb, kc = rng.integers(0, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi, size=3)
+            a = rng.uniform(-1, 1) * amp * (abs(base[q]) if q in (0, 4) else 1.0)
+            f = f + a * (np.cos(2 * math.pi * ka * I / ni + ph[0]) * np.cos(2 * math.pi * kb * J / nj + ph[1]) *
+                         np.cos(2 * math.pi * kc * K / nk + ph[2]))
+        fields.append(np.broadcast_to(f, shape))
+    return cons_from_prim(*fields)
+
+
+def periodic_case(ni, nj, nk, xyz, Q, **prm) -> dict:
+    return dict(name=f"box{ni}x{nj}x{nk}", ni=ni, nj=nj, nk=nk, bc=(0, 0, 0), xyz=xyz, Q=Q,
+                params=flow_params(**prm), p_inf=1.0 / GAMMA)
+
+
+def interior(a: np.ndarray) -> np.ndarray:
+    """Interior view (nf, nk, nj, ni) of a padded array."""
+    return a[..., 2:-2, 2:-2, 2:-2]

@@ -1,0 +1,453 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms (free-stream preservation, Fourier symbol of the dissipation, a
+geometric pressure profile, the RK amplification polynomial), invariants
+(discrete conservation, axis-permutation symmetry, one-dimensional
+reduction), the exact solution of the continuous equations (manufactured
+solutions, isentropic vortex) at the second order the paper states, and the
+paper's printed constants.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2003_08746_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _case(ni, nj, nk, xyz, Q, bc=(0, 0, 0), **prm):
+    c = I.periodic_case(ni, nj, nk, xyz, Q, **prm)
+    c["bc"] = bc
+    return c
+
+
+def _inviscid_scale(m, Q, gamma=I.GAMMA):
+    """max over nodes and directions of |metric row| * |Cartesian flux| * J:
+    the size of one flux-difference term of R."""
+    mi = I.interior(m)
+    Qi = I.interior(Q)
+    rho = Qi[0]
+    vel = Qi[1:4] / rho
+    p = (gamma - 1) * (Qi[4] - 0.5 * rho * (vel ** 2).sum(0))
+    fl = np.maximum.reduce([np.abs(rho * np.sqrt((vel ** 2).sum(0))), rho * (vel ** 2).sum(0) + p,
+                            (Qi[4] + p) * np.sqrt((vel ** 2).sum(0))])
+    rows = [np.sqrt(mi[3 * d] ** 2 + mi[3 * d + 1] ** 2 + mi[3 * d + 2] ** 2) for d in range(3)]
+    return float((np.maximum.reduce(rows) * fl * mi[9]).max())
+
+
+# ---------------------------------------------------------------------------
+# P1: free-stream preservation on curvilinear grids (closed form R = 0).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sgs,k2,k4,alpha", [(1, 0.25, 1 / 64, 0.5), (0, 0.5, 1 / 32, 0.7)])
+def test_freestream_wavy_periodic(orc, sgs, k2, k4, alpha):
+    n = (24, 20, 16)
+    xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
+    vel = tuple(1.4 * np.array([1.0, 1.0, 1.0]) / math.sqrt(3.0))
+    Q = I.uniform_state((n[2] + 4, n[1] + 4, n[0] + 4), vel=vel)
+    case = _case(*n, xyz, Q, sgs=sgs, k2=k2, k4=k4, alpha=alpha, mu_ref=1e-3)
+    m = orc.metrics(case)
+    # every metric term is non-trivial on this grid
+    assert all(np.abs(I.interior(m[c])).max() > 0 for c in range(9))
+    R = orc.residual(case, m, Q)
+    scale = _inviscid_scale(m, Q)
+    assert np.abs(I.interior(R)).max() <= 1e-13 * scale
+    Qn = Q.copy()
+    for _ in range(10):
+        Qn, _, _, _ = orc.rk_step(case, m, Qn)
+    rel = np.abs(I.interior(Qn) - I.interior(Q)).max(axis=(1, 2, 3)) / np.abs(I.interior(Q)).max(axis=(1, 2, 3))
+    assert rel.max() <= 1e-13
+
+
+def test_freestream_jet_grid(orc):
+    """The jet shard grid (tanh clustering, wavy mapping, frozen j ghosts)."""
+    ni, nj, nk = 32, 24, 16
+    c = I.jet_case(ni, nj, nk)
+    Q = I.uniform_state((nk + 4, nj + 4, ni + 4), vel=(1.4, 0.0, 0.0))
+    c["Q"] = Q
+    m = orc.metrics(c)
+    R = orc.residual(c, m, Q)
+    assert np.abs(I.interior(R)).max() <= 1e-13 * _inviscid_scale(m, Q)
+
+
+# ---------------------------------------------------------------------------
+# P2: discrete conservation on periodic boxes (telescoping face fluxes).
+# ---------------------------------------------------------------------------
+def _conservation(orc, case, steps):
+    m = orc.metrics(case)
+    Q = case["Q"]
+    R = orc.residual(case, m, Q)
+    invJ = 1.0 / I.interior(m)[9]
+    RJ = I.interior(R) * invJ
+    s = RJ.reshape(5, -1).sum(1)
+    a = np.abs(RJ).reshape(5, -1).sum(1)
+    assert (np.abs(s) <= 1e-13 * a).all(), (s, a)
+    tot0 = (I.interior(Q) * invJ).reshape(5, -1).sum(1)
+    Qn = Q
+    for _ in range(steps):
+        Qn, _, _, _ = orc.rk_step(case, m, Qn)
+    tot = (I.interior(Qn) * invJ).reshape(5, -1).sum(1)
+    scale = (np.abs(I.interior(Q)) * invJ).reshape(5, -1).sum(1)
+    scale[1:4] = scale[1:4].max()  # a momentum component may start at zero
+    assert (np.abs(tot - tot0) <= 1e-13 * scale).all(), (tot - tot0, scale)
+
+
+def test_conservation_tgv(orc):
+    _conservation(orc, I.tgv_case(32), steps=10)
+
+
+def test_conservation_wavy_smooth(orc):
+    n = (20, 18, 16)
+    xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
+    Q = I.smooth_state(*n, seed=3, amp=0.1)
+    _conservation(orc, _case(*n, xyz, Q, mu_ref=2e-3), steps=10)
+
+
+# ---------------------------------------------------------------------------
+# P3: second-order convergence to the continuous equations (manufactured
+# solution, exact right-hand side from sympy).  A wrong heat-flux sign, a
+# dropped viscous or SGS term, a transposed metric or a wrong chain rule all
+# give an O(1) error that does not converge.
+# ---------------------------------------------------------------------------
+def _mms_errors(orc, grid, ns, prm_over, ls=0.0, exact_over=None):
+    from tests import mms
+    prm = I.flow_params(**(prm_over if exact_over is None else exact_over))
+    prim_fn, rhs_fn = mms.exact_rhs(prm["gamma"], prm["R_gas"], prm["mu_ref"], prm["T_ref"], prm["S_suth"],
+                                    prm["Pr"], prm["Pr_sgs"], ls)
+    errs = []
+    for n in ns:
+        if grid == "cart":
+            h = 2 * math.pi / n
+            Iv = I.padded_indices(n)
+            sh = (n + 4,) * 3
+            xyz = np.ascontiguousarray(np.stack([np.broadcast_to(h * Iv[None, None, :], sh),
+                                                 np.broadcast_to(h * Iv[None, :, None], sh),
+                                                 np.broadcast_to(h * Iv[:, None, None], sh)]))
+        else:
+            xyz = I.wavy_grid(n, n, n, L=(2 * math.pi,) * 3, amp=0.4)
+        prim = mms.evaluate(prim_fn, xyz)
+        Q = I.cons_from_prim(*prim, gamma=prm["gamma"])
+        over = dict(prm_over)
+        if ls > 0:
+            over["Cs"] = ls / (2 * math.pi / n)
+            over["sgs"] = 1
+        case = _case(n, n, n, xyz, Q, **over)
+        m = orc.metrics(case)
+        R = I.interior(orc.residual(case, m, Q))
+        ex = I.interior(mms.evaluate(rhs_fn, xyz))
+        errs.append(np.abs(R - ex).reshape(5, -1).max(1))
+    return np.array(errs)
+
+
+def _orders(errs):
+    return np.log2(errs[:-1] / errs[1:])
+
+
+@pytest.mark.parametrize("grid", ["cart", "wavy"])
+def test_mms_second_order_viscous(orc, grid):
+    # large molecular viscosity (Sutherland) so that the viscous and heat-flux
+    # terms are O(1) parts of the right-hand side
+    over = dict(mu_ref=0.05, sgs=0)
+    errs = _mms_errors(orc, grid, [16, 32, 64], over)
+    orders = _orders(errs)
+    # at least second order everywhere (the wavy grid is still pre-asymptotic
+    # from above at these sizes); a lost term would stall the error at O(1)
+    assert (orders[-1] > 1.85).all() and (orders[-1] < 3.0).all(), (errs, orders)
+    assert (orders[0] > 1.6).all(), (errs, orders)
+
+
+def test_mms_second_order_sgs(orc):
+    # eddy viscosity with a fixed length ls (Cs * Delta = ls): the SGS stress
+    # and SGS heat flux are then O(1) and must converge like the rest
+    over = dict(mu_ref=0.01, sgs=1)
+    errs = _mms_errors(orc, "cart", [16, 32, 64], over, ls=0.3)
+    orders = _orders(errs)
+    assert (orders[-1] > 1.85).all() and (orders[-1] < 2.2).all(), (errs, orders)
+
+
+def test_mms_heat_flux_sign_matters(orc):
+    """Control for the test above: flipping the sign of conduction (through a
+    negative Prandtl number) must break convergence of the energy equation."""
+    errs = _mms_errors(orc, "cart", [32, 64], dict(mu_ref=0.05, sgs=0, Pr=-0.72),
+                       exact_over=dict(mu_ref=0.05, sgs=0, Pr=0.72))
+    # the energy residual no longer approaches the physical RHS; the other
+    # equations still converge at second order
+    assert errs[-1][4] > 0.9 * errs[0][4]
+    assert (_orders(errs)[0][:4] > 1.85).all()
+
+
+# ---------------------------------------------------------------------------
+# Dissipation: Fourier symbol of the linearized operator on an anisotropic
+# Cartesian grid (pins k4, the anisotropic Lambda with exponent alpha, the
+# Jacobian factor and the sign), and a geometric pressure profile whose
+# sensor is constant (pins the sensor, k2, eps4 = max(0, k4 - eps2), the
+# third difference and the sign).
+# ---------------------------------------------------------------------------
+def _aniso_grid(ni, nj, nk, hx, hy, hz):
+    sh = (nk + 4, nj + 4, ni + 4)
+    return np.ascontiguousarray(np.stack([
+        np.broadcast_to(hx * I.padded_indices(ni)[None, None, :], sh),
+        np.broadcast_to(hy * I.padded_indices(nj)[None, :, None], sh),
+        np.broadcast_to(hz * I.padded_indices(nk)[:, None, None], sh)]))
+
+
+@pytest.mark.parametrize("alpha", [0.5, 1.0, 0.3])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_dissipation_fourier_symbol(orc, alpha, axis):
+    n = [12, 10, 8]
+    h = [0.7, 1.3, 0.45]
+    k4 = 1.0 / 64
+    xyz = _aniso_grid(*n, *h)
+    sh = (n[2] + 4, n[1] + 4, n[0] + 4)
+    mode = 2
+    idx = [I.padded_indices(n[0])[None, None, :], I.padded_indices(n[1])[:, None][None],
+           I.padded_indices(n[2])[:, None, None]][axis]
+    theta = 2 * math.pi * mode / n[axis]
+    eps = 1e-6
+    rho0, p0 = 1.0, 1.0 / I.GAMMA
+    rho = np.broadcast_to(rho0 * (1 + eps * np.cos(theta * idx)), sh)
+    zero = np.zeros(sh)
+    Q = I.cons_from_prim(rho, zero, zero, zero, np.full(sh, p0))
+    case = _case(*n, xyz, Q, mu_ref=0.0, sgs=0, k2=0.25, k4=k4, alpha=alpha)
+    m = orc.metrics(case)
+    R = I.interior(orc.residual(case, m, Q))
+    # metric row norms |grad d / J| on this grid
+    row = [h[1] * h[2], h[0] * h[2], h[0] * h[1]]
+    a = row[axis]
+    others = [row[(axis + 1) % 3], row[(axis + 2) % 3]]
+    K = a + a ** (1 - alpha) * (others[0] ** alpha + others[1] ** alpha)
+    c0 = math.sqrt(I.GAMMA * p0 / rho0)
+    J = 1.0 / (h[0] * h[1] * h[2])
+    amp = J * k4 * c0 * K * 16 * math.sin(theta / 2) ** 4 * rho0 * eps
+    shape = [1, 1, 1]
+    shape[2 - axis] = n[axis]
+    expect = np.broadcast_to(amp * np.cos(theta * np.arange(n[axis], dtype=float)).reshape(shape), R.shape[1:])
+    assert np.abs(R[0] - expect).max() <= 1e-5 * abs(amp)
+    assert np.abs(R[1:]).max() <= 1e-12 * abs(amp)
+
+
+@pytest.mark.parametrize("r", [1.02, 1.15, 2.0])
+def test_dissipation_geometric_pressure(orc, r):
+    """p_i = p0 r^i and rho_i = rho0 r^i (uniform T), u = 0, along a frozen
+    Dirichlet i-direction: the sensor is the constant (r-1)^2/(r+1)^2, and
+    R_rho,i = -J Lam rho0 r^(i-1) (r-1) [eps2 (r-1) - eps4 (r-1)^3 / r]."""
+    n = [8, 6, 6]
+    h = [0.5, 0.8, 1.1]
+    k2, k4, alpha = 0.25, 1.0 / 64, 0.5
+    xyz = _aniso_grid(*n, *h)
+    sh = (n[2] + 4, n[1] + 4, n[0] + 4)
+    i = I.padded_indices(n[0])[None, None, :]
+    rho0, p0 = 1.0, 1.0 / I.GAMMA
+    rho = np.broadcast_to(rho0 * r ** i, sh)
+    p = np.broadcast_to(p0 * r ** i, sh)
+    zero = np.zeros(sh)
+    Q = I.cons_from_prim(rho, zero, zero, zero, p)
+    case = _case(*n, xyz, Q, bc=(1, 0, 0), mu_ref=0.0, sgs=0, k2=k2, k4=k4, alpha=alpha)
+    m = orc.metrics(case)
+    R = I.interior(orc.residual(case, m, Q))
+    nu = (r - 1) ** 2 / (r + 1) ** 2
+    eps2 = k2 * nu
+    eps4 = max(0.0, k4 - eps2)
+    row = [h[1] * h[2], h[0] * h[2], h[0] * h[1]]
+    c0 = math.sqrt(I.GAMMA * p0 / rho0)
+    Lam = c0 * (row[0] + row[0] ** (1 - alpha) * (row[1] ** alpha + row[2] ** alpha))
+    J = 1.0 / (h[0] * h[1] * h[2])
+    A = eps2 * (r - 1) - eps4 * (r - 1) ** 3 / r
+    ii = np.arange(n[0])
+    expect_rho = -J * Lam * rho0 * r ** (ii - 1.0) * (r - 1) * A
+    e0 = p0 / (I.GAMMA - 1)
+    expect_e = -J * Lam * e0 * r ** (ii - 1.0) * (r - 1) * A
+    # a difference of third differences of O(1) values: relative rounding
+    # grows like 1e-16 / (r-1)^4
+    tol = max(1e-13, 2e-15 / (r - 1) ** 4)
+    assert np.allclose(R[0], np.broadcast_to(expect_rho, R[0].shape), rtol=tol, atol=0)
+    assert np.allclose(R[4], np.broadcast_to(expect_e, R[4].shape), rtol=tol, atol=0)
+    if r > 5.0 / 3.0:
+        assert eps4 == 0.0  # the second-difference branch alone is active
+
+
+# ---------------------------------------------------------------------------
+# P5: RK amplification polynomial; 2nd order (Sec. 4).
+# ---------------------------------------------------------------------------
+def test_rk_amplification_polynomial(orc):
+    coef = [1.0, 1.0, 0.5, 3.0 / 16.0, 1.0 / 32.0, 1.0 / 128.0]
+    for lam in [-1.0, -0.3 + 2.0j, 1.7j, -2.5 + 0.5j]:
+        for dt in [0.1, 0.7]:
+            z = lam * dt
+            G = sum(c * z ** k for k, c in enumerate(coef))
+            assert abs(orc.rk_scalar(lam, dt) - G) <= 1e-15 * max(1.0, abs(G))
+    # second order: the error against exp(z) shrinks like dt^3 per step
+    lam = -1.0 + 1.0j
+    e1 = abs(orc.rk_scalar(lam, 0.01) - np.exp(lam * 0.01))
+    e2 = abs(orc.rk_scalar(lam, 0.005) - np.exp(lam * 0.005))
+    assert 2.8 < math.log2(e1 / e2) < 3.2
+
+
+# ---------------------------------------------------------------------------
+# P6 / P7 / P8: reductions, symmetry, TGV sanity.
+# ---------------------------------------------------------------------------
+def test_one_dimensional_reduction(orc):
+    """Fields that vary in x only on a Cartesian grid: R varies in x only and
+    the y, z momentum residuals vanish."""
+    n = 16
+    xyz = _aniso_grid(n, 8, 6, 1.0, 1.0, 1.0)
+    sh = (6 + 4, 8 + 4, n + 4)
+    x = np.broadcast_to(I.padded_indices(n)[None, None, :], sh)
+    th = 2 * math.pi * x / n
+    rho = 1 + 0.1 * np.sin(th)
+    u = 0.3 + 0.2 * np.cos(th)
+    p = (1 + 0.1 * np.cos(th + 0.4)) / I.GAMMA
+    zero = np.zeros(sh)
+    Q = I.cons_from_prim(rho, u, zero, zero, p)
+    case = _case(n, 8, 6, xyz, Q, mu_ref=0.01, sgs=1)
+    m = orc.metrics(case)
+    R = I.interior(orc.residual(case, m, Q))
+    assert np.abs(R[2]).max() == 0.0 and np.abs(R[3]).max() == 0.0
+    spread = np.abs(R - R[:, :1, :1, :]).max()
+    assert spread <= 1e-14 * np.abs(R).max()
+
+
+def test_axis_permutation_symmetry(orc):
+    """Cyclic relabelling (i, j, k) -> (j, k, i) of indices, coordinates and
+    velocity components permutes the residual in the same way."""
+    n = (14, 12, 10)
+    xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
+    Q = I.smooth_state(*n, seed=5, amp=0.1)
+    case = _case(*n, xyz, Q, mu_ref=5e-3, sgs=1)
+    m = orc.metrics(case)
+    R = orc.residual(case, m, Q)
+    # new index axes: i' = k, j' = i, k' = j  ->  array axes (k', j', i') = (j, i, k)
+    def perm(a):
+        return np.ascontiguousarray(np.transpose(a, (0, 2, 3, 1)))
+    # coordinates: x' = z, y' = x, z' = y;  velocity likewise
+    xyz2 = perm(xyz[[2, 0, 1]])
+    Q2 = perm(Q[[0, 3, 1, 2, 4]])
+    case2 = _case(n[2], n[0], n[1], xyz2, Q2, mu_ref=5e-3, sgs=1)
+    m2 = orc.metrics(case2)
+    R2 = orc.residual(case2, m2, Q2)
+    Rp = perm(R[[0, 3, 1, 2, 4]])
+    scale = np.abs(I.interior(R)).max(axis=(1, 2, 3))
+    err = np.abs(I.interior(R2) - I.interior(Rp)).max(axis=(1, 2, 3))
+    assert (err <= 1e-12 * scale).all(), (err, scale)
+
+
+def test_tgv_sanity(orc):
+    c = I.tgv_case(32)
+    m = orc.metrics(c)
+    Q = c["Q"]
+    mom0 = I.interior(Q)[1:4].reshape(3, -1).sum(1)
+    scale = np.abs(I.interior(Q)[1:4]).sum()
+    assert np.abs(mom0).max() <= 1e-14 * scale
+
+    def ke(q):
+        qi = I.interior(q)
+        return 0.5 * ((qi[1] ** 2 + qi[2] ** 2 + qi[3] ** 2) / qi[0]).sum()
+    k_prev = ke(Q)
+    for _ in range(10):
+        Q, dt, norms, _ = orc.rk_step(c, m, Q)
+        mom = I.interior(Q)[1:4].reshape(3, -1).sum(1)
+        assert np.abs(mom).max() <= 1e-13 * scale
+        k = ke(Q)
+        assert k <= k_prev
+        k_prev = k
+        assert np.isfinite(norms).all() and dt > 0
+
+
+# ---------------------------------------------------------------------------
+# Isentropic vortex (textbook exact solution of the Euler equations: pure
+# translation with the free stream); the RK + residual error converges at
+# second order with the CFL number fixed.
+# ---------------------------------------------------------------------------
+def _vortex(xyz, t, gamma, uinf, vinf, beta, L):
+    x = xyz[0] - uinf * t
+    y = xyz[1] - vinf * t
+    x = (x + L / 2) % L - L / 2
+    y = (y + L / 2) % L - L / 2
+    r2 = x * x + y * y
+    f = np.exp((1 - r2) / 2)
+    du = -beta / (2 * math.pi) * f * y
+    dv = beta / (2 * math.pi) * f * x
+    T = 1 - (gamma - 1) * beta ** 2 / (8 * gamma * math.pi ** 2) * f * f
+    rho = T ** (1 / (gamma - 1))
+    p = rho * T
+    return rho, uinf + du, vinf + dv, np.zeros_like(rho), p
+
+
+def test_isentropic_vortex_second_order(orc):
+    gamma, uinf, vinf, beta, L = I.GAMMA, 0.5, 0.3, 5.0, 10.0
+    t_end = 1.0
+    errs = []
+    for n in (48, 96):
+        h = L / n
+        nk = 5
+        sh = (nk + 4, n + 4, n + 4)
+        xyz = np.ascontiguousarray(np.stack([
+            np.broadcast_to(-L / 2 + h * I.padded_indices(n)[None, None, :], sh),
+            np.broadcast_to(-L / 2 + h * I.padded_indices(n)[None, :, None], sh),
+            np.broadcast_to(h * I.padded_indices(nk)[:, None, None], sh)]))
+        Q = I.cons_from_prim(*_vortex(xyz, 0.0, gamma, uinf, vinf, beta, L), gamma=gamma)
+        case = _case(n, n, nk, xyz, Q, mu_ref=0.0, sgs=0, R_gas=1.0, k2=0.25, k4=1.0 / 256)
+        m = orc.metrics(case)
+        dt0 = orc.cfl_dt(case, m, Q)
+        nsteps = int(math.ceil(t_end / dt0))
+        dt = t_end / nsteps
+        for _ in range(nsteps):
+            Q, _, _, _ = orc.rk_step(case, m, Q, dt=dt)
+        ex = I.cons_from_prim(*_vortex(xyz, t_end, gamma, uinf, vinf, beta, L), gamma=gamma)
+        errs.append(np.abs(I.interior(Q) - I.interior(ex)).reshape(5, -1).max(1))
+    errs = np.array(errs)
+    order = np.log2(errs[0] / errs[1])
+    # density, x/y momenta and energy converge at second order (w stays 0)
+    assert (order[[0, 1, 2, 4]] > 1.85).all(), (errs, order)
+    assert errs[:, 3].max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Dual-number tangent of the oracle against central finite differences, and
+# the source term R12.
+# ---------------------------------------------------------------------------
+def test_tangent_matches_finite_differences(orc):
+    n = (12, 10, 8)
+    xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
+    Q = I.smooth_state(*n, seed=7, amp=0.1)
+    case = _case(*n, xyz, Q, mu_ref=5e-3, sgs=1)
+    m = orc.metrics(case)
+    rng = np.random.default_rng(11)
+    dQ = rng.standard_normal(Q.shape) * np.abs(Q).mean(axis=(1, 2, 3))[:, None, None, None]
+    f = rng.standard_normal((5, n[2], n[1])) * 1e-3
+    df = rng.standard_normal(f.shape)
+    R, dR = orc.residual_tangent(case, m, Q, dQ, f=f, df=df, i_f=3)
+    h = 1e-6
+    Rp = orc.residual(case, m, Q + h * dQ, f=f + h * df, i_f=3)
+    Rm = orc.residual(case, m, Q - h * dQ, f=f - h * df, i_f=3)
+    fd = (Rp - Rm) / (2 * h)
+    scale = np.abs(I.interior(dR)).max()
+    assert np.abs(I.interior(fd - dR)).max() <= 1e-6 * scale
+
+
+def test_source_plane(orc):
+    n = (10, 8, 6)
+    xyz = I.wavy_grid(*n, amp=0.2)
+    Q = I.smooth_state(*n, seed=1)
+    case = _case(*n, xyz, Q)
+    m = orc.metrics(case)
+    f = np.random.default_rng(0).standard_normal((5, n[2], n[1]))
+    R0 = orc.residual(case, m, Q)
+    R1 = orc.residual(case, m, Q, f=f, i_f=4)
+    d = I.interior(R1 - R0)
+    assert np.array_equal(d[:, :, :, 4], -f) or np.allclose(d[:, :, :, 4], -f, rtol=1e-15, atol=1e-15)
+    d[:, :, :, 4] = 0
+    assert np.abs(d).max() == 0.0
+
+
+def test_paper_constants():
+    g = json.load(open(os.path.join(HERE, "golden", "paper_constants.json")))
+    p = I.flow_params()
+    assert p["Pr"] == g["Pr"]["value"]
+    assert p["Pr_sgs"] == g["Pr_sgs"]["value"]
+    assert abs(p["S_suth"] * 288.15 - g["S1_kelvin"]["value"]) < 1e-12
+    assert abs(p["mu_ref"] - g["mach_jet"]["value"] / g["reynolds_jet"]["value"]) < 1e-20
