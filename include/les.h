@@ -1,0 +1,189 @@
+/* les.h -- C ABI of the MI355X (gfx950) LES residual / Runge-Kutta library.
+ *
+ * Implements the hot path of the solver described in "Strong Scaling of
+ * Numerical Solver for Supersonic Jet Flow Configurations" (arXiv 2003.08746):
+ * the explicit five-stage Runge-Kutta update (Sec. 3 end, Sec. 4, Alg. 2) of
+ * the conserved vector Q = [rho, rho u, rho v, rho w, e] (Eq. 13) on one
+ * structured curvilinear block, whose residual (Eq. 12, 14, 15) combines
+ * centred inviscid and viscous fluxes through the grid metrics, Turkel-Vatsa
+ * artificial dissipation and a static-Smagorinsky eddy viscosity (Eq. 3-11).
+ *
+ * Memory: every pointer named "device" is HIP device memory owned by the
+ * caller.  The library owns only what it allocates in les_create (metrics,
+ * stage buffers, reduction scratch) and frees it in les_destroy.  Pointers
+ * named "host" are ordinary host memory.
+ *
+ * Streams: every call enqueues its kernels on the stream given to
+ * les_create and returns without waiting, except where a host output is
+ * requested (dt_out, norms, J_out); then the call synchronises that stream.
+ *
+ * Errors: every call returns an les_status; it never aborts the process.  A
+ * readable message is available from les_last_error (per context) or
+ * les_last_create_error (for a failed les_create).  A non-finite value found
+ * by a reduction is reported as LES_ERR_NONFINITE by the call that
+ * synchronises (the state is left in place for inspection).
+ *
+ * Threads: a context is not thread-safe; distinct contexts are independent.
+ *
+ * Field layout ("library layout"): a state or metric array holds nf fields
+ * of field_elems doubles each.  Within a field, node (i, j, k) -- interior
+ * indices 0..n-1, ghost indices -2, -1, n, n+1 -- sits at element
+ *     origin + i + j * stride_j + k * stride_k
+ * with the values returned by les_layout (i is contiguous; two ghost layers
+ * per side as in Sec. 4, Fig. 3; rows are padded for alignment; padding
+ * elements are never read).  "Dense padded layout" means the plain array
+ * [nf][nk+4][nj+4][ni+4] with node (i, j, k) at ((k+2)(nj+4) + j+2)(ni+4) + i+2.
+ */
+#ifndef LES_H
+#define LES_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct les_ctx les_ctx;
+
+typedef enum {
+  LES_OK = 0,
+  LES_ERR_ARG = -1,       /* invalid argument (null pointer, size, value) */
+  LES_ERR_HIP = -2,       /* a HIP runtime call failed */
+  LES_ERR_NOMEM = -3,     /* device allocation failed */
+  LES_ERR_NONFINITE = -4, /* NaN/Inf (or non-positive density/pressure) met */
+  LES_ERR_STATE = -5      /* call not valid in the context's state */
+} les_status;
+
+typedef enum { LES_FP64 = 0, LES_MIXED = 1 } les_precision;
+
+typedef enum { LES_BC_PERIODIC = 0, LES_BC_DIRICHLET = 1 } les_bc;
+
+/* One structured block.  ni, nj, nk >= 5 interior points.
+ * bc[d] for d = i, j, k:
+ *   LES_BC_PERIODIC  -- period-wrap (Sec. 3: azimuthal periodicity); the
+ *                       ghost coordinates must be the period-shifted images;
+ *   LES_BC_DIRICHLET -- ghost nodes keep the values the caller stored in the
+ *                       state's ghost layers (frozen far field).
+ * xyz: device, dense padded layout [3][nk+4][nj+4][ni+4], coordinates on every
+ * node including ghosts and edges (read during les_create only). */
+typedef struct {
+  int ni, nj, nk;
+  int bc[3];
+  const double *xyz;
+} les_grid;
+
+/* Flow and scheme parameters (nondimensional).  Sec. 3, Eq. 2-11:
+ *   gamma, R_gas (p = rho R T), Pr (kappa = mu Cp/Pr), Pr_sgs
+ *   (kappa_sgs = mu_sgs Cp/Pr_sgs), Sutherland mu = mu_ref (T/T_ref)^1.5
+ *   (1+S)/(T/T_ref+S) with S = S1/T_ref (S_suth).
+ *   sgs = 0: mu_sgs = 0 (the paper's runs); sgs = 1: static Smagorinsky
+ *   mu_sgs = rho (Cs Delta)^2 sqrt(2 S_ij S_ij), Delta = (1/J)^(1/3).
+ * Turkel-Vatsa dissipation constants k2, k4 and anisotropy exponent alpha:
+ *   D = Lam_face (eps2 dQ - eps4 d3Q), eps2 = k2 max(nu_a, nu_b),
+ *   eps4 = max(0, k4 - eps2), nu = |p+ - 2p + p-| / (p+ + 2p + p-),
+ *   Lam_d = lam_d [1 + sum_{e != d} (lam_e / lam_d)^alpha],
+ *   lam_d = |U~_d| + c |grad d / J|.
+ * cfl: time step used when les_rk_step gets dt <= 0:
+ *   dt = cfl * min_interior 1 / (sum_d (|U_d| + c |grad d|)
+ *                               + 2 max(4/3, gamma/Pr) (mu/rho) sum_d |grad d|^2).
+ * prec: LES_FP64, or LES_MIXED (stage states, fluxes and dissipation in FP32;
+ *   Q^n, the RK accumulation, metrics and all reductions in FP64). */
+typedef struct {
+  double gamma, Pr, Pr_sgs;
+  double mu_ref, T_ref, S_suth;
+  double R_gas;
+  int sgs;
+  double Cs;
+  double k2, k4, alpha;
+  double cfl;
+  int prec;
+} les_flow_params;
+
+/* Create a context for one block (Alg. 2: read mesh, compute Jacobian and
+ * metrics, create ghost points).  The metrics are computed on the device from
+ * grid->xyz by the conservative (Thomas-Lombard) central-difference form,
+ * which preserves a uniform flow exactly up to rounding; in a periodic
+ * direction the ghost-layer metrics are copies of the wrapped interior ones.
+ * metrics_dense (device, dense padded layout [10][..]: xi_x/J, xi_y/J, xi_z/J,
+ * eta_x/J, ..., zeta_z/J, J) may be given instead (grid->xyz is then
+ * ignored and may be NULL); it must be valid on all nodes with indices in
+ * [-1, n].  hip_stream: a hipStream_t (NULL = default stream).
+ * Returns LES_ERR_ARG for a null out/grid/params, n < 5, bad bc, gamma <= 1,
+ * R_gas <= 0, Pr <= 0, negative k2/k4/mu_ref, unknown prec. */
+int les_create(les_ctx **out, const les_grid *grid, const double *metrics_dense,
+               const les_flow_params *params, void *hip_stream);
+
+void les_destroy(les_ctx *ctx);
+
+/* Library layout of state arrays (see top of file).  strides[0] = 1,
+ * strides[1] = stride_j, strides[2] = stride_k; *origin = element offset of
+ * interior node (0, 0, 0) within a field; *field_elems = field pitch. */
+int les_layout(const les_ctx *ctx, long long strides[3], long long *origin, long long *field_elems);
+
+/* Same layout without a context (for allocating before les_create). */
+int les_layout_for(int ni, int nj, int nk, long long strides[3], long long *origin, long long *field_elems);
+
+/* Copy the library's metrics (library layout) to a caller array
+ * (device, dense padded layout [10][nk+4][nj+4][ni+4]); nodes outside
+ * [-1, n]^3 are written as 0. */
+int les_get_metrics(les_ctx *ctx, double *dense_out);
+
+/* Residual R(Q) = J * sum_d [F_{d,+1/2} - F_{d,-1/2}] - f * [i == i_f]
+ * (Eq. 12: dQ/dt = -R), F = (H_a + H_b)/2 - D with node fluxes
+ * H = inviscid - viscous contravariant flux (Eq. 15).
+ * Q: device, library layout [5][field_elems], FP64; its ghost layers are
+ *    filled in place (periodic wrap; Dirichlet ghosts untouched); interior
+ *    values are not modified.
+ * R: device, library layout [5][field_elems]; interior nodes written.
+ * norms: host double[10] or NULL: RMS of R per variable (5) then max |R| (5)
+ *    over the interior. */
+int les_residual(les_ctx *ctx, double *Q, double *R, double *norms);
+
+/* Time step dt (CFL rule above) of the interior of Q; dt_out: host. */
+int les_cfl_dt(les_ctx *ctx, const double *Q, double *dt_out);
+
+/* Constant source f on the plane i = i_f (dQ/dt = -R + f); f: device, dense
+ * [5][nk][nj]; the library keeps its own copy.  f = NULL removes it. */
+int les_set_forcing(les_ctx *ctx, const double *f, int i_f);
+
+/* One step of Jameson's five-stage scheme (Sec. 4, Alg. 2):
+ *   Q^(0) = Q^n;  Q^(l) = Q^(0) - alpha_l dt R(Q^(l-1)),  l = 1..5,
+ *   alpha = (1/4, 1/6, 3/8, 1/2, 1);  Q^{n+1} = Q^(5),
+ * with the ghost layers refreshed before every residual evaluation.
+ * Q: device, library layout, FP64, in/out (interior updated in place; its
+ *    periodic ghosts hold the wrap of Q^n on return).
+ * dt > 0: used as is; dt <= 0: the CFL time step of Q^n (computed on the
+ *    device; no host round trip unless dt_out is given).
+ * dt_out: host or NULL.  norms: host double[10] or NULL, norms of R(Q^n).
+ * stage_ckpt: device or NULL; FP64 [5 stages][5 fields][field_elems]
+ *    receives the stage inputs Q^(0..4) (ghosts filled) for les_adjoint_step. */
+int les_rk_step(les_ctx *ctx, double *Q, double dt, double *dt_out, double *norms, double *stage_ckpt);
+
+/* Reverse (adjoint) of one les_rk_step at fixed dt, from its stage inputs:
+ *   qbar <- Qbar;  acc = 0;  for l = 5..1:  acc += qbar;
+ *      fbar += alpha_l dt qbar[plane i_f];
+ *      qbar = -alpha_l dt (dR/dQ |_{Q^(l-1)})^T qbar;
+ *   Qbar <- acc + qbar.
+ * dR/dQ includes the ghost fill (periodic ghost adjoints are folded onto the
+ * interior; frozen Dirichlet ghosts carry no dependence).  Non-smooth points
+ * take the derivative of the active branch: d|x|/dx = sign(x) (0 at 0),
+ * max(a, b) follows a when a >= b.
+ * stage_ckpt: device, as written by les_rk_step with the same dt.
+ * Qbar: device, library layout, FP64, in: dJ/dQ^{n+1} (interior), out: dJ/dQ^n
+ *    (interior; ghost layers are used as scratch).
+ * fbar: device, dense [5][nk][nj], accumulated, or NULL. */
+int les_adjoint_step(les_ctx *ctx, const double *stage_ckpt, double dt, double *Qbar, double *fbar);
+
+/* Probe objective on the plane i = i_p (interior of Q):
+ *   *J_accum += weight * sum_{j,k} (p - p_inf)^2          (J_accum: device)
+ *   Qbar[i_p plane] += weight * 2 (p - p_inf) dp/dQ       (Qbar: device or NULL)
+ * with p = (gamma - 1)(e - (m_1^2 + m_2^2 + m_3^2) / (2 rho)). */
+int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, double weight, double *J_accum,
+                        double *Qbar);
+
+const char *les_last_error(const les_ctx *ctx);
+const char *les_last_create_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LES_H */

@@ -1,0 +1,21 @@
+// les_adjoint.hpp -- reverse-mode (adjoint) of one Runge-Kutta step.
+#pragma once
+#include "les_common.hpp"
+
+namespace les {
+
+struct AdjArgs {
+  Layout L;
+  Phys P;
+  const double* M;
+  int bc0, bc1, bc2;
+  int i_f;
+};
+
+// Device work elements (doubles) needed by run_adjoint_step.
+size_t adjoint_work_elems(const Layout& L);
+
+hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt, double dt, double* Qbar,
+                            double* fbar, double* work);
+
+}  // namespace les

@@ -1,0 +1,356 @@
+// les_api.hip -- implementation of the C ABI declared in include/les.h.
+//
+// Host code only: argument checks, device allocations owned by the context,
+// and the launch sequence of one residual evaluation / one five-stage
+// Runge-Kutta step (Sec. 4, Alg. 2) on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "les.h"
+#include "les_launch.hpp"
+#include "les_stage.hpp"
+#include "les_adjoint.hpp"
+
+struct les_ctx {
+  les::Layout L;
+  les::Phys P;
+  int bc[3];
+  int prec;
+  hipStream_t s;
+  int device;
+  double* M = nullptr;               // metrics [10][fe]
+  double* S[2] = {nullptr, nullptr}; // FP64 stage buffers [5][fe]
+  float* Sf[2] = {nullptr, nullptr}; // FP32 stage buffers [5][fe] (mixed precision)
+  double* f = nullptr;               // source [5][nk][nj]
+  int i_f = -1;
+  double* part = nullptr;            // per-block reduction partials
+  long long part_n = 0;              // capacity in blocks (10 doubles each)
+  double* scal = nullptr;            // [0] dt, [1..10] norms, [11..15] spare
+  int* flag = nullptr;               // bit 0: bad dt, bit 1: non-finite norm
+  double* adj = nullptr;             // adjoint work arrays
+  long long adj_n = 0;
+  int use_ref = 0;                   // 1: stage through the reference kernel
+  char err[512];
+};
+
+static thread_local char g_create_err[512] = "";
+
+static int fail(les_ctx* c, int code, const char* fmt, ...) {
+  char* buf = c ? c->err : g_create_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail((ctx), LES_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+static void free_all(les_ctx* c) {
+  if (!c) return;
+  (void)hipFree(c->M);
+  (void)hipFree(c->S[0]);
+  (void)hipFree(c->S[1]);
+  (void)hipFree(c->Sf[0]);
+  (void)hipFree(c->Sf[1]);
+  (void)hipFree(c->f);
+  (void)hipFree(c->part);
+  (void)hipFree(c->scal);
+  (void)hipFree(c->flag);
+  (void)hipFree(c->adj);
+}
+
+extern "C" {
+
+const char* les_last_create_error(void) { return g_create_err; }
+
+const char* les_last_error(const les_ctx* ctx) { return ctx ? ctx->err : g_create_err; }
+
+int les_layout_for(int ni, int nj, int nk, long long strides[3], long long* origin, long long* field_elems) {
+  if (ni < 5 || nj < 5 || nk < 5) return fail(nullptr, LES_ERR_ARG, "les_layout_for: sizes must be >= 5");
+  les::Layout L = les::make_layout(ni, nj, nk);
+  if (strides) {
+    strides[0] = 1;
+    strides[1] = L.sj;
+    strides[2] = L.sk;
+  }
+  if (origin) *origin = L.o;
+  if (field_elems) *field_elems = L.fe;
+  return LES_OK;
+}
+
+int les_layout(const les_ctx* ctx, long long strides[3], long long* origin, long long* field_elems) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_layout: null context");
+  if (strides) {
+    strides[0] = 1;
+    strides[1] = ctx->L.sj;
+    strides[2] = ctx->L.sk;
+  }
+  if (origin) *origin = ctx->L.o;
+  if (field_elems) *field_elems = ctx->L.fe;
+  return LES_OK;
+}
+
+int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense, const les_flow_params* prm,
+               void* hip_stream) {
+  if (!out) return fail(nullptr, LES_ERR_ARG, "les_create: out is NULL");
+  *out = nullptr;
+  if (!grid || !prm) return fail(nullptr, LES_ERR_ARG, "les_create: grid or params is NULL");
+  if (grid->ni < 5 || grid->nj < 5 || grid->nk < 5)
+    return fail(nullptr, LES_ERR_ARG, "les_create: every interior size must be >= 5 (got %d x %d x %d)", grid->ni,
+                grid->nj, grid->nk);
+  if ((long long)grid->ni * grid->nj * grid->nk > (1LL << 34))
+    return fail(nullptr, LES_ERR_ARG, "les_create: block too large");
+  for (int d = 0; d < 3; ++d)
+    if (grid->bc[d] != LES_BC_PERIODIC && grid->bc[d] != LES_BC_DIRICHLET)
+      return fail(nullptr, LES_ERR_ARG, "les_create: bc[%d] = %d is not a known boundary type", d, grid->bc[d]);
+  if (!metrics_dense && !grid->xyz) return fail(nullptr, LES_ERR_ARG, "les_create: need xyz or metrics");
+  if (!(prm->gamma > 1.0) || !(prm->R_gas > 0.0) || !(prm->Pr > 0.0) || !(prm->Pr_sgs > 0.0) ||
+      !(prm->mu_ref >= 0.0) || !(prm->T_ref > 0.0) || !(prm->S_suth >= 0.0) || !(prm->k2 >= 0.0) ||
+      !(prm->k4 >= 0.0) || !(prm->alpha > 0.0) || !(prm->cfl > 0.0) || !(prm->Cs >= 0.0) ||
+      (prm->sgs != 0 && prm->sgs != 1))
+    return fail(nullptr, LES_ERR_ARG, "les_create: a flow parameter is out of range");
+  if (prm->prec != LES_FP64 && prm->prec != LES_MIXED)
+    return fail(nullptr, LES_ERR_ARG, "les_create: unknown precision %d", prm->prec);
+
+  les_ctx* c = new les_ctx();
+  c->err[0] = 0;
+  c->L = les::make_layout(grid->ni, grid->nj, grid->nk);
+  for (int d = 0; d < 3; ++d) c->bc[d] = grid->bc[d];
+  c->prec = prm->prec;
+  c->s = (hipStream_t)hip_stream;
+  les::Phys& P = c->P;
+  P.gamma = prm->gamma;
+  P.gm1 = prm->gamma - 1.0;
+  P.inv_R = 1.0 / prm->R_gas;
+  const double Cp = prm->gamma * prm->R_gas / (prm->gamma - 1.0);
+  P.Cp_over_Pr = Cp / prm->Pr;
+  P.Cp_over_Prsgs = Cp / prm->Pr_sgs;
+  P.mu_ref = prm->mu_ref;
+  P.inv_Tref = 1.0 / prm->T_ref;
+  P.S = prm->S_suth;
+  P.one_plus_S = 1.0 + prm->S_suth;
+  P.Cs2 = prm->Cs * prm->Cs;
+  P.k2 = prm->k2;
+  P.k4 = prm->k4;
+  P.alpha = prm->alpha;
+  P.alpha_half = prm->alpha == 0.5;
+  P.cfl = prm->cfl;
+  P.nu_fac = fmax(4.0 / 3.0, prm->gamma / prm->Pr);
+  P.sgs = prm->sgs;
+
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, LES_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  }
+  const size_t fe = (size_t)c->L.fe;
+  c->part_n = les::ref_blocks(c->L);
+  long long sb = les::stage_blocks(c->L);
+  if (sb > c->part_n) c->part_n = sb;
+  bool ok = hipMalloc(&c->M, 10 * fe * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->S[0], 5 * fe * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->S[1], 5 * fe * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->part, (size_t)c->part_n * 10 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->scal, 16 * sizeof(double)) == hipSuccess && hipMalloc(&c->flag, sizeof(int)) == hipSuccess;
+  if (ok && c->prec == LES_MIXED)
+    ok = hipMalloc(&c->Sf[0], 5 * fe * sizeof(float)) == hipSuccess &&
+         hipMalloc(&c->Sf[1], 5 * fe * sizeof(float)) == hipSuccess;
+  if (!ok) {
+    free_all(c);
+    delete c;
+    return fail(nullptr, LES_ERR_NOMEM, "les_create: device allocation failed (%zu bytes per field)",
+                fe * sizeof(double));
+  }
+  int rc = LES_OK;
+  do {
+    if (hipMemsetAsync(c->M, 0, 10 * fe * sizeof(double), c->s) != hipSuccess ||
+        hipMemsetAsync(c->S[0], 0, 5 * fe * sizeof(double), c->s) != hipSuccess ||
+        hipMemsetAsync(c->S[1], 0, 5 * fe * sizeof(double), c->s) != hipSuccess ||
+        hipMemsetAsync(c->scal, 0, 16 * sizeof(double), c->s) != hipSuccess ||
+        hipMemsetAsync(c->flag, 0, sizeof(int), c->s) != hipSuccess) {
+      rc = fail(nullptr, LES_ERR_HIP, "les_create: hipMemsetAsync failed");
+      break;
+    }
+    if (c->Sf[0] && (hipMemsetAsync(c->Sf[0], 0, 5 * fe * sizeof(float), c->s) != hipSuccess ||
+                     hipMemsetAsync(c->Sf[1], 0, 5 * fe * sizeof(float), c->s) != hipSuccess)) {
+      rc = fail(nullptr, LES_ERR_HIP, "les_create: hipMemsetAsync failed");
+      break;
+    }
+    e = metrics_dense ? les::launch_metrics_copy(c->s, c->L, metrics_dense, c->M)
+                      : les::launch_metrics(c->s, c->L, c->bc, grid->xyz, c->M);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+    if (e != hipSuccess) {
+      rc = fail(nullptr, LES_ERR_HIP, "les_create: metrics: %s", hipGetErrorString(e));
+      break;
+    }
+  } while (0);
+  if (rc != LES_OK) {
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return LES_OK;
+}
+
+void les_destroy(les_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->s);
+  free_all(ctx);
+  delete ctx;
+}
+
+int les_get_metrics(les_ctx* ctx, double* dense_out) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_get_metrics: null context");
+  if (!dense_out) return fail(ctx, LES_ERR_ARG, "les_get_metrics: null output");
+  HIPCHK(ctx, les::launch_metrics_export(ctx->s, ctx->L, ctx->M, dense_out));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->s));
+  return LES_OK;
+}
+
+// Read back the host outputs and the non-finite flag (synchronises).
+static int sync_outputs(les_ctx* c, double* dt_out, double* norms) {
+  double host[16];
+  int flag = 0;
+  HIPCHK(c, hipMemcpyAsync(host, c->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  if (dt_out) *dt_out = host[0];
+  if (norms)
+    for (int q = 0; q < 10; ++q) norms[q] = host[1 + q];
+  if (flag) {
+    HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->s));
+    return fail(c, LES_ERR_NONFINITE, "non-finite value detected (flag %d): %s", flag,
+                (flag & 1) ? "time step (density/pressure not positive or NaN)" : "residual norm");
+  }
+  return LES_OK;
+}
+
+int les_residual(les_ctx* ctx, double* Q, double* R, double* norms) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual: null context");
+  if (!Q || !R) return fail(ctx, LES_ERR_ARG, "les_residual: Q and R must be device pointers");
+  if (Q == R) return fail(ctx, LES_ERR_ARG, "les_residual: Q and R must not alias");
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5));
+  HIPCHK(ctx, les::launch_residual_ref(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->f, ctx->i_f, R,
+                                       norms ? ctx->part : nullptr));
+  if (!norms) return LES_OK;
+  const double cnt = (double)ctx->L.ni * ctx->L.nj * ctx->L.nk;
+  HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::ref_blocks(ctx->L), cnt, ctx->scal + 1, ctx->flag));
+  return sync_outputs(ctx, nullptr, norms);
+}
+
+int les_cfl_dt(les_ctx* ctx, const double* Q, double* dt_out) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_cfl_dt: null context");
+  if (!Q || !dt_out) return fail(ctx, LES_ERR_ARG, "les_cfl_dt: null pointer");
+  HIPCHK(ctx, les::launch_cfl(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag));
+  return sync_outputs(ctx, dt_out, nullptr);
+}
+
+int les_set_forcing(les_ctx* ctx, const double* f, int i_f) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_set_forcing: null context");
+  if (!f) {
+    ctx->i_f = -1;
+    return LES_OK;
+  }
+  if (i_f < 0 || i_f >= ctx->L.ni) return fail(ctx, LES_ERR_ARG, "les_set_forcing: plane %d outside [0, %d)", i_f, ctx->L.ni);
+  const size_t bytes = (size_t)5 * ctx->L.nk * ctx->L.nj * sizeof(double);
+  if (!ctx->f && hipMalloc(&ctx->f, bytes) != hipSuccess) return fail(ctx, LES_ERR_NOMEM, "les_set_forcing: allocation");
+  HIPCHK(ctx, hipMemcpyAsync(ctx->f, f, bytes, hipMemcpyDeviceToDevice, ctx->s));
+  ctx->i_f = i_f;
+  return LES_OK;
+}
+
+int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norms, double* stage_ckpt) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_rk_step: null context");
+  if (!Q) return fail(ctx, LES_ERR_ARG, "les_rk_step: Q is NULL");
+  if (dt != dt) return fail(ctx, LES_ERR_ARG, "les_rk_step: dt is NaN");
+  if (stage_ckpt && ctx->prec != LES_FP64)
+    return fail(ctx, LES_ERR_STATE, "les_rk_step: stage checkpoints need an FP64 context");
+  les::Layout& L = ctx->L;
+  const size_t fe = (size_t)L.fe;
+  const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5));
+  const double* dtp = nullptr;
+  if (!(dt > 0.0)) {
+    HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag));
+    dtp = ctx->scal;
+  } else {
+    dtp = nullptr;
+  }
+  const double cnt = (double)L.ni * L.nj * L.nk;
+  if (ctx->prec == LES_MIXED) {
+    les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f};
+    HIPCHK(ctx, les::run_rk_mixed(ctx->s, a, ctx->bc, Q, ctx->Sf, dtp, dt, norms ? ctx->part : nullptr));
+    if (norms) HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::stage_blocks(L), cnt, ctx->scal + 1, ctx->flag));
+  } else {
+    if (stage_ckpt) HIPCHK(ctx, hipMemcpyAsync(stage_ckpt, Q, 5 * fe * sizeof(double), hipMemcpyDeviceToDevice, ctx->s));
+    const double* in = stage_ckpt ? stage_ckpt : Q;
+    for (int l = 0; l < 5; ++l) {
+      double* out = l == 4 ? Q : (stage_ckpt ? stage_ckpt + (size_t)(l + 1) * 5 * fe : ctx->S[l & 1]);
+      if (l > 0 || stage_ckpt) HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, (double*)in, Q, 5));
+      double* part = (l == 0 && norms) ? ctx->part : nullptr;
+      if (ctx->use_ref) {
+        HIPCHK(ctx, les::launch_stage_ref(ctx->s, L, ctx->P, ctx->M, in, Q, out, dtp, dt, les::rk_alpha(l), f,
+                                          ctx->i_f, part));
+      } else {
+        les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f};
+        HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, in, Q, out, dtp, dt, les::rk_alpha(l), part));
+      }
+      in = out;
+    }
+    if (norms) {
+      long long nb = ctx->use_ref ? les::ref_blocks(L) : les::stage_blocks(L);
+      HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
+    }
+  }
+  if (!dt_out && !norms) return LES_OK;
+  int rc = sync_outputs(ctx, dt_out, norms);
+  if (dt_out && dtp == nullptr) *dt_out = dt;
+  return rc;
+}
+
+int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* Qbar, double* fbar) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_adjoint_step: null context");
+  if (!stage_ckpt || !Qbar) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: stage_ckpt and Qbar are required");
+  if (!(dt > 0.0)) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: dt must be > 0 (the step's fixed dt)");
+  if (ctx->prec != LES_FP64) return fail(ctx, LES_ERR_STATE, "les_adjoint_step: needs an FP64 context");
+  const size_t need = les::adjoint_work_elems(ctx->L);
+  if ((long long)need > ctx->adj_n) {
+    (void)hipFree(ctx->adj);
+    ctx->adj = nullptr;
+    ctx->adj_n = 0;
+    if (hipMalloc(&ctx->adj, need * sizeof(double)) != hipSuccess)
+      return fail(ctx, LES_ERR_NOMEM, "les_adjoint_step: work allocation (%zu bytes)", need * sizeof(double));
+    ctx->adj_n = (long long)need;
+  }
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f};
+  HIPCHK(ctx, les::run_adjoint_step(ctx->s, a, stage_ckpt, dt, Qbar, ctx->i_f >= 0 ? fbar : nullptr, ctx->adj));
+  return LES_OK;
+}
+
+int les_probe_objective(les_ctx* ctx, const double* Q, int i_p, double p_inf, double weight, double* J_accum,
+                        double* Qbar) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_probe_objective: null context");
+  if (!Q || !J_accum) return fail(ctx, LES_ERR_ARG, "les_probe_objective: Q and J_accum are required");
+  if (i_p < 0 || i_p >= ctx->L.ni) return fail(ctx, LES_ERR_ARG, "les_probe_objective: plane %d outside [0, %d)", i_p, ctx->L.ni);
+  HIPCHK(ctx, les::launch_probe(ctx->s, ctx->L, ctx->P, Q, i_p, p_inf, weight, J_accum, Qbar));
+  return LES_OK;
+}
+
+// Select the stage kernel: 0 = fused tiled kernel (default), 1 = reference
+// kernel.  Not declared in les.h: a testing switch used to cross-check the
+// two formulations.
+int les_debug_use_reference(les_ctx* ctx, int on) {
+  if (!ctx) return LES_ERR_ARG;
+  ctx->use_ref = on ? 1 : 0;
+  return LES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// les_common.hpp -- types and device building blocks shared by the gfx950
+// kernels of the LES residual / Runge-Kutta library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace les {
+
+constexpr int GH = 2;    // ghost layers per side (Sec. 4, Fig. 3)
+constexpr int LEAD = 8;  // element offset of interior i = 0 inside a row (64 B)
+
+// Library layout of one field (see include/les.h).
+struct Layout {
+  int ni, nj, nk;
+  long long sj, sk;  // element strides of j and k (stride of i is 1)
+  long long fe;      // field pitch in elements
+  long long o;       // element offset of interior node (0, 0, 0)
+  __host__ __device__ long long at(int i, int j, int k) const {
+    return o + (long long)i + (long long)j * sj + (long long)k * sk;
+  }
+};
+
+inline Layout make_layout(int ni, int nj, int nk) {
+  Layout L;
+  L.ni = ni; L.nj = nj; L.nk = nk;
+  long long pitch = ((long long)LEAD + ni + GH + 15) / 16 * 16;
+  L.sj = pitch;
+  L.sk = pitch * (nj + 2 * GH);
+  L.fe = (L.sk * (nk + 2 * GH) + 31) / 32 * 32;
+  L.o = LEAD + GH * L.sj + GH * L.sk;
+  return L;
+}
+
+// Dense padded layout [nk+4][nj+4][ni+4].
+struct Dense {
+  int ni, nj, nk;
+  __host__ __device__ long long at(int i, int j, int k) const {
+    return ((long long)(k + GH) * (nj + 2 * GH) + (j + GH)) * (long long)(ni + 2 * GH) + (i + GH);
+  }
+  __host__ __device__ long long n() const { return (long long)(ni + 4) * (nj + 4) * (nk + 4); }
+};
+
+// Flow / scheme constants, derived once on the host.
+struct Phys {
+  double gamma, gm1, inv_R, Cp_over_Pr, Cp_over_Prsgs;
+  double mu_ref, inv_Tref, S, one_plus_S;
+  double Cs2;  // Cs^2
+  double k2, k4, alpha;
+  double cfl, nu_fac;  // nu_fac = max(4/3, gamma/Pr)
+  int sgs;
+  int alpha_half;  // alpha == 1/2: Lam_d = lam_d + sqrt(lam_d)(sqrt(lam_e) + sqrt(lam_f))
+};
+
+// Runge-Kutta coefficients of the five-stage scheme.
+__host__ __device__ inline double rk_alpha(int l) {
+  return l == 0 ? 0.25 : l == 1 ? (1.0 / 6.0) : l == 2 ? 0.375 : l == 3 ? 0.5 : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise physics (templated on the compute type T).
+// ---------------------------------------------------------------------------
+// Primitive variables from Q (Eq. 2, 7): u, v, w, p, T.
+template <class T>
+__device__ __forceinline__ void prim_from_q(T q0, T q1, T q2, T q3, T q4, const Phys& P, T& u, T& v, T& w, T& p,
+                                            T& tem) {
+  T ir = T(1) / q0;
+  u = q1 * ir;
+  v = q2 * ir;
+  w = q3 * ir;
+  p = T(P.gm1) * (q4 - T(0.5) * q0 * (u * u + v * v + w * w));
+  tem = p * ir * T(P.inv_R);
+}
+
+// Sutherland's law (Eq. 6): mu_ref (T/T_ref)^{3/2} (1+S)/(T/T_ref + S).
+template <class T>
+__device__ __forceinline__ T sutherland(T tem, const Phys& P) {
+  T th = tem * T(P.inv_Tref);
+  return T(P.mu_ref * P.one_plus_S) * th * sqrt(th) / (th + T(P.S));
+}
+
+// Anisotropic spectral-radius scaling of Turkel and Vatsa for direction d
+// given lam_d and the other two radii.
+template <class T>
+__device__ __forceinline__ T aniso(T ld, T le, T lf, const Phys& P) {
+  if (P.alpha_half) {
+    T sd = sqrt(ld);
+    return ld + sd * (sqrt(le) + sqrt(lf));
+  }
+  return ld * (T(1) + pow(le / ld, T(P.alpha)) + pow(lf / ld, T(P.alpha)));
+}
+
+template <class T>
+__device__ __forceinline__ T tmax(T a, T b) { return a >= b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Wavefront / block reductions (64-lane wavefronts).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_down(v, off, 64);
+    v = (o > v || o != o) ? o : v;  // NaN wins so that it is reported
+  }
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_down(v, off, 64);
+    v = (o < v || o != o) ? o : v;
+  }
+  return v;
+}
+
+}  // namespace les

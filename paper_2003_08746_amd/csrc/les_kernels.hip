@@ -1,0 +1,538 @@
+// les_kernels.hip -- setup, boundary, reduction and reference-residual kernels.
+//
+// * k_metrics: Jacobian and metric terms (Alg. 2, "Calc(Jacob., Metric)")
+//   in the conservative central-difference form.
+// * k_ghost_fill: two ghost layers (Sec. 4, Fig. 3): periodic wrap (Sec. 3,
+//   azimuthal periodicity) or frozen Dirichlet values.
+// * k_cfl_partial / k_cfl_final: global CFL time step (FP64 min reduction).
+// * k_residual_ref / k_stage_ref: one thread per interior node evaluating the
+//   residual (Eq. 12-15 with Turkel-Vatsa dissipation) directly from global
+//   memory, recomputing every neighbour quantity.  It is the simple,
+//   structure-independent GPU formulation used by les_residual and to
+//   cross-check the fused stage kernel.
+// * k_norm_final: RMS / max norms of R from per-block partials (FP64).
+// * k_probe: pressure-fluctuation objective on a plane and its gradient.
+#include "les_common.hpp"
+
+namespace les {
+
+// ---------------------------------------------------------------------------
+// Metrics: m[0..8] = xi_x/J .. zeta_z/J, m[9] = J on nodes in [-1, n]^3.
+// ---------------------------------------------------------------------------
+__global__ void k_metrics(Layout L, Dense D, int bc0, int bc1, int bc2, const double* __restrict__ xyz,
+                          double* __restrict__ M) {
+  const int ext_i = L.ni + 2, ext_j = L.nj + 2;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long tot = (long long)ext_i * ext_j * (L.nk + 2);
+  if (t >= tot) return;
+  int i = (int)(t % ext_i) - 1;
+  int j = (int)((t / ext_i) % ext_j) - 1;
+  int k = (int)(t / ((long long)ext_i * ext_j)) - 1;
+  // a periodic ghost takes the metrics of its wrapped interior node
+  int id[3] = {i, j, k};
+  const int nn[3] = {L.ni, L.nj, L.nk};
+  const int bc[3] = {bc0, bc1, bc2};
+  for (int d = 0; d < 3; ++d)
+    if (bc[d] == 0) id[d] = (id[d] + nn[d]) % nn[d];
+  const long long N = D.n();
+  auto X = [&](int c, int a, int b, int e) { return xyz[c * N + D.at(a, b, e)]; };
+  // central difference of coordinate c along direction d at node (a, b, e)
+  auto dX = [&](int c, int d, int a, int b, int e) {
+    int da = d == 0, db = d == 1, de = d == 2;
+    return 0.5 * (X(c, a + da, b + db, e + de) - X(c, a - da, b - db, e - de));
+  };
+  const long long out = L.at(i, j, k);
+  for (int a = 0; a < 3; ++a) {
+    int bd = (a + 1) % 3, cd = (a + 2) % 3;
+    int bi = bd == 0, bj = bd == 1, bk = bd == 2;
+    int ci = cd == 0, cj = cd == 1, ck = cd == 2;
+    for (int l = 0; l < 3; ++l) {
+      int l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+      double t1 = 0.5 * (dX(l1, bd, id[0] + ci, id[1] + cj, id[2] + ck) * X(l2, id[0] + ci, id[1] + cj, id[2] + ck) -
+                         dX(l1, bd, id[0] - ci, id[1] - cj, id[2] - ck) * X(l2, id[0] - ci, id[1] - cj, id[2] - ck));
+      double t2 = 0.5 * (dX(l1, cd, id[0] + bi, id[1] + bj, id[2] + bk) * X(l2, id[0] + bi, id[1] + bj, id[2] + bk) -
+                         dX(l1, cd, id[0] - bi, id[1] - bj, id[2] - bk) * X(l2, id[0] - bi, id[1] - bj, id[2] - bk));
+      M[(3 * a + l) * L.fe + out] = t1 - t2;
+    }
+  }
+  double a11 = dX(0, 0, id[0], id[1], id[2]), a12 = dX(0, 1, id[0], id[1], id[2]), a13 = dX(0, 2, id[0], id[1], id[2]);
+  double a21 = dX(1, 0, id[0], id[1], id[2]), a22 = dX(1, 1, id[0], id[1], id[2]), a23 = dX(1, 2, id[0], id[1], id[2]);
+  double a31 = dX(2, 0, id[0], id[1], id[2]), a32 = dX(2, 1, id[0], id[1], id[2]), a33 = dX(2, 2, id[0], id[1], id[2]);
+  double vol = a11 * (a22 * a33 - a23 * a32) - a12 * (a21 * a33 - a23 * a31) + a13 * (a21 * a32 - a22 * a31);
+  M[9 * L.fe + out] = 1.0 / vol;
+}
+
+// Copy caller metrics (dense) into the library layout on [-1, n]^3.
+__global__ void k_metrics_copy(Layout L, Dense D, const double* __restrict__ src, double* __restrict__ M) {
+  const int ext_i = L.ni + 2, ext_j = L.nj + 2;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long tot = (long long)ext_i * ext_j * (L.nk + 2);
+  if (t >= tot) return;
+  int i = (int)(t % ext_i) - 1;
+  int j = (int)((t / ext_i) % ext_j) - 1;
+  int k = (int)(t / ((long long)ext_i * ext_j)) - 1;
+  for (int c = 0; c < 10; ++c) M[c * L.fe + L.at(i, j, k)] = src[c * D.n() + D.at(i, j, k)];
+}
+
+// Library metrics -> dense array (nodes outside [-1, n]^3 are zero).
+__global__ void k_metrics_export(Layout L, Dense D, const double* __restrict__ M, double* __restrict__ dst) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= D.n()) return;
+  int pi = L.ni + 4, pj = L.nj + 4;
+  int i = (int)(t % pi) - 2;
+  int j = (int)((t / pi) % pj) - 2;
+  int k = (int)(t / ((long long)pi * pj)) - 2;
+  bool ok = i >= -1 && i <= L.ni && j >= -1 && j <= L.nj && k >= -1 && k <= L.nk;
+  for (int c = 0; c < 10; ++c) dst[c * D.n() + t] = ok ? M[c * L.fe + L.at(i, j, k)] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Ghost fill.  Threads enumerate only the ghost shell: the k-ghost slabs
+// (full i, j extent), then the j-ghost slabs inside interior k, then the
+// i-ghost columns inside interior j, k.  A node that is a ghost in a
+// Dirichlet direction copies its frozen value from `frozen` (nothing to do
+// when frozen == q); any other ghost copies the interior node obtained by
+// wrapping its periodic indices.  Sources are always interior nodes or the
+// frozen array, never a node this kernel writes.
+// ---------------------------------------------------------------------------
+__global__ void k_ghost_fill(Layout L, int bc0, int bc1, int bc2, double* q, const double* frozen, int nf) {
+  const int PI = L.ni + 4, PJ = L.nj + 4;
+  const long long cA = 4LL * PJ * PI;
+  const long long cB = (long long)L.nk * 4 * PI;
+  const long long cC = (long long)L.nk * L.nj * 4;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t < cA) {
+    int kk = (int)(t / ((long long)PJ * PI));
+    long long r = t % ((long long)PJ * PI);
+    k = kk < 2 ? kk - 2 : L.nk + kk - 2;
+    j = (int)(r / PI) - 2;
+    i = (int)(r % PI) - 2;
+  } else if (t < cA + cB) {
+    long long u = t - cA;
+    k = (int)(u / (4LL * PI));
+    long long r = u % (4LL * PI);
+    int jj = (int)(r / PI);
+    j = jj < 2 ? jj - 2 : L.nj + jj - 2;
+    i = (int)(r % PI) - 2;
+  } else if (t < cA + cB + cC) {
+    long long u = t - cA - cB;
+    k = (int)(u / (4LL * L.nj));
+    long long r = u % (4LL * L.nj);
+    j = (int)(r / 4);
+    int ii = (int)(r % 4);
+    i = ii < 2 ? ii - 2 : L.ni + ii - 2;
+  } else {
+    return;
+  }
+  const int id[3] = {i, j, k};
+  const int nn[3] = {L.ni, L.nj, L.nk};
+  const int bc[3] = {bc0, bc1, bc2};
+  bool dir = false;
+  int w[3];
+  for (int d = 0; d < 3; ++d) {
+    bool g = id[d] < 0 || id[d] >= nn[d];
+    if (g && bc[d] == 1) dir = true;
+    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d] : id[d];
+  }
+  const long long dst = L.at(i, j, k);
+  if (dir) {
+    if (frozen != q)
+      for (int f = 0; f < nf; ++f) q[f * L.fe + dst] = frozen[f * L.fe + dst];
+    return;
+  }
+  const long long src = L.at(w[0], w[1], w[2]);
+  for (int f = 0; f < nf; ++f) q[f * L.fe + dst] = q[f * L.fe + src];
+}
+
+// ---------------------------------------------------------------------------
+// CFL time step: per-block minima, then one block for the global minimum.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cfl_partial(Layout L, Phys P, const double* __restrict__ M,
+                                                     const double* __restrict__ Q, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  double loc = INFINITY;
+  if (i < L.ni && j < L.nj) {
+    long long n = L.at(i, j, k);
+    double q0 = Q[n], q1 = Q[L.fe + n], q2 = Q[2 * L.fe + n], q3 = Q[3 * L.fe + n], q4 = Q[4 * L.fe + n];
+    double u, v, w, p, tem;
+    prim_from_q(q0, q1, q2, q3, q4, P, u, v, w, p, tem);
+    double c = sqrt(P.gamma * p / q0);
+    double mu = sutherland(tem, P);
+    double nuv = P.nu_fac * mu / q0;
+    double J = M[9 * L.fe + n];
+    double lam = 0.0, g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double gx = J * M[(3 * d) * L.fe + n], gy = J * M[(3 * d + 1) * L.fe + n], gz = J * M[(3 * d + 2) * L.fe + n];
+      double U = gx * u + gy * v + gz * w;
+      double gg = gx * gx + gy * gy + gz * gz;
+      lam += fabs(U) + c * sqrt(gg);
+      g2 += gg;
+    }
+    loc = 1.0 / (lam + 2.0 * nuv * g2);
+    if (!(loc > 0.0) || !(q0 > 0.0) || !(p > 0.0)) loc = NAN;
+  }
+  loc = wave_min(loc);
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  if ((tid & 63) == 0) red[tid >> 6] = loc;
+  __syncthreads();
+  if (tid == 0) {
+    double m = red[0];
+    for (int a = 1; a < 4; ++a) m = (red[a] < m || red[a] != red[a]) ? red[a] : m;
+    part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = m;
+  }
+}
+
+// scal[0] = dt; flag |= 1 when the minimum is not a positive finite number.
+__global__ void __launch_bounds__(256) k_cfl_final(const double* __restrict__ part, long long np, double cfl,
+                                                   double* __restrict__ scal, int* __restrict__ flag) {
+  __shared__ double red[4];
+  double m = INFINITY;
+  for (long long b = threadIdx.x; b < np; b += 256) {
+    double v = part[b];
+    m = (v < m || v != v) ? v : m;
+  }
+  m = wave_min(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int a = 1; a < 4; ++a) r = (red[a] < r || red[a] != red[a]) ? red[a] : r;
+    double dt = cfl * r;
+    if (!(dt > 0.0) || !(dt < INFINITY)) *flag |= 1;
+    scal[0] = dt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reference residual: one thread per interior node, every neighbour
+// quantity recomputed from global memory.
+// ---------------------------------------------------------------------------
+struct RefArgs {
+  Layout L;
+  Phys P;
+  const double* M;
+  const double* Q;
+};
+
+__device__ inline void ref_prim(const RefArgs& A, long long n, double& rho, double& u, double& v, double& w,
+                                double& p, double& tem) {
+  const long long fe = A.L.fe;
+  rho = A.Q[n];
+  prim_from_q(rho, A.Q[fe + n], A.Q[2 * fe + n], A.Q[3 * fe + n], A.Q[4 * fe + n], A.P, u, v, w, p, tem);
+}
+
+__device__ inline long long dstride(const Layout& L, int d) { return d == 0 ? 1LL : (d == 1 ? L.sj : L.sk); }
+
+// Node flux H_d = inviscid - viscous (Eq. 15) at node n.
+__device__ void ref_node_flux(const RefArgs& A, int d, long long n, double H[5]) {
+  const Layout& L = A.L;
+  const Phys& P = A.P;
+  const long long fe = L.fe;
+  double rho, u, v, w, p, tem;
+  ref_prim(A, n, rho, u, v, w, p, tem);
+  // gradients of u, v, w, T along the index directions
+  double dd[3][4];
+  for (int e = 0; e < 3; ++e) {
+    long long s = dstride(L, e);
+    double r1, u1, v1, w1, p1, t1, r0, u0, v0, w0, p0, t0;
+    ref_prim(A, n + s, r1, u1, v1, w1, p1, t1);
+    ref_prim(A, n - s, r0, u0, v0, w0, p0, t0);
+    dd[e][0] = 0.5 * (u1 - u0);
+    dd[e][1] = 0.5 * (v1 - v0);
+    dd[e][2] = 0.5 * (w1 - w0);
+    dd[e][3] = 0.5 * (t1 - t0);
+  }
+  const double J = A.M[9 * fe + n];
+  double m[9];
+  for (int c = 0; c < 9; ++c) m[c] = A.M[c * fe + n];
+  double g[4][3];  // g[q][x] = d phi_q / d x
+  for (int q = 0; q < 4; ++q)
+    for (int x = 0; x < 3; ++x) g[q][x] = J * (m[x] * dd[0][q] + m[3 + x] * dd[1][q] + m[6 + x] * dd[2][q]);
+  double S[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) S[a][b] = 0.5 * (g[a][b] + g[b][a]);
+  double skk = S[0][0] + S[1][1] + S[2][2];
+  double mu = sutherland(tem, P);
+  double mus = 0.0;
+  if (P.sgs) {
+    double ss = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) ss += S[a][b] * S[a][b];
+    double delta2 = cbrt(1.0 / J);
+    delta2 *= delta2;
+    mus = rho * P.Cs2 * delta2 * sqrt(2.0 * ss);
+  }
+  const double mt2 = 2.0 * (mu + mus);
+  double tau[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) tau[a][b] = mt2 * (S[a][b] - (a == b ? skk / 3.0 : 0.0));
+  const double kap = mu * P.Cp_over_Pr + mus * P.Cp_over_Prsgs;
+  const double uu[3] = {u, v, w};
+  double th[3];
+  for (int x = 0; x < 3; ++x) th[x] = uu[0] * tau[0][x] + uu[1] * tau[1][x] + uu[2] * tau[2][x] + kap * g[3][x];
+  const double mx = m[3 * d], my = m[3 * d + 1], mz = m[3 * d + 2];
+  const double U = mx * u + my * v + mz * w;
+  H[0] = rho * U;
+  H[1] = rho * u * U + mx * p - (mx * tau[0][0] + my * tau[0][1] + mz * tau[0][2]);
+  H[2] = rho * v * U + my * p - (mx * tau[1][0] + my * tau[1][1] + mz * tau[1][2]);
+  H[3] = rho * w * U + mz * p - (mx * tau[2][0] + my * tau[2][1] + mz * tau[2][2]);
+  H[4] = (A.Q[4 * fe + n] + p) * U - (mx * th[0] + my * th[1] + mz * th[2]);
+}
+
+// Lambda_d (anisotropic spectral radius) and pressure at node n.
+__device__ double ref_Lambda(const RefArgs& A, int d, long long n) {
+  const long long fe = A.L.fe;
+  double rho, u, v, w, p, tem;
+  ref_prim(A, n, rho, u, v, w, p, tem);
+  double c = sqrt(A.P.gamma * p / rho);
+  double lam[3];
+  for (int e = 0; e < 3; ++e) {
+    double mx = A.M[(3 * e) * fe + n], my = A.M[(3 * e + 1) * fe + n], mz = A.M[(3 * e + 2) * fe + n];
+    lam[e] = fabs(mx * u + my * v + mz * w) + c * sqrt(mx * mx + my * my + mz * mz);
+  }
+  return aniso(lam[d], lam[(d + 1) % 3], lam[(d + 2) % 3], A.P);
+}
+
+__device__ inline double ref_p(const RefArgs& A, long long n) {
+  double rho, u, v, w, p, tem;
+  ref_prim(A, n, rho, u, v, w, p, tem);
+  return p;
+}
+
+// Dissipation flux at the face between a and a + e_d.
+__device__ void ref_face_diss(const RefArgs& A, int d, long long a, double D[5]) {
+  const long long s = dstride(A.L, d), fe = A.L.fe;
+  const double pm = ref_p(A, a - s), p0 = ref_p(A, a), p1 = ref_p(A, a + s), p2 = ref_p(A, a + 2 * s);
+  const double nua = fabs(p1 - 2.0 * p0 + pm) / (p1 + 2.0 * p0 + pm);
+  const double nub = fabs(p2 - 2.0 * p1 + p0) / (p2 + 2.0 * p1 + p0);
+  const double e2 = A.P.k2 * tmax(nua, nub);
+  const double e4 = tmax(0.0, A.P.k4 - e2);
+  const double Lf = 0.5 * (ref_Lambda(A, d, a) + ref_Lambda(A, d, a + s));
+  for (int q = 0; q < 5; ++q) {
+    const double* Qq = A.Q + q * fe;
+    double d1 = Qq[a + s] - Qq[a];
+    double d3 = Qq[a + 2 * s] - 3.0 * Qq[a + s] + 3.0 * Qq[a] - Qq[a - s];
+    D[q] = Lf * (e2 * d1 - e4 * d3);
+  }
+}
+
+__device__ void ref_residual(const RefArgs& A, int i, int j, int k, const double* f, int i_f, double R[5]) {
+  const long long n = A.L.at(i, j, k);
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    const long long s = dstride(A.L, d);
+    double Hp[5], Hm[5], Dp[5], Dm[5];
+    ref_node_flux(A, d, n + s, Hp);
+    ref_node_flux(A, d, n - s, Hm);
+    ref_face_diss(A, d, n, Dp);
+    ref_face_diss(A, d, n - s, Dm);
+    for (int q = 0; q < 5; ++q) acc[q] += 0.5 * (Hp[q] - Hm[q]) - (Dp[q] - Dm[q]);
+  }
+  const double J = A.M[9 * A.L.fe + n];
+  for (int q = 0; q < 5; ++q) {
+    R[q] = J * acc[q];
+    if (f && i == i_f) R[q] -= f[((long long)q * A.L.nk + k) * A.L.nj + j];
+  }
+}
+
+// Per-block partial norms: part[b*10 + q] = sum R_q^2, part[b*10 + 5 + q] = max |R_q|.
+__device__ inline void block_norms(const double R[5], bool active, double* part, long long bid) {
+  __shared__ double red[4][10];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  for (int q = 0; q < 5; ++q) {
+    double s = active ? R[q] * R[q] : 0.0;
+    double m = active ? fabs(R[q]) : 0.0;
+    s = wave_sum(s);
+    m = wave_max(m);
+    if ((tid & 63) == 0) {
+      red[tid >> 6][q] = s;
+      red[tid >> 6][5 + q] = m;
+    }
+  }
+  __syncthreads();
+  if (tid < 10) {
+    double v = red[0][tid];
+    const int nw = (blockDim.x * blockDim.y) >> 6;
+    for (int a = 1; a < nw; ++a) {
+      double o = red[a][tid];
+      v = tid < 5 ? v + o : ((o > v || o != o) ? o : v);
+    }
+    part[bid * 10 + tid] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_residual_ref(RefArgs A, const double* __restrict__ f, int i_f,
+                                                      double* __restrict__ R, double* __restrict__ part) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  const bool active = i < A.L.ni && j < A.L.nj;
+  double r[5] = {0, 0, 0, 0, 0};
+  if (active) {
+    ref_residual(A, i, j, k, f, i_f, r);
+    const long long n = A.L.at(i, j, k);
+    for (int q = 0; q < 5; ++q) R[q * A.L.fe + n] = r[q];
+  }
+  if (part) block_norms(r, active, part, ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+}
+
+// Q_out = Q0 - alpha dt R(Q_in) on the interior.
+// Q0 and Qout may be the same array (last stage): each thread reads Q0 at
+// its own node before writing Qout there, and the stencil reads only A.Q.
+__global__ void __launch_bounds__(256) k_stage_ref(RefArgs A, const double* Q0, double* Qout,
+                                                   const double* __restrict__ dtp, double dt_host, double alpha, const double* __restrict__ f, int i_f,
+                                                   double* __restrict__ part) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  const bool active = i < A.L.ni && j < A.L.nj;
+  double r[5] = {0, 0, 0, 0, 0};
+  if (active) {
+    ref_residual(A, i, j, k, f, i_f, r);
+    const long long n = A.L.at(i, j, k);
+    const double c = alpha * (dtp ? dtp[0] : dt_host);
+    for (int q = 0; q < 5; ++q) Qout[q * A.L.fe + n] = Q0[q * A.L.fe + n] - c * r[q];
+  }
+  if (part) block_norms(r, active, part, ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+}
+
+// norms[q] = sqrt(sum/N), norms[5+q] = max; flag |= 2 if any is not finite.
+__global__ void __launch_bounds__(256) k_norm_final(const double* __restrict__ part, long long np, double count,
+                                                    double* __restrict__ norms, int* __restrict__ flag) {
+  __shared__ double red[4][10];
+  double acc[10];
+  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+  for (long long b = threadIdx.x; b < np; b += 256)
+    for (int q = 0; q < 10; ++q) {
+      double v = part[b * 10 + q];
+      acc[q] = q < 5 ? acc[q] + v : ((v > acc[q] || v != v) ? v : acc[q]);
+    }
+  for (int q = 0; q < 10; ++q) {
+    double v = q < 5 ? wave_sum(acc[q]) : wave_max(acc[q]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 10) {
+    const int q = threadIdx.x;
+    double v = red[0][q];
+    for (int a = 1; a < 4; ++a) v = q < 5 ? v + red[a][q] : ((red[a][q] > v || red[a][q] != red[a][q]) ? red[a][q] : v);
+    double out = q < 5 ? sqrt(v / count) : v;
+    norms[q] = out;
+    if (!(out < INFINITY)) atomicOr(flag, 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Probe objective on plane i_p: one block; J += w sum (p - p_inf)^2 and
+// Qbar += w 2 (p - p_inf) dp/dQ.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_probe(Layout L, Phys P, const double* __restrict__ Q, int i_p, double p_inf,
+                                               double weight, double* __restrict__ Jacc, double* __restrict__ Qbar) {
+  __shared__ double red[4];
+  double s = 0.0;
+  const long long cnt = (long long)L.nj * L.nk;
+  for (long long t = threadIdx.x; t < cnt; t += 256) {
+    int j = (int)(t % L.nj), k = (int)(t / L.nj);
+    long long n = L.at(i_p, j, k);
+    double rho = Q[n], m1 = Q[L.fe + n], m2 = Q[2 * L.fe + n], m3 = Q[3 * L.fe + n], e = Q[4 * L.fe + n];
+    double u = m1 / rho, v = m2 / rho, w = m3 / rho;
+    double p = P.gm1 * (e - 0.5 * rho * (u * u + v * v + w * w));
+    double dp = p - p_inf;
+    s += dp * dp;
+    if (Qbar) {
+      double g = weight * 2.0 * dp * P.gm1;
+      Qbar[n] += g * 0.5 * (u * u + v * v + w * w);
+      Qbar[L.fe + n] -= g * u;
+      Qbar[2 * L.fe + n] -= g * v;
+      Qbar[3 * L.fe + n] -= g * w;
+      Qbar[4 * L.fe + n] += g;
+    }
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) Jacc[0] += weight * (red[0] + red[1] + red[2] + red[3]);
+}
+
+}  // namespace les
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+namespace les {
+
+static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_metrics(hipStream_t s, const Layout& L, const int bc[3], const double* xyz, double* M) {
+  Dense D{L.ni, L.nj, L.nk};
+  long long tot = (long long)(L.ni + 2) * (L.nj + 2) * (L.nk + 2);
+  k_metrics<<<nblk(tot, 256), 256, 0, s>>>(L, D, bc[0], bc[1], bc[2], xyz, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics_copy(hipStream_t s, const Layout& L, const double* src, double* M) {
+  Dense D{L.ni, L.nj, L.nk};
+  long long tot = (long long)(L.ni + 2) * (L.nj + 2) * (L.nk + 2);
+  k_metrics_copy<<<nblk(tot, 256), 256, 0, s>>>(L, D, src, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics_export(hipStream_t s, const Layout& L, const double* M, double* dst) {
+  Dense D{L.ni, L.nj, L.nk};
+  k_metrics_export<<<nblk(D.n(), 256), 256, 0, s>>>(L, D, M, dst);
+  return hipGetLastError();
+}
+
+long long ghost_count(const Layout& L) {
+  return 4LL * (L.nj + 4) * (L.ni + 4) + (long long)L.nk * 4 * (L.ni + 4) + (long long)L.nk * L.nj * 4;
+}
+
+hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], double* q, const double* frozen, int nf) {
+  k_ghost_fill<<<nblk(ghost_count(L), 256), 256, 0, s>>>(L, bc[0], bc[1], bc[2], q, frozen, nf);
+  return hipGetLastError();
+}
+
+long long ref_blocks(const Layout& L) { return (long long)nblk(L.ni, 64) * nblk(L.nj, 4) * L.nk; }
+
+hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
+                      double* scal, int* flag) {
+  dim3 g(nblk(L.ni, 64), nblk(L.nj, 4), L.nk), b(64, 4);
+  k_cfl_partial<<<g, b, 0, s>>>(L, P, M, Q, part);
+  k_cfl_final<<<1, 256, 0, s>>>(part, ref_blocks(L), P.cfl, scal, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q,
+                               const double* f, int i_f, double* R, double* part) {
+  dim3 g(nblk(L.ni, 64), nblk(L.nj, 4), L.nk), b(64, 4);
+  RefArgs A{L, P, M, Q};
+  k_residual_ref<<<g, b, 0, s>>>(A, f, i_f, R, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Qin,
+                            const double* Q0, double* Qout, const double* dtp, double dt, double alpha,
+                            const double* f, int i_f, double* part) {
+  dim3 g(nblk(L.ni, 64), nblk(L.nj, 4), L.nk), b(64, 4);
+  RefArgs A{L, P, M, Qin};
+  k_stage_ref<<<g, b, 0, s>>>(A, Q0, Qout, dtp, dt, alpha, f, i_f, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_final(hipStream_t s, const double* part, long long np, double count, double* norms, int* flag) {
+  k_norm_final<<<1, 256, 0, s>>>(part, np, count, norms, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe(hipStream_t s, const Layout& L, const Phys& P, const double* Q, int i_p, double p_inf,
+                        double weight, double* Jacc, double* Qbar) {
+  k_probe<<<1, 256, 0, s>>>(L, P, Q, i_p, p_inf, weight, Jacc, Qbar);
+  return hipGetLastError();
+}
+
+}  // namespace les

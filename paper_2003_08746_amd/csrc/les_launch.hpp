@@ -1,0 +1,25 @@
+// les_launch.hpp -- host launchers of the gfx950 kernels (one translation
+// unit per kernel family; the C-ABI implementation calls only these).
+#pragma once
+#include "les_common.hpp"
+
+namespace les {
+
+hipError_t launch_metrics(hipStream_t s, const Layout& L, const int bc[3], const double* xyz, double* M);
+hipError_t launch_metrics_copy(hipStream_t s, const Layout& L, const double* src, double* M);
+hipError_t launch_metrics_export(hipStream_t s, const Layout& L, const double* M, double* dst);
+long long ghost_count(const Layout& L);
+hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], double* q, const double* frozen, int nf);
+long long ref_blocks(const Layout& L);
+hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
+                      double* scal, int* flag);
+hipError_t launch_residual_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q,
+                               const double* f, int i_f, double* R, double* part);
+hipError_t launch_stage_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Qin,
+                            const double* Q0, double* Qout, const double* dtp, double dt, double alpha,
+                            const double* f, int i_f, double* part);
+hipError_t launch_norm_final(hipStream_t s, const double* part, long long np, double count, double* norms, int* flag);
+hipError_t launch_probe(hipStream_t s, const Layout& L, const Phys& P, const double* Q, int i_p, double p_inf,
+                        double weight, double* Jacc, double* Qbar);
+
+}  // namespace les

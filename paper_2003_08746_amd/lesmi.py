@@ -1,0 +1,289 @@
+"""Python binding of the C ABI in include/les.h (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of liblesmi.so; this module
+only converts arguments.  torch supplies device memory and the current HIP
+stream.  There is no CPU fallback: importing works without a GPU (for
+inspection), but every call that computes needs the built library and a
+gfx950 device, and raises otherwise.
+
+The functions keep the C names (les_create, les_residual, les_rk_step,
+les_adjoint_step, ...).  ``Solver`` bundles a context with helpers that move
+dense padded arrays in and out of the library layout.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblesmi.so")
+
+LES_OK, LES_ERR_ARG, LES_ERR_HIP, LES_ERR_NOMEM, LES_ERR_NONFINITE, LES_ERR_STATE = 0, -1, -2, -3, -4, -5
+LES_FP64, LES_MIXED = 0, 1
+LES_BC_PERIODIC, LES_BC_DIRICHLET = 0, 1
+
+EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",
+            "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_adjoint_step", "les_probe_objective",
+            "les_last_error", "les_last_create_error"]
+
+
+class LesError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class LesGrid(ctypes.Structure):
+    _fields_ = [("ni", ctypes.c_int), ("nj", ctypes.c_int), ("nk", ctypes.c_int), ("bc", ctypes.c_int * 3),
+                ("xyz", ctypes.c_void_p)]
+
+
+class LesFlowParams(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("Pr", ctypes.c_double), ("Pr_sgs", ctypes.c_double),
+                ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("S_suth", ctypes.c_double),
+                ("R_gas", ctypes.c_double), ("sgs", ctypes.c_int), ("Cs", ctypes.c_double),
+                ("k2", ctypes.c_double), ("k4", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("prec", ctypes.c_int)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_llp = ctypes.POINTER(ctypes.c_longlong)
+
+
+def lib():
+    """Load liblesmi.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.les_create.restype = ctypes.c_int
+    L.les_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(LesGrid), _vp, ctypes.POINTER(LesFlowParams), _vp]
+    L.les_destroy.restype = None
+    L.les_destroy.argtypes = [_vp]
+    L.les_layout.restype = ctypes.c_int
+    L.les_layout.argtypes = [_vp, _llp, _llp, _llp]
+    L.les_layout_for.restype = ctypes.c_int
+    L.les_layout_for.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _llp, _llp, _llp]
+    L.les_get_metrics.restype = ctypes.c_int
+    L.les_get_metrics.argtypes = [_vp, _vp]
+    L.les_residual.restype = ctypes.c_int
+    L.les_residual.argtypes = [_vp, _vp, _vp, _dp]
+    L.les_cfl_dt.restype = ctypes.c_int
+    L.les_cfl_dt.argtypes = [_vp, _vp, _dp]
+    L.les_set_forcing.restype = ctypes.c_int
+    L.les_set_forcing.argtypes = [_vp, _vp, ctypes.c_int]
+    L.les_rk_step.restype = ctypes.c_int
+    L.les_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _dp, _dp, _vp]
+    L.les_adjoint_step.restype = ctypes.c_int
+    L.les_adjoint_step.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp]
+    L.les_probe_objective.restype = ctypes.c_int
+    L.les_probe_objective.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp, _vp]
+    L.les_last_error.restype = ctypes.c_char_p
+    L.les_last_error.argtypes = [_vp]
+    L.les_last_create_error.restype = ctypes.c_char_p
+    L.les_last_create_error.argtypes = []
+    L.les_debug_use_reference.restype = ctypes.c_int
+    L.les_debug_use_reference.argtypes = [_vp, ctypes.c_int]
+    _lib = L
+    return L
+
+
+def _check(rc, ctx=None, what=""):
+    if rc != LES_OK:
+        L = lib()
+        msg = (L.les_last_error(ctx) if ctx else L.les_last_create_error()) or b""
+        raise LesError(rc, f"{what}: {msg.decode(errors='replace')}")
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def flow_params_struct(p: dict, prec: int = LES_FP64) -> LesFlowParams:
+    s = LesFlowParams()
+    for k in ["gamma", "Pr", "Pr_sgs", "mu_ref", "T_ref", "S_suth", "R_gas", "Cs", "k2", "k4", "alpha", "cfl"]:
+        setattr(s, k, float(p[k]))
+    s.sgs = int(p["sgs"])
+    s.prec = int(prec)
+    return s
+
+
+# ---------------------------------------------------------------------------
+# C names
+# ---------------------------------------------------------------------------
+def les_create(grid: LesGrid, metrics_dense_ptr, params: LesFlowParams, stream_ptr) -> int:
+    ctx = _vp()
+    rc = lib().les_create(ctypes.byref(ctx), ctypes.byref(grid), metrics_dense_ptr, ctypes.byref(params),
+                          stream_ptr)
+    _check(rc, None, "les_create")
+    return ctx.value
+
+
+def les_destroy(ctx) -> None:
+    lib().les_destroy(ctx)
+
+
+def les_layout(ctx):
+    st = (ctypes.c_longlong * 3)()
+    o = ctypes.c_longlong()
+    fe = ctypes.c_longlong()
+    _check(lib().les_layout(ctx, st, ctypes.byref(o), ctypes.byref(fe)), ctx, "les_layout")
+    return tuple(st), o.value, fe.value
+
+
+def les_layout_for(ni, nj, nk):
+    st = (ctypes.c_longlong * 3)()
+    o = ctypes.c_longlong()
+    fe = ctypes.c_longlong()
+    _check(lib().les_layout_for(ni, nj, nk, st, ctypes.byref(o), ctypes.byref(fe)), None, "les_layout_for")
+    return tuple(st), o.value, fe.value
+
+
+def les_get_metrics(ctx, dense_out_ptr):
+    _check(lib().les_get_metrics(ctx, dense_out_ptr), ctx, "les_get_metrics")
+
+
+def les_residual(ctx, Q_ptr, R_ptr, want_norms=False):
+    norms = (ctypes.c_double * 10)() if want_norms else None
+    rc = lib().les_residual(ctx, Q_ptr, R_ptr, norms)
+    _check(rc, ctx, "les_residual")
+    return np.array(norms[:]) if want_norms else None
+
+
+def les_cfl_dt(ctx, Q_ptr) -> float:
+    dt = ctypes.c_double()
+    _check(lib().les_cfl_dt(ctx, Q_ptr, ctypes.byref(dt)), ctx, "les_cfl_dt")
+    return dt.value
+
+
+def les_set_forcing(ctx, f_ptr, i_f):
+    _check(lib().les_set_forcing(ctx, f_ptr, int(i_f)), ctx, "les_set_forcing")
+
+
+def les_rk_step(ctx, Q_ptr, dt=0.0, want_dt=False, want_norms=False, ckpt_ptr=None):
+    dto = ctypes.c_double() if want_dt else None
+    norms = (ctypes.c_double * 10)() if want_norms else None
+    rc = lib().les_rk_step(ctx, Q_ptr, float(dt), ctypes.byref(dto) if want_dt else None, norms, ckpt_ptr)
+    _check(rc, ctx, "les_rk_step")
+    return (dto.value if want_dt else None), (np.array(norms[:]) if want_norms else None)
+
+
+def les_adjoint_step(ctx, ckpt_ptr, dt, Qbar_ptr, fbar_ptr=None):
+    _check(lib().les_adjoint_step(ctx, ckpt_ptr, float(dt), Qbar_ptr, fbar_ptr), ctx, "les_adjoint_step")
+
+
+def les_probe_objective(ctx, Q_ptr, i_p, p_inf, weight, J_ptr, Qbar_ptr=None):
+    _check(lib().les_probe_objective(ctx, Q_ptr, int(i_p), float(p_inf), float(weight), J_ptr, Qbar_ptr), ctx,
+           "les_probe_objective")
+
+
+def les_debug_use_reference(ctx, on: bool):
+    _check(lib().les_debug_use_reference(ctx, 1 if on else 0), ctx, "les_debug_use_reference")
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper around one context
+# ---------------------------------------------------------------------------
+class Solver:
+    """One block on one GPU.  ``case`` is a dict from ``inputs`` (ni, nj, nk,
+    bc, xyz (dense padded numpy or torch), params)."""
+
+    def __init__(self, case: dict, prec: int = LES_FP64, device: str = "cuda", stream=None, xyz=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.ni, self.nj, self.nk = int(case["ni"]), int(case["nj"]), int(case["nk"])
+        self.bc = tuple(int(b) for b in case["bc"])
+        self.params = dict(case["params"])
+        self.prec = prec
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if xyz is None:
+            xyz = case["xyz"]
+        xyz_t = xyz if isinstance(xyz, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(xyz))
+        xyz_t = xyz_t.to(self.device, torch.float64).contiguous()
+        g = LesGrid()
+        g.ni, g.nj, g.nk = self.ni, self.nj, self.nk
+        for d in range(3):
+            g.bc[d] = self.bc[d]
+        g.xyz = xyz_t.data_ptr()
+        with torch.cuda.stream(self.stream):
+            self.ctx = les_create(g, None, flow_params_struct(self.params, prec), int(self.stream.cuda_stream))
+        del xyz_t
+        self.strides, self.origin, self.fe = les_layout(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            les_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- memory helpers (layout marshalling) ---
+    def empty_state(self, nf=5, dtype=None):
+        t = self.torch
+        return t.zeros(nf * self.fe, dtype=dtype or t.float64, device=self.device)
+
+    def view(self, state, nf=5):
+        """Dense padded view (nf, nk+4, nj+4, ni+4) of a library-layout array."""
+        sj, sk = self.strides[1], self.strides[2]
+        start = self.origin - 2 - 2 * sj - 2 * sk
+        return state.as_strided((nf, self.nk + 4, self.nj + 4, self.ni + 4), (self.fe, sk, sj, 1),
+                                state.storage_offset() + start)
+
+    def upload(self, dense, nf=5):
+        t = self.torch
+        st = self.empty_state(nf)
+        src = dense if isinstance(dense, t.Tensor) else t.from_numpy(np.ascontiguousarray(dense))
+        self.view(st, nf).copy_(src.to(self.device, t.float64))
+        return st
+
+    def download(self, state, nf=5) -> np.ndarray:
+        return self.view(state, nf).cpu().numpy().copy()
+
+    def metrics_dense(self) -> np.ndarray:
+        t = self.torch
+        out = t.zeros((10, self.nk + 4, self.nj + 4, self.ni + 4), dtype=t.float64, device=self.device)
+        les_get_metrics(self.ctx, out.data_ptr())
+        return out.cpu().numpy()
+
+    # --- method calls ---
+    def residual(self, Q, want_norms=False):
+        R = self.empty_state()
+        norms = les_residual(self.ctx, Q.data_ptr(), R.data_ptr(), want_norms)
+        return (R, norms) if want_norms else R
+
+    def cfl_dt(self, Q) -> float:
+        return les_cfl_dt(self.ctx, Q.data_ptr())
+
+    def rk_step(self, Q, dt=0.0, want_dt=False, want_norms=False, ckpt=None):
+        return les_rk_step(self.ctx, Q.data_ptr(), dt, want_dt, want_norms, _ptr(ckpt))
+
+    def set_forcing(self, f, i_f):
+        les_set_forcing(self.ctx, None if f is None else f.data_ptr(), i_f)
+
+    def adjoint_step(self, ckpt, dt, Qbar, fbar=None):
+        les_adjoint_step(self.ctx, ckpt.data_ptr(), dt, Qbar.data_ptr(), _ptr(fbar))
+
+    def probe_objective(self, Q, i_p, p_inf, weight, J, Qbar=None):
+        les_probe_objective(self.ctx, Q.data_ptr(), i_p, p_inf, weight, J.data_ptr(), _ptr(Qbar))
+
+    def use_reference(self, on=True):
+        les_debug_use_reference(self.ctx, on)
