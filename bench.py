@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of the LES Runge-Kutta hot path on one MI355X.
+
+Workload: the 256 x 128 x 128 curvilinear jet shard (one GPU's share of the
+paper's Mach 1.4, Re_D = 1.57e6 jet, Sec. 5.1), FP64, CFL 0.5.  One "step" is
+one five-stage Runge-Kutta step: ghost fill, the device-side CFL time step,
+five fused residual + stage-update launches, and the residual-norm
+reduction (no host synchronisation inside the timed region).
+
+Prints one JSON line:
+  value      Mpoint-RK-stages/s = N * 5 * steps / wall time / 1e6 (inputs
+             resident in HBM before the timed region);
+  roofline   the stage kernel's algorithmic HBM bytes per launch
+             (192 B per point: mean of 160 B for stage 1 and 200 B for
+             stages 2-5) over its mean launch time, measured with HIP
+             events around every stage launch, against 8 TB/s;
+  cpu_baseline  the plain FP64 CPU oracle on a bounded sample of the same
+             workload (rank 0, host cores of this machine).
+Extra keys report the mixed-precision path and the adjoint/forward cost
+when those paths are available.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpoint-RK-stages/s & % HBM peak; FP32-mixed vs FP64; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+BYTES_FP64 = 192.0  # algorithmic bytes per point-stage, FP64 path
+BYTES_MIXED = 168.0
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ["les_stage.hip", "les_stage.hpp", "les_common.hpp"]:
+        p = os.path.join(ROOT, "paper_2003_08746_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(key):
+    """HBM bytes per stage launch from committed rocprofv3 counter runs, only
+    if they were taken on the current stage-kernel source."""
+    p = os.path.join(ROOT, "profiles", "stage_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        e = d.get(key)
+        if e and e.get("kernel_hash") == kernel_hash():
+            return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+    return None
+
+
+def time_gpu(case, prec, steps, warmup):
+    import torch
+    from paper_2003_08746_amd import lesmi
+    s = lesmi.Solver(case, prec=prec)
+    Q = s.upload(case["Q"])
+    for _ in range(warmup):
+        s.rk_step(Q)
+    dt0 = s.cfl_dt(Q)  # synchronises; also checks the warmed-up state is finite
+    timing = prec == lesmi.LES_FP64
+    if timing:
+        lesmi.les_debug_stage_timing(s.ctx, True)
+    stream = s.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        s.rk_step(Q)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    stage_ms, launches = (lesmi.les_debug_stage_time(s.ctx) if timing else (None, 0))
+    if timing:
+        lesmi.les_debug_stage_timing(s.ctx, False)
+    _, norms = s.rk_step(Q, 0.0, want_norms=True)  # raises on a non-finite state
+    out = dict(wall_s=wall, gpu_ms=gpu_ms, stage_ms=stage_ms, launches=launches, dt0=dt0, norms=list(norms))
+    s.close()
+    return out
+
+
+def cpu_baseline(case, target_s=10.0, max_steps=3):
+    import oracle
+    m = oracle.metrics(case)
+    Q = case["Q"]
+    n = case["ni"] * case["nj"] * case["nk"]
+    t0 = time.perf_counter()
+    done = 0
+    while done < max_steps:
+        Q, _, _, _ = oracle.rk_step(case, m, Q)
+        done += 1
+        if time.perf_counter() - t0 >= target_s:
+            break
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return dict(value=n * 5 * done / el / 1e6, unit="Mpoint-RK-stages/s", cores=cores, kind="oracle",
+                sample=f"{done} RK step(s) ({done * 5} stages) of the {case['ni']}x{case['nj']}x{case['nk']} "
+                       f"jet shard, FP64, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--ni", type=int, default=256)
+    ap.add_argument("--nj", type=int, default=128)
+    ap.add_argument("--nk", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and adjoint legs")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the residual/RK path runs on one GPU's share of the domain "
+              "(multi-GPU halo exchange is not part of this build); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2003_08746_amd import inputs, lesmi
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    case = inputs.jet_case(args.ni, args.nj, args.nk, seed=0)
+    npts = args.ni * args.nj * args.nk
+    print(f"[bench] workload jet {args.ni}x{args.nj}x{args.nk} FP64 warmup {args.warmup} steps {args.steps}",
+          file=sys.stderr, flush=True)
+    r = time_gpu(case, lesmi.LES_FP64, args.steps, args.warmup)
+    value = npts * 5 * args.steps / r["wall_s"] / 1e6
+    ms_per_step = r["wall_s"] * 1e3 / args.steps
+    avg_launch_s = r["stage_ms"] / r["launches"] / 1e3
+    bytes_per_launch = BYTES_FP64 * npts
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = load_traffic("jet_fp64")
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mpoint-RK-stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"jet shard {args.ni}x{args.nj}x{args.nk}, curvilinear (tanh-clustered, wavy), "
+                               "Mach 1.4, Re_D 1.57e6, Smagorinsky SGS on, CFL 0.5, FP64",
+                   "points": npts, "stages_per_step": 5},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / avg_launch_s / 1e9, 1),
+                     "kernel": "stage (fused residual + RK update)",
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": int(bytes_per_launch)},
+        "gpu_event_ms_per_step": round(r["gpu_ms"] / args.steps, 4),
+    }
+    if not args.no_extra:
+        extra = {}
+        try:
+            rm = time_gpu(case, lesmi.LES_MIXED, args.steps, args.warmup)
+            vm = npts * 5 * args.steps / rm["wall_s"] / 1e6
+            extra["mixed"] = {"value": round(vm, 2), "unit": "Mpoint-RK-stages/s",
+                              "speedup_vs_fp64": round(vm / value, 3),
+                              "algorithmic_GBps": round(BYTES_MIXED * npts * 5 * args.steps / rm["wall_s"] / 1e9, 1)}
+        except Exception as e:  # the path reports its own error; the FP64 line stands
+            extra["mixed"] = {"error": str(e)[:200]}
+        out["extra"] = extra
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -32,6 +32,15 @@ struct les_ctx {
   double* adj = nullptr;             // adjoint work arrays
   long long adj_n = 0;
   int use_ref = 0;                   // 1: stage through the reference kernel
+  int kchunk = 0;                    // k planes per block of the fused kernel
+  // optional HIP-event timing of every stage-kernel launch
+  int timing = 0;
+  static const int TMAX = 4096;
+  hipEvent_t ev[2 * 4096];
+  int nev = 0;                       // events created
+  int nrec = 0;                      // launches recorded since the last read
+  double t_ms = 0.0;                 // resolved total
+  long long t_cnt = 0;
   char err[512];
 };
 
@@ -54,6 +63,8 @@ static int fail(les_ctx* c, int code, const char* fmt, ...) {
 
 static void free_all(les_ctx* c) {
   if (!c) return;
+  for (int e = 0; e < c->nev; ++e) (void)hipEventDestroy(c->ev[e]);
+  c->nev = 0;
   (void)hipFree(c->M);
   (void)hipFree(c->S[0]);
   (void)hipFree(c->S[1]);
@@ -64,6 +75,41 @@ static void free_all(les_ctx* c) {
   (void)hipFree(c->scal);
   (void)hipFree(c->flag);
   (void)hipFree(c->adj);
+}
+
+// Resolve recorded event pairs into the running total (synchronises).
+static int resolve_timing(les_ctx* c) {
+  if (c->nrec == 0) return LES_OK;
+  HIPCHK(c, hipEventSynchronize(c->ev[2 * c->nrec - 1]));
+  for (int r = 0; r < c->nrec; ++r) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * r], c->ev[2 * r + 1]));
+    c->t_ms += ms;
+  }
+  c->t_cnt += c->nrec;
+  c->nrec = 0;
+  return LES_OK;
+}
+
+static int timing_begin(les_ctx* c) {
+  if (!c->timing) return LES_OK;
+  if (c->nrec == les_ctx::TMAX) {
+    int rc = resolve_timing(c);
+    if (rc != LES_OK) return rc;
+  }
+  while (c->nev < 2 * (c->nrec + 1)) {
+    HIPCHK(c, hipEventCreate(&c->ev[c->nev]));
+    c->nev++;
+  }
+  HIPCHK(c, hipEventRecord(c->ev[2 * c->nrec], c->s));
+  return LES_OK;
+}
+
+static int timing_end(les_ctx* c) {
+  if (!c->timing) return LES_OK;
+  HIPCHK(c, hipEventRecord(c->ev[2 * c->nrec + 1], c->s));
+  c->nrec++;
+  return LES_OK;
 }
 
 extern "C" {
@@ -105,8 +151,12 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
   if (grid->ni < 5 || grid->nj < 5 || grid->nk < 5)
     return fail(nullptr, LES_ERR_ARG, "les_create: every interior size must be >= 5 (got %d x %d x %d)", grid->ni,
                 grid->nj, grid->nk);
-  if ((long long)grid->ni * grid->nj * grid->nk > (1LL << 34))
-    return fail(nullptr, LES_ERR_ARG, "les_create: block too large");
+  {
+    // the stage kernels address a field with 32-bit byte offsets
+    les::Layout Lc = les::make_layout(grid->ni, grid->nj, grid->nk);
+    if (Lc.fe >= (1LL << 29))
+      return fail(nullptr, LES_ERR_ARG, "les_create: block too large (%lld elements per field, limit 2^29)", Lc.fe);
+  }
   for (int d = 0; d < 3; ++d)
     if (grid->bc[d] != LES_BC_PERIODIC && grid->bc[d] != LES_BC_DIRICHLET)
       return fail(nullptr, LES_ERR_ARG, "les_create: bc[%d] = %d is not a known boundary type", d, grid->bc[d]);
@@ -151,8 +201,9 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
     return fail(nullptr, LES_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
   }
   const size_t fe = (size_t)c->L.fe;
-  c->part_n = les::ref_blocks(c->L);
-  long long sb = les::stage_blocks(c->L);
+  c->kchunk = les::stage_kchunk(c->L);
+  c->part_n = les::ref_blocks(c->L);  // partials of the reference and the fused kernel
+  long long sb = les::stage_blocks(c->L, c->kchunk);
   if (sb > c->part_n) c->part_n = sb;
   bool ok = hipMalloc(&c->M, 10 * fe * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->S[0], 5 * fe * sizeof(double)) == hipSuccess &&
@@ -286,29 +337,43 @@ int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norm
   }
   const double cnt = (double)L.ni * L.nj * L.nk;
   if (ctx->prec == LES_MIXED) {
-    les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f};
-    HIPCHK(ctx, les::run_rk_mixed(ctx->s, a, ctx->bc, Q, ctx->Sf, dtp, dt, norms ? ctx->part : nullptr));
-    if (norms) HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::stage_blocks(L), cnt, ctx->scal + 1, ctx->flag));
+    les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
+    for (int l = 0; l < 5; ++l) {
+      const float* in32 = l == 0 ? nullptr : ctx->Sf[(l - 1) & 1];
+      if (l > 0) HIPCHK(ctx, les::launch_ghost_fill_f32(ctx->s, L, ctx->bc, (float*)in32, Q));
+      int trc = timing_begin(ctx);
+      if (trc != LES_OK) return trc;
+      HIPCHK(ctx, les::launch_stage_mixed(ctx->s, a, l == 0 ? Q : nullptr, in32, Q, l == 4 ? Q : nullptr,
+                                          l == 4 ? nullptr : ctx->Sf[l & 1], dtp, dt, les::rk_alpha(l),
+                                          l == 0 ? ctx->part : nullptr));
+      trc = timing_end(ctx);
+      if (trc != LES_OK) return trc;
+    }
+    HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::stage_blocks(L, ctx->kchunk), cnt, ctx->scal + 1, ctx->flag));
   } else {
     if (stage_ckpt) HIPCHK(ctx, hipMemcpyAsync(stage_ckpt, Q, 5 * fe * sizeof(double), hipMemcpyDeviceToDevice, ctx->s));
     const double* in = stage_ckpt ? stage_ckpt : Q;
     for (int l = 0; l < 5; ++l) {
       double* out = l == 4 ? Q : (stage_ckpt ? stage_ckpt + (size_t)(l + 1) * 5 * fe : ctx->S[l & 1]);
       if (l > 0 || stage_ckpt) HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, (double*)in, Q, 5));
-      double* part = (l == 0 && norms) ? ctx->part : nullptr;
+      // the residual norms of R(Q^n) are always reduced on the device (fused
+      // into stage 1); only their copy to the host is optional
+      double* part = l == 0 ? ctx->part : nullptr;
+      int trc = timing_begin(ctx);
+      if (trc != LES_OK) return trc;
       if (ctx->use_ref) {
         HIPCHK(ctx, les::launch_stage_ref(ctx->s, L, ctx->P, ctx->M, in, Q, out, dtp, dt, les::rk_alpha(l), f,
                                           ctx->i_f, part));
       } else {
-        les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f};
+        les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
         HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, in, Q, out, dtp, dt, les::rk_alpha(l), part));
       }
+      trc = timing_end(ctx);
+      if (trc != LES_OK) return trc;
       in = out;
     }
-    if (norms) {
-      long long nb = ctx->use_ref ? les::ref_blocks(L) : les::stage_blocks(L);
-      HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
-    }
+    long long nb = ctx->use_ref ? les::ref_blocks(L) : les::stage_blocks(L, ctx->kchunk);
+    HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
   }
   if (!dt_out && !norms) return LES_OK;
   int rc = sync_outputs(ctx, dt_out, norms);
@@ -351,6 +416,30 @@ int les_debug_use_reference(les_ctx* ctx, int on) {
   if (!ctx) return LES_ERR_ARG;
   ctx->use_ref = on ? 1 : 0;
   return LES_OK;
+}
+
+// Stage-kernel timing (not declared in les.h; used by the benchmark):
+// on != 0 starts recording a HIP event pair around every stage-kernel
+// launch on the context's stream; les_debug_stage_time synchronises and
+// returns the summed elapsed milliseconds and the launch count since
+// timing was switched on, then resets them.
+int les_debug_stage_timing(les_ctx* ctx, int on) {
+  if (!ctx) return LES_ERR_ARG;
+  int rc = resolve_timing(ctx);
+  ctx->timing = on ? 1 : 0;
+  ctx->t_ms = 0.0;
+  ctx->t_cnt = 0;
+  return rc;
+}
+
+int les_debug_stage_time(les_ctx* ctx, double* total_ms, long long* launches) {
+  if (!ctx || !total_ms || !launches) return LES_ERR_ARG;
+  int rc = resolve_timing(ctx);
+  *total_ms = ctx->t_ms;
+  *launches = ctx->t_cnt;
+  ctx->t_ms = 0.0;
+  ctx->t_cnt = 0;
+  return rc;
 }
 
 }  // extern "C"

@@ -145,6 +145,58 @@ __global__ void k_ghost_fill(Layout L, int bc0, int bc1, int bc2, double* q, con
   for (int f = 0; f < nf; ++f) q[f * L.fe + dst] = q[f * L.fe + src];
 }
 
+// FP32 stage state: same shell enumeration; Dirichlet ghosts take the
+// rounded frozen FP64 values, periodic ghosts wrap.
+__global__ void k_ghost_fill_f32(Layout L, int bc0, int bc1, int bc2, float* __restrict__ q,
+                                 const double* __restrict__ frozen) {
+  const int PI = L.ni + 4, PJ = L.nj + 4;
+  const long long cA = 4LL * PJ * PI;
+  const long long cB = (long long)L.nk * 4 * PI;
+  const long long cC = (long long)L.nk * L.nj * 4;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t < cA) {
+    int kk = (int)(t / ((long long)PJ * PI));
+    long long r = t % ((long long)PJ * PI);
+    k = kk < 2 ? kk - 2 : L.nk + kk - 2;
+    j = (int)(r / PI) - 2;
+    i = (int)(r % PI) - 2;
+  } else if (t < cA + cB) {
+    long long u = t - cA;
+    k = (int)(u / (4LL * PI));
+    long long r = u % (4LL * PI);
+    int jj = (int)(r / PI);
+    j = jj < 2 ? jj - 2 : L.nj + jj - 2;
+    i = (int)(r % PI) - 2;
+  } else if (t < cA + cB + cC) {
+    long long u = t - cA - cB;
+    k = (int)(u / (4LL * L.nj));
+    long long r = u % (4LL * L.nj);
+    j = (int)(r / 4);
+    int ii = (int)(r % 4);
+    i = ii < 2 ? ii - 2 : L.ni + ii - 2;
+  } else {
+    return;
+  }
+  const int id[3] = {i, j, k};
+  const int nn[3] = {L.ni, L.nj, L.nk};
+  const int bc[3] = {bc0, bc1, bc2};
+  bool dir = false;
+  int w[3];
+  for (int d = 0; d < 3; ++d) {
+    bool g = id[d] < 0 || id[d] >= nn[d];
+    if (g && bc[d] == 1) dir = true;
+    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d] : id[d];
+  }
+  const long long dst = L.at(i, j, k);
+  if (dir) {
+    for (int f = 0; f < 5; ++f) q[f * L.fe + dst] = (float)frozen[f * L.fe + dst];
+    return;
+  }
+  const long long src = L.at(w[0], w[1], w[2]);
+  for (int f = 0; f < 5; ++f) q[f * L.fe + dst] = q[f * L.fe + src];
+}
+
 // ---------------------------------------------------------------------------
 // CFL time step: per-block minima, then one block for the global minimum.
 // ---------------------------------------------------------------------------
@@ -494,6 +546,11 @@ long long ghost_count(const Layout& L) {
 
 hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], double* q, const double* frozen, int nf) {
   k_ghost_fill<<<nblk(ghost_count(L), 256), 256, 0, s>>>(L, bc[0], bc[1], bc[2], q, frozen, nf);
+  return hipGetLastError();
+}
+
+hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3], float* q, const double* frozen) {
+  k_ghost_fill_f32<<<nblk(ghost_count(L), 256), 256, 0, s>>>(L, bc[0], bc[1], bc[2], q, frozen);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@ hipError_t launch_metrics_copy(hipStream_t s, const Layout& L, const double* src
 hipError_t launch_metrics_export(hipStream_t s, const Layout& L, const double* M, double* dst);
 long long ghost_count(const Layout& L);
 hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], double* q, const double* frozen, int nf);
+hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3], float* q, const double* frozen);
 long long ref_blocks(const Layout& L);
 hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
                       double* scal, int* flag);

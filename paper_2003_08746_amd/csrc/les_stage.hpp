@@ -10,10 +10,15 @@ struct StageArgs {
   const double* M;  // metrics [10][fe]
   const double* f;  // source [5][nk][nj] or null
   int i_f;
+  int kchunk;       // k planes per block (from stage_kchunk, fixed per context)
 };
 
+// k planes per block of the fused kernel for this layout (LES_KCHUNK in
+// the environment overrides the automatic choice; read once per context).
+int stage_kchunk(const Layout& L);
+
 // Number of per-block norm partials written by one fused stage launch.
-long long stage_blocks(const Layout& L);
+long long stage_blocks(const Layout& L, int kchunk);
 
 // One FP64 stage: Qout = Q0 - alpha dt R(Qin) on the interior (Qin's ghosts
 // already filled).  dtp (device) overrides dt when non-null.  part: norm
@@ -21,8 +26,11 @@ long long stage_blocks(const Layout& L);
 hipError_t launch_stage_fp64(hipStream_t s, const StageArgs& a, const double* Qin, const double* Q0, double* Qout,
                              const double* dtp, double dt, double alpha, double* part);
 
-// A whole mixed-precision step (FP32 stage states, FP64 Q^n and update).
-hipError_t run_rk_mixed(hipStream_t s, const StageArgs& a, const int bc[3], double* Q, float* Sf[2],
-                        const double* dtp, double dt, double* part);
+// One mixed-precision stage: the stencil input is FP64 (Qin64, stage 1) or
+// FP32 (Qin32); fluxes and dissipation in FP32; the update Q0 - alpha dt R
+// in FP64, written as FP64 (Qout) and/or as an FP32 stage state (Qsh).
+hipError_t launch_stage_mixed(hipStream_t s, const StageArgs& a, const double* Qin64, const float* Qin32,
+                              const double* Q0, double* Qout, float* Qsh, const double* dtp, double dt, double alpha,
+                              double* part);
 
 }  // namespace les

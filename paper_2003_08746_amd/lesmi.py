@@ -92,6 +92,10 @@ def lib():
     L.les_last_create_error.argtypes = []
     L.les_debug_use_reference.restype = ctypes.c_int
     L.les_debug_use_reference.argtypes = [_vp, ctypes.c_int]
+    L.les_debug_stage_timing.restype = ctypes.c_int
+    L.les_debug_stage_timing.argtypes = [_vp, ctypes.c_int]
+    L.les_debug_stage_time.restype = ctypes.c_int
+    L.les_debug_stage_time.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_longlong)]
     _lib = L
     return L
 
@@ -193,6 +197,17 @@ def les_probe_objective(ctx, Q_ptr, i_p, p_inf, weight, J_ptr, Qbar_ptr=None):
 
 def les_debug_use_reference(ctx, on: bool):
     _check(lib().les_debug_use_reference(ctx, 1 if on else 0), ctx, "les_debug_use_reference")
+
+
+def les_debug_stage_timing(ctx, on: bool):
+    _check(lib().les_debug_stage_timing(ctx, 1 if on else 0), ctx, "les_debug_stage_timing")
+
+
+def les_debug_stage_time(ctx):
+    ms = ctypes.c_double()
+    n = ctypes.c_longlong()
+    _check(lib().les_debug_stage_time(ctx, ctypes.byref(ms), ctypes.byref(n)), ctx, "les_debug_stage_time")
+    return ms.value, n.value
 
 
 # ---------------------------------------------------------------------------
