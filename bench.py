@@ -121,7 +121,19 @@ def main():
     ap.add_argument("--nk", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and adjoint legs")
+    ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB, 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_kernel:
+        import torch
+        n = args.copy_kernel * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_kernel_bytes_read": n * 8, "copy_kernel_bytes_written": n * 8, "launches": 5}))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the residual/RK path runs on one GPU's share of the domain "

@@ -7,29 +7,34 @@
 //
 // Decomposition.  A block of 32 x 16 threads owns the nodes of a 32 x 16
 // patch of one k-plane: the 30 x 14 output tile and a one-node halo ring.
-// It marches along k over a chunk of planes.  Each thread keeps the
-// k-direction stencil of its own column in registers (primitives at
-// t-1, t, t+1, conserved variables at t-2..t+1, the zeta node flux, the
-// zeta face flux and the partial residual of the previous plane), so the
-// zeta direction needs no LDS.  The in-plane (xi, eta) stencil goes through
-// LDS in three phases per plane, separated by barriers:
-//   B  fill:   every node of the patch (and a second halo ring along the
-//              axes, loaded by helper threads) stores Q, p, u, v, w, T;
-//   C  node:   every non-corner node of the patch computes its velocity /
-//              temperature gradient (chain rule through its metrics), the
-//              viscous stress with Sutherland and Smagorinsky viscosity,
-//              the node fluxes it is responsible for, the Turkel-Vatsa
-//              anisotropic spectral radii and pressure sensors;
-//   E  face:   tile nodes difference the node fluxes, build the four
-//              in-plane dissipation faces from LDS and the zeta face from
-//              registers, and finish the residual of the plane below.
-// Each node quantity is computed once per patch (the halo ring costs 22%
-// extra node work); every HBM array is read once per stage apart from the
-// halo overlap between neighbouring patches, which L2 serves.
+// Blocks are persistent (one per CU): block v marches a contiguous range of
+// (tile, k) planes, tile-major, so neighbouring tiles -- which share halo
+// lines -- run on the same XCD and the per-tile start-up cost (two extra
+// planes) is paid once per range, not once per k chunk.  Each thread keeps
+// the k-direction stencil of its own column in registers (conserved
+// variables at t-2 .. t+1, primitives at t-1 and t+1, the zeta node flux and
+// the partial residual of the plane below), so the zeta direction needs no
+// LDS.  The in-plane (xi, eta) stencil goes through LDS in three phases per
+// plane, separated by barriers:
+//   B  fill:  every node of the patch (and a second halo ring along the
+//             axes, written by helper threads) stores Q, p, u, v, w, T;
+//   C  node:  every non-corner node of the patch computes its velocity and
+//             temperature gradient (chain rule through its metrics), the
+//             viscous stress with Sutherland and Smagorinsky viscosity, the
+//             node fluxes it is responsible for, the Turkel-Vatsa
+//             anisotropic spectral radii and the pressure sensors;
+//   E  face:  tile nodes difference the node fluxes, build the four in-plane
+//             dissipation faces from LDS and the zeta face from registers,
+//             and finish the residual and stage update of the plane below.
+// Memory latency is taken off the critical path: right after phase C the
+// block issues the metrics of the next plane as asynchronous global->LDS
+// copies (global_load_lds), the helper ring of the next plane and
+// Q^(0) of the plane being finished; they land while phase E (and the next
+// phase B) compute.
 //
 // Work per thread is independent of the floating-point type T (double for
-// the FP64 path, float for the mixed path); Q^(0), the stage update, J and
-// all reductions stay in FP64.
+// the FP64 path, float for the mixed path); metrics, Q^(0), the stage
+// update, J and all reductions stay in FP64.
 #include <stdlib.h>
 
 #include "les_stage.hpp"
@@ -43,6 +48,8 @@ constexpr int BX = 32, BY = 16, NT = BX * BY;  // patch (threads)
 constexpr int TX = BX - 2, TY = BY - 2;        // output tile
 constexpr int EX = BX + 2, EY = BY + 2;        // patch + axis halo (LDS planes)
 constexpr int NH2 = 2 * TY + 2 * TX;           // second-ring helper nodes
+constexpr int NW = NT / 64;                    // waves per block
+constexpr int MROWS = 10 * BY;                 // metric rows per plane (fields x rows)
 
 struct KArgs {
   Layout L;
@@ -50,11 +57,11 @@ struct KArgs {
   const double* M;
   const double* f;
   int i_f;
-  int kchunk;     // planes per block
-  int ntx, nty;   // tiles in i, j
-  int nkc;        // k chunks
-  int nblocks;    // real blocks (grid may be padded to a multiple of 8)
-  int per_xcd;    // blocks per XCD in the remapped order
+  int ntx, nty;         // tiles in i, j
+  long long total;      // tile-planes = ntx * nty * nk
+  long long per_block;  // tile-planes per block (contiguous range)
+  int nblocks;          // blocks with work
+  int per_xcd;          // blocks per XCD in the remapped order
 };
 
 template <class T>
@@ -62,10 +69,10 @@ struct Smem {
   T q[5][EY][EX];
   T p[EY][EX];
   T u[EY][EX], v[EY][EX], w[EY][EX], tem[EY][EX];
-  T hx[5][BY][BX];
-  T hy[5][BY][BX];
-  T lx[BY][BX], ly[BY][BX];
-  T nx[BY][BX], ny[BY][BX];
+  T hx[5][TY][BX];  // xi node flux, patch rows 1..TY
+  T hy[5][BY][TX];  // eta node flux, patch columns 1..TX
+  T lx[TY][BX], nx[TY][BX];
+  T ly[BY][TX], ny[BY][TX];
 };
 
 // Global accesses use a uniform (scalar) base per field plus a 32-bit
@@ -116,73 +123,70 @@ __device__ __forceinline__ void norm_accumulate(const double s2[5], const double
   }
 }
 
+// Asynchronous copy of the ten metric fields of one plane of the patch into
+// LDS (mb[field][row][col] = M at node (i0-1+col, j0-1+row)).  Each wave
+// instruction moves one patch row of one field: 64 lanes x 4 bytes; lane l
+// copies half (l & 1) of column l >> 1, at byte offset lane_off from node
+// i0-1 of the row.  Rows or columns past the last needed node (ragged tiles) read a
+// clamped node.
+__device__ __forceinline__ void dma_metrics(const double* __restrict__ M, const Layout& L, int i0, int j0, int t,
+                                            double (*mb)[BY][BX], int wave, unsigned lane_off) {
+#pragma unroll 1
+  for (int r = 0; r < MROWS / NW; ++r) {
+    const int g = wave * (MROWS / NW) + r;  // field-row index handled by this instruction (uniform)
+    const int fld = g / BY, row = g % BY;
+    const int jc = min(j0 - 1 + row, L.nj);
+    // uniform base of (field, node (i0-1, jc, t)) plus the lane's byte offset
+    // (lane_off >= 0: columns are counted from i0-1)
+    const char* base =
+        (const char*)(M + fld * L.fe + (long long)(i0 - 1) + (long long)jc * L.sj + (long long)t * L.sk + L.o);
+    __builtin_amdgcn_global_load_lds((const void*)(base + lane_off),
+                                     (__attribute__((address_space(3))) void*)&mb[fld][row][0], 4, 0, 0);
+  }
+}
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left unconstrained)
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 template <class T, class QI, bool NORM>
 __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qin, const double* Q0, double* Qout,
                                               float* Qsh, const double* __restrict__ dtp, double dt_host,
                                               double alpha, double* __restrict__ part) {
+  // the FP32 path has the registers to prefetch the helper ring one plane
+  // ahead; the FP64 path loads it at phase B
+  constexpr bool kPrefetchRing = sizeof(T) == 4;
   __shared__ Smem<T> s;
-  __shared__ double red[NT / 64][10];  // per-wave norm partials (NORM only)
+  __shared__ double mb[10][BY][BX];  // metrics of the current plane (LDS DMA target)
+  __shared__ double red[NW][10];     // per-wave norm partials (NORM only)
   const Layout& L = a.L;
   const Phys& P = a.P;
   const long long fe = L.fe;
 
-  // XCD-aware block order: consecutive virtual blocks land on one XCD.
-  const int b = blockIdx.x;
-  const int v = (b & 7) * a.per_xcd + (b >> 3);
+  // XCD-aware order: consecutive virtual blocks land on one XCD.
+  const int hb = blockIdx.x;
+  const int v = (hb & 7) * a.per_xcd + (hb >> 3);
   if (v >= a.nblocks) return;
-  const int kci = v % a.nkc;
-  const int tile = v / a.nkc;
-  const int tix = tile % a.ntx, tiy = tile / a.ntx;
-  const int i0 = tix * TX, j0 = tiy * TY;
-  const int kb = kci * a.kchunk;
-  const int ke = min(kb + a.kchunk, L.nk);
+  const long long w_begin = (long long)v * a.per_block;
+  const long long w_end = min(a.total, w_begin + a.per_block);
 
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
   const int ex = tx + 1, ey = ty + 1;
-  const int i = i0 - 1 + tx, j = j0 - 1 + ty;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const bool xh = (tx == 0 || tx == BX - 1), yh = (ty == 0 || ty == BY - 1);
-  const bool load_ok = i <= L.ni + 1 && j <= L.nj + 1;
-  const bool node_ok = load_ok && i <= L.ni && j <= L.nj && !(xh && yh);
-  const bool need_x = node_ok && !yh;  // xi node flux / sensor needed here
-  const bool need_y = node_ok && !xh;  // eta node flux / sensor needed here
-  const bool out_ok = !xh && !yh && i < L.ni && j < L.nj;
+  if (NORM && tid < NW * 10) red[tid / 10][tid % 10] = 0.0;
+  const unsigned sk = (unsigned)L.sk;
+  const double adt = alpha * (dtp ? dtp[0] : dt_host);
 
-  // second halo ring along the axes (helper thread h < NH2)
-  int hx2 = 0, hy2 = 0, hi = 0, hj = 0;
-  bool h_ok = false;
+  // second halo ring along the axes: helper thread h < NH2 owns LDS slot (hy2, hx2)
+  int hx2 = 0, hy2 = 0;
   if (tid < NH2) {
-    int h = tid;
+    const int h = tid;
     if (h < TY) { hx2 = 0; hy2 = 2 + h; }
     else if (h < 2 * TY) { hx2 = EX - 1; hy2 = 2 + h - TY; }
     else if (h < 2 * TY + TX) { hy2 = 0; hx2 = 2 + h - 2 * TY; }
     else { hy2 = EY - 1; hx2 = 2 + h - 2 * TY - TX; }
-    hi = i0 - 2 + hx2;
-    hj = j0 - 2 + hy2;
-    h_ok = hi <= L.ni + 1 && hj <= L.nj + 1;
   }
-  if (NORM && tid < NT / 64 * 10) red[tid / 10][tid % 10] = 0.0;
-
-  // element offsets of nodes (i, j, 0) and (hi, hj, 0); every node of the
-  // padded box lies below 2^29 elements per field (checked at creation)
-  const unsigned col = (unsigned)((long long)i + (long long)j * L.sj + L.o);
-  const unsigned hcol = (unsigned)((long long)hi + (long long)hj * L.sj + L.o);
-  const unsigned sk = (unsigned)L.sk;
-  const double dt = dtp ? dtp[0] : dt_host;
-  const double adt = alpha * dt;
-
-  // ---- column queues (own node); plane-t values live in LDS ----
-  T qm1[5], qp1[5];   // Q at t-1 and t+1
-  T um1[4], up1[4];   // u, v, w, T at t-1 and t+1
-  T pm1 = 0, pp1 = 0; // p at t-1 and t+1
-  T hz_prev[5];       // zeta node flux at t-1
-  T racc[5];          // partial residual of plane t-1: in-plane part - zeta face (t-3/2)
-  T lz_prev = 0, nz_prev = 0;
-  double J_prev = 0.0;
-#pragma unroll
-  for (int c = 0; c < 5; ++c) qm1[c] = qp1[c] = hz_prev[c] = racc[c] = T(0);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) um1[c] = up1[c] = T(0);
 
   auto prims = [&](const T q[5], T uu[4], T& pp) {
     T u, vv, w, p, tem;
@@ -191,216 +195,266 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
     pp = p;
   };
 
-  // prime: plane kb-2 -> t-1 slot, plane kb-1 -> the slot written to LDS at t = kb-1
-  if (load_ok) {
-    load_q<T>(Qin, fe, col + (unsigned)(kb - 2) * sk, qm1);
-    prims(qm1, um1, pm1);
-    load_q<T>(Qin, fe, col + (unsigned)(kb - 1) * sk, qp1);
-  }
+  for (long long wq = w_begin; wq < w_end;) {
+    // ---- one segment: planes [kb, ke) of one tile ----
+    const int tile = (int)(wq / L.nk);
+    const int kb = (int)(wq % L.nk);
+    const int ke = (int)min((long long)L.nk, (long long)kb + (w_end - wq));
+    wq += ke - kb;
+    const int tix = tile % a.ntx, tiy = tile / a.ntx;
+    const int i0 = tix * TX, j0 = tiy * TY;
+    const int i = i0 - 1 + tx, j = j0 - 1 + ty;
+    const bool load_ok = i <= L.ni + 1 && j <= L.nj + 1;
+    const bool node_ok = load_ok && i <= L.ni && j <= L.nj && !(xh && yh);
+    const bool need_x = node_ok && !yh;  // xi node flux / sensor needed here
+    const bool need_y = node_ok && !xh;  // eta node flux / sensor needed here
+    const bool out_ok = !xh && !yh && i < L.ni && j < L.nj;
+    const int hi = i0 - 2 + hx2, hj = j0 - 2 + hy2;
+    const bool h_ok = tid < NH2 && hi <= L.ni + 1 && hj <= L.nj + 1;
+    // element offsets of nodes (i, j, 0) and (hi, hj, 0); every node of the
+    // padded box lies below 2^29 elements per field (checked at creation)
+    const unsigned col = (unsigned)((long long)i + (long long)j * L.sj + L.o);
+    const unsigned hcol = (unsigned)((long long)hi + (long long)hj * L.sj + L.o);
 
-  for (int t = kb - 1; t <= ke; ++t) {
-    const unsigned nt = col + (unsigned)t * sk;
-    // the first and last plane of a chunk only provide zeta quantities of
-    // the tile columns; their in-plane fluxes and residual are not needed
-    const bool inner = t >= kb && t < ke;
-    const bool nx_t = need_x && inner, ny_t = need_y && inner;
-    const bool node_t = inner ? node_ok : out_ok;
+    // ---- column queues (own node) ----
+    T qw[5], qa[5];         // Q at t (written at B) and t+1
+    T qm1[5], qm2[5];       // Q at t-1, t-2
+    T um1[4], up1[4];       // u, v, w, T at t-1; at t+1 (at B: plane t)
+    T pm1 = 0, pp1 = 0;
+    T hq[5];                // helper node, next plane
+    T hz_prev[5], racc[5];  // zeta node flux at t-1; partial residual of t-1
+    T lz_prev = 0, nz_prev = 0;
+    double J_prev = 0.0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) qw[c] = qa[c] = qm1[c] = qm2[c] = hq[c] = hz_prev[c] = racc[c] = T(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) um1[c] = up1[c] = T(0);
 
-    // ---- B: fill LDS plane t (own node from the queue, second ring by helpers) ----
+    // prime for t = kb-1: metrics(kb-1) -> LDS; Q(kb-2), Q(kb-1), Q(kb) of
+    // the own column; helper Q(kb-1)
+    // byte offset of this lane's metric half-word from node i0-1 of a row;
+    // columns past i = ni (ragged last tile) re-read column ni
+    const unsigned lane_off = (unsigned)((min(i0 - 1 + (lane >> 1), L.ni) - (i0 - 1)) * 8 + (lane & 1) * 4);
+    dma_metrics(a.M, L, i0, j0, kb - 1, mb, wave, lane_off);
     if (load_ok) {
-      T u4[4], pc;
-      prims(qp1, u4, pc);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) s.q[c][ey][ex] = qp1[c];
-      s.p[ey][ex] = pc;
-      s.u[ey][ex] = u4[0]; s.v[ey][ex] = u4[1]; s.w[ey][ex] = u4[2]; s.tem[ey][ex] = u4[3];
-      // ---- A: load plane t+1 of the own column ----
-      load_q<T>(Qin, fe, nt + sk, qp1);
-      prims(qp1, up1, pp1);
+      load_q<T>(Qin, fe, col + (unsigned)(kb - 2) * sk, qm1);
+      load_q<T>(Qin, fe, col + (unsigned)(kb - 1) * sk, qw);
+      prims(qm1, um1, pm1);
+      prims(qw, up1, pp1);  // plane kb-1, written at the first B
     }
-    if (h_ok) {
-      T hq[5], hu[4], hp;
-      load_q<T>(Qin, fe, hcol + (unsigned)t * sk, hq);
-      prims(hq, hu, hp);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) s.q[c][hy2][hx2] = hq[c];
-      s.p[hy2][hx2] = hp;
-      s.u[hy2][hx2] = hu[0]; s.v[hy2][hx2] = hu[1]; s.w[hy2][hx2] = hu[2]; s.tem[hy2][hx2] = hu[3];
-    }
-    __syncthreads();
+    if (kPrefetchRing && h_ok) load_q<T>(Qin, fe, hcol + (unsigned)(kb - 1) * sk, hq);
 
-    // ---- C: node work at plane t ----
-    T hz[5] = {0, 0, 0, 0, 0};
-    T lz = 0, nz = 0;
-    double Jn = 0.0;
-    if (node_t) {
-      double m[10];
-#pragma unroll
-      for (int c = 0; c < 10; ++c) m[c] = ldo(a.M + c * fe, nt);
-      Jn = m[9];
-      T mt[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) mt[c] = (T)m[c];
-      const T Jt = (T)Jn;
-      T g[4][3];
-      {
-        // derivatives along xi, eta (LDS) and zeta (registers), chain rule
-        const T (*F[4])[EX] = {s.u, s.v, s.w, s.tem};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T dx = T(0.5) * (F[q][ey][ex + 1] - F[q][ey][ex - 1]);
-          const T dy = T(0.5) * (F[q][ey + 1][ex] - F[q][ey - 1][ex]);
-          const T dz = T(0.5) * (up1[q] - um1[q]);
-#pragma unroll
-          for (int x = 0; x < 3; ++x) g[q][x] = Jt * (mt[x] * dx + mt[3 + x] * dy + mt[6 + x] * dz);
-        }
-      }
-      const T s11 = g[0][0], s22 = g[1][1], s33 = g[2][2];
-      const T s12 = T(0.5) * (g[0][1] + g[1][0]);
-      const T s13 = T(0.5) * (g[0][2] + g[2][0]);
-      const T s23 = T(0.5) * (g[1][2] + g[2][1]);
-      const T skk3 = (s11 + s22 + s33) / T(3);
-      const T rho = s.q[0][ey][ex];
-      const T u = s.u[ey][ex], vv = s.v[ey][ex], w = s.w[ey][ex];
-      const T mu = sutherland(s.tem[ey][ex], P);
-      T mus = T(0);
-      if (P.sgs) {
-        const T ss = s11 * s11 + s22 * s22 + s33 * s33 + T(2) * (s12 * s12 + s13 * s13 + s23 * s23);
-        T d2 = (T)cbrt(1.0 / Jn);
-        d2 *= d2;
-        mus = rho * T(P.Cs2) * d2 * sqrt(T(2) * ss);
-      }
-      const T mt2 = T(2) * (mu + mus);
-      const T t11 = mt2 * (s11 - skk3), t22 = mt2 * (s22 - skk3), t33 = mt2 * (s33 - skk3);
-      const T t12 = mt2 * s12, t13 = mt2 * s13, t23 = mt2 * s23;
-      const T kap = mu * T(P.Cp_over_Pr) + mus * T(P.Cp_over_Prsgs);
-      const T th0 = u * t11 + vv * t12 + w * t13 + kap * g[3][0];
-      const T th1 = u * t12 + vv * t22 + w * t23 + kap * g[3][1];
-      const T th2 = u * t13 + vv * t23 + w * t33 + kap * g[3][2];
-      const T p = s.p[ey][ex];
-      const T c = sqrt(T(P.gamma) * p / rho);
-      // spectral radii of the three directions
-      T lam[3], U[3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const T mx = mt[3 * e], my = mt[3 * e + 1], mz = mt[3 * e + 2];
-        U[e] = mx * u + my * vv + mz * w;
-        lam[e] = fabs(U[e]) + c * sqrt(mx * mx + my * my + mz * mz);
-      }
-      auto node_flux = [&](int e, T H[5]) {
-        const T mx = mt[3 * e], my = mt[3 * e + 1], mz = mt[3 * e + 2];
-        const T Ue = U[e];
-        H[0] = rho * Ue;
-        H[1] = s.q[1][ey][ex] * Ue + mx * p - (mx * t11 + my * t12 + mz * t13);
-        H[2] = s.q[2][ey][ex] * Ue + my * p - (mx * t12 + my * t22 + mz * t23);
-        H[3] = s.q[3][ey][ex] * Ue + mz * p - (mx * t13 + my * t23 + mz * t33);
-        H[4] = (s.q[4][ey][ex] + p) * Ue - (mx * th0 + my * th1 + mz * th2);
-      };
-      if (nx_t) {
-        T H[5];
-        node_flux(0, H);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) s.hx[q][ty][tx] = H[q];
-        s.lx[ty][tx] = aniso(lam[0], lam[1], lam[2], P);
-        const T pa = s.p[ey][ex + 1], pb = s.p[ey][ex - 1];
-        s.nx[ty][tx] = fabs(pa - T(2) * p + pb) / (pa + T(2) * p + pb);
-      }
-      if (ny_t) {
-        T H[5];
-        node_flux(1, H);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) s.hy[q][ty][tx] = H[q];
-        s.ly[ty][tx] = aniso(lam[1], lam[2], lam[0], P);
-        const T pa = s.p[ey + 1][ex], pb = s.p[ey - 1][ex];
-        s.ny[ty][tx] = fabs(pa - T(2) * p + pb) / (pa + T(2) * p + pb);
-      }
-      if (out_ok) {
-        node_flux(2, hz);
-        lz = aniso(lam[2], lam[0], lam[1], P);
-        nz = fabs(pp1 - T(2) * p + pm1) / (pp1 + T(2) * p + pm1);
-      }
-    }
-    __syncthreads();
+    for (int t = kb - 1; t <= ke; ++t) {
+      const unsigned nt = col + (unsigned)t * sk;
+      // the first and last plane of a segment only provide zeta quantities
+      // of the tile columns; their in-plane fluxes and residual are not needed
+      const bool inner = t >= kb && t < ke;
+      const bool nx_t = need_x && inner, ny_t = need_y && inner;
+      const bool node_t = inner ? node_ok : out_ok;
 
-    // ---- E: residual (tile nodes) ----
-    double s2[5] = {0, 0, 0, 0, 0}, sm[5] = {0, 0, 0, 0, 0};
-    if (out_ok) {
-      T r[5] = {0, 0, 0, 0, 0};
-      if (inner) {
-        // central differences of the in-plane node fluxes
+      // ---- B: fill LDS plane t ----
+      if (load_ok) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q)
-          r[q] = T(0.5) * (s.hx[q][ty][tx + 1] - s.hx[q][ty][tx - 1]) +
-                 T(0.5) * (s.hy[q][ty + 1][tx] - s.hy[q][ty - 1][tx]);
-        // in-plane dissipation faces
-        T qa[5], qb[5], qc[5], qd[5], qe[5], D1[5], D0[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          qa[c] = s.q[c][ey][ex - 2]; qb[c] = s.q[c][ey][ex - 1]; qc[c] = s.q[c][ey][ex];
-          qd[c] = s.q[c][ey][ex + 1]; qe[c] = s.q[c][ey][ex + 2];
-        }
-        face_diss(P, s.lx[ty][tx], s.lx[ty][tx + 1], s.nx[ty][tx], s.nx[ty][tx + 1], qb, qc, qd, qe, D1);
-        face_diss(P, s.lx[ty][tx - 1], s.lx[ty][tx], s.nx[ty][tx - 1], s.nx[ty][tx], qa, qb, qc, qd, D0);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) r[c] -= D1[c] - D0[c];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          qa[c] = s.q[c][ey - 2][ex]; qb[c] = s.q[c][ey - 1][ex];
-          qd[c] = s.q[c][ey + 1][ex]; qe[c] = s.q[c][ey + 2][ex];
-        }
-        face_diss(P, s.ly[ty][tx], s.ly[ty + 1][tx], s.ny[ty][tx], s.ny[ty + 1][tx], qb, qc, qd, qe, D1);
-        face_diss(P, s.ly[ty - 1][tx], s.ly[ty][tx], s.ny[ty - 1][tx], s.ny[ty][tx], qa, qb, qc, qd, D0);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) r[c] -= D1[c] - D0[c];
+        for (int c = 0; c < 5; ++c) s.q[c][ey][ex] = qw[c];
+        s.p[ey][ex] = pp1;
+        s.u[ey][ex] = up1[0]; s.v[ey][ex] = up1[1]; s.w[ey][ex] = up1[2]; s.tem[ey][ex] = up1[3];
+        load_q<T>(Qin, fe, nt + sk, qa);  // plane t+1 of the own column
       }
-      if (t >= kb) {
-        // zeta face t - 1/2 between plane t-1 and plane t (Q at t-2 re-read; L2 hit)
-        T qm2[5], qc[5], D[5];
-        load_q<T>(Qin, fe, nt - 2 * sk, qm2);
+      if (h_ok) {
+        T hu[4], hp;
+        if (!kPrefetchRing) load_q<T>(Qin, fe, hcol + (unsigned)t * sk, hq);
+        prims(hq, hu, hp);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) qc[c] = s.q[c][ey][ex];
-        face_diss(P, lz_prev, lz, nz_prev, nz, qm2, qm1, qc, qp1, D);
-        T fz[5];
+        for (int c = 0; c < 5; ++c) s.q[c][hy2][hx2] = hq[c];
+        s.p[hy2][hx2] = hp;
+        s.u[hy2][hx2] = hu[0]; s.v[hy2][hx2] = hu[1]; s.w[hy2][hx2] = hu[2]; s.tem[hy2][hx2] = hu[3];
+      }
+      wait_vm_all();  // this wave's metric copies, helper ring and plane t+1 have landed
+      __syncthreads();
+
+      // ---- C: node work at plane t ----
+      if (load_ok) prims(qa, up1, pp1);  // plane t+1 of the own column
+      T hz[5] = {0, 0, 0, 0, 0};
+      T lz = 0, nz = 0;
+      double Jn = 0.0;
+      if (node_t) {
+        Jn = mb[9][ty][tx];
+        T mt[9];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) fz[c] = T(0.5) * (hz_prev[c] + hz[c]) - D[c];
-        if (t > kb) {
-          // residual of plane t-1 and its stage update
-          const int k = t - 1;
-          const unsigned n = nt - sk;
+        for (int c = 0; c < 9; ++c) mt[c] = (T)mb[c][ty][tx];
+        const T Jt = (T)Jn;
+        T g[4][3];
+        {
+          // derivatives along xi, eta (LDS) and zeta (registers), chain rule
+          const T(*F[4])[EX] = {s.u, s.v, s.w, s.tem};
 #pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            double R = J_prev * (double)(racc[c] + fz[c]);
-            if (a.f && i == a.i_f) R -= a.f[((long long)c * L.nk + k) * L.nj + j];
-            const double qn = ldo(Q0 + c * fe, n) - adt * R;
-            if (Qout) sto(Qout + c * fe, n, qn);
-            if (Qsh) sto(Qsh + c * fe, n, (float)qn);
-            if (NORM) {
-              s2[c] = R * R;
-              sm[c] = fabs(R);
-            }
+          for (int q = 0; q < 4; ++q) {
+            const T dx = T(0.5) * (F[q][ey][ex + 1] - F[q][ey][ex - 1]);
+            const T dy = T(0.5) * (F[q][ey + 1][ex] - F[q][ey - 1][ex]);
+            const T dz = T(0.5) * (up1[q] - um1[q]);
+#pragma unroll
+            for (int x = 0; x < 3; ++x) g[q][x] = Jt * (mt[x] * dx + mt[3 + x] * dy + mt[6 + x] * dz);
           }
         }
+        const T s11 = g[0][0], s22 = g[1][1], s33 = g[2][2];
+        const T s12 = T(0.5) * (g[0][1] + g[1][0]);
+        const T s13 = T(0.5) * (g[0][2] + g[2][0]);
+        const T s23 = T(0.5) * (g[1][2] + g[2][1]);
+        const T skk3 = (s11 + s22 + s33) / T(3);
+        const T rho = s.q[0][ey][ex];
+        const T u = s.u[ey][ex], vv = s.v[ey][ex], w = s.w[ey][ex];
+        const T mu = sutherland(s.tem[ey][ex], P);
+        T mus = T(0);
+        if (P.sgs) {
+          const T ss = s11 * s11 + s22 * s22 + s33 * s33 + T(2) * (s12 * s12 + s13 * s13 + s23 * s23);
+          T d2 = (T)cbrt(1.0 / Jn);
+          d2 *= d2;
+          mus = rho * T(P.Cs2) * d2 * sqrt(T(2) * ss);
+        }
+        const T mt2 = T(2) * (mu + mus);
+        const T t11 = mt2 * (s11 - skk3), t22 = mt2 * (s22 - skk3), t33 = mt2 * (s33 - skk3);
+        const T t12 = mt2 * s12, t13 = mt2 * s13, t23 = mt2 * s23;
+        const T kap = mu * T(P.Cp_over_Pr) + mus * T(P.Cp_over_Prsgs);
+        const T th0 = u * t11 + vv * t12 + w * t13 + kap * g[3][0];
+        const T th1 = u * t12 + vv * t22 + w * t23 + kap * g[3][1];
+        const T th2 = u * t13 + vv * t23 + w * t33 + kap * g[3][2];
+        const T p = s.p[ey][ex];
+        const T c = sqrt(T(P.gamma) * p / rho);
+        // spectral radii of the three directions
+        T lam[3], U[3];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) racc[c] = r[c] - fz[c];
-      } else {
+        for (int e = 0; e < 3; ++e) {
+          const T mx = mt[3 * e], my = mt[3 * e + 1], mz = mt[3 * e + 2];
+          U[e] = mx * u + my * vv + mz * w;
+          lam[e] = fabs(U[e]) + c * sqrt(mx * mx + my * my + mz * mz);
+        }
+        auto node_flux = [&](int e, T H[5]) {
+          const T mx = mt[3 * e], my = mt[3 * e + 1], mz = mt[3 * e + 2];
+          const T Ue = U[e];
+          H[0] = rho * Ue;
+          H[1] = s.q[1][ey][ex] * Ue + mx * p - (mx * t11 + my * t12 + mz * t13);
+          H[2] = s.q[2][ey][ex] * Ue + my * p - (mx * t12 + my * t22 + mz * t23);
+          H[3] = s.q[3][ey][ex] * Ue + mz * p - (mx * t13 + my * t23 + mz * t33);
+          H[4] = (s.q[4][ey][ex] + p) * Ue - (mx * th0 + my * th1 + mz * th2);
+        };
+        if (nx_t) {
+          T H[5];
+          node_flux(0, H);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) racc[c] = r[c];
+          for (int q = 0; q < 5; ++q) s.hx[q][ty - 1][tx] = H[q];
+          s.lx[ty - 1][tx] = aniso(lam[0], lam[1], lam[2], P);
+          const T pa = s.p[ey][ex + 1], pb = s.p[ey][ex - 1];
+          s.nx[ty - 1][tx] = fabs(pa - T(2) * p + pb) / (pa + T(2) * p + pb);
+        }
+        if (ny_t) {
+          T H[5];
+          node_flux(1, H);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) s.hy[q][ty][tx - 1] = H[q];
+          s.ly[ty][tx - 1] = aniso(lam[1], lam[2], lam[0], P);
+          const T pa = s.p[ey + 1][ex], pb = s.p[ey - 1][ex];
+          s.ny[ty][tx - 1] = fabs(pa - T(2) * p + pb) / (pa + T(2) * p + pb);
+        }
+        if (out_ok) {
+          node_flux(2, hz);
+          lz = aniso(lam[2], lam[0], lam[1], P);
+          nz = fabs(pp1 - T(2) * p + pm1) / (pp1 + T(2) * p + pm1);
+        }
       }
+      __syncthreads();
+
+      // ---- prefetch for the next plane (lands during E and the next B) ----
+      if (t < ke) dma_metrics(a.M, L, i0, j0, t + 1, mb, wave, lane_off);
+      if (kPrefetchRing && h_ok && t < ke) load_q<T>(Qin, fe, hcol + (unsigned)(t + 1) * sk, hq);
+      double q0v[5] = {0, 0, 0, 0, 0};
+      if (out_ok && t > kb) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) hz_prev[c] = hz[c];
-      lz_prev = lz;
-      nz_prev = nz;
-      J_prev = Jn;
-    }
-    if (NORM && t > kb) norm_accumulate(s2, sm, red, tid);
-    // ---- shift the column queues (plane t values from LDS) ----
-    if (load_ok) {
+        for (int c = 0; c < 5; ++c) q0v[c] = ldo(Q0 + c * fe, nt - sk);
+      }
+
+      // ---- E: residual (tile nodes) ----
+      double s2[5] = {0, 0, 0, 0, 0}, sm[5] = {0, 0, 0, 0, 0};
+      if (out_ok) {
+        const int cx = tx - 1, cy = ty - 1;  // tile-local column / row
+        T r[5] = {0, 0, 0, 0, 0};
+        if (inner) {
+          // central differences of the in-plane node fluxes
 #pragma unroll
-      for (int c = 0; c < 5; ++c) qm1[c] = s.q[c][ey][ex];
-      um1[0] = s.u[ey][ex]; um1[1] = s.v[ey][ex]; um1[2] = s.w[ey][ex]; um1[3] = s.tem[ey][ex];
-      pm1 = s.p[ey][ex];
+          for (int q = 0; q < 5; ++q)
+            r[q] = T(0.5) * (s.hx[q][cy][tx + 1] - s.hx[q][cy][tx - 1]) +
+                   T(0.5) * (s.hy[q][ty + 1][cx] - s.hy[q][ty - 1][cx]);
+          // in-plane dissipation faces
+          T q_a[5], q_b[5], q_c[5], q_d[5], q_e[5], D1[5], D0[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            q_a[c] = s.q[c][ey][ex - 2]; q_b[c] = s.q[c][ey][ex - 1]; q_c[c] = s.q[c][ey][ex];
+            q_d[c] = s.q[c][ey][ex + 1]; q_e[c] = s.q[c][ey][ex + 2];
+          }
+          face_diss(P, s.lx[cy][tx], s.lx[cy][tx + 1], s.nx[cy][tx], s.nx[cy][tx + 1], q_b, q_c, q_d, q_e, D1);
+          face_diss(P, s.lx[cy][tx - 1], s.lx[cy][tx], s.nx[cy][tx - 1], s.nx[cy][tx], q_a, q_b, q_c, q_d, D0);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) r[c] -= D1[c] - D0[c];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            q_a[c] = s.q[c][ey - 2][ex]; q_b[c] = s.q[c][ey - 1][ex];
+            q_d[c] = s.q[c][ey + 1][ex]; q_e[c] = s.q[c][ey + 2][ex];
+          }
+          face_diss(P, s.ly[ty][cx], s.ly[ty + 1][cx], s.ny[ty][cx], s.ny[ty + 1][cx], q_b, q_c, q_d, q_e, D1);
+          face_diss(P, s.ly[ty - 1][cx], s.ly[ty][cx], s.ny[ty - 1][cx], s.ny[ty][cx], q_a, q_b, q_c, q_d, D0);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) r[c] -= D1[c] - D0[c];
+        }
+        if (t >= kb) {
+          // zeta face t - 1/2 between plane t-1 and plane t
+          T qc[5], D[5], fz[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) qc[c] = s.q[c][ey][ex];
+          face_diss(P, lz_prev, lz, nz_prev, nz, qm2, qm1, qc, qa, D);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) fz[c] = T(0.5) * (hz_prev[c] + hz[c]) - D[c];
+          if (t > kb) {
+            // residual of plane t-1 and its stage update
+            const int k = t - 1;
+            const unsigned n = nt - sk;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+              double R = J_prev * (double)(racc[c] + fz[c]);
+              if (a.f && i == a.i_f) R -= a.f[((long long)c * L.nk + k) * L.nj + j];
+              const double qn = q0v[c] - adt * R;
+              if (Qout) sto(Qout + c * fe, n, qn);
+              if (Qsh) sto(Qsh + c * fe, n, (float)qn);
+              if (NORM) {
+                s2[c] = R * R;
+                sm[c] = fabs(R);
+              }
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 5; ++c) racc[c] = r[c] - fz[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) racc[c] = r[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) hz_prev[c] = hz[c];
+        lz_prev = lz;
+        nz_prev = nz;
+        J_prev = Jn;
+      }
+      if (NORM && t > kb) norm_accumulate(s2, sm, red, tid);
+      // ---- shift the column queues (plane t values from LDS) ----
+      if (load_ok) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          qm2[c] = qm1[c];
+          qm1[c] = s.q[c][ey][ex];
+          qw[c] = qa[c];
+        }
+        um1[0] = s.u[ey][ex]; um1[1] = s.v[ey][ex]; um1[2] = s.w[ey][ex]; um1[3] = s.tem[ey][ex];
+        pm1 = s.p[ey][ex];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // ---- block partial norms ----
@@ -408,7 +462,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
     __syncthreads();
     if (tid < 10) {
       double r = red[0][tid];
-      for (int w = 1; w < NT / 64; ++w) {
+      for (int w = 1; w < NW; ++w) {
         const double o = red[w][tid];
         r = tid < 5 ? r + o : ((o > r || o != o) ? o : r);
       }
@@ -419,24 +473,25 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
 
 // Stage kernel configuration for a layout.
 struct Config {
-  int ntx, nty, nkc, kchunk, nblocks, grid, per_xcd;
+  int ntx, nty, nblocks, grid, per_xcd;
+  long long total, per_block;
 };
 
-int auto_kchunk(const Layout& L) {
+long long auto_per_block(const Layout& L) {
   const long long tiles = (long long)((L.ni + TX - 1) / TX) * ((L.nj + TY - 1) / TY);
-  // enough blocks to fill the 256 CUs at least twice, chunks of >= 8 planes
-  int chunk = L.nk;
-  while (chunk > 8 && tiles * ((L.nk + chunk - 1) / chunk) < 2 * 256) chunk = (chunk + 1) / 2;
-  return chunk;
+  const long long total = tiles * L.nk;
+  // one persistent block per CU, at least 8 planes each
+  long long pb = (total + 255) / 256;
+  return pb < 8 ? 8 : pb;
 }
 
-Config config(const Layout& L, int kchunk) {
+Config config(const Layout& L, long long per_block) {
   Config c;
   c.ntx = (L.ni + TX - 1) / TX;
   c.nty = (L.nj + TY - 1) / TY;
-  c.kchunk = kchunk < 1 ? 1 : (kchunk > L.nk ? L.nk : kchunk);
-  c.nkc = (L.nk + c.kchunk - 1) / c.kchunk;
-  c.nblocks = c.ntx * c.nty * c.nkc;
+  c.total = (long long)c.ntx * c.nty * L.nk;
+  c.per_block = per_block < 1 ? 1 : per_block;
+  c.nblocks = (int)((c.total + c.per_block - 1) / c.per_block);
   c.per_xcd = (c.nblocks + 7) / 8;
   c.grid = c.per_xcd * 8;
   return c;
@@ -446,7 +501,7 @@ template <class T, class QI>
 hipError_t launch(hipStream_t st, const StageArgs& sa, const QI* Qin, const double* Q0, double* Qout, float* Qsh,
                   const double* dtp, double dt, double alpha, double* part) {
   Config c = config(sa.L, sa.kchunk);
-  KArgs a{sa.L, sa.P, sa.M, sa.f, sa.i_f, c.kchunk, c.ntx, c.nty, c.nkc, c.nblocks, c.per_xcd};
+  KArgs a{sa.L, sa.P, sa.M, sa.f, sa.i_f, c.ntx, c.nty, c.total, c.per_block, c.nblocks, c.per_xcd};
   if (part)
     k_stage<T, QI, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part);
   else
@@ -457,9 +512,9 @@ hipError_t launch(hipStream_t st, const StageArgs& sa, const QI* Qin, const doub
 }  // namespace
 
 int stage_kchunk(const Layout& L) {
-  const char* env = getenv("LES_KCHUNK");
-  if (env && atoi(env) > 0) return atoi(env) < L.nk ? atoi(env) : L.nk;
-  return auto_kchunk(L);
+  const char* env = getenv("LES_SEG");
+  if (env && atoi(env) > 0) return atoi(env);
+  return (int)auto_per_block(L);
 }
 
 long long stage_blocks(const Layout& L, int kchunk) { return config(L, kchunk).nblocks; }

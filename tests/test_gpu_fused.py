@@ -28,14 +28,17 @@ def _rel(a, b):
     return np.abs(ai - bi).reshape(ai.shape[0], -1).max(1) / den
 
 
-@pytest.mark.parametrize("shape,chunk", [((61, 29, 23), "5"), ((31, 15, 9), "4"), ((93, 43, 17), "")])
-def test_fused_matches_reference_kernel(lesmi, shape, chunk, monkeypatch):
+@pytest.mark.parametrize("shape,seg", [((61, 29, 23), "5"), ((31, 15, 9), "4"), ((93, 43, 17), ""),
+                                       ((40, 20, 12), "7")])
+def test_fused_matches_reference_kernel(lesmi, shape, seg, monkeypatch):
     """tiles 30 x 14 in (i, j): every shape leaves a ragged last tile; the
-    chunk sizes put chunk boundaries inside k."""
-    if chunk:
-        monkeypatch.setenv("LES_KCHUNK", chunk)
+    segment sizes (tile-planes per persistent block) put segment starts and
+    ends inside k and segments that span two tiles."""
+    if seg:
+        monkeypatch.setenv("LES_SEG", seg)
     else:
-        monkeypatch.delenv("LES_KCHUNK", raising=False)
+        monkeypatch.delenv("LES_SEG", raising=False)
+    chunk = seg
     ni, nj, nk = shape
     case = I.jet_case(ni, nj, nk, seed=11)
     print(f"[gpu] fused vs reference {shape} chunk={chunk or 'auto'}", flush=True)
