@@ -172,6 +172,19 @@ int les_rk_step(les_ctx *ctx, double *Q, double dt, double *dt_out, double *norm
  * fbar: device, dense [5][nk][nj], accumulated, or NULL. */
 int les_adjoint_step(les_ctx *ctx, const double *stage_ckpt, double dt, double *Qbar, double *fbar);
 
+/* Adjoint (vector-Jacobian product) of the residual at Q:
+ *   Qbar = (dR/dQ)^T Rbar on the interior,
+ * the building block of les_adjoint_step.  dR/dQ includes the ghost fill
+ * (periodic ghost adjoints are folded onto the interior; frozen Dirichlet
+ * ghosts carry no dependence) and uses the same non-smooth rules as
+ * les_adjoint_step (and d|S|/dS = 0 at |S| = 0 in the eddy viscosity).
+ * Q: device, library layout, FP64; its ghost layers are filled in place.
+ * Rbar: device, library layout; only interior values are read.
+ * Qbar: device, library layout; interior written (must not alias Q or Rbar).
+ * Allocates the adjoint work arrays on first use (51 fields of field_elems
+ * doubles, kept by the context). */
+int les_residual_adjoint(les_ctx *ctx, double *Q, const double *Rbar, double *Qbar);
+
 /* Probe objective on the plane i = i_p (interior of Q):
  *   *J_accum += weight * sum_{j,k} (p - p_inf)^2          (J_accum: device)
  *   Qbar[i_p plane] += weight * 2 (p - p_inf) dp/dQ       (Qbar: device or NULL)

@@ -65,6 +65,9 @@ def _load():
     lib.orc_rk_step.restype = ctypes.c_double
     lib.orc_rk_step.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, ctypes.c_double,
                                 _dp, ctypes.c_int, _dp, _dp]
+    lib.orc_rk_step_tangent.restype = None
+    lib.orc_rk_step_tangent.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp,
+                                        ctypes.c_double, _dp, _dp, ctypes.c_int]
     lib.orc_objective_rollout.restype = ctypes.c_double
     lib.orc_objective_rollout.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp,
                                           _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -170,6 +173,17 @@ def rk_step(case, m, Q, dt=0.0, prm=None, f=None, i_f=-1, want_stages=False):
     dt_used = lib.orc_rk_step(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Qn),
                               float(dt), _ptr(None if f is None else _c(f)), int(i_f), _ptr(norms), _ptr(stages))
     return Qn, dt_used, norms, stages
+
+
+def rk_step_tangent(case, m, Q, dQ, dt, f=None, df=None, i_f=-1):
+    """One RK step at fixed dt with its exact tangent: returns (Q_next, dQ_next)."""
+    lib = _load()
+    Qn = _c(Q).copy()
+    dQn = _c(dQ).copy()
+    lib.orc_rk_step_tangent(ctypes.byref(_dims_of(case)), ctypes.byref(params(case["params"])), _ptr(_c(m)),
+                            _ptr(Qn), _ptr(dQn), float(dt), _ptr(None if f is None else _c(f)),
+                            _ptr(None if df is None else _c(df)), int(i_f))
+    return Qn, dQn
 
 
 def objective_rollout(case, m, Q0, f, df, i_f, i_p, p_inf, nsteps, dt, dQ0=None):

@@ -50,7 +50,7 @@
 //       given (frozen) value; every other ghost node takes the value of the
 //       node whose periodic indices are wrapped into the interior.
 //   R11 non-smooth derivatives (dual numbers): d|x|/dx = sign(x), 0 at 0;
-//       max(a, b) follows a when a >= b.
+//       max(a, b) follows a when a >= b; d sqrt(x)/dx = 0 at x = 0.
 //   R12 an optional constant source f on the plane i = i_f: dQ/dt = -R + f.
 //
 // Data layout (all arrays): padded box [nk+4][nj+4][ni+4], i fastest, two
@@ -96,9 +96,10 @@ static inline double val(double a) { return a; }
 static inline double val(const Dual& a) { return a.v; }
 
 static inline double s_sqrt(double a) { return std::sqrt(a); }
+// R11: sqrt has derivative 0 at 0 (the eddy viscosity's |S| at rest).
 static inline Dual s_sqrt(Dual a) {
   double s = std::sqrt(a.v);
-  return Dual(s, a.d / (2.0 * s));
+  return Dual(s, s > 0.0 ? a.d / (2.0 * s) : 0.0);
 }
 static inline double s_pow(double a, double e) { return std::pow(a, e); }
 static inline Dual s_pow(Dual a, double e) {
@@ -628,6 +629,26 @@ double orc_rk_step(const orc_dims* d, const orc_params* P, const double* m, doub
   if (!(dt > 0.0)) dt = cfl_dt(b, *P, m, Q);
   rk_step(b, *P, m, Q, dt, f, i_f, norms, stages);
   return dt;
+}
+
+// Tangent of one RK step at fixed dt: (Q, dQ) -> (Q^{n+1}, dQ^{n+1}) for the
+// perturbation (dQ, df) of the state and of the source f on plane i_f.
+void orc_rk_step_tangent(const orc_dims* d, const orc_params* P, const double* m, double* Q, double* dQ, double dt,
+                         const double* f, const double* df, int i_f) {
+  Box b(*d);
+  std::vector<Dual> q(5 * b.N);
+  for (size_t n = 0; n < 5 * b.N; ++n) q[n] = Dual(Q[n], dQ[n]);
+  std::vector<Dual> fd;
+  if (f) {
+    size_t nf = (size_t)5 * b.nk * b.nj;
+    fd.resize(nf);
+    for (size_t n = 0; n < nf; ++n) fd[n] = Dual(f[n], df ? df[n] : 0.0);
+  }
+  rk_step(b, *P, m, q.data(), dt, f ? fd.data() : nullptr, i_f, nullptr, (Dual*)nullptr);
+  for (size_t n = 0; n < 5 * b.N; ++n) {
+    Q[n] = q[n].v;
+    dQ[n] = q[n].d;
+  }
 }
 
 // Objective of the differentiation workload: run nsteps RK steps at fixed dt

@@ -1,12 +1,604 @@
-// les_adjoint.hip -- adjoint of the Runge-Kutta step.
+// les_adjoint.hip -- reverse mode (adjoint) of the residual and of one
+// Runge-Kutta step, written as gather kernels.
+//
+// For a residual weight Rbar on the interior, Qbar = (dR/dQ)^T Rbar is the
+// reverse of the residual's composition (Eq. 12-15 with the Turkel-Vatsa
+// dissipation): node primitives -> node gradients -> stress / heat flux /
+// eddy viscosity -> node fluxes and spectral radii / sensors -> face fluxes
+// -> residual.  Every backward step that would scatter is written as a
+// gather over stored per-node weights, so no atomics are needed:
+//   pass 1 (node, nodes with indices in [-1, n]): with W = J Rbar (zero off
+//      the interior) the node flux adjoint is Hbar_d(n) = (W(n-e_d) -
+//      W(n+e_d))/2; the thread reverses its node flux, viscous stress, heat
+//      flux, Smagorinsky and Sutherland viscosity and its share of the two
+//      dissipation faces on each side, and stores: the adjoint in primitive
+//      variables (rho, u, v, w, p, T), the direct Q adjoint of the fluxes,
+//      the gradient-stencil weights a_{q,d} = J m_d . gbar_q, the sensor
+//      weights for p at n +- e_d, and the face coefficients
+//      Lambda eps2, Lambda eps4 of the face (n, n + e_d);
+//   pass 2 (gather, every node of the padded box): collects the gradient
+//      and sensor weights of its neighbours and the dissipation faces whose
+//      five-point stencil contains it, and maps the primitive adjoint back
+//      to conserved variables;
+//   pass 3 (fold): adds the adjoint of every periodic ghost image to its
+//      interior node (frozen Dirichlet ghosts carry no dependence).
+// Non-smooth points take the derivative of the active branch: d|x|/dx =
+// sign(x) with 0 at 0, max(a, b) follows a when a >= b, and the eddy
+// viscosity's |S| has derivative 0 at |S| = 0.
+//
+// les_adjoint_step applies it stage by stage in reverse from the stage
+// inputs saved by les_rk_step: for l = 5..1, acc += qbar, fbar += alpha_l dt
+// qbar on the source plane, qbar = (dR/dQ|Q^(l-1))^T (-alpha_l dt qbar);
+// finally Qbar = acc + qbar.
 #include "les_adjoint.hpp"
 
 namespace les {
 
-size_t adjoint_work_elems(const Layout& L) { return (size_t)L.fe; }
+namespace {
 
-hipError_t run_adjoint_step(hipStream_t, const AdjArgs&, const double*, double, double*, double*, double*) {
-  return hipErrorNotSupported;
+// Work-array field indices (library layout, one field each).
+enum {
+  W_PRHO = 0, W_PU, W_PV, W_PW, W_PP, W_PT,  // primitive-variable adjoint (local part)
+  W_QD1, W_QD2, W_QD3, W_QD4,                 // direct Q adjoint of the node fluxes
+  W_A = 10,                                   // a_{q,d}: 12 fields, index W_A + 3 q + d
+  W_CP = 22,                                  // sensor weights for p(n +- e_d): 3 fields
+  W_A2 = 25,                                  // Lambda eps2 of face (n, n+e_d): 3 fields
+  W_A4 = 28,                                  // Lambda eps4 of face (n, n+e_d): 3 fields
+  W_G = 31,                                   // pass-2 output: Q adjoint per node, 5 fields
+  W_Q1 = 36,                                  // stage adjoint ping-pong: 5 + 5 fields
+  W_ACC = 46,                                 // accumulated adjoint of Q^(0): 5 fields
+  W_NF = 51
+};
+
+struct Prim {
+  double rho, u, v, w, p, T;
+};
+
+__device__ __forceinline__ Prim prim_at(const double* __restrict__ Q, long long fe, long long n, const Phys& P) {
+  Prim r;
+  r.rho = Q[n];
+  prim_from_q(r.rho, Q[fe + n], Q[2 * fe + n], Q[3 * fe + n], Q[4 * fe + n], P, r.u, r.v, r.w, r.p, r.T);
+  return r;
+}
+
+__device__ __forceinline__ long long dstr(const Layout& L, int d) { return d == 0 ? 1LL : (d == 1 ? L.sj : L.sk); }
+
+__device__ __forceinline__ bool interior(const Layout& L, int i, int j, int k) {
+  return i >= 0 && i < L.ni && j >= 0 && j < L.nj && k >= 0 && k < L.nk;
+}
+
+// Does the face (a, a + e_d) exist, i.e. is it used by an interior residual?
+__device__ __forceinline__ bool face_ok(const Layout& L, int d, int i, int j, int k) {
+  const int id[3] = {i, j, k};
+  const int nn[3] = {L.ni, L.nj, L.nk};
+  for (int e = 0; e < 3; ++e) {
+    if (e == d) {
+      if (id[e] < -1 || id[e] > nn[e] - 1) return false;
+    } else if (id[e] < 0 || id[e] >= nn[e]) {
+      return false;
+    }
+  }
+  return true;
+}
+
+// W = coef * J * qbar on the interior, zero elsewhere.
+__device__ __forceinline__ void Wat(const Layout& L, const double* __restrict__ M, const double* __restrict__ qb,
+                                    double coef, int i, int j, int k, double W[5]) {
+  if (!interior(L, i, j, k)) {
+    for (int c = 0; c < 5; ++c) W[c] = 0.0;
+    return;
+  }
+  const long long n = L.at(i, j, k);
+  const double s = coef * M[9 * L.fe + n];
+  for (int c = 0; c < 5; ++c) W[c] = s * qb[c * L.fe + n];
+}
+
+// Spectral radii and their ingredients at node n.
+struct Radii {
+  double lam[3], U[3], nrm[3], c;
+};
+
+__device__ __forceinline__ Radii radii_at(const double* __restrict__ M, long long fe, long long n, const Prim& q,
+                                          const Phys& P) {
+  Radii r;
+  r.c = sqrt(P.gamma * q.p / q.rho);
+  for (int e = 0; e < 3; ++e) {
+    const double mx = M[(3 * e) * fe + n], my = M[(3 * e + 1) * fe + n], mz = M[(3 * e + 2) * fe + n];
+    r.U[e] = mx * q.u + my * q.v + mz * q.w;
+    r.nrm[e] = sqrt(mx * mx + my * my + mz * mz);
+    r.lam[e] = fabs(r.U[e]) + r.c * r.nrm[e];
+  }
+  return r;
+}
+
+// Anisotropic scaling Lam_d and its partial derivatives w.r.t. (lam_d, lam_e, lam_f).
+__device__ __forceinline__ double aniso_d(double ld, double le, double lf, const Phys& P, double& dd, double& de,
+                                          double& df) {
+  const double a = P.alpha;
+  const double re = pow(le / ld, a), rf = pow(lf / ld, a);
+  dd = 1.0 + (1.0 - a) * (re + rf);
+  de = a * re * ld / le;
+  df = a * rf * ld / lf;
+  return ld * (1.0 + re + rf);
+}
+
+__device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+// Pressure sensor of direction d at node n (p at n-e, n, n+e).
+__device__ __forceinline__ double sensor(double pm, double p0, double pp) {
+  return fabs(pp - 2.0 * p0 + pm) / (pp + 2.0 * p0 + pm);
+}
+
+struct AdjK {
+  Layout L;
+  Phys P;
+  const double* M;
+  int bc0, bc1, bc2;
+};
+
+// ---------------------------------------------------------------------------
+// Pass 1
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adj_node(AdjK A, const double* __restrict__ Q, const double* __restrict__ qb,
+                                                  double coef, double* __restrict__ Wk) {
+  const Layout& L = A.L;
+  const Phys& P = A.P;
+  const long long fe = L.fe;
+  const double* __restrict__ M = A.M;
+  const int ext_i = L.ni + 2, ext_j = L.nj + 2;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)ext_i * ext_j * (L.nk + 2)) return;
+  const int i = (int)(t % ext_i) - 1;
+  const int j = (int)((t / ext_i) % ext_j) - 1;
+  const int k = (int)(t / ((long long)ext_i * ext_j)) - 1;
+  const long long n = L.at(i, j, k);
+  const int id[3] = {i, j, k};
+
+  const Prim q = prim_at(Q, fe, n, P);
+  double m[9];
+  for (int c = 0; c < 9; ++c) m[c] = M[c * fe + n];
+  const double J = M[9 * fe + n];
+
+  // ---- forward recomputation at the node ----
+  double g[4][3];
+  {
+    double dd[3][4];
+    for (int d = 0; d < 3; ++d) {
+      const long long s = dstr(L, d);
+      const Prim a = prim_at(Q, fe, n + s, P), b = prim_at(Q, fe, n - s, P);
+      dd[d][0] = 0.5 * (a.u - b.u);
+      dd[d][1] = 0.5 * (a.v - b.v);
+      dd[d][2] = 0.5 * (a.w - b.w);
+      dd[d][3] = 0.5 * (a.T - b.T);
+    }
+    for (int qq = 0; qq < 4; ++qq)
+      for (int x = 0; x < 3; ++x) g[qq][x] = J * (m[x] * dd[0][qq] + m[3 + x] * dd[1][qq] + m[6 + x] * dd[2][qq]);
+  }
+  const double S11 = g[0][0], S22 = g[1][1], S33 = g[2][2];
+  const double S12 = 0.5 * (g[0][1] + g[1][0]), S13 = 0.5 * (g[0][2] + g[2][0]), S23 = 0.5 * (g[1][2] + g[2][1]);
+  const double skk3 = (S11 + S22 + S33) / 3.0;
+  const double th = q.T * P.inv_Tref;
+  const double mu = P.mu_ref * P.one_plus_S * th * sqrt(th) / (th + P.S);
+  double mus = 0.0, Smag = 0.0, cd2 = 0.0;
+  if (P.sgs) {
+    Smag = sqrt(2.0 * (S11 * S11 + S22 * S22 + S33 * S33 + 2.0 * (S12 * S12 + S13 * S13 + S23 * S23)));
+    double d2 = cbrt(1.0 / J);
+    cd2 = P.Cs2 * d2 * d2;
+    mus = q.rho * cd2 * Smag;
+  }
+  const double mt = mu + mus;
+  const double mt2 = 2.0 * mt;
+  const double tau[3][3] = {{mt2 * (S11 - skk3), mt2 * S12, mt2 * S13},
+                            {mt2 * S12, mt2 * (S22 - skk3), mt2 * S23},
+                            {mt2 * S13, mt2 * S23, mt2 * (S33 - skk3)}};
+  const double kap = mu * P.Cp_over_Pr + mus * P.Cp_over_Prsgs;
+  const double uu[3] = {q.u, q.v, q.w};
+
+  // ---- adjoint accumulators ----
+  double rb = 0, ub[3] = {0, 0, 0}, pb = 0, Tb = 0;  // primitive adjoint
+  double qd[4] = {0, 0, 0, 0};                        // direct Q1..Q4 adjoint
+  double tb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // tau adjoint (full, symmetrised below)
+  double thb[3] = {0, 0, 0};                          // Theta adjoint
+  const double Qv[5] = {q.rho, Q[fe + n], Q[2 * fe + n], Q[3 * fe + n], Q[4 * fe + n]};
+
+  // ---- node flux adjoints Hbar_d = (W(n-e) - W(n+e)) / 2 ----
+  for (int d = 0; d < 3; ++d) {
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    double Wm[5], Wp[5];
+    Wat(L, M, qb, coef, i - di, j - dj, k - dk, Wm);
+    Wat(L, M, qb, coef, i + di, j + dj, k + dk, Wp);
+    double Hb[5];
+    bool any = false;
+    for (int c = 0; c < 5; ++c) {
+      Hb[c] = 0.5 * (Wm[c] - Wp[c]);
+      any = any || Hb[c] != 0.0;
+    }
+    if (!any) continue;
+    const double mx = m[3 * d], my = m[3 * d + 1], mz = m[3 * d + 2];
+    const double mm[3] = {mx, my, mz};
+    const double U = mx * q.u + my * q.v + mz * q.w;
+    double Ub = 0.0;
+    // H0 = rho U
+    rb += Hb[0] * U;
+    Ub += Hb[0] * q.rho;
+    // H_{1+a} = Q_{1+a} U + m_a p - m . tau_a
+    for (int a = 0; a < 3; ++a) {
+      qd[a] += Hb[1 + a] * U;
+      Ub += Hb[1 + a] * Qv[1 + a];
+      pb += Hb[1 + a] * mm[a];
+      for (int x = 0; x < 3; ++x) tb[a][x] -= Hb[1 + a] * mm[x];
+    }
+    // H4 = (e + p) U - m . Theta
+    qd[3] += Hb[4] * U;
+    pb += Hb[4] * U;
+    Ub += Hb[4] * (Qv[4] + q.p);
+    for (int x = 0; x < 3; ++x) thb[x] -= Hb[4] * mm[x];
+    ub[0] += Ub * mx;
+    ub[1] += Ub * my;
+    ub[2] += Ub * mz;
+  }
+  // ---- Theta_x = u_a tau_ax + kappa dT/dx ----
+  double kapb = 0.0;
+  double gb[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int x = 0; x < 3; ++x) {
+    for (int a = 0; a < 3; ++a) {
+      ub[a] += thb[x] * tau[a][x];
+      tb[a][x] += uu[a] * thb[x];
+    }
+    kapb += thb[x] * g[3][x];
+    gb[3][x] += kap * thb[x];
+  }
+  // ---- tau = 2 mt (S - delta skk/3), symmetric ----
+  const double t11 = tb[0][0], t22 = tb[1][1], t33 = tb[2][2];
+  const double t12 = tb[0][1] + tb[1][0], t13 = tb[0][2] + tb[2][0], t23 = tb[1][2] + tb[2][1];
+  const double mtb = 2.0 * ((S11 - skk3) * t11 + (S22 - skk3) * t22 + (S33 - skk3) * t33 + S12 * t12 + S13 * t13 +
+                            S23 * t23);
+  const double tr = (t11 + t22 + t33) / 3.0;
+  double Sb11 = mt2 * (t11 - tr), Sb22 = mt2 * (t22 - tr), Sb33 = mt2 * (t33 - tr);
+  double Sb12 = mt2 * t12, Sb13 = mt2 * t13, Sb23 = mt2 * t23;
+  // ---- viscosities ----
+  const double mub = mtb + kapb * P.Cp_over_Pr;
+  if (P.sgs) {
+    const double musb = mtb + kapb * P.Cp_over_Prsgs;
+    rb += musb * cd2 * Smag;
+    if (Smag > 0.0) {
+      const double sb = musb * q.rho * cd2 / Smag;
+      Sb11 += 2.0 * S11 * sb;
+      Sb22 += 2.0 * S22 * sb;
+      Sb33 += 2.0 * S33 * sb;
+      Sb12 += 4.0 * S12 * sb;
+      Sb13 += 4.0 * S13 * sb;
+      Sb23 += 4.0 * S23 * sb;
+    }
+  }
+  // Sutherland: dmu/dT = mu (3/(2 th) - 1/(th + S)) / T_ref
+  Tb += mub * mu * (1.5 / th - 1.0 / (th + P.S)) * P.inv_Tref;
+  // ---- S from the velocity gradient ----
+  gb[0][0] += Sb11;
+  gb[1][1] += Sb22;
+  gb[2][2] += Sb33;
+  gb[0][1] += 0.5 * Sb12;
+  gb[1][0] += 0.5 * Sb12;
+  gb[0][2] += 0.5 * Sb13;
+  gb[2][0] += 0.5 * Sb13;
+  gb[1][2] += 0.5 * Sb23;
+  gb[2][1] += 0.5 * Sb23;
+  // gradient-stencil weights a_{q,d} = J m_d . gbar_q
+  for (int qq = 0; qq < 4; ++qq)
+    for (int d = 0; d < 3; ++d)
+      Wk[(W_A + 3 * qq + d) * fe + n] = J * (m[3 * d] * gb[qq][0] + m[3 * d + 1] * gb[qq][1] + m[3 * d + 2] * gb[qq][2]);
+
+  // ---- dissipation: the faces (n-e, n) and (n, n+e) of each direction ----
+  const Radii r0 = radii_at(M, fe, n, q, P);
+  double lamb[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    const long long s = dstr(L, d);
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    const bool f_lo = face_ok(L, d, i - di, j - dj, k - dk);  // face (n-e, n)
+    const bool f_hi = face_ok(L, d, i, j, k);                 // face (n, n+e)
+    double A2 = 0.0, A4 = 0.0, cpw = 0.0;
+    if (f_lo || f_hi) {
+      // sensors and Lambda at n-e (only with the lower face), n, n+e (only
+      // with the upper face): every node read lies in the padded box and
+      // every metric read in [-1, n]
+      const Prim qm = prim_at(Q, fe, n - s, P), qp = prim_at(Q, fe, n + s, P);
+      const double nu_0 = sensor(qm.p, q.p, qp.p);
+      double dd, de, df;
+      const double L0 = aniso_d(r0.lam[d], r0.lam[(d + 1) % 3], r0.lam[(d + 2) % 3], P, dd, de, df);
+      double nu_m = 0.0, nu_p = 0.0, Lm = 0.0, Lp = 0.0;
+      if (f_lo) {
+        nu_m = sensor(prim_at(Q, fe, n - 2 * s, P).p, qm.p, q.p);
+        const Radii rm = radii_at(M, fe, n - s, qm, P);
+        Lm = aniso_d(rm.lam[d], rm.lam[(d + 1) % 3], rm.lam[(d + 2) % 3], P, dd, de, df);
+      }
+      if (f_hi) {
+        nu_p = sensor(q.p, qp.p, prim_at(Q, fe, n + 2 * s, P).p);
+        const Radii rp = radii_at(M, fe, n + s, qp, P);
+        Lp = aniso_d(rp.lam[d], rp.lam[(d + 1) % 3], rp.lam[(d + 2) % 3], P, dd, de, df);
+      }
+      double Lamb = 0.0, nub = 0.0;
+      for (int side = 0; side < 2; ++side) {
+        // side 0: face (n-e, n) with the node as b; side 1: face (n, n+e) with the node as a
+        if (side == 0 && !f_lo) continue;
+        if (side == 1 && !f_hi) continue;
+        const int ai = side == 0 ? i - di : i, aj = side == 0 ? j - dj : j, ak = side == 0 ? k - dk : k;
+        const long long an = L.at(ai, aj, ak);
+        const double na = side == 0 ? nu_m : nu_0, nb = side == 0 ? nu_0 : nu_p;
+        const double La = side == 0 ? Lm : L0, Lb = side == 0 ? L0 : Lp;
+        const double e2 = P.k2 * (na >= nb ? na : nb);
+        const double e4raw = P.k4 - e2;
+        const bool e4_active = !(0.0 >= e4raw);  // max(0, x) follows 0 on ties
+        const double e4 = e4_active ? e4raw : 0.0;
+        const double Lf = 0.5 * (La + Lb);
+        // Dbar = W(a+e) - W(a)
+        double Wa[5], Wb[5];
+        Wat(L, M, qb, coef, ai, aj, ak, Wa);
+        Wat(L, M, qb, coef, ai + di, aj + dj, ak + dk, Wb);
+        double Lfb = 0.0, e2b = 0.0, e4b = 0.0;
+        for (int c = 0; c < 5; ++c) {
+          const double Db = Wb[c] - Wa[c];
+          const double* Qc = Q + c * fe;
+          const double d1 = Qc[an + s] - Qc[an];
+          const double d3 = Qc[an + 2 * s] - 3.0 * Qc[an + s] + 3.0 * Qc[an] - Qc[an - s];
+          Lfb += Db * (e2 * d1 - e4 * d3);
+          e2b += Db * Lf * d1;
+          e4b -= Db * Lf * d3;
+        }
+        if (e4_active) e2b -= e4b;
+        Lamb += 0.5 * Lfb;  // this node's share of the face mean
+        // eps2 = k2 max(nu_a, nu_b): the node is b on side 0, a on side 1
+        const bool a_wins = na >= nb;
+        if ((side == 0 && !a_wins) || (side == 1 && a_wins)) nub += P.k2 * e2b;
+        if (side == 1) {
+          A2 = Lf * e2;
+          A4 = Lf * e4;
+        }
+      }
+      // Lambda_d(n) -> lam_d, lam_e, lam_f
+      {
+        double dd0, de0, df0;
+        aniso_d(r0.lam[d], r0.lam[(d + 1) % 3], r0.lam[(d + 2) % 3], P, dd0, de0, df0);
+        lamb[d] += Lamb * dd0;
+        lamb[(d + 1) % 3] += Lamb * de0;
+        lamb[(d + 2) % 3] += Lamb * df0;
+      }
+      // nu_d(n) = |Delta2| / Sigma with p(n-e), p(n), p(n+e)
+      {
+        const double D2 = qp.p - 2.0 * q.p + qm.p, Sg = qp.p + 2.0 * q.p + qm.p;
+        const double sd = sgn(D2) / Sg, sv = nu_0 / Sg;
+        pb += nub * (-2.0 * sd - 2.0 * sv);
+        cpw = nub * (sd - sv);  // weight of p(n - e) and p(n + e)
+      }
+    }
+    Wk[(W_CP + d) * fe + n] = cpw;
+    Wk[(W_A2 + d) * fe + n] = A2;
+    Wk[(W_A4 + d) * fe + n] = A4;
+  }
+  // lam_e = |U_e| + c |m_e|
+  double cb = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    if (lamb[e] == 0.0) continue;
+    const double Ueb = sgn(r0.U[e]) * lamb[e];
+    cb += r0.nrm[e] * lamb[e];
+    ub[0] += Ueb * m[3 * e];
+    ub[1] += Ueb * m[3 * e + 1];
+    ub[2] += Ueb * m[3 * e + 2];
+  }
+  // c = sqrt(gamma p / rho)
+  if (cb != 0.0) {
+    pb += cb * P.gamma / (2.0 * r0.c * q.rho);
+    rb -= cb * r0.c / (2.0 * q.rho);
+  }
+  Wk[W_PRHO * fe + n] = rb;
+  Wk[W_PU * fe + n] = ub[0];
+  Wk[W_PV * fe + n] = ub[1];
+  Wk[W_PW * fe + n] = ub[2];
+  Wk[W_PP * fe + n] = pb;
+  Wk[W_PT * fe + n] = Tb;
+  for (int a = 0; a < 4; ++a) Wk[(W_QD1 + a) * fe + n] = qd[a];
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool in_b1(const Layout& L, int i, int j, int k) {
+  return i >= -1 && i <= L.ni && j >= -1 && j <= L.nj && k >= -1 && k <= L.nk;
+}
+
+__global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __restrict__ Q, const double* __restrict__ qb,
+                                                    double coef, double* __restrict__ Wk) {
+  const Layout& L = A.L;
+  const Phys& P = A.P;
+  const long long fe = L.fe;
+  const int pi = L.ni + 4, pj = L.nj + 4;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)pi * pj * (L.nk + 4)) return;
+  const int i = (int)(t % pi) - 2;
+  const int j = (int)((t / pi) % pj) - 2;
+  const int k = (int)(t / ((long long)pi * pj)) - 2;
+  const long long n = L.at(i, j, k);
+  const bool b1 = in_b1(L, i, j, k);
+
+  double rb = 0, ub[3] = {0, 0, 0}, pb = 0, Tb = 0;
+  double out[5] = {0, 0, 0, 0, 0};
+  if (b1) {
+    rb = Wk[W_PRHO * fe + n];
+    ub[0] = Wk[W_PU * fe + n];
+    ub[1] = Wk[W_PV * fe + n];
+    ub[2] = Wk[W_PW * fe + n];
+    pb = Wk[W_PP * fe + n];
+    Tb = Wk[W_PT * fe + n];
+    for (int a = 0; a < 4; ++a) out[1 + a] += Wk[(W_QD1 + a) * fe + n];
+  }
+  // gradient-stencil and sensor weights of the neighbours
+  for (int d = 0; d < 3; ++d) {
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    const long long s = dstr(L, d);
+    const bool lo = in_b1(L, i - di, j - dj, k - dk), hi = in_b1(L, i + di, j + dj, k + dk);
+    double phib[4] = {0, 0, 0, 0};
+    for (int qq = 0; qq < 4; ++qq) {
+      const double* a = Wk + (W_A + 3 * qq + d) * fe;
+      phib[qq] = 0.5 * ((lo ? a[n - s] : 0.0) - (hi ? a[n + s] : 0.0));
+    }
+    ub[0] += phib[0];
+    ub[1] += phib[1];
+    ub[2] += phib[2];
+    Tb += phib[3];
+    const double* cp = Wk + (W_CP + d) * fe;
+    pb += (lo ? cp[n - s] : 0.0) + (hi ? cp[n + s] : 0.0);
+  }
+  // primitive adjoint -> conserved variables (nodes without any adjoint skip
+  // the map, so unused ghost corners are never read)
+  if (rb != 0.0 || ub[0] != 0.0 || ub[1] != 0.0 || ub[2] != 0.0 || pb != 0.0 || Tb != 0.0) {
+  const Prim q = prim_at(Q, fe, n, P);
+  pb += Tb * P.inv_R / q.rho;
+  rb -= Tb * q.T / q.rho;
+  out[4] += P.gm1 * pb;
+  out[1] -= P.gm1 * q.u * pb;
+  out[2] -= P.gm1 * q.v * pb;
+  out[3] -= P.gm1 * q.w * pb;
+  out[0] += P.gm1 * 0.5 * (q.u * q.u + q.v * q.v + q.w * q.w) * pb;
+  out[1] += ub[0] / q.rho;
+  out[2] += ub[1] / q.rho;
+  out[3] += ub[2] / q.rho;
+  out[0] -= (ub[0] * q.u + ub[1] * q.v + ub[2] * q.w) / q.rho;
+  out[0] += rb;
+  }
+  // dissipation faces whose five-point stencil contains this node:
+  //   face a = n-e (node is b):    +(A2 + 3 A4) Dbar
+  //   face a = n   (node is a):    -(A2 + 3 A4) Dbar
+  //   face a = n-2e (node is b+e): -A4 Dbar
+  //   face a = n+e (node is a-e):  +A4 Dbar
+  for (int d = 0; d < 3; ++d) {
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    const long long s = dstr(L, d);
+    const int off[4] = {-1, 0, -2, 1};
+    for (int r = 0; r < 4; ++r) {
+      const int ai = i + off[r] * di, aj = j + off[r] * dj, ak = k + off[r] * dk;
+      if (!face_ok(L, d, ai, aj, ak)) continue;
+      const long long an = n + off[r] * s;
+      const double A2 = Wk[(W_A2 + d) * fe + an], A4 = Wk[(W_A4 + d) * fe + an];
+      const double w = r == 0 ? (A2 + 3.0 * A4) : (r == 1 ? -(A2 + 3.0 * A4) : (r == 2 ? -A4 : A4));
+      if (w == 0.0) continue;
+      double Wa[5], Wb[5];
+      Wat(L, A.M, qb, coef, ai, aj, ak, Wa);
+      Wat(L, A.M, qb, coef, ai + di, aj + dj, ak + dk, Wb);
+      for (int c = 0; c < 5; ++c) out[c] += w * (Wb[c] - Wa[c]);
+    }
+  }
+  for (int c = 0; c < 5; ++c) Wk[(W_G + c) * fe + n] = out[c];
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3: fold periodic ghost images onto the interior:
+// qout(n) = sum over padded images of n of G (+ add, when non-null).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restrict__ G, const double* __restrict__ add,
+                                                  double* __restrict__ qout) {
+  const Layout& L = A.L;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)L.ni * L.nj * L.nk) return;
+  const int i = (int)(t % L.ni);
+  const int j = (int)((t / L.ni) % L.nj);
+  const int k = (int)(t / ((long long)L.ni * L.nj));
+  const int bc[3] = {A.bc0, A.bc1, A.bc2};
+  const int id[3] = {i, j, k};
+  const int nn[3] = {L.ni, L.nj, L.nk};
+  int cand[3][3], nc[3];
+  for (int d = 0; d < 3; ++d) {
+    nc[d] = 0;
+    cand[d][nc[d]++] = id[d];
+    if (bc[d] == 0) {
+      if (id[d] + nn[d] <= nn[d] + 1) cand[d][nc[d]++] = id[d] + nn[d];
+      if (id[d] - nn[d] >= -2) cand[d][nc[d]++] = id[d] - nn[d];
+    }
+  }
+  const long long n0 = L.at(i, j, k);
+  for (int c = 0; c < 5; ++c) {
+    double s = add ? add[c * L.fe + n0] : 0.0;
+    for (int a = 0; a < nc[0]; ++a)
+      for (int b = 0; b < nc[1]; ++b)
+        for (int e = 0; e < nc[2]; ++e) s += G[c * L.fe + L.at(cand[0][a], cand[1][b], cand[2][e])];
+    qout[c * L.fe + n0] = s;
+  }
+}
+
+// out = a + b on the interior (5 fields)
+// (out may alias a: each thread reads and writes only its own node)
+__global__ void __launch_bounds__(256) k_axpy_interior(Layout L, const double* a, const double* b, double* out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)L.ni * L.nj * L.nk) return;
+  const int i = (int)(t % L.ni);
+  const int j = (int)((t / L.ni) % L.nj);
+  const int k = (int)(t / ((long long)L.ni * L.nj));
+  const long long n = L.at(i, j, k);
+  for (int c = 0; c < 5; ++c) out[c * L.fe + n] = a[c * L.fe + n] + (b ? b[c * L.fe + n] : 0.0);
+}
+
+// fbar[c][k][j] += w * qbar_c(i_f, j, k)
+__global__ void __launch_bounds__(256) k_fbar(Layout L, int i_f, double w, const double* __restrict__ qb,
+                                              double* __restrict__ fbar) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)L.nj * L.nk) return;
+  const int j = (int)(t % L.nj), k = (int)(t / L.nj);
+  const long long n = L.at(i_f, j, k);
+  for (int c = 0; c < 5; ++c) fbar[((long long)c * L.nk + k) * L.nj + j] += w * qb[c * L.fe + n];
+}
+
+inline unsigned nb(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Qbar_out = (dR/dQ|Q)^T (coef * qb) on the interior.
+hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const double* qb, double coef, double* Wk,
+                        const double* add, double* qout) {
+  const Layout& L = A.L;
+  const long long nB1 = (long long)(L.ni + 2) * (L.nj + 2) * (L.nk + 2);
+  const long long nPad = (long long)(L.ni + 4) * (L.nj + 4) * (L.nk + 4);
+  const long long nIn = (long long)L.ni * L.nj * L.nk;
+  k_adj_node<<<nb(nB1, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
+  k_adj_gather<<<nb(nPad, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
+  k_adj_fold<<<nb(nIn, 256), 256, 0, s>>>(A, Wk + (long long)W_G * L.fe, add, qout);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t adjoint_work_elems(const Layout& L) { return (size_t)W_NF * (size_t)L.fe; }
+
+hipError_t run_residual_vjp(hipStream_t s, const AdjArgs& a, const double* Q, const double* Rbar, double* Qbar,
+                            double* work) {
+  AdjK A{a.L, a.P, a.M, a.bc0, a.bc1, a.bc2};
+  return residual_vjp(s, A, Q, Rbar, 1.0, work, nullptr, Qbar);
+}
+
+hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt, double dt, double* Qbar,
+                            double* fbar, double* work) {
+  AdjK A{a.L, a.P, a.M, a.bc0, a.bc1, a.bc2};
+  const Layout& L = a.L;
+  const long long fe = L.fe;
+  const long long nIn = (long long)L.ni * L.nj * L.nk;
+  double* qcur = work + (long long)W_Q1 * fe;
+  double* qnext = work + (long long)(W_Q1 + 5) * fe;
+  double* acc = work + (long long)W_ACC * fe;
+  // qcur = Qbar, acc = 0 (interior)
+  k_axpy_interior<<<nb(nIn, 256), 256, 0, s>>>(L, Qbar, nullptr, qcur);
+  hipError_t e = hipMemsetAsync(acc, 0, (size_t)5 * fe * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  for (int l = 4; l >= 0; --l) {
+    const double al = rk_alpha(l) * dt;
+    // acc += qbar_l
+    k_axpy_interior<<<nb(nIn, 256), 256, 0, s>>>(L, acc, qcur, acc);
+    if (fbar && a.i_f >= 0)
+      k_fbar<<<nb((long long)L.nj * L.nk, 256), 256, 0, s>>>(L, a.i_f, al, qcur, fbar);
+    // qbar_{l-1} = (dR/dQ|Q^(l-1))^T (-alpha_l dt qbar_l)
+    const double* Ql = ckpt + (long long)l * 5 * fe;
+    e = residual_vjp(s, A, Ql, qcur, -al, work, nullptr, qnext);
+    if (e != hipSuccess) return e;
+    double* tmp = qcur;
+    qcur = qnext;
+    qnext = tmp;
+  }
+  k_axpy_interior<<<nb(nIn, 256), 256, 0, s>>>(L, acc, qcur, Qbar);
+  return hipGetLastError();
 }
 
 }  // namespace les

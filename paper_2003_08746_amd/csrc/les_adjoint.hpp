@@ -15,6 +15,10 @@ struct AdjArgs {
 // Device work elements (doubles) needed by run_adjoint_step.
 size_t adjoint_work_elems(const Layout& L);
 
+// Qbar = (dR/dQ|Q)^T Rbar on the interior (Q with ghosts filled).
+hipError_t run_residual_vjp(hipStream_t s, const AdjArgs& a, const double* Q, const double* Rbar, double* Qbar,
+                            double* work);
+
 hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt, double dt, double* Qbar,
                             double* fbar, double* work);
 

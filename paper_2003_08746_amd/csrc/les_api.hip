@@ -112,6 +112,19 @@ static int timing_end(les_ctx* c) {
   return LES_OK;
 }
 
+// Adjoint work arrays are allocated on first use and kept by the context.
+static int ensure_adj_work(les_ctx* c) {
+  const size_t need = les::adjoint_work_elems(c->L);
+  if ((long long)need <= c->adj_n) return LES_OK;
+  (void)hipFree(c->adj);
+  c->adj = nullptr;
+  c->adj_n = 0;
+  if (hipMalloc(&c->adj, need * sizeof(double)) != hipSuccess)
+    return fail(c, LES_ERR_NOMEM, "adjoint work allocation (%zu bytes)", need * sizeof(double));
+  c->adj_n = (long long)need;
+  return LES_OK;
+}
+
 extern "C" {
 
 const char* les_last_create_error(void) { return g_create_err; }
@@ -386,17 +399,22 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
   if (!stage_ckpt || !Qbar) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: stage_ckpt and Qbar are required");
   if (!(dt > 0.0)) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: dt must be > 0 (the step's fixed dt)");
   if (ctx->prec != LES_FP64) return fail(ctx, LES_ERR_STATE, "les_adjoint_step: needs an FP64 context");
-  const size_t need = les::adjoint_work_elems(ctx->L);
-  if ((long long)need > ctx->adj_n) {
-    (void)hipFree(ctx->adj);
-    ctx->adj = nullptr;
-    ctx->adj_n = 0;
-    if (hipMalloc(&ctx->adj, need * sizeof(double)) != hipSuccess)
-      return fail(ctx, LES_ERR_NOMEM, "les_adjoint_step: work allocation (%zu bytes)", need * sizeof(double));
-    ctx->adj_n = (long long)need;
-  }
+  int rc = ensure_adj_work(ctx);
+  if (rc != LES_OK) return rc;
   les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f};
   HIPCHK(ctx, les::run_adjoint_step(ctx->s, a, stage_ckpt, dt, Qbar, ctx->i_f >= 0 ? fbar : nullptr, ctx->adj));
+  return LES_OK;
+}
+
+int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qbar) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual_adjoint: null context");
+  if (!Q || !Rbar || !Qbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Q, Rbar and Qbar are required");
+  if (Qbar == Q || Qbar == Rbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Qbar must not alias Q or Rbar");
+  int rc = ensure_adj_work(ctx);
+  if (rc != LES_OK) return rc;
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5));
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f};
+  HIPCHK(ctx, les::run_residual_vjp(ctx->s, a, Q, Rbar, Qbar, ctx->adj));
   return LES_OK;
 }
 

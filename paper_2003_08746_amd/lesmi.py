@@ -26,7 +26,8 @@ LES_FP64, LES_MIXED = 0, 1
 LES_BC_PERIODIC, LES_BC_DIRICHLET = 0, 1
 
 EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",
-            "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_adjoint_step", "les_probe_objective",
+            "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_adjoint_step", "les_residual_adjoint",
+            "les_probe_objective",
             "les_last_error", "les_last_create_error"]
 
 
@@ -84,6 +85,8 @@ def lib():
     L.les_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _dp, _dp, _vp]
     L.les_adjoint_step.restype = ctypes.c_int
     L.les_adjoint_step.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp]
+    L.les_residual_adjoint.restype = ctypes.c_int
+    L.les_residual_adjoint.argtypes = [_vp, _vp, _vp, _vp]
     L.les_probe_objective.restype = ctypes.c_int
     L.les_probe_objective.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp, _vp]
     L.les_last_error.restype = ctypes.c_char_p
@@ -188,6 +191,10 @@ def les_rk_step(ctx, Q_ptr, dt=0.0, want_dt=False, want_norms=False, ckpt_ptr=No
 
 def les_adjoint_step(ctx, ckpt_ptr, dt, Qbar_ptr, fbar_ptr=None):
     _check(lib().les_adjoint_step(ctx, ckpt_ptr, float(dt), Qbar_ptr, fbar_ptr), ctx, "les_adjoint_step")
+
+
+def les_residual_adjoint(ctx, Q_ptr, Rbar_ptr, Qbar_ptr):
+    _check(lib().les_residual_adjoint(ctx, Q_ptr, Rbar_ptr, Qbar_ptr), ctx, "les_residual_adjoint")
 
 
 def les_probe_objective(ctx, Q_ptr, i_p, p_inf, weight, J_ptr, Qbar_ptr=None):
@@ -296,6 +303,11 @@ class Solver:
 
     def adjoint_step(self, ckpt, dt, Qbar, fbar=None):
         les_adjoint_step(self.ctx, ckpt.data_ptr(), dt, Qbar.data_ptr(), _ptr(fbar))
+
+    def residual_adjoint(self, Q, Rbar):
+        Qbar = self.empty_state()
+        les_residual_adjoint(self.ctx, Q.data_ptr(), Rbar.data_ptr(), Qbar.data_ptr())
+        return Qbar
 
     def probe_objective(self, Q, i_p, p_inf, weight, J, Qbar=None):
         les_probe_objective(self.ctx, Q.data_ptr(), i_p, p_inf, weight, J.data_ptr(), _ptr(Qbar))
