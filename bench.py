@@ -68,7 +68,7 @@ def time_gpu(case, prec, steps, warmup):
     for _ in range(warmup):
         s.rk_step(Q)
     dt0 = s.cfl_dt(Q)  # synchronises; also checks the warmed-up state is finite
-    timing = prec == lesmi.LES_FP64
+    timing = True
     if timing:
         lesmi.les_debug_stage_timing(s.ctx, True)
     stream = s.stream
@@ -89,6 +89,70 @@ def time_gpu(case, prec, steps, warmup):
     _, norms = s.rk_step(Q, 0.0, want_norms=True)  # raises on a non-finite state
     out = dict(wall_s=wall, gpu_ms=gpu_ms, stage_ms=stage_ms, launches=launches, dt0=dt0, norms=list(norms))
     s.close()
+    return out
+
+
+def time_adjoint(ni=128, nj=64, nk=64, nsteps=50, i_f=8, i_p=16):
+    """Forcing workload: forward rollout (stage checkpoints + probe
+    objective) against the backward pass (probe adjoint + les_adjoint_step),
+    both timed with HIP events on the solver's stream."""
+    import numpy as np
+    import torch
+    from paper_2003_08746_amd import inputs, lesmi
+    from paper_2003_08746_amd.rollout import LesRollout
+    case = inputs.jet_case(ni, nj, nk, seed=0)
+    f = torch.from_numpy(1e-3 * np.random.default_rng(1).uniform(-1, 1, size=(5, nk, nj))).cuda()
+    s = lesmi.Solver(case)
+    Q0 = s.upload(case["Q"])
+    dt = s.cfl_dt(Q0)
+    p_inf = 1.0 / inputs.GAMMA
+    res = {}
+    for rep in range(2):  # the first repetition warms up (allocations)
+        ft = f.clone().requires_grad_(True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        J = LesRollout.apply(ft, Q0, s, nsteps, dt, i_f, i_p, p_inf, "stages")
+        e1.record(s.stream)
+        J.backward()
+        e2.record(s.stream)
+        torch.cuda.synchronize()
+        res = dict(forward_ms=e0.elapsed_time(e1), backward_ms=e1.elapsed_time(e2))
+    # plain forward steps (no checkpoints, no objective) for reference
+    Q = Q0.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    for _ in range(nsteps):
+        s.rk_step(Q, dt)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    plain = e0.elapsed_time(e1)
+    s.close()
+    return {"workload": f"jet grid {ni}x{nj}x{nk}, FP64, {nsteps} RK steps, source plane i={i_f}, probe plane i={i_p}",
+            "forward_ms": round(res["forward_ms"], 3), "backward_ms": round(res["backward_ms"], 3),
+            "plain_forward_ms": round(plain, 3),
+            "adjoint_over_forward": round(res["backward_ms"] / res["forward_ms"], 3),
+            "adjoint_over_plain_forward": round(res["backward_ms"] / plain, 3)}
+
+
+def time_large(steps, ni=800, nj=500, nk=500):
+    """The 800 x 500 x 500 shard (2.0e8 points), generated on the device."""
+    import torch
+    from paper_2003_08746_amd import inputs, lesmi
+    case = inputs.jet_case_device(ni, nj, nk, seed=0)
+    npts = ni * nj * nk
+    out = {"workload": f"jet shard {ni}x{nj}x{nk} ({npts:.3g} points)"}
+    for name, prec, byts in (("fp64", lesmi.LES_FP64, BYTES_FP64), ("mixed", lesmi.LES_MIXED, BYTES_MIXED)):
+        r = time_gpu(case, prec, steps, 1)
+        v = npts * 5 * steps / r["wall_s"] / 1e6
+        o = {"value": round(v, 2), "unit": "Mpoint-RK-stages/s", "ms_per_step": round(r["wall_s"] * 1e3 / steps, 3),
+             "algorithmic_GBps": round(byts * npts * 5 * steps / r["wall_s"] / 1e9, 1)}
+        if r["stage_ms"]:
+            o["avg_stage_launch_us"] = round(r["stage_ms"] / r["launches"] * 1e3, 1)
+        out[name] = o
+        torch.cuda.empty_cache()
+    del case
+    torch.cuda.empty_cache()
     return out
 
 
@@ -121,6 +185,9 @@ def main():
     ap.add_argument("--nk", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and adjoint legs")
+    ap.add_argument("--large", action="store_true",
+                    help="also time the 800 x 500 x 500 shard (FP64 and mixed, 20 steps each)")
+    ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -189,7 +256,13 @@ def main():
                               "algorithmic_GBps": round(BYTES_MIXED * npts * 5 * args.steps / rm["wall_s"] / 1e9, 1)}
         except Exception as e:  # the path reports its own error; the FP64 line stands
             extra["mixed"] = {"error": str(e)[:200]}
+        try:
+            extra["adjoint"] = time_adjoint()
+        except Exception as e:
+            extra["adjoint"] = {"error": str(e)[:200]}
         out["extra"] = extra
+    if args.large:
+        out.setdefault("extra", {})["large"] = time_large(args.large_steps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case)

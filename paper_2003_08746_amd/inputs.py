@@ -205,3 +205,58 @@ def periodic_case(ni, nj, nk, xyz, Q, **prm) -> dict:
 def interior(a: np.ndarray) -> np.ndarray:
     """Interior view (nf, nk, nj, ni) of a padded array."""
     return a[..., 2:-2, 2:-2, 2:-2]
+
+
+# ---------------------------------------------------------------------------
+# Device-side generator for large shards (same formulas, torch on the GPU;
+# the random perturbations come from torch's device generator, so they differ
+# from the numpy stream of jet_state).  Used for sizes whose host arrays
+# would dominate the run time (e.g. 800 x 500 x 500).
+# ---------------------------------------------------------------------------
+def jet_case_device(ni, nj, nk, seed=0, device="cuda", Lx=None, Ly=10.0, Lz=None, m=2, amp=0.2, mach=1.4,
+                    R=0.5, theta=0.05, pert=0.01):
+    import torch
+    Lx = 7.5 * ni / 256 if Lx is None else Lx
+    Lz = 2.5 * nk / 128 if Lz is None else Lz
+    f64 = dict(dtype=torch.float64, device=device)
+    I_ = torch.arange(-2, ni + 2, **f64).view(1, 1, -1)
+    J_ = torch.arange(-2, nj + 2, **f64).view(1, -1, 1)
+    K_ = torch.arange(-2, nk + 2, **f64).view(-1, 1, 1)
+    t = -1.0 + 2.0 * J_ / (nj - 1)
+
+    def cl(x, a=0.8, w=0.05, tR=0.55):
+        lc = lambda z: torch.logaddexp(z, -z) - math.log(2.0)
+        return x - a * (w / 2.0) * (lc((x + tR) / w) - lc((x - tR) / w))
+    Y1 = float(cl(torch.tensor([1.0], **f64))[0])
+    Y = (Ly / 2.0) * cl(t) / Y1
+    tin = -1.0 + 2.0 * torch.arange(nj, **f64) / (nj - 1)
+    dY = float(torch.diff((Ly / 2.0) * cl(tin) / Y1).min())
+    W = torch.sin(2 * math.pi * m * I_ / ni) * torch.sin(2 * math.pi * m * K_ / nk) * torch.cos(math.pi * t)
+    shape = (nk + 4, nj + 4, ni + 4)
+    xyz = torch.empty((3,) + shape, **f64)
+    xyz[0] = (Lx * I_ / ni + amp * (Lx / ni) * W).expand(shape)
+    xyz[1] = (Y + amp * dY * W).expand(shape)
+    xyz[2] = (Lz * K_ / nk + amp * (Lz / nk) * W).expand(shape)
+    y = xyz[1]
+    u = 0.5 * mach * (torch.tanh((R + y) / (2 * theta)) + torch.tanh((R - y) / (2 * theta)))
+    s_ = u / mach
+    T = 1.0 + 0.5 * (GAMMA - 1.0) * mach * mach * s_ * (1.0 - s_)
+    p = torch.full_like(u, 1.0 / GAMMA)
+    rho = p / ((1.0 / GAMMA) * T)
+    env = 4.0 * s_ * (1.0 - s_)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    vel = [u, torch.zeros_like(u), torch.zeros_like(u)]
+    inner = (slice(2, nk + 2), slice(2, nj + 2), slice(2, ni + 2))
+    for c in range(3):
+        r = torch.rand((nk, nj, ni), generator=g, **f64) * 2.0 - 1.0
+        vel[c][inner] += pert * mach * r * env[inner]
+        del r
+    Q = torch.empty((5,) + shape, **f64)
+    Q[0] = rho
+    Q[1] = rho * vel[0]
+    Q[2] = rho * vel[1]
+    Q[3] = rho * vel[2]
+    Q[4] = p / (GAMMA - 1.0) + 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2)
+    return dict(name=f"jet{ni}x{nj}x{nk}", ni=ni, nj=nj, nk=nk, bc=(0, 1, 0), xyz=xyz, Q=Q, params=flow_params(),
+                p_inf=1.0 / GAMMA, period=(Lx, None, Lz))
