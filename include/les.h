@@ -148,8 +148,9 @@ int les_set_forcing(les_ctx *ctx, const double *f, int i_f);
  *   Q^(0) = Q^n;  Q^(l) = Q^(0) - alpha_l dt R(Q^(l-1)),  l = 1..5,
  *   alpha = (1/4, 1/6, 3/8, 1/2, 1);  Q^{n+1} = Q^(5),
  * with the ghost layers refreshed before every residual evaluation.
- * Q: device, library layout, FP64, in/out (interior updated in place; its
- *    periodic ghosts hold the wrap of Q^n on return).
+ * Q: device, library layout, FP64, 16-byte aligned (LES_ERR_ARG otherwise),
+ *    in/out (interior updated in place; its periodic ghosts hold the wrap of
+ *    Q^n on return).
  * dt > 0: used as is; dt <= 0: the CFL time step of Q^n (computed on the
  *    device; no host round trip unless dt_out is given).
  * dt_out: host or NULL.  norms: host double[10] or NULL, norms of R(Q^n).

@@ -204,6 +204,7 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
   P.k4 = prm->k4;
   P.alpha = prm->alpha;
   P.alpha_half = prm->alpha == 0.5;
+  P.gamma_R = prm->gamma * prm->R_gas;
   P.cfl = prm->cfl;
   P.nu_fac = fmax(4.0 / 3.0, prm->gamma / prm->Pr);
   P.sgs = prm->sgs;
@@ -334,6 +335,7 @@ int les_set_forcing(les_ctx* ctx, const double* f, int i_f) {
 int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norms, double* stage_ckpt) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_rk_step: null context");
   if (!Q) return fail(ctx, LES_ERR_ARG, "les_rk_step: Q is NULL");
+  if (((uintptr_t)Q) & 15) return fail(ctx, LES_ERR_ARG, "les_rk_step: Q must be 16-byte aligned");
   if (dt != dt) return fail(ctx, LES_ERR_ARG, "les_rk_step: dt is NaN");
   if (stage_ckpt && ctx->prec != LES_FP64)
     return fail(ctx, LES_ERR_STATE, "les_rk_step: stage checkpoints need an FP64 context");

@@ -8,7 +8,7 @@
 namespace les {
 
 constexpr int GH = 2;    // ghost layers per side (Sec. 4, Fig. 3)
-constexpr int LEAD = 8;  // element offset of interior i = 0 inside a row (64 B)
+constexpr int LEAD = 9;  // element offset of interior i = 0 inside a row (node i = -1 at 64 B)
 
 // Library layout of one field (see include/les.h).
 struct Layout {
@@ -50,6 +50,7 @@ struct Phys {
   double cfl, nu_fac;  // nu_fac = max(4/3, gamma/Pr)
   int sgs;
   int alpha_half;  // alpha == 1/2: Lam_d = lam_d + sqrt(lam_d)(sqrt(lam_e) + sqrt(lam_f))
+  double gamma_R;  // gamma * R (c^2 = gamma R T)
 };
 
 // Runge-Kutta coefficients of the five-stage scheme.
@@ -92,6 +93,74 @@ __device__ __forceinline__ T aniso(T ld, T le, T lf, const Phys& P) {
 
 template <class T>
 __device__ __forceinline__ T tmax(T a, T b) { return a >= b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Short reciprocal / square-root sequences for the stage kernel: the
+// hardware approximation refined by Newton steps, without the scaling and
+// special-value handling of the IEEE sequences.  Valid for finite, normal,
+// positive arguments (rcp: nonzero); the result is within a few ulp.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+// sqrt(x), x > 0: y ~ 1/sqrt(x) refined once (y += y (1 - x y^2) / 2), then
+// s = x y corrected once (s += (x - s^2) y / 2).
+__device__ __forceinline__ double sqrt_pos(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hy = 0.5 * y;
+  y = fma(hy, fma(-x * y, y, 1.0), y);
+  double s = x * y;
+  return fma(0.5 * y, fma(-s, s, x), s);
+}
+__device__ __forceinline__ float sqrt_pos(float x) { return __builtin_amdgcn_sqrtf(x); }
+// sqrt(x) for x >= 0 (0 at 0)
+template <class T>
+__device__ __forceinline__ T sqrt_nn(T x) { return x > T(0) ? sqrt_pos(x) : T(0); }
+
+// J^(-1/3), J > 0: single-precision seed 2^(-log2(J)/3), then two Newton
+// steps y += y (1 - J y^3) / 3 (each squares the relative error).
+__device__ __forceinline__ double icbrt(double J) {
+  const float jf = (float)J;
+  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(jf) * (-1.0f / 3.0f));
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-J * y, y * y, 1.0);
+    y = fma(y * (1.0 / 3.0), e, y);
+  }
+  return y;
+}
+__device__ __forceinline__ float icbrt(float J) {
+  float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(J) * (-1.0f / 3.0f));
+  const float e = fmaf(-J * y, y * y, 1.0f);
+  return fmaf(y * (1.0f / 3.0f), e, y);
+}
+
+// Primitive variables (as prim_from_q) with the short reciprocal.
+template <class T>
+__device__ __forceinline__ void prim_from_q_fast(T q0, T q1, T q2, T q3, T q4, const Phys& P, T& u, T& v, T& w,
+                                                 T& p, T& tem) {
+  T ir = rcp_nr(q0);
+  u = q1 * ir;
+  v = q2 * ir;
+  w = q3 * ir;
+  p = T(P.gm1) * (q4 - T(0.5) * q0 * (u * u + v * v + w * w));
+  tem = p * ir * T(P.inv_R);
+}
+
+// Sutherland's law (as sutherland) with the short sequences.
+template <class T>
+__device__ __forceinline__ T sutherland_fast(T tem, const Phys& P) {
+  T th = tem * T(P.inv_Tref);
+  return T(P.mu_ref * P.one_plus_S) * th * sqrt_pos(th) * rcp_nr(th + T(P.S));
+}
 
 // ---------------------------------------------------------------------------
 // Wavefront / block reductions (64-lane wavefronts).

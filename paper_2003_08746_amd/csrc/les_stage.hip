@@ -26,11 +26,16 @@
 //   E  face:  tile nodes difference the node fluxes, build the four in-plane
 //             dissipation faces from LDS and the zeta face from registers,
 //             and finish the residual and stage update of the plane below.
-// Memory latency is taken off the critical path: right after phase C the
-// block issues the metrics of the next plane as asynchronous global->LDS
-// copies (global_load_lds), the helper ring of the next plane and
-// Q^(0) of the plane being finished; they land while phase E (and the next
-// phase B) compute.
+// Memory.  Wave w owns patch rows 2w and 2w+1.  The ten metric fields and
+// Q^(0) of those rows are wave-private, so they travel as asynchronous
+// global->LDS copies (16 bytes per lane) into per-wave LDS blocks with no
+// barrier: the next plane's metrics are issued in phase C right after the
+// wave has read the current ones, and Q^(0) of the plane being finished is
+// issued in phase B; both land while the wave computes.  The flow constants
+// are read from the kernel-argument segment where they are used, instead of
+// occupying scalar registers across the loop.  Divisions and square roots
+// use short Newton-refined sequences (valid for the positive, normal
+// arguments met here).
 //
 // Work per thread is independent of the floating-point type T (double for
 // the FP64 path, float for the mixed path); metrics, Q^(0), the stage
@@ -49,7 +54,6 @@ constexpr int TX = BX - 2, TY = BY - 2;        // output tile
 constexpr int EX = BX + 2, EY = BY + 2;        // patch + axis halo (LDS planes)
 constexpr int NH2 = 2 * TY + 2 * TX;           // second-ring helper nodes
 constexpr int NW = NT / 64;                    // waves per block
-constexpr int MROWS = 10 * BY;                 // metric rows per plane (fields x rows)
 
 struct KArgs {
   Layout L;
@@ -123,43 +127,55 @@ __device__ __forceinline__ void norm_accumulate(const double s2[5], const double
   }
 }
 
-// Asynchronous copy of the ten metric fields of one plane of the patch into
-// LDS (mb[field][row][col] = M at node (i0-1+col, j0-1+row)).  Each wave
-// instruction moves one patch row of one field: 64 lanes x 4 bytes; lane l
-// copies half (l & 1) of column l >> 1, at byte offset lane_off from node
-// i0-1 of the row.  Rows or columns past the last needed node (ragged tiles) read a
-// clamped node.
-__device__ __forceinline__ void dma_metrics(const double* __restrict__ M, const Layout& L, int i0, int j0, int t,
-                                            double (*mb)[BY][BX], int wave, unsigned lane_off) {
-#pragma unroll 1
-  for (int r = 0; r < MROWS / NW; ++r) {
-    const int g = wave * (MROWS / NW) + r;  // field-row index handled by this instruction (uniform)
-    const int fld = g / BY, row = g % BY;
-    const int jc = min(j0 - 1 + row, L.nj);
-    // uniform base of (field, node (i0-1, jc, t)) plus the lane's byte offset
-    // (lane_off >= 0: columns are counted from i0-1)
-    const char* base =
-        (const char*)(M + fld * L.fe + (long long)(i0 - 1) + (long long)jc * L.sj + (long long)t * L.sk + L.o);
-    __builtin_amdgcn_global_load_lds((const void*)(base + lane_off),
-                                     (__attribute__((address_space(3))) void*)&mb[fld][row][0], 4, 0, 0);
+// Per-wave row staging.  Wave w owns patch rows 2w and 2w+1 (the rows of its
+// own threads), so the metrics and Q^(0) of those rows can be copied into a
+// wave-private LDS block with no barrier.  One asynchronous global->LDS copy
+// moves 16 bytes (two doubles) per lane: lanes 0-15 the 32 columns of field f
+// row 2w, lanes 16-31 field f row 2w+1, lanes 32-63 the same for field f+1;
+// they land contiguously at [f][r][col] of the block.  src is the lane's
+// byte address for field (lane >> 5); fstep2 is two fields in bytes.  With
+// an odd field count the last copy uses lanes 0-31 only.
+template <int NF>
+__device__ __forceinline__ void dma_rows(const char* src, long long fstep2, double* dst, int lane) {
+#pragma unroll
+  for (int q = 0; q < NF / 2; ++q)
+    __builtin_amdgcn_global_load_lds((const void*)(src + q * fstep2),
+                                     (__attribute__((address_space(3))) void*)(dst + q * 128), 16, 0, 0);
+  if (NF & 1) {
+    if (lane < 32)
+      __builtin_amdgcn_global_load_lds((const void*)(src + (NF / 2) * fstep2),
+                                       (__attribute__((address_space(3))) void*)(dst + (NF / 2) * 128), 16, 0, 0);
   }
 }
 
-// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left unconstrained)
-__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// s_waitcnt vmcnt(N): all but the N most recent vector memory operations of
+// this wave have completed (expcnt and lgkmcnt left unconstrained)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+// s_waitcnt lgkmcnt(0): this wave's LDS reads have returned
+__device__ __forceinline__ void wait_lgkm_all() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 template <class T, class QI, bool NORM>
 __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qin, const double* Q0, double* Qout,
                                               float* Qsh, const double* __restrict__ dtp, double dt_host,
                                               double alpha, double* __restrict__ part) {
   // the FP32 path has the registers to prefetch the helper ring one plane
-  // ahead; the FP64 path loads it at phase B
+  // ahead; the FP64 path loads it at phase B (holding it would spill)
   constexpr bool kPrefetchRing = sizeof(T) == 4;
   __shared__ Smem<T> s;
-  __shared__ double mb[10][BY][BX];  // metrics of the current plane (LDS DMA target)
-  __shared__ double red[NW][10];     // per-wave norm partials (NORM only)
+  __shared__ double mbw[NW][10][2][BX];  // per-wave metrics rows of the current plane
+  __shared__ double q0w[NW][5][2][BX];   // per-wave Q^(0) rows of the plane being finished
+  __shared__ double red[NW][10];         // per-wave norm partials (NORM only)
   const Layout& L = a.L;
-  const Phys& P = a.P;
+  // a (the first kernel argument) sits at the start of the kernel-argument
+  // segment; the loop re-reads the flow constants through this pointer
+  // (scalar loads) where they are used, so that they do not hold scalar
+  // registers across the loop
+  typedef __attribute__((address_space(4))) const KArgs CKArgs;
+  CKArgs* const ka = (CKArgs*)__builtin_amdgcn_kernarg_segment_ptr();
   const long long fe = L.fe;
 
   // XCD-aware order: consecutive virtual blocks land on one XCD.
@@ -173,6 +189,8 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
   const int tx = tid % BX, ty = tid / BX;
   const int ex = tx + 1, ey = ty + 1;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int fsel = lane >> 5, rsel = (lane >> 4) & 1, pr = lane & 15;  // row-copy lane geometry
+  const int ty1 = ty & 1;                                             // own row within the wave's pair
   const bool xh = (tx == 0 || tx == BX - 1), yh = (ty == 0 || ty == BY - 1);
   if (NORM && tid < NW * 10) red[tid / 10][tid % 10] = 0.0;
   const unsigned sk = (unsigned)L.sk;
@@ -188,9 +206,9 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
     else { hy2 = EY - 1; hx2 = 2 + h - 2 * TY - TX; }
   }
 
-  auto prims = [&](const T q[5], T uu[4], T& pp) {
+  auto prims = [&](const Phys& P, const T q[5], T uu[4], T& pp) {
     T u, vv, w, p, tem;
-    prim_from_q(q[0], q[1], q[2], q[3], q[4], P, u, vv, w, p, tem);
+    prim_from_q_fast(q[0], q[1], q[2], q[3], q[4], P, u, vv, w, p, tem);
     uu[0] = u; uu[1] = vv; uu[2] = w; uu[3] = tem;
     pp = p;
   };
@@ -230,22 +248,37 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
 #pragma unroll
     for (int c = 0; c < 4; ++c) um1[c] = up1[c] = T(0);
 
-    // prime for t = kb-1: metrics(kb-1) -> LDS; Q(kb-2), Q(kb-1), Q(kb) of
-    // the own column; helper Q(kb-1)
-    // byte offset of this lane's metric half-word from node i0-1 of a row;
-    // columns past i = ni (ragged last tile) re-read column ni
-    const unsigned lane_off = (unsigned)((min(i0 - 1 + (lane >> 1), L.ni) - (i0 - 1)) * 8 + (lane & 1) * 4);
-    dma_metrics(a.M, L, i0, j0, kb - 1, mb, wave, lane_off);
+    // (the empty asm hides the pointer's origin, so the loads below are not
+    // hoisted out of the loop)
+    CKArgs* kp4 = ka;
+    asm volatile("" : "+s"(kp4));
+    const KArgs* kp = (const KArgs*)kp4;
+    // prime for t = kb-1: metrics(kb-1) -> LDS; Q(kb-2), Q(kb-1) of the own
+    // column; helper Q(kb-1)
+    //
+    // element offset (plane 0) of this lane's row copy: field fsel, row
+    // 2 wave + rsel, column pair starting at i0-1+2pr (16-byte aligned);
+    // pairs past i = ni (ragged last tile) re-read the last pair within the row
+    int icp = i0 - 1 + 2 * pr;
+    if (icp > L.ni) icp = L.ni - ((LEAD + L.ni) & 1);
+    const int jcp = min(j0 - 1 + 2 * wave + rsel, L.nj);
+    const long long lane_el = (long long)fsel * fe + L.o + icp + (long long)jcp * L.sj;
+    const long long fstep2 = 2 * fe * (long long)sizeof(double);
+    dma_rows<10>((const char*)(kp->M + lane_el + (long long)(kb - 1) * L.sk), fstep2, &mbw[wave][0][0][0], lane);
     if (load_ok) {
       load_q<T>(Qin, fe, col + (unsigned)(kb - 2) * sk, qm1);
       load_q<T>(Qin, fe, col + (unsigned)(kb - 1) * sk, qw);
-      prims(qm1, um1, pm1);
-      prims(qw, up1, pp1);  // plane kb-1, written at the first B
+      prims(kp->P, qm1, um1, pm1);
+      prims(kp->P, qw, up1, pp1);  // plane kb-1, written at the first B
     }
     if (kPrefetchRing && h_ok) load_q<T>(Qin, fe, hcol + (unsigned)(kb - 1) * sk, hq);
 
     for (int t = kb - 1; t <= ke; ++t) {
       const unsigned nt = col + (unsigned)t * sk;
+      CKArgs* kq4 = ka;
+      asm volatile("" : "+s"(kq4));
+      const KArgs* kq = (const KArgs*)kq4;
+      const Phys& P = kq->P;
       // the first and last plane of a segment only provide zeta quantities
       // of the tile columns; their in-plane fluxes and residual are not needed
       const bool inner = t >= kb && t < ke;
@@ -263,25 +296,37 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
       if (h_ok) {
         T hu[4], hp;
         if (!kPrefetchRing) load_q<T>(Qin, fe, hcol + (unsigned)t * sk, hq);
-        prims(hq, hu, hp);
+        prims(P, hq, hu, hp);
 #pragma unroll
         for (int c = 0; c < 5; ++c) s.q[c][hy2][hx2] = hq[c];
         s.p[hy2][hx2] = hp;
         s.u[hy2][hx2] = hu[0]; s.v[hy2][hx2] = hu[1]; s.w[hy2][hx2] = hu[2]; s.tem[hy2][hx2] = hu[3];
       }
-      wait_vm_all();  // this wave's metric copies, helper ring and plane t+1 have landed
+      // Q^(0) rows of the plane finished in this iteration (t-1), needed in E
+      if (t > kb) {
+        dma_rows<5>((const char*)(Q0 + lane_el + (long long)(t - 1) * L.sk), fstep2, &q0w[wave][0][0][0], lane);
+        wait_vm<3>();  // all but the three Q^(0) copies: metrics, helper ring, plane t+1
+      } else {
+        wait_vm<0>();
+      }
       __syncthreads();
 
       // ---- C: node work at plane t ----
-      if (load_ok) prims(qa, up1, pp1);  // plane t+1 of the own column
+      if (load_ok) prims(P, qa, up1, pp1);  // plane t+1 of the own column
       T hz[5] = {0, 0, 0, 0, 0};
       T lz = 0, nz = 0;
       double Jn = 0.0;
-      if (node_t) {
-        Jn = mb[9][ty][tx];
-        T mt[9];
+      T mt[9];
+      Jn = mbw[wave][9][ty1][tx];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) mt[c] = (T)mb[c][ty][tx];
+      for (int c = 0; c < 9; ++c) mt[c] = (T)mbw[wave][c][ty1][tx];
+      wait_lgkm_all();  // the wave's metric reads are done before its copies overwrite them
+      // issue the next plane's loads now so that they land during C and E:
+      // helper ring (FP32 path), then the wave's metric rows (five copies)
+      if (kPrefetchRing && h_ok && t < ke) load_q<T>(Qin, fe, hcol + (unsigned)(t + 1) * sk, hq);
+      if (t < ke)
+        dma_rows<10>((const char*)(kq->M + lane_el + (long long)(t + 1) * L.sk), fstep2, &mbw[wave][0][0][0], lane);
+      if (node_t) {
         const T Jt = (T)Jn;
         T g[4][3];
         {
@@ -300,16 +345,17 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
         const T s12 = T(0.5) * (g[0][1] + g[1][0]);
         const T s13 = T(0.5) * (g[0][2] + g[2][0]);
         const T s23 = T(0.5) * (g[1][2] + g[2][1]);
-        const T skk3 = (s11 + s22 + s33) / T(3);
+        const T skk3 = (s11 + s22 + s33) * T(1.0 / 3.0);
         const T rho = s.q[0][ey][ex];
         const T u = s.u[ey][ex], vv = s.v[ey][ex], w = s.w[ey][ex];
-        const T mu = sutherland(s.tem[ey][ex], P);
+        const T tn = s.tem[ey][ex];
+        const T mu = sutherland_fast(tn, P);
         T mus = T(0);
         if (P.sgs) {
           const T ss = s11 * s11 + s22 * s22 + s33 * s33 + T(2) * (s12 * s12 + s13 * s13 + s23 * s23);
-          T d2 = (T)cbrt(1.0 / Jn);
+          T d2 = (T)icbrt(Jn);  // (1/J)^(1/3)
           d2 *= d2;
-          mus = rho * T(P.Cs2) * d2 * sqrt(T(2) * ss);
+          mus = rho * T(P.Cs2) * d2 * sqrt_nn(T(2) * ss);
         }
         const T mt2 = T(2) * (mu + mus);
         const T t11 = mt2 * (s11 - skk3), t22 = mt2 * (s22 - skk3), t33 = mt2 * (s33 - skk3);
@@ -319,15 +365,21 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
         const T th1 = u * t12 + vv * t22 + w * t23 + kap * g[3][1];
         const T th2 = u * t13 + vv * t23 + w * t33 + kap * g[3][2];
         const T p = s.p[ey][ex];
-        const T c = sqrt(T(P.gamma) * p / rho);
-        // spectral radii of the three directions
-        T lam[3], U[3];
+        const T c2 = T(P.gamma_R) * tn;  // c^2 = gamma p / rho = gamma R T
+        // spectral radii of the three directions and their square roots
+        T lam[3], U[3], sl[3];
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
           const T mx = mt[3 * e], my = mt[3 * e + 1], mz = mt[3 * e + 2];
           U[e] = mx * u + my * vv + mz * w;
-          lam[e] = fabs(U[e]) + c * sqrt(mx * mx + my * my + mz * mz);
+          lam[e] = fabs(U[e]) + sqrt_pos(c2 * (mx * mx + my * my + mz * mz));
+          sl[e] = sqrt_pos(lam[e]);
         }
+        // anisotropic scaling Lam_d = lam_d [1 + sum_e (lam_e / lam_d)^alpha]
+        auto aniso_n = [&](int d, int e, int f) -> T {
+          if (P.alpha_half) return lam[d] + sl[d] * (sl[e] + sl[f]);
+          return aniso(lam[d], lam[e], lam[f], P);
+        };
         auto node_flux = [&](int e, T H[5]) {
           const T mx = mt[3 * e], my = mt[3 * e + 1], mz = mt[3 * e + 2];
           const T Ue = U[e];
@@ -342,34 +394,34 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           node_flux(0, H);
 #pragma unroll
           for (int q = 0; q < 5; ++q) s.hx[q][ty - 1][tx] = H[q];
-          s.lx[ty - 1][tx] = aniso(lam[0], lam[1], lam[2], P);
+          s.lx[ty - 1][tx] = aniso_n(0, 1, 2);
           const T pa = s.p[ey][ex + 1], pb = s.p[ey][ex - 1];
-          s.nx[ty - 1][tx] = fabs(pa - T(2) * p + pb) / (pa + T(2) * p + pb);
+          s.nx[ty - 1][tx] = fabs(pa - T(2) * p + pb) * rcp_nr(pa + T(2) * p + pb);
         }
         if (ny_t) {
           T H[5];
           node_flux(1, H);
 #pragma unroll
           for (int q = 0; q < 5; ++q) s.hy[q][ty][tx - 1] = H[q];
-          s.ly[ty][tx - 1] = aniso(lam[1], lam[2], lam[0], P);
+          s.ly[ty][tx - 1] = aniso_n(1, 2, 0);
           const T pa = s.p[ey + 1][ex], pb = s.p[ey - 1][ex];
-          s.ny[ty][tx - 1] = fabs(pa - T(2) * p + pb) / (pa + T(2) * p + pb);
+          s.ny[ty][tx - 1] = fabs(pa - T(2) * p + pb) * rcp_nr(pa + T(2) * p + pb);
         }
         if (out_ok) {
           node_flux(2, hz);
-          lz = aniso(lam[2], lam[0], lam[1], P);
-          nz = fabs(pp1 - T(2) * p + pm1) / (pp1 + T(2) * p + pm1);
+          lz = aniso_n(2, 0, 1);
+          nz = fabs(pp1 - T(2) * p + pm1) * rcp_nr(pp1 + T(2) * p + pm1);
         }
       }
       __syncthreads();
 
-      // ---- prefetch for the next plane (lands during E and the next B) ----
-      if (t < ke) dma_metrics(a.M, L, i0, j0, t + 1, mb, wave, lane_off);
-      if (kPrefetchRing && h_ok && t < ke) load_q<T>(Qin, fe, hcol + (unsigned)(t + 1) * sk, hq);
       double q0v[5] = {0, 0, 0, 0, 0};
-      if (out_ok && t > kb) {
+      if (t > kb) {
+        // Q^(0) copies (issued at B) are older than the metric copies of this plane
+        if (t < ke) wait_vm<5>();
+        else wait_vm<0>();
 #pragma unroll
-        for (int c = 0; c < 5; ++c) q0v[c] = ldo(Q0 + c * fe, nt - sk);
+        for (int c = 0; c < 5; ++c) q0v[c] = q0w[wave][c][ty1][tx];
       }
 
       // ---- E: residual (tile nodes) ----
@@ -419,7 +471,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
               double R = J_prev * (double)(racc[c] + fz[c]);
-              if (a.f && i == a.i_f) R -= a.f[((long long)c * L.nk + k) * L.nj + j];
+              if (kq->f && i == kq->i_f) R -= kq->f[((long long)c * kq->L.nk + k) * kq->L.nj + j];
               const double qn = q0v[c] - adt * R;
               if (Qout) sto(Qout + c * fe, n, qn);
               if (Qsh) sto(Qsh + c * fe, n, (float)qn);

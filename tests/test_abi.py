@@ -28,9 +28,12 @@ def test_header_symbols_exported():
 
 def test_layout_for():
     st, o, fe = lesmi.les_layout_for(256, 128, 128)
-    assert st[0] == 1 and st[1] % 16 == 0 and st[1] >= 8 + 256 + 2
+    assert st[0] == 1 and st[1] % 16 == 0 and st[1] >= 9 + 256 + 2
     assert st[2] == st[1] * (128 + 4)
-    assert o == 8 + 2 * st[1] + 2 * st[2]
+    # interior i = 0 sits 9 elements into a row, so node i = -1 (the first
+    # node a stage-kernel tile copies) starts on a 64-byte boundary
+    assert o == 9 + 2 * st[1] + 2 * st[2]
+    assert (o - 1) % 8 == 0
     assert fe >= st[2] * (128 + 4) and fe % 32 == 0
     # every node of the padded box lies inside [0, fe)
     assert o - 2 - 2 * st[1] - 2 * st[2] >= 0

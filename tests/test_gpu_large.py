@@ -97,6 +97,7 @@ def test_large_shard_fp64_windows(orc, lesmi, shard):
     _, norms = s.rk_step(Q, DT, want_norms=True)
     torch.cuda.synchronize()
     Qv = s.view(Q)
+    res = []
     for (win, idx, core), st in zip(wins, starts):
         m = orc.metrics(win)
         # global CFL minimum <= this window's minimum; global max|R| >= this window's
@@ -107,16 +108,16 @@ def test_large_shard_fp64_windows(orc, lesmi, shard):
         R = I.interior(orc.residual(win, m, win["Q"]))
         assert (norms[5:] >= np.abs(R).reshape(5, -1).max(1) * (1 - 1e-12)).all(), (st, norms[5:])
         Qo, _, _, _ = orc.rk_step(win, m, win["Q"], dt=DT)
-        Qg = _gather(Qv, *idx)
-        a, b, q0 = Qg[core], Qo[core], win["Q"][core]
+        res.append((st, _gather(Qv, *idx)[core], Qo[core], win["Q"][core]))
+    # the increment Q^{n+1} - Q^n is measured against its largest value over
+    # all windows (oracle side; the shear-layer windows set it): inside the
+    # jet core the residual nearly cancels, and its own scale would only
+    # magnify rounding
+    inc_scale = np.max([np.abs(b - q0).reshape(5, -1).max(1) for _, _, b, q0 in res], axis=0)
+    for st, a, b, q0 in res:
         err = _err(a, b, scale)
-        # the increment Q^{n+1} - Q^n against its own scale, for fields whose
-        # increment is resolved (in the far field at rest it is rounding only)
-        inc_scale = np.abs(b - q0).reshape(5, -1).max(1)
-        resolved = inc_scale > 1e-8 * scale
-        inc = np.where(resolved, _err(a - q0, b - q0, np.where(resolved, inc_scale, 1.0)), 0.0)
-        print(f"[gpu] window {st}: core {a.shape[1:]} rel {err.max():.2e} increment {inc.max():.2e} "
-              f"(resolved {resolved.astype(int)})", flush=True)
+        inc = _err(a - q0, b - q0, inc_scale)
+        print(f"[gpu] window {st}: core {a.shape[1:]} rel {err.max():.2e} increment {inc.max():.2e}", flush=True)
         assert (err <= TOL).all(), (st, err)
         assert (inc <= 1e-9).all(), (st, inc)
     s.close()

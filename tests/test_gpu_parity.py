@@ -235,4 +235,8 @@ def test_argument_errors(lesmi):
     with pytest.raises(lesmi.LesError) as e:
         lesmi.les_rk_step(s.ctx, Q.data_ptr(), float("nan"))
     assert e.value.code == lesmi.LES_ERR_ARG
+    # the state must be 16-byte aligned (checked before any kernel is launched)
+    with pytest.raises(lesmi.LesError) as e:
+        lesmi.les_rk_step(s.ctx, Q.data_ptr() + 8, 1e-3)
+    assert e.value.code == lesmi.LES_ERR_ARG
     s.close()
