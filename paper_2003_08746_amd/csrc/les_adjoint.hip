@@ -57,7 +57,7 @@ struct Prim {
 __device__ __forceinline__ Prim prim_at(const double* __restrict__ Q, long long fe, long long n, const Phys& P) {
   Prim r;
   r.rho = Q[n];
-  prim_from_q(r.rho, Q[fe + n], Q[2 * fe + n], Q[3 * fe + n], Q[4 * fe + n], P, r.u, r.v, r.w, r.p, r.T);
+  prim_from_q_fast(r.rho, Q[fe + n], Q[2 * fe + n], Q[3 * fe + n], Q[4 * fe + n], P, r.u, r.v, r.w, r.p, r.T);
   return r;
 }
 
@@ -101,11 +101,11 @@ struct Radii {
 __device__ __forceinline__ Radii radii_at(const double* __restrict__ M, long long fe, long long n, const Prim& q,
                                           const Phys& P) {
   Radii r;
-  r.c = sqrt(P.gamma * q.p / q.rho);
+  r.c = sqrt_pos(P.gamma_R * q.T);  // c^2 = gamma p / rho = gamma R T
   for (int e = 0; e < 3; ++e) {
     const double mx = M[(3 * e) * fe + n], my = M[(3 * e + 1) * fe + n], mz = M[(3 * e + 2) * fe + n];
     r.U[e] = mx * q.u + my * q.v + mz * q.w;
-    r.nrm[e] = sqrt(mx * mx + my * my + mz * mz);
+    r.nrm[e] = sqrt_pos(mx * mx + my * my + mz * mz);
     r.lam[e] = fabs(r.U[e]) + r.c * r.nrm[e];
   }
   return r;
@@ -114,6 +114,14 @@ __device__ __forceinline__ Radii radii_at(const double* __restrict__ M, long lon
 // Anisotropic scaling Lam_d and its partial derivatives w.r.t. (lam_d, lam_e, lam_f).
 __device__ __forceinline__ double aniso_d(double ld, double le, double lf, const Phys& P, double& dd, double& de,
                                           double& df) {
+  if (P.alpha_half) {
+    // Lam = ld + sqrt(ld) (sqrt(le) + sqrt(lf))
+    const double sd = sqrt_pos(ld), se = sqrt_pos(le), sf = sqrt_pos(lf);
+    dd = 1.0 + 0.5 * (se + sf) * rcp_nr(sd);
+    de = 0.5 * sd * rcp_nr(se);
+    df = 0.5 * sd * rcp_nr(sf);
+    return ld + sd * (se + sf);
+  }
   const double a = P.alpha;
   const double re = pow(le / ld, a), rf = pow(lf / ld, a);
   dd = 1.0 + (1.0 - a) * (re + rf);
@@ -126,7 +134,7 @@ __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.
 
 // Pressure sensor of direction d at node n (p at n-e, n, n+e).
 __device__ __forceinline__ double sensor(double pm, double p0, double pp) {
-  return fabs(pp - 2.0 * p0 + pm) / (pp + 2.0 * p0 + pm);
+  return fabs(pp - 2.0 * p0 + pm) * rcp_nr(pp + 2.0 * p0 + pm);
 }
 
 struct AdjK {
@@ -139,18 +147,19 @@ struct AdjK {
 // ---------------------------------------------------------------------------
 // Pass 1
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_adj_node(AdjK A, const double* __restrict__ Q, const double* __restrict__ qb,
+__global__ void __launch_bounds__(256, 2) k_adj_node(AdjK A, const double* __restrict__ Q, const double* __restrict__ qb,
                                                   double coef, double* __restrict__ Wk) {
   const Layout& L = A.L;
   const Phys& P = A.P;
   const long long fe = L.fe;
   const double* __restrict__ M = A.M;
-  const int ext_i = L.ni + 2, ext_j = L.nj + 2;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)ext_i * ext_j * (L.nk + 2)) return;
+  // (every box of nodes here has fewer than 2^29 nodes: 32-bit index math)
+  const unsigned ext_i = L.ni + 2, ext_j = L.nj + 2;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ext_i * ext_j * (unsigned)(L.nk + 2)) return;
   const int i = (int)(t % ext_i) - 1;
   const int j = (int)((t / ext_i) % ext_j) - 1;
-  const int k = (int)(t / ((long long)ext_i * ext_j)) - 1;
+  const int k = (int)(t / (ext_i * ext_j)) - 1;
   const long long n = L.at(i, j, k);
   const int id[3] = {i, j, k};
 
@@ -176,13 +185,14 @@ __global__ void __launch_bounds__(256) k_adj_node(AdjK A, const double* __restri
   }
   const double S11 = g[0][0], S22 = g[1][1], S33 = g[2][2];
   const double S12 = 0.5 * (g[0][1] + g[1][0]), S13 = 0.5 * (g[0][2] + g[2][0]), S23 = 0.5 * (g[1][2] + g[2][1]);
-  const double skk3 = (S11 + S22 + S33) / 3.0;
+  const double skk3 = (S11 + S22 + S33) * (1.0 / 3.0);
   const double th = q.T * P.inv_Tref;
-  const double mu = P.mu_ref * P.one_plus_S * th * sqrt(th) / (th + P.S);
+  const double ithS = rcp_nr(th + P.S);
+  const double mu = P.mu_ref * P.one_plus_S * th * sqrt_pos(th) * ithS;
   double mus = 0.0, Smag = 0.0, cd2 = 0.0;
   if (P.sgs) {
-    Smag = sqrt(2.0 * (S11 * S11 + S22 * S22 + S33 * S33 + 2.0 * (S12 * S12 + S13 * S13 + S23 * S23)));
-    double d2 = cbrt(1.0 / J);
+    Smag = sqrt_nn(2.0 * (S11 * S11 + S22 * S22 + S33 * S33 + 2.0 * (S12 * S12 + S13 * S13 + S23 * S23)));
+    double d2 = icbrt(J);  // (1/J)^(1/3)
     cd2 = P.Cs2 * d2 * d2;
     mus = q.rho * cd2 * Smag;
   }
@@ -253,7 +263,7 @@ __global__ void __launch_bounds__(256) k_adj_node(AdjK A, const double* __restri
   const double t12 = tb[0][1] + tb[1][0], t13 = tb[0][2] + tb[2][0], t23 = tb[1][2] + tb[2][1];
   const double mtb = 2.0 * ((S11 - skk3) * t11 + (S22 - skk3) * t22 + (S33 - skk3) * t33 + S12 * t12 + S13 * t13 +
                             S23 * t23);
-  const double tr = (t11 + t22 + t33) / 3.0;
+  const double tr = (t11 + t22 + t33) * (1.0 / 3.0);
   double Sb11 = mt2 * (t11 - tr), Sb22 = mt2 * (t22 - tr), Sb33 = mt2 * (t33 - tr);
   double Sb12 = mt2 * t12, Sb13 = mt2 * t13, Sb23 = mt2 * t23;
   // ---- viscosities ----
@@ -262,7 +272,7 @@ __global__ void __launch_bounds__(256) k_adj_node(AdjK A, const double* __restri
     const double musb = mtb + kapb * P.Cp_over_Prsgs;
     rb += musb * cd2 * Smag;
     if (Smag > 0.0) {
-      const double sb = musb * q.rho * cd2 / Smag;
+      const double sb = musb * q.rho * cd2 * rcp_nr(Smag);
       Sb11 += 2.0 * S11 * sb;
       Sb22 += 2.0 * S22 * sb;
       Sb33 += 2.0 * S33 * sb;
@@ -272,7 +282,7 @@ __global__ void __launch_bounds__(256) k_adj_node(AdjK A, const double* __restri
     }
   }
   // Sutherland: dmu/dT = mu (3/(2 th) - 1/(th + S)) / T_ref
-  Tb += mub * mu * (1.5 / th - 1.0 / (th + P.S)) * P.inv_Tref;
+  Tb += mub * mu * (1.5 * rcp_nr(th) - ithS) * P.inv_Tref;
   // ---- S from the velocity gradient ----
   gb[0][0] += Sb11;
   gb[1][1] += Sb22;
@@ -365,7 +375,8 @@ __global__ void __launch_bounds__(256) k_adj_node(AdjK A, const double* __restri
       // nu_d(n) = |Delta2| / Sigma with p(n-e), p(n), p(n+e)
       {
         const double D2 = qp.p - 2.0 * q.p + qm.p, Sg = qp.p + 2.0 * q.p + qm.p;
-        const double sd = sgn(D2) / Sg, sv = nu_0 / Sg;
+        const double iSg = rcp_nr(Sg);
+        const double sd = sgn(D2) * iSg, sv = nu_0 * iSg;
         pb += nub * (-2.0 * sd - 2.0 * sv);
         cpw = nub * (sd - sv);  // weight of p(n - e) and p(n + e)
       }
@@ -386,8 +397,9 @@ __global__ void __launch_bounds__(256) k_adj_node(AdjK A, const double* __restri
   }
   // c = sqrt(gamma p / rho)
   if (cb != 0.0) {
-    pb += cb * P.gamma / (2.0 * r0.c * q.rho);
-    rb -= cb * r0.c / (2.0 * q.rho);
+    const double ir2 = rcp_nr(2.0 * q.rho);
+    pb += cb * P.gamma * rcp_nr(r0.c) * ir2;
+    rb -= cb * r0.c * ir2;
   }
   Wk[W_PRHO * fe + n] = rb;
   Wk[W_PU * fe + n] = ub[0];
@@ -410,12 +422,12 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
   const Layout& L = A.L;
   const Phys& P = A.P;
   const long long fe = L.fe;
-  const int pi = L.ni + 4, pj = L.nj + 4;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)pi * pj * (L.nk + 4)) return;
+  const unsigned pi = L.ni + 4, pj = L.nj + 4;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= pi * pj * (unsigned)(L.nk + 4)) return;
   const int i = (int)(t % pi) - 2;
   const int j = (int)((t / pi) % pj) - 2;
-  const int k = (int)(t / ((long long)pi * pj)) - 2;
+  const int k = (int)(t / (pi * pj)) - 2;
   const long long n = L.at(i, j, k);
   const bool b1 = in_b1(L, i, j, k);
 
@@ -451,17 +463,18 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
   // the map, so unused ghost corners are never read)
   if (rb != 0.0 || ub[0] != 0.0 || ub[1] != 0.0 || ub[2] != 0.0 || pb != 0.0 || Tb != 0.0) {
   const Prim q = prim_at(Q, fe, n, P);
-  pb += Tb * P.inv_R / q.rho;
-  rb -= Tb * q.T / q.rho;
+  const double ir = rcp_nr(q.rho);
+  pb += Tb * P.inv_R * ir;
+  rb -= Tb * q.T * ir;
   out[4] += P.gm1 * pb;
   out[1] -= P.gm1 * q.u * pb;
   out[2] -= P.gm1 * q.v * pb;
   out[3] -= P.gm1 * q.w * pb;
   out[0] += P.gm1 * 0.5 * (q.u * q.u + q.v * q.v + q.w * q.w) * pb;
-  out[1] += ub[0] / q.rho;
-  out[2] += ub[1] / q.rho;
-  out[3] += ub[2] / q.rho;
-  out[0] -= (ub[0] * q.u + ub[1] * q.v + ub[2] * q.w) / q.rho;
+  out[1] += ub[0] * ir;
+  out[2] += ub[1] * ir;
+  out[3] += ub[2] * ir;
+  out[0] -= (ub[0] * q.u + ub[1] * q.v + ub[2] * q.w) * ir;
   out[0] += rb;
   }
   // dissipation faces whose five-point stencil contains this node:
@@ -496,11 +509,12 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
 __global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restrict__ G, const double* __restrict__ add,
                                                   double* __restrict__ qout) {
   const Layout& L = A.L;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)L.ni * L.nj * L.nk) return;
-  const int i = (int)(t % L.ni);
-  const int j = (int)((t / L.ni) % L.nj);
-  const int k = (int)(t / ((long long)L.ni * L.nj));
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
+  if (t >= nij * (unsigned)L.nk) return;
+  const int i = (int)(t % ni);
+  const int j = (int)((t % nij) / ni);
+  const int k = (int)(t / nij);
   const int bc[3] = {A.bc0, A.bc1, A.bc2};
   const int id[3] = {i, j, k};
   const int nn[3] = {L.ni, L.nj, L.nk};
@@ -526,11 +540,12 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restri
 // out = a + b on the interior (5 fields)
 // (out may alias a: each thread reads and writes only its own node)
 __global__ void __launch_bounds__(256) k_axpy_interior(Layout L, const double* a, const double* b, double* out) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)L.ni * L.nj * L.nk) return;
-  const int i = (int)(t % L.ni);
-  const int j = (int)((t / L.ni) % L.nj);
-  const int k = (int)(t / ((long long)L.ni * L.nj));
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
+  if (t >= nij * (unsigned)L.nk) return;
+  const int i = (int)(t % ni);
+  const int j = (int)((t % nij) / ni);
+  const int k = (int)(t / nij);
   const long long n = L.at(i, j, k);
   for (int c = 0; c < 5; ++c) out[c * L.fe + n] = a[c * L.fe + n] + (b ? b[c * L.fe + n] : 0.0);
 }
@@ -538,9 +553,9 @@ __global__ void __launch_bounds__(256) k_axpy_interior(Layout L, const double* a
 // fbar[c][k][j] += w * qbar_c(i_f, j, k)
 __global__ void __launch_bounds__(256) k_fbar(Layout L, int i_f, double w, const double* __restrict__ qb,
                                               double* __restrict__ fbar) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)L.nj * L.nk) return;
-  const int j = (int)(t % L.nj), k = (int)(t / L.nj);
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (unsigned)L.nj * L.nk) return;
+  const int j = (int)(t % (unsigned)L.nj), k = (int)(t / (unsigned)L.nj);
   const long long n = L.at(i_f, j, k);
   for (int c = 0; c < 5; ++c) fbar[((long long)c * L.nk + k) * L.nj + j] += w * qb[c * L.fe + n];
 }
