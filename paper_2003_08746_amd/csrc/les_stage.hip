@@ -25,7 +25,9 @@
 //             anisotropic spectral radii and the pressure sensors;
 //   E  face:  tile nodes difference the node fluxes, build the four in-plane
 //             dissipation faces from LDS and the zeta face from registers,
-//             and finish the residual and stage update of the plane below.
+//             and finish the residual and stage update of the plane below
+//             (stage 1 also accumulates R^2 and max |R| per thread; the
+//             block reduces them once, after its last plane).
 // Memory.  Wave w owns patch rows 2w and 2w+1.  The ten metric fields and
 // Q^(0) of those rows are wave-private, so they travel as asynchronous
 // global->LDS copies (16 bytes per lane) into per-wave LDS blocks with no
@@ -112,7 +114,7 @@ __device__ __forceinline__ void face_diss(const Phys& P, T La, T Lb, T na, T nb,
   }
 }
 
-// Per-wave reduction of one plane's R^2 sums and |R| maxima, accumulated in
+// Per-wave reduction of the threads' R^2 sums and |R| maxima, accumulated in
 // the wave's row of `red` (all lanes of the wave must call it).
 __device__ __forceinline__ void norm_accumulate(const double s2[5], const double sm[5], double (*red)[10], int tid) {
 #pragma unroll
@@ -213,6 +215,9 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
     pp = p;
   };
 
+  // residual norms: per-thread running sums of R^2 and maxima of |R| over
+  // all planes of the block (NORM only), reduced once at the end
+  double n2[5] = {0, 0, 0, 0, 0}, nm[5] = {0, 0, 0, 0, 0};
   for (long long wq = w_begin; wq < w_end;) {
     // ---- one segment: planes [kb, ke) of one tile ----
     const int tile = (int)(wq / L.nk);
@@ -425,7 +430,6 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
       }
 
       // ---- E: residual (tile nodes) ----
-      double s2[5] = {0, 0, 0, 0, 0}, sm[5] = {0, 0, 0, 0, 0};
       if (out_ok) {
         const int cx = tx - 1, cy = ty - 1;  // tile-local column / row
         T r[5] = {0, 0, 0, 0, 0};
@@ -476,8 +480,9 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
               if (Qout) sto(Qout + c * fe, n, qn);
               if (Qsh) sto(Qsh + c * fe, n, (float)qn);
               if (NORM) {
-                s2[c] = R * R;
-                sm[c] = fabs(R);
+                n2[c] += R * R;
+                const double a = fabs(R);
+                nm[c] = (a > nm[c] || a != a) ? a : nm[c];  // NaN wins so that it is reported
               }
             }
           }
@@ -493,7 +498,6 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
         nz_prev = nz;
         J_prev = Jn;
       }
-      if (NORM && t > kb) norm_accumulate(s2, sm, red, tid);
       // ---- shift the column queues (plane t values from LDS) ----
       if (load_ok) {
 #pragma unroll
@@ -509,6 +513,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
     }
   }
 
+  if (NORM) norm_accumulate(n2, nm, red, tid);
   // ---- block partial norms ----
   if (NORM) {
     __syncthreads();
