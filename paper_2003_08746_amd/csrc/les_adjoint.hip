@@ -44,10 +44,16 @@ enum {
   W_CP = 22,                                  // sensor weights for p(n +- e_d): 3 fields
   W_A2 = 25,                                  // Lambda eps2 of face (n, n+e_d): 3 fields
   W_A4 = 28,                                  // Lambda eps4 of face (n, n+e_d): 3 fields
-  W_G = 31,                                   // pass-2 output: Q adjoint per node, 5 fields
-  W_Q1 = 36,                                  // stage adjoint ping-pong: 5 + 5 fields
-  W_ACC = 46,                                 // accumulated adjoint of Q^(0): 5 fields
-  W_NF = 51
+  W_LAM = 31,                                 // Lambda_d at the node: 3 fields
+  W_NU = 34,                                  // pressure sensor nu_d at the node: 3 fields
+  W_G = 31,                                   // gather output: Q adjoint per node, 5 fields
+                                              // (reuses W_LAM / W_NU, dead by then)
+  W_LH = 37,                                  // half the face-mean adjoint of face (n, n+e_d): 3
+  W_NUA = 40,                                 // sensor adjoint of face (n, n+e_d) for node n: 3
+  W_NUB = 43,                                 // ... for node n + e_d: 3
+  W_Q1 = 46,                                  // stage adjoint ping-pong: 5 + 5 fields
+  W_ACC = 56,                                 // accumulated adjoint of Q^(0): 5 fields
+  W_NF = 61
 };
 
 struct Prim {
@@ -147,7 +153,7 @@ struct AdjK {
 // ---------------------------------------------------------------------------
 // Pass 1
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256, 2) k_adj_node(AdjK A, const double* __restrict__ Q, const double* __restrict__ qb,
+__global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restrict__ Q, const double* __restrict__ qb,
                                                   double coef, double* __restrict__ Wk) {
   const Layout& L = A.L;
   const Phys& P = A.P;
@@ -298,109 +304,6 @@ __global__ void __launch_bounds__(256, 2) k_adj_node(AdjK A, const double* __res
     for (int d = 0; d < 3; ++d)
       Wk[(W_A + 3 * qq + d) * fe + n] = J * (m[3 * d] * gb[qq][0] + m[3 * d + 1] * gb[qq][1] + m[3 * d + 2] * gb[qq][2]);
 
-  // ---- dissipation: the faces (n-e, n) and (n, n+e) of each direction ----
-  const Radii r0 = radii_at(M, fe, n, q, P);
-  double lamb[3] = {0, 0, 0};
-  for (int d = 0; d < 3; ++d) {
-    const long long s = dstr(L, d);
-    const int di = d == 0, dj = d == 1, dk = d == 2;
-    const bool f_lo = face_ok(L, d, i - di, j - dj, k - dk);  // face (n-e, n)
-    const bool f_hi = face_ok(L, d, i, j, k);                 // face (n, n+e)
-    double A2 = 0.0, A4 = 0.0, cpw = 0.0;
-    if (f_lo || f_hi) {
-      // sensors and Lambda at n-e (only with the lower face), n, n+e (only
-      // with the upper face): every node read lies in the padded box and
-      // every metric read in [-1, n]
-      const Prim qm = prim_at(Q, fe, n - s, P), qp = prim_at(Q, fe, n + s, P);
-      const double nu_0 = sensor(qm.p, q.p, qp.p);
-      double dd, de, df;
-      const double L0 = aniso_d(r0.lam[d], r0.lam[(d + 1) % 3], r0.lam[(d + 2) % 3], P, dd, de, df);
-      double nu_m = 0.0, nu_p = 0.0, Lm = 0.0, Lp = 0.0;
-      if (f_lo) {
-        nu_m = sensor(prim_at(Q, fe, n - 2 * s, P).p, qm.p, q.p);
-        const Radii rm = radii_at(M, fe, n - s, qm, P);
-        Lm = aniso_d(rm.lam[d], rm.lam[(d + 1) % 3], rm.lam[(d + 2) % 3], P, dd, de, df);
-      }
-      if (f_hi) {
-        nu_p = sensor(q.p, qp.p, prim_at(Q, fe, n + 2 * s, P).p);
-        const Radii rp = radii_at(M, fe, n + s, qp, P);
-        Lp = aniso_d(rp.lam[d], rp.lam[(d + 1) % 3], rp.lam[(d + 2) % 3], P, dd, de, df);
-      }
-      double Lamb = 0.0, nub = 0.0;
-      for (int side = 0; side < 2; ++side) {
-        // side 0: face (n-e, n) with the node as b; side 1: face (n, n+e) with the node as a
-        if (side == 0 && !f_lo) continue;
-        if (side == 1 && !f_hi) continue;
-        const int ai = side == 0 ? i - di : i, aj = side == 0 ? j - dj : j, ak = side == 0 ? k - dk : k;
-        const long long an = L.at(ai, aj, ak);
-        const double na = side == 0 ? nu_m : nu_0, nb = side == 0 ? nu_0 : nu_p;
-        const double La = side == 0 ? Lm : L0, Lb = side == 0 ? L0 : Lp;
-        const double e2 = P.k2 * (na >= nb ? na : nb);
-        const double e4raw = P.k4 - e2;
-        const bool e4_active = !(0.0 >= e4raw);  // max(0, x) follows 0 on ties
-        const double e4 = e4_active ? e4raw : 0.0;
-        const double Lf = 0.5 * (La + Lb);
-        // Dbar = W(a+e) - W(a)
-        double Wa[5], Wb[5];
-        Wat(L, M, qb, coef, ai, aj, ak, Wa);
-        Wat(L, M, qb, coef, ai + di, aj + dj, ak + dk, Wb);
-        double Lfb = 0.0, e2b = 0.0, e4b = 0.0;
-        for (int c = 0; c < 5; ++c) {
-          const double Db = Wb[c] - Wa[c];
-          const double* Qc = Q + c * fe;
-          const double d1 = Qc[an + s] - Qc[an];
-          const double d3 = Qc[an + 2 * s] - 3.0 * Qc[an + s] + 3.0 * Qc[an] - Qc[an - s];
-          Lfb += Db * (e2 * d1 - e4 * d3);
-          e2b += Db * Lf * d1;
-          e4b -= Db * Lf * d3;
-        }
-        if (e4_active) e2b -= e4b;
-        Lamb += 0.5 * Lfb;  // this node's share of the face mean
-        // eps2 = k2 max(nu_a, nu_b): the node is b on side 0, a on side 1
-        const bool a_wins = na >= nb;
-        if ((side == 0 && !a_wins) || (side == 1 && a_wins)) nub += P.k2 * e2b;
-        if (side == 1) {
-          A2 = Lf * e2;
-          A4 = Lf * e4;
-        }
-      }
-      // Lambda_d(n) -> lam_d, lam_e, lam_f
-      {
-        double dd0, de0, df0;
-        aniso_d(r0.lam[d], r0.lam[(d + 1) % 3], r0.lam[(d + 2) % 3], P, dd0, de0, df0);
-        lamb[d] += Lamb * dd0;
-        lamb[(d + 1) % 3] += Lamb * de0;
-        lamb[(d + 2) % 3] += Lamb * df0;
-      }
-      // nu_d(n) = |Delta2| / Sigma with p(n-e), p(n), p(n+e)
-      {
-        const double D2 = qp.p - 2.0 * q.p + qm.p, Sg = qp.p + 2.0 * q.p + qm.p;
-        const double iSg = rcp_nr(Sg);
-        const double sd = sgn(D2) * iSg, sv = nu_0 * iSg;
-        pb += nub * (-2.0 * sd - 2.0 * sv);
-        cpw = nub * (sd - sv);  // weight of p(n - e) and p(n + e)
-      }
-    }
-    Wk[(W_CP + d) * fe + n] = cpw;
-    Wk[(W_A2 + d) * fe + n] = A2;
-    Wk[(W_A4 + d) * fe + n] = A4;
-  }
-  // lam_e = |U_e| + c |m_e|
-  double cb = 0.0;
-  for (int e = 0; e < 3; ++e) {
-    if (lamb[e] == 0.0) continue;
-    const double Ueb = sgn(r0.U[e]) * lamb[e];
-    cb += r0.nrm[e] * lamb[e];
-    ub[0] += Ueb * m[3 * e];
-    ub[1] += Ueb * m[3 * e + 1];
-    ub[2] += Ueb * m[3 * e + 2];
-  }
-  // c = sqrt(gamma p / rho)
-  if (cb != 0.0) {
-    const double ir2 = rcp_nr(2.0 * q.rho);
-    pb += cb * P.gamma * rcp_nr(r0.c) * ir2;
-    rb -= cb * r0.c * ir2;
-  }
   Wk[W_PRHO * fe + n] = rb;
   Wk[W_PU * fe + n] = ub[0];
   Wk[W_PV * fe + n] = ub[1];
@@ -408,6 +311,166 @@ __global__ void __launch_bounds__(256, 2) k_adj_node(AdjK A, const double* __res
   Wk[W_PP * fe + n] = pb;
   Wk[W_PT * fe + n] = Tb;
   for (int a = 0; a < 4; ++a) Wk[(W_QD1 + a) * fe + n] = qd[a];
+}
+
+// ---- dissipation adjoint, face by face ----
+// Pass 1b (nodes in [-1, n]^3): Lambda_d and the pressure sensor nu_d.
+__global__ void __launch_bounds__(256) k_adj_lnu(AdjK A, const double* __restrict__ Q, double* __restrict__ Wk) {
+  const Layout& L = A.L;
+  const Phys& P = A.P;
+  const long long fe = L.fe;
+  const unsigned ext_i = L.ni + 2, ext_j = L.nj + 2;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ext_i * ext_j * (unsigned)(L.nk + 2)) return;
+  const int i = (int)(t % ext_i) - 1;
+  const int j = (int)((t / ext_i) % ext_j) - 1;
+  const int k = (int)(t / (ext_i * ext_j)) - 1;
+  const long long n = L.at(i, j, k);
+  const Prim q = prim_at(Q, fe, n, P);
+  const Radii r = radii_at(A.M, fe, n, q, P);
+  for (int d = 0; d < 3; ++d) {
+    const long long s = dstr(L, d);
+    const double pm = prim_at(Q, fe, n - s, P).p, pp = prim_at(Q, fe, n + s, P).p;
+    double dd, de, df;
+    Wk[(W_LAM + d) * fe + n] = aniso_d(r.lam[d], r.lam[(d + 1) % 3], r.lam[(d + 2) % 3], P, dd, de, df);
+    Wk[(W_NU + d) * fe + n] = sensor(pm, q.p, pp);
+  }
+}
+
+// Pass 1c (one thread per face (a, b = a + e_d) used by an interior
+// residual): the face's dissipation D = Lf (eps2 dQ - eps4 d3Q) reversed
+// with Dbar = W(b) - W(a).  Stores the face coefficients Lambda eps2,
+// Lambda eps4 (for the gather), half the adjoint of the face mean Lf (one
+// share per end node) and the sensor adjoint k2 eps2bar, given to the end
+// node whose sensor wins max(nu_a, nu_b) (a on ties).
+__global__ void __launch_bounds__(256) k_adj_face(AdjK A, const double* __restrict__ Q, const double* __restrict__ qb,
+                                                  double coef, double* __restrict__ Wk) {
+  const Layout& L = A.L;
+  const Phys& P = A.P;
+  const long long fe = L.fe;
+  const unsigned ni = L.ni, nj = L.nj, nk = L.nk;
+  const unsigned F0 = (ni + 1) * nj * nk, F1 = ni * (nj + 1) * nk, F2 = ni * nj * (nk + 1);
+  unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F0 + F1 + F2) return;
+  int d, ai, aj, ak;
+  if (t < F0) {
+    d = 0;
+    ai = (int)(t % (ni + 1)) - 1; aj = (int)((t / (ni + 1)) % nj); ak = (int)(t / ((ni + 1) * nj));
+  } else if (t < F0 + F1) {
+    t -= F0;
+    d = 1;
+    ai = (int)(t % ni); aj = (int)((t / ni) % (nj + 1)) - 1; ak = (int)(t / (ni * (nj + 1)));
+  } else {
+    t -= F0 + F1;
+    d = 2;
+    ai = (int)(t % ni); aj = (int)((t / ni) % nj); ak = (int)(t / (ni * nj)) - 1;
+  }
+  const int di = d == 0, dj = d == 1, dk = d == 2;
+  const long long s = dstr(L, d);
+  const long long an = L.at(ai, aj, ak), bn = an + s;
+  const double La = Wk[(W_LAM + d) * fe + an], Lb = Wk[(W_LAM + d) * fe + bn];
+  const double na = Wk[(W_NU + d) * fe + an], nb = Wk[(W_NU + d) * fe + bn];
+  const double e2 = P.k2 * (na >= nb ? na : nb);
+  const double e4raw = P.k4 - e2;
+  const bool e4_active = !(0.0 >= e4raw);  // max(0, x) follows 0 on ties
+  const double e4 = e4_active ? e4raw : 0.0;
+  const double Lf = 0.5 * (La + Lb);
+  double Wa[5], Wb[5];
+  Wat(L, A.M, qb, coef, ai, aj, ak, Wa);
+  Wat(L, A.M, qb, coef, ai + di, aj + dj, ak + dk, Wb);
+  double Lfb = 0.0, e2b = 0.0, e4b = 0.0;
+  for (int c = 0; c < 5; ++c) {
+    const double Db = Wb[c] - Wa[c];
+    const double* Qc = Q + c * fe;
+    const double d1 = Qc[bn] - Qc[an];
+    const double d3 = Qc[bn + s] - 3.0 * Qc[bn] + 3.0 * Qc[an] - Qc[an - s];
+    Lfb += Db * (e2 * d1 - e4 * d3);
+    e2b += Db * Lf * d1;
+    e4b -= Db * Lf * d3;
+  }
+  if (e4_active) e2b -= e4b;
+  const bool a_wins = na >= nb;
+  Wk[(W_A2 + d) * fe + an] = Lf * e2;
+  Wk[(W_A4 + d) * fe + an] = Lf * e4;
+  Wk[(W_LH + d) * fe + an] = 0.5 * Lfb;
+  Wk[(W_NUA + d) * fe + an] = a_wins ? P.k2 * e2b : 0.0;
+  Wk[(W_NUB + d) * fe + an] = a_wins ? 0.0 : P.k2 * e2b;
+}
+
+// Pass 1d (nodes in [-1, n]^3): the node's shares of its two faces per
+// direction, back through Lambda_d(lam_d, lam_e, lam_f), lam = |U| + c|m|
+// and nu_d(p(n-e), p, p(n+e)) to the primitive variables (added to pass 1a's
+// part); stores the sensor weight of p(n +- e) for the gather.
+__global__ void __launch_bounds__(256) k_adj_dnode(AdjK A, const double* __restrict__ Q, double* __restrict__ Wk) {
+  const Layout& L = A.L;
+  const Phys& P = A.P;
+  const long long fe = L.fe;
+  const double* __restrict__ M = A.M;
+  const unsigned ext_i = L.ni + 2, ext_j = L.nj + 2;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ext_i * ext_j * (unsigned)(L.nk + 2)) return;
+  const int i = (int)(t % ext_i) - 1;
+  const int j = (int)((t / ext_i) % ext_j) - 1;
+  const int k = (int)(t / (ext_i * ext_j)) - 1;
+  const long long n = L.at(i, j, k);
+
+  double rb = 0, ub[3] = {0, 0, 0}, pb = 0;
+  double lamb[3] = {0, 0, 0};
+  bool any = false;
+  Prim q;
+  Radii r0;
+  for (int d = 0; d < 3; ++d) {
+    const long long s = dstr(L, d);
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    const bool f_lo = face_ok(L, d, i - di, j - dj, k - dk);  // face (n-e, n): node is b
+    const bool f_hi = face_ok(L, d, i, j, k);                 // face (n, n+e): node is a
+    double cpw = 0.0;
+    if (f_lo || f_hi) {
+      if (!any) {
+        q = prim_at(Q, fe, n, P);
+        r0 = radii_at(M, fe, n, q, P);
+        any = true;
+      }
+      const double Lamb = (f_lo ? Wk[(W_LH + d) * fe + n - s] : 0.0) + (f_hi ? Wk[(W_LH + d) * fe + n] : 0.0);
+      const double nub = (f_lo ? Wk[(W_NUB + d) * fe + n - s] : 0.0) + (f_hi ? Wk[(W_NUA + d) * fe + n] : 0.0);
+      // Lambda_d(n) -> lam_d, lam_e, lam_f
+      double dd0, de0, df0;
+      aniso_d(r0.lam[d], r0.lam[(d + 1) % 3], r0.lam[(d + 2) % 3], P, dd0, de0, df0);
+      lamb[d] += Lamb * dd0;
+      lamb[(d + 1) % 3] += Lamb * de0;
+      lamb[(d + 2) % 3] += Lamb * df0;
+      // nu_d(n) = |Delta2| / Sigma with p(n-e), p(n), p(n+e)
+      const double pm = prim_at(Q, fe, n - s, P).p, pp = prim_at(Q, fe, n + s, P).p;
+      const double D2 = pp - 2.0 * q.p + pm, Sg = pp + 2.0 * q.p + pm;
+      const double iSg = rcp_nr(Sg);
+      const double sd = sgn(D2) * iSg, sv = fabs(D2) * iSg * iSg;
+      pb += nub * (-2.0 * sd - 2.0 * sv);
+      cpw = nub * (sd - sv);  // weight of p(n - e) and p(n + e)
+    }
+    Wk[(W_CP + d) * fe + n] = cpw;
+  }
+  if (!any) return;
+  // lam_e = |U_e| + c |m_e|
+  double cb = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    if (lamb[e] == 0.0) continue;
+    const double Ueb = sgn(r0.U[e]) * lamb[e];
+    cb += r0.nrm[e] * lamb[e];
+    ub[0] += Ueb * M[(3 * e) * fe + n];
+    ub[1] += Ueb * M[(3 * e + 1) * fe + n];
+    ub[2] += Ueb * M[(3 * e + 2) * fe + n];
+  }
+  // c = sqrt(gamma p / rho)
+  if (cb != 0.0) {
+    const double ir2 = rcp_nr(2.0 * q.rho);
+    pb += cb * P.gamma * rcp_nr(r0.c) * ir2;
+    rb -= cb * r0.c * ir2;
+  }
+  Wk[W_PRHO * fe + n] += rb;
+  Wk[W_PU * fe + n] += ub[0];
+  Wk[W_PV * fe + n] += ub[1];
+  Wk[W_PW * fe + n] += ub[2];
+  Wk[W_PP * fe + n] += pb;
 }
 
 // ---------------------------------------------------------------------------
@@ -569,7 +632,12 @@ hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const dou
   const long long nB1 = (long long)(L.ni + 2) * (L.nj + 2) * (L.nk + 2);
   const long long nPad = (long long)(L.ni + 4) * (L.nj + 4) * (L.nk + 4);
   const long long nIn = (long long)L.ni * L.nj * L.nk;
-  k_adj_node<<<nb(nB1, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
+  const long long nFace = (long long)(L.ni + 1) * L.nj * L.nk + (long long)L.ni * (L.nj + 1) * L.nk +
+                         (long long)L.ni * L.nj * (L.nk + 1);
+  k_adj_flux<<<nb(nB1, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
+  k_adj_lnu<<<nb(nB1, 256), 256, 0, s>>>(A, Q, Wk);
+  k_adj_face<<<nb(nFace, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
+  k_adj_dnode<<<nb(nB1, 256), 256, 0, s>>>(A, Q, Wk);
   k_adj_gather<<<nb(nPad, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
   k_adj_fold<<<nb(nIn, 256), 256, 0, s>>>(A, Wk + (long long)W_G * L.fe, add, qout);
   return hipGetLastError();
