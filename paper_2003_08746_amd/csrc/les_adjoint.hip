@@ -45,7 +45,7 @@ enum {
   W_A2 = 25,                                  // Lambda eps2 of face (n, n+e_d): 3 fields
   W_A4 = 28,                                  // Lambda eps4 of face (n, n+e_d): 3 fields
   W_LAM = 31,                                 // Lambda_d at the node: 3 fields
-  W_NU = 34,                                  // pressure sensor nu_d at the node: 3 fields
+  W_NU = 34,                                  // signed sensor (p+ - 2p + p-) / Sigma: 3 fields
   W_G = 31,                                   // gather output: Q adjoint per node, 5 fields
                                               // (reuses W_LAM / W_NU, dead by then)
   W_LH = 37,                                  // half the face-mean adjoint of face (n, n+e_d): 3
@@ -53,7 +53,9 @@ enum {
   W_NUB = 43,                                 // ... for node n + e_d: 3
   W_Q1 = 46,                                  // stage adjoint ping-pong: 5 + 5 fields
   W_ACC = 56,                                 // accumulated adjoint of Q^(0): 5 fields
-  W_NF = 61
+  W_DB = 61,                                  // Dbar = W(n+e_d) - W(n) of face (n, n+e_d): 15
+  W_IS = 76,                                  // 1 / Sigma of the sensor, Sigma = p+ + 2p + p-: 3
+  W_NF = 79
 };
 
 struct Prim {
@@ -185,9 +187,21 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
       dd[d][1] = 0.5 * (a.v - b.v);
       dd[d][2] = 0.5 * (a.w - b.w);
       dd[d][3] = 0.5 * (a.T - b.T);
+      // for the dissipation adjoint: signed sensor (p+ - 2p + p-) / Sigma and 1 / Sigma
+      const double iS = rcp_nr(a.p + 2.0 * q.p + b.p);
+      Wk[(W_NU + d) * fe + n] = (a.p - 2.0 * q.p + b.p) * iS;
+      Wk[(W_IS + d) * fe + n] = iS;
     }
     for (int qq = 0; qq < 4; ++qq)
       for (int x = 0; x < 3; ++x) g[qq][x] = J * (m[x] * dd[0][qq] + m[3 + x] * dd[1][qq] + m[6 + x] * dd[2][qq]);
+  }
+  {
+    // for the dissipation adjoint: Lambda_d at the node
+    const Radii r = radii_at(M, fe, n, q, P);
+    for (int d = 0; d < 3; ++d) {
+      double dd0, de0, df0;
+      Wk[(W_LAM + d) * fe + n] = aniso_d(r.lam[d], r.lam[(d + 1) % 3], r.lam[(d + 2) % 3], P, dd0, de0, df0);
+    }
   }
   const double S11 = g[0][0], S22 = g[1][1], S33 = g[2][2];
   const double S12 = 0.5 * (g[0][1] + g[1][0]), S13 = 0.5 * (g[0][2] + g[2][0]), S23 = 0.5 * (g[1][2] + g[2][1]);
@@ -313,30 +327,9 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
   for (int a = 0; a < 4; ++a) Wk[(W_QD1 + a) * fe + n] = qd[a];
 }
 
-// ---- dissipation adjoint, face by face ----
-// Pass 1b (nodes in [-1, n]^3): Lambda_d and the pressure sensor nu_d.
-__global__ void __launch_bounds__(256) k_adj_lnu(AdjK A, const double* __restrict__ Q, double* __restrict__ Wk) {
-  const Layout& L = A.L;
-  const Phys& P = A.P;
-  const long long fe = L.fe;
-  const unsigned ext_i = L.ni + 2, ext_j = L.nj + 2;
-  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ext_i * ext_j * (unsigned)(L.nk + 2)) return;
-  const int i = (int)(t % ext_i) - 1;
-  const int j = (int)((t / ext_i) % ext_j) - 1;
-  const int k = (int)(t / (ext_i * ext_j)) - 1;
-  const long long n = L.at(i, j, k);
-  const Prim q = prim_at(Q, fe, n, P);
-  const Radii r = radii_at(A.M, fe, n, q, P);
-  for (int d = 0; d < 3; ++d) {
-    const long long s = dstr(L, d);
-    const double pm = prim_at(Q, fe, n - s, P).p, pp = prim_at(Q, fe, n + s, P).p;
-    double dd, de, df;
-    Wk[(W_LAM + d) * fe + n] = aniso_d(r.lam[d], r.lam[(d + 1) % 3], r.lam[(d + 2) % 3], P, dd, de, df);
-    Wk[(W_NU + d) * fe + n] = sensor(pm, q.p, pp);
-  }
-}
-
+// ---- dissipation adjoint, face by face (pass 1a also stores, per node and
+// direction, Lambda_d, the signed pressure sensor (p+ - 2p + p-) / Sigma and
+// 1 / Sigma) ----
 // Pass 1c (one thread per face (a, b = a + e_d) used by an interior
 // residual): the face's dissipation D = Lf (eps2 dQ - eps4 d3Q) reversed
 // with Dbar = W(b) - W(a).  Stores the face coefficients Lambda eps2,
@@ -369,7 +362,7 @@ __global__ void __launch_bounds__(256) k_adj_face(AdjK A, const double* __restri
   const long long s = dstr(L, d);
   const long long an = L.at(ai, aj, ak), bn = an + s;
   const double La = Wk[(W_LAM + d) * fe + an], Lb = Wk[(W_LAM + d) * fe + bn];
-  const double na = Wk[(W_NU + d) * fe + an], nb = Wk[(W_NU + d) * fe + bn];
+  const double na = fabs(Wk[(W_NU + d) * fe + an]), nb = fabs(Wk[(W_NU + d) * fe + bn]);
   const double e2 = P.k2 * (na >= nb ? na : nb);
   const double e4raw = P.k4 - e2;
   const bool e4_active = !(0.0 >= e4raw);  // max(0, x) follows 0 on ties
@@ -381,6 +374,7 @@ __global__ void __launch_bounds__(256) k_adj_face(AdjK A, const double* __restri
   double Lfb = 0.0, e2b = 0.0, e4b = 0.0;
   for (int c = 0; c < 5; ++c) {
     const double Db = Wb[c] - Wa[c];
+    Wk[(W_DB + 5 * d + c) * fe + an] = Db;
     const double* Qc = Q + c * fe;
     const double d1 = Qc[bn] - Qc[an];
     const double d3 = Qc[bn + s] - 3.0 * Qc[bn] + 3.0 * Qc[an] - Qc[an - s];
@@ -439,11 +433,10 @@ __global__ void __launch_bounds__(256) k_adj_dnode(AdjK A, const double* __restr
       lamb[d] += Lamb * dd0;
       lamb[(d + 1) % 3] += Lamb * de0;
       lamb[(d + 2) % 3] += Lamb * df0;
-      // nu_d(n) = |Delta2| / Sigma with p(n-e), p(n), p(n+e)
-      const double pm = prim_at(Q, fe, n - s, P).p, pp = prim_at(Q, fe, n + s, P).p;
-      const double D2 = pp - 2.0 * q.p + pm, Sg = pp + 2.0 * q.p + pm;
-      const double iSg = rcp_nr(Sg);
-      const double sd = sgn(D2) * iSg, sv = fabs(D2) * iSg * iSg;
+      // nu_d(n) = |Delta2| / Sigma with p(n-e), p(n), p(n+e): from the
+      // pre-pass, Delta2 / Sigma (signed) and 1 / Sigma
+      const double ns = Wk[(W_NU + d) * fe + n], iSg = Wk[(W_IS + d) * fe + n];
+      const double sd = sgn(ns) * iSg, sv = fabs(ns) * iSg;
       pb += nub * (-2.0 * sd - 2.0 * sv);
       cpw = nub * (sd - sv);  // weight of p(n - e) and p(n + e)
     }
@@ -556,10 +549,8 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
       const double A2 = Wk[(W_A2 + d) * fe + an], A4 = Wk[(W_A4 + d) * fe + an];
       const double w = r == 0 ? (A2 + 3.0 * A4) : (r == 1 ? -(A2 + 3.0 * A4) : (r == 2 ? -A4 : A4));
       if (w == 0.0) continue;
-      double Wa[5], Wb[5];
-      Wat(L, A.M, qb, coef, ai, aj, ak, Wa);
-      Wat(L, A.M, qb, coef, ai + di, aj + dj, ak + dk, Wb);
-      for (int c = 0; c < 5; ++c) out[c] += w * (Wb[c] - Wa[c]);
+      // Dbar of the face, stored by the face pass
+      for (int c = 0; c < 5; ++c) out[c] += w * Wk[(W_DB + 5 * d + c) * fe + an];
     }
   }
   for (int c = 0; c < 5; ++c) Wk[(W_G + c) * fe + n] = out[c];
@@ -567,10 +558,13 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
 
 // ---------------------------------------------------------------------------
 // Pass 3: fold periodic ghost images onto the interior:
-// qout(n) = sum over padded images of n of G (+ add, when non-null).
+// qout(n) = sum over padded images of n of G (+ add, when non-null); with
+// acc non-null also acc(n) += accsrc(n) (the Runge-Kutta accumulation of the
+// adjoint step, fused into this pass over the interior).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restrict__ G, const double* __restrict__ add,
-                                                  double* __restrict__ qout) {
+                                                  double* __restrict__ qout, double* __restrict__ acc,
+                                                  const double* __restrict__ accsrc) {
   const Layout& L = A.L;
   const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
@@ -597,6 +591,7 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restri
       for (int b = 0; b < nc[1]; ++b)
         for (int e = 0; e < nc[2]; ++e) s += G[c * L.fe + L.at(cand[0][a], cand[1][b], cand[2][e])];
     qout[c * L.fe + n0] = s;
+    if (acc) acc[c * L.fe + n0] += accsrc[c * L.fe + n0];
   }
 }
 
@@ -627,7 +622,7 @@ inline unsigned nb(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Qbar_out = (dR/dQ|Q)^T (coef * qb) on the interior.
 hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const double* qb, double coef, double* Wk,
-                        const double* add, double* qout) {
+                        const double* add, double* qout, double* acc = nullptr) {
   const Layout& L = A.L;
   const long long nB1 = (long long)(L.ni + 2) * (L.nj + 2) * (L.nk + 2);
   const long long nPad = (long long)(L.ni + 4) * (L.nj + 4) * (L.nk + 4);
@@ -635,11 +630,10 @@ hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const dou
   const long long nFace = (long long)(L.ni + 1) * L.nj * L.nk + (long long)L.ni * (L.nj + 1) * L.nk +
                          (long long)L.ni * L.nj * (L.nk + 1);
   k_adj_flux<<<nb(nB1, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
-  k_adj_lnu<<<nb(nB1, 256), 256, 0, s>>>(A, Q, Wk);
   k_adj_face<<<nb(nFace, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
   k_adj_dnode<<<nb(nB1, 256), 256, 0, s>>>(A, Q, Wk);
   k_adj_gather<<<nb(nPad, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
-  k_adj_fold<<<nb(nIn, 256), 256, 0, s>>>(A, Wk + (long long)W_G * L.fe, add, qout);
+  k_adj_fold<<<nb(nIn, 256), 256, 0, s>>>(A, Wk + (long long)W_G * L.fe, add, qout, acc, qb);
   return hipGetLastError();
 }
 
@@ -668,13 +662,12 @@ hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt,
   if (e != hipSuccess) return e;
   for (int l = 4; l >= 0; --l) {
     const double al = rk_alpha(l) * dt;
-    // acc += qbar_l
-    k_axpy_interior<<<nb(nIn, 256), 256, 0, s>>>(L, acc, qcur, acc);
     if (fbar && a.i_f >= 0)
       k_fbar<<<nb((long long)L.nj * L.nk, 256), 256, 0, s>>>(L, a.i_f, al, qcur, fbar);
-    // qbar_{l-1} = (dR/dQ|Q^(l-1))^T (-alpha_l dt qbar_l)
+    // qbar_{l-1} = (dR/dQ|Q^(l-1))^T (-alpha_l dt qbar_l), and acc += qbar_l
+    // (in the fold pass, which reads qbar_l after the gather is done with it)
     const double* Ql = ckpt + (long long)l * 5 * fe;
-    e = residual_vjp(s, A, Ql, qcur, -al, work, nullptr, qnext);
+    e = residual_vjp(s, A, Ql, qcur, -al, work, nullptr, qnext, acc);
     if (e != hipSuccess) return e;
     double* tmp = qcur;
     qcur = qnext;

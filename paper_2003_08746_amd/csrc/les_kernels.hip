@@ -483,12 +483,15 @@ __global__ void __launch_bounds__(256) k_norm_final(const double* __restrict__ p
 // Probe objective on plane i_p: one block; J += w sum (p - p_inf)^2 and
 // Qbar += w 2 (p - p_inf) dp/dQ.
 // ---------------------------------------------------------------------------
+// Pass 1: every block sums its share of the plane into part[blockIdx.x]
+// (and adds the objective's Q adjoint, node by node); pass 2 adds the block
+// sums in a fixed order, so that the objective does not depend on timing.
 __global__ void __launch_bounds__(256) k_probe(Layout L, Phys P, const double* __restrict__ Q, int i_p, double p_inf,
-                                               double weight, double* __restrict__ Jacc, double* __restrict__ Qbar) {
+                                               double weight, double* __restrict__ part, double* __restrict__ Qbar) {
   __shared__ double red[4];
   double s = 0.0;
   const long long cnt = (long long)L.nj * L.nk;
-  for (long long t = threadIdx.x; t < cnt; t += 256) {
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < cnt; t += (long long)gridDim.x * 256) {
     int j = (int)(t % L.nj), k = (int)(t / L.nj);
     long long n = L.at(i_p, j, k);
     double rho = Q[n], m1 = Q[L.fe + n], m2 = Q[2 * L.fe + n], m3 = Q[3 * L.fe + n], e = Q[4 * L.fe + n];
@@ -508,7 +511,15 @@ __global__ void __launch_bounds__(256) k_probe(Layout L, Phys P, const double* _
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) Jacc[0] += weight * (red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(64) k_probe_final(const double* __restrict__ part, int nparts, double weight,
+                                                    double* __restrict__ Jacc) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 64) s += part[b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) Jacc[0] += weight * s;
 }
 
 }  // namespace les
@@ -587,8 +598,11 @@ hipError_t launch_norm_final(hipStream_t s, const double* part, long long np, do
 }
 
 hipError_t launch_probe(hipStream_t s, const Layout& L, const Phys& P, const double* Q, int i_p, double p_inf,
-                        double weight, double* Jacc, double* Qbar) {
-  k_probe<<<1, 256, 0, s>>>(L, P, Q, i_p, p_inf, weight, Jacc, Qbar);
+                        double weight, double* Jacc, double* Qbar, double* part) {
+  // up to 64 blocks (part holds at least that many doubles)
+  const unsigned nb = min(64u, nblk((long long)L.nj * L.nk, 256));
+  k_probe<<<nb, 256, 0, s>>>(L, P, Q, i_p, p_inf, weight, part, Qbar);
+  k_probe_final<<<1, 64, 0, s>>>(part, (int)nb, weight, Jacc);
   return hipGetLastError();
 }
 
