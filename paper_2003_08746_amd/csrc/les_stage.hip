@@ -37,7 +37,11 @@
 // are read from the kernel-argument segment where they are used, instead of
 // occupying scalar registers across the loop.  Divisions and square roots
 // use short Newton-refined sequences (valid for the positive, normal
-// arguments met here).
+// arguments met here).  Scheduling fences split phases C and E into short
+// regions (gradient / stress / spectral radii / each node flux; each
+// dissipation direction / zeta face / residual): without them the scheduler
+// hoists LDS reads of later regions over the FP64 work of earlier ones and
+// the live ranges exceed the 256 registers of a two-wave-per-SIMD launch.
 //
 // Work per thread is independent of the floating-point type T (double for
 // the FP64 path, float for the mixed path); metrics, Q^(0), the stage
@@ -346,6 +350,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
             for (int x = 0; x < 3; ++x) g[q][x] = Jt * (mt[x] * dx + mt[3 + x] * dy + mt[6 + x] * dz);
           }
         }
+        __builtin_amdgcn_sched_barrier(0);
         const T s11 = g[0][0], s22 = g[1][1], s33 = g[2][2];
         const T s12 = T(0.5) * (g[0][1] + g[1][0]);
         const T s13 = T(0.5) * (g[0][2] + g[2][0]);
@@ -369,6 +374,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
         const T th0 = u * t11 + vv * t12 + w * t13 + kap * g[3][0];
         const T th1 = u * t12 + vv * t22 + w * t23 + kap * g[3][1];
         const T th2 = u * t13 + vv * t23 + w * t33 + kap * g[3][2];
+        __builtin_amdgcn_sched_barrier(0);
         const T p = s.p[ey][ex];
         const T c2 = T(P.gamma_R) * tn;  // c^2 = gamma p / rho = gamma R T
         // spectral radii of the three directions and their square roots
@@ -394,6 +400,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           H[3] = s.q[3][ey][ex] * Ue + mz * p - (mx * t13 + my * t23 + mz * t33);
           H[4] = (s.q[4][ey][ex] + p) * Ue - (mx * th0 + my * th1 + mz * th2);
         };
+        __builtin_amdgcn_sched_barrier(0);
         if (nx_t) {
           T H[5];
           node_flux(0, H);
@@ -403,6 +410,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           const T pa = s.p[ey][ex + 1], pb = s.p[ey][ex - 1];
           s.nx[ty - 1][tx] = fabs(pa - T(2) * p + pb) * rcp_nr(pa + T(2) * p + pb);
         }
+        __builtin_amdgcn_sched_barrier(0);
         if (ny_t) {
           T H[5];
           node_flux(1, H);
@@ -412,6 +420,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           const T pa = s.p[ey + 1][ex], pb = s.p[ey - 1][ex];
           s.ny[ty][tx - 1] = fabs(pa - T(2) * p + pb) * rcp_nr(pa + T(2) * p + pb);
         }
+        __builtin_amdgcn_sched_barrier(0);
         if (out_ok) {
           node_flux(2, hz);
           lz = aniso_n(2, 0, 1);
@@ -450,6 +459,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           face_diss(P, s.lx[cy][tx - 1], s.lx[cy][tx], s.nx[cy][tx - 1], s.nx[cy][tx], q_a, q_b, q_c, q_d, D0);
 #pragma unroll
           for (int c = 0; c < 5; ++c) r[c] -= D1[c] - D0[c];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
             q_a[c] = s.q[c][ey - 2][ex]; q_b[c] = s.q[c][ey - 1][ex];
@@ -460,6 +470,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
 #pragma unroll
           for (int c = 0; c < 5; ++c) r[c] -= D1[c] - D0[c];
         }
+        __builtin_amdgcn_sched_barrier(0);
         if (t >= kb) {
           // zeta face t - 1/2 between plane t-1 and plane t
           T qc[5], D[5], fz[5];
@@ -468,6 +479,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           face_diss(P, lz_prev, lz, nz_prev, nz, qm2, qm1, qc, qa, D);
 #pragma unroll
           for (int c = 0; c < 5; ++c) fz[c] = T(0.5) * (hz_prev[c] + hz[c]) - D[c];
+          __builtin_amdgcn_sched_barrier(0);
           if (t > kb) {
             // residual of plane t-1 and its stage update
             const int k = t - 1;
