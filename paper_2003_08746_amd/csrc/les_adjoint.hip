@@ -16,12 +16,13 @@
 //      the gradient-stencil weights a_{q,d} = J m_d . gbar_q, the sensor
 //      weights for p at n +- e_d, and the face coefficients
 //      Lambda eps2, Lambda eps4 of the face (n, n + e_d);
-//   pass 2 (gather, every node of the padded box): collects the gradient
-//      and sensor weights of its neighbours and the dissipation faces whose
-//      five-point stencil contains it, and maps the primitive adjoint back
-//      to conserved variables;
-//   pass 3 (fold): adds the adjoint of every periodic ghost image to its
-//      interior node (frozen Dirichlet ghosts carry no dependence).
+//   pass 2 (gather, interior nodes and their periodic ghost images):
+//      collects the gradient and sensor weights of its neighbours and the
+//      dissipation faces whose five-point stencil contains it, and maps the
+//      primitive adjoint back to conserved variables;
+//   pass 3 (fold, interior nodes next to a periodic seam): adds the adjoint
+//      of every periodic ghost image to its interior node (frozen Dirichlet
+//      ghosts carry no dependence).
 // Non-smooth points take the derivative of the active branch: d|x|/dx =
 // sign(x) with 0 at 0, max(a, b) follows a when a >= b, and the eddy
 // viscosity's |S| has derivative 0 at |S| = 0.
@@ -29,7 +30,8 @@
 // les_adjoint_step applies it stage by stage in reverse from the stage
 // inputs saved by les_rk_step: for l = 5..1, acc += qbar, fbar += alpha_l dt
 // qbar on the source plane, qbar = (dR/dQ|Q^(l-1))^T (-alpha_l dt qbar);
-// finally Qbar = acc + qbar.
+// finally Qbar = acc + qbar.  The accumulation, the fbar update and the
+// final sum run inside passes 2 and 3 of the next (or last) stage.
 #include "les_adjoint.hpp"
 
 namespace les {
@@ -46,8 +48,6 @@ enum {
   W_A4 = 28,                                  // Lambda eps4 of face (n, n+e_d): 3 fields
   W_LAM = 31,                                 // Lambda_d at the node: 3 fields
   W_NU = 34,                                  // signed sensor (p+ - 2p + p-) / Sigma: 3 fields
-  W_G = 31,                                   // gather output: Q adjoint per node, 5 fields
-                                              // (reuses W_LAM / W_NU, dead by then)
   W_LH = 37,                                  // half the face-mean adjoint of face (n, n+e_d): 3
   W_NUA = 40,                                 // sensor adjoint of face (n, n+e_d) for node n: 3
   W_NUB = 43,                                 // ... for node n + e_d: 3
@@ -55,7 +55,8 @@ enum {
   W_ACC = 56,                                 // accumulated adjoint of Q^(0): 5 fields
   W_DB = 61,                                  // Dbar = W(n+e_d) - W(n) of face (n, n+e_d): 15
   W_IS = 76,                                  // 1 / Sigma of the sensor, Sigma = p+ + 2p + p-: 3
-  W_NF = 79
+  W_GG = 79,                                  // gather result at periodic ghost images: 5
+  W_NF = 84
 };
 
 struct Prim {
@@ -473,17 +474,45 @@ __device__ __forceinline__ bool in_b1(const Layout& L, int i, int j, int k) {
   return i >= -1 && i <= L.ni && j >= -1 && j <= L.nj && k >= -1 && k <= L.nk;
 }
 
-__global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __restrict__ Q, const double* __restrict__ qb,
-                                                    double coef, double* __restrict__ Wk) {
+// Does interior node (i, j, k) have periodic ghost images (x <= 1 or
+// x >= n_d - 2 along a periodic axis)?
+__device__ __forceinline__ bool in_band(const AdjK& A, int i, int j, int k) {
+  const Layout& L = A.L;
+  return (A.bc0 == 0 && (i <= 1 || i >= L.ni - 2)) || (A.bc1 == 0 && (j <= 1 || j >= L.nj - 2)) ||
+         (A.bc2 == 0 && (k <= 1 || k >= L.nk - 2));
+}
+
+// Last steps at an interior node whose adjoint q is complete: in the
+// Runge-Kutta reverse, fbar[c][k][j] += fw q_c on the source plane (fbar
+// non-null, on_f) and, after the last stage, qfin = acc + q (qfin non-null).
+__device__ __forceinline__ void finish_node(const Layout& L, long long n, int j, int k, const double q[5],
+                                            const double* __restrict__ acc, double* __restrict__ fbar, bool on_f,
+                                            double fw, double* __restrict__ qfin) {
+  if (fbar && on_f)
+    for (int c = 0; c < 5; ++c) fbar[((long long)c * L.nk + k) * L.nj + j] += fw * q[c];
+  if (qfin)
+    for (int c = 0; c < 5; ++c) qfin[c * L.fe + n] = acc[c * L.fe + n] + q[c];
+}
+
+// Pass 2 runs over B = R_i x R_j x R_k, R_d = [-2, n_d + 1] along a periodic
+// axis and [0, n_d) otherwise (frozen Dirichlet ghosts carry no dependence).
+// An interior node writes its gather to qout (and, in the Runge-Kutta
+// reverse, does acc += accsrc); a ghost node -- a periodic image of an
+// interior node -- writes it to W_GG for pass 3.
+__global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __restrict__ Q, double* __restrict__ Wk,
+                                                    double* __restrict__ qout, double* __restrict__ acc,
+                                                    const double* __restrict__ accsrc, double* __restrict__ fbar,
+                                                    int i_f, double fw, double* __restrict__ qfin) {
   const Layout& L = A.L;
   const Phys& P = A.P;
   const long long fe = L.fe;
-  const unsigned pi = L.ni + 4, pj = L.nj + 4;
+  const unsigned gi = A.bc0 == 0 ? 4 : 0, gj = A.bc1 == 0 ? 4 : 0, gk = A.bc2 == 0 ? 4 : 0;
+  const unsigned ri = L.ni + gi, rj = L.nj + gj;
   const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= pi * pj * (unsigned)(L.nk + 4)) return;
-  const int i = (int)(t % pi) - 2;
-  const int j = (int)((t / pi) % pj) - 2;
-  const int k = (int)(t / (pi * pj)) - 2;
+  if (t >= ri * rj * (unsigned)(L.nk + gk)) return;
+  const int i = (int)(t % ri) - (int)(gi >> 1);
+  const int j = (int)((t / ri) % rj) - (int)(gj >> 1);
+  const int k = (int)(t / (ri * rj)) - (int)(gk >> 1);
   const long long n = L.at(i, j, k);
   const bool b1 = in_b1(L, i, j, k);
 
@@ -553,28 +582,68 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
       for (int c = 0; c < 5; ++c) out[c] += w * Wk[(W_DB + 5 * d + c) * fe + an];
     }
   }
-  for (int c = 0; c < 5; ++c) Wk[(W_G + c) * fe + n] = out[c];
+  if (interior(L, i, j, k)) {
+    for (int c = 0; c < 5; ++c) qout[c * fe + n] = out[c];
+    if (acc)
+      for (int c = 0; c < 5; ++c) acc[c * fe + n] += accsrc[c * fe + n];
+    // nodes without periodic images are final here; pass 3 finishes the rest
+    if (!in_band(A, i, j, k)) finish_node(L, n, j, k, out, acc, fbar, i == i_f, fw, qfin);
+  } else {
+    for (int c = 0; c < 5; ++c) Wk[(W_GG + c) * fe + n] = out[c];
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Pass 3: fold periodic ghost images onto the interior:
-// qout(n) = sum over padded images of n of G (+ add, when non-null); with
-// acc non-null also acc(n) += accsrc(n) (the Runge-Kutta accumulation of the
-// adjoint step, fused into this pass over the interior).
+// Pass 3: add the periodic ghost images' gathers to their interior nodes:
+// qout(n) += W_GG over the images of n (at x + n_d for x <= 1 and at x - n_d
+// for x >= n_d - 2 along each periodic axis, all combinations, in a fixed
+// order).  Only nodes in the band {x <= 1 or x >= n_d - 2} of some periodic
+// axis have images; threads enumerate the band as three disjoint slabs
+// (band of k; core of k x band of j; core of k and j x band of i; the core
+// of an axis is [2, n_d - 2), all of [0, n_d) along a non-periodic axis).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restrict__ G, const double* __restrict__ add,
-                                                  double* __restrict__ qout, double* __restrict__ acc,
-                                                  const double* __restrict__ accsrc) {
+__device__ __forceinline__ int band_coord(unsigned u, int n) { return n <= 4 ? (int)u : (u < 2 ? (int)u : n - 4 + (int)u); }
+
+__global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restrict__ Wk, double* __restrict__ qout,
+                                                  const double* __restrict__ acc, double* __restrict__ fbar, int i_f,
+                                                  double fw, double* __restrict__ qfin) {
   const Layout& L = A.L;
-  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-  const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
-  if (t >= nij * (unsigned)L.nk) return;
-  const int i = (int)(t % ni);
-  const int j = (int)((t % nij) / ni);
-  const int k = (int)(t / nij);
-  const int bc[3] = {A.bc0, A.bc1, A.bc2};
-  const int id[3] = {i, j, k};
   const int nn[3] = {L.ni, L.nj, L.nk};
+  const int bc[3] = {A.bc0, A.bc1, A.bc2};
+  unsigned bs[3], cs[3];  // band and core sizes
+  int c0[3];              // first core coordinate
+  for (int d = 0; d < 3; ++d) {
+    if (bc[d] == 0) {
+      bs[d] = nn[d] < 4 ? nn[d] : 4;
+      cs[d] = nn[d] > 4 ? nn[d] - 4 : 0;
+      c0[d] = 2;
+    } else {
+      bs[d] = 0;
+      cs[d] = nn[d];
+      c0[d] = 0;
+    }
+  }
+  const unsigned ni = nn[0], nj = nn[1];
+  const unsigned S2 = bs[2] * nj * ni, S1 = cs[2] * bs[1] * ni, S0 = cs[2] * cs[1] * bs[0];
+  unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S2 + S1 + S0) return;
+  int i, j, k;
+  if (t < S2) {
+    i = (int)(t % ni);
+    j = (int)((t / ni) % nj);
+    k = band_coord(t / (ni * nj), nn[2]);
+  } else if (t < S2 + S1) {
+    t -= S2;
+    i = (int)(t % ni);
+    j = band_coord((t / ni) % bs[1], nn[1]);
+    k = c0[2] + (int)(t / (ni * bs[1]));
+  } else {
+    t -= S2 + S1;
+    i = band_coord(t % bs[0], nn[0]);
+    j = c0[1] + (int)((t / bs[0]) % cs[1]);
+    k = c0[2] + (int)(t / (bs[0] * cs[1]));
+  }
+  const int id[3] = {i, j, k};
   int cand[3][3], nc[3];
   for (int d = 0; d < 3; ++d) {
     nc[d] = 0;
@@ -585,19 +654,25 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restri
     }
   }
   const long long n0 = L.at(i, j, k);
+  const double* G = Wk + (long long)W_GG * L.fe;
+  double q[5];
   for (int c = 0; c < 5; ++c) {
-    double s = add ? add[c * L.fe + n0] : 0.0;
+    double s = qout[c * L.fe + n0];
     for (int a = 0; a < nc[0]; ++a)
       for (int b = 0; b < nc[1]; ++b)
-        for (int e = 0; e < nc[2]; ++e) s += G[c * L.fe + L.at(cand[0][a], cand[1][b], cand[2][e])];
+        for (int e = 0; e < nc[2]; ++e)
+          if (a | b | e) s += G[c * L.fe + L.at(cand[0][a], cand[1][b], cand[2][e])];
     qout[c * L.fe + n0] = s;
-    if (acc) acc[c * L.fe + n0] += accsrc[c * L.fe + n0];
+    q[c] = s;
   }
+  finish_node(L, n0, j, k, q, acc, fbar, i == i_f, fw, qfin);
 }
 
-// out = a + b on the interior (5 fields)
-// (out may alias a: each thread reads and writes only its own node)
-__global__ void __launch_bounds__(256) k_axpy_interior(Layout L, const double* a, const double* b, double* out) {
+// Start of the Runge-Kutta reverse (interior): qcur = Qbar, acc = 0, and
+// fbar[c][k][j] += w Qbar_c on the source plane (fbar non-null).
+__global__ void __launch_bounds__(256) k_adj_init(Layout L, const double* __restrict__ Qbar, double* __restrict__ qcur,
+                                                  double* __restrict__ acc, double* __restrict__ fbar, int i_f,
+                                                  double w) {
   const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
   if (t >= nij * (unsigned)L.nk) return;
@@ -605,35 +680,44 @@ __global__ void __launch_bounds__(256) k_axpy_interior(Layout L, const double* a
   const int j = (int)((t % nij) / ni);
   const int k = (int)(t / nij);
   const long long n = L.at(i, j, k);
-  for (int c = 0; c < 5; ++c) out[c * L.fe + n] = a[c * L.fe + n] + (b ? b[c * L.fe + n] : 0.0);
-}
-
-// fbar[c][k][j] += w * qbar_c(i_f, j, k)
-__global__ void __launch_bounds__(256) k_fbar(Layout L, int i_f, double w, const double* __restrict__ qb,
-                                              double* __restrict__ fbar) {
-  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (unsigned)L.nj * L.nk) return;
-  const int j = (int)(t % (unsigned)L.nj), k = (int)(t / (unsigned)L.nj);
-  const long long n = L.at(i_f, j, k);
-  for (int c = 0; c < 5; ++c) fbar[((long long)c * L.nk + k) * L.nj + j] += w * qb[c * L.fe + n];
+  for (int c = 0; c < 5; ++c) {
+    const double q = Qbar[c * L.fe + n];
+    qcur[c * L.fe + n] = q;
+    acc[c * L.fe + n] = 0.0;
+    if (fbar && i == i_f) fbar[((long long)c * L.nk + k) * L.nj + j] += w * q;
+  }
 }
 
 inline unsigned nb(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// Qbar_out = (dR/dQ|Q)^T (coef * qb) on the interior.
+// qout = (dR/dQ|Q)^T (coef * qb) on the interior; with acc non-null also
+// acc += qb (the gather pass is the last one that reads qb); fbar, qfin: see
+// finish_node.
 hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const double* qb, double coef, double* Wk,
-                        const double* add, double* qout, double* acc = nullptr) {
+                        double* qout, double* acc = nullptr, double* fbar = nullptr, int i_f = -1, double fw = 0.0,
+                        double* qfin = nullptr) {
   const Layout& L = A.L;
   const long long nB1 = (long long)(L.ni + 2) * (L.nj + 2) * (L.nk + 2);
-  const long long nPad = (long long)(L.ni + 4) * (L.nj + 4) * (L.nk + 4);
-  const long long nIn = (long long)L.ni * L.nj * L.nk;
   const long long nFace = (long long)(L.ni + 1) * L.nj * L.nk + (long long)L.ni * (L.nj + 1) * L.nk +
                          (long long)L.ni * L.nj * (L.nk + 1);
+  const long long gi = A.bc0 == 0 ? 4 : 0, gj = A.bc1 == 0 ? 4 : 0, gk = A.bc2 == 0 ? 4 : 0;
+  const long long nB = (L.ni + gi) * (L.nj + gj) * (L.nk + gk);
+  long long nBand = 0;
+  {
+    const long long nn[3] = {L.ni, L.nj, L.nk};
+    const int bc[3] = {A.bc0, A.bc1, A.bc2};
+    long long bs[3], cs[3];
+    for (int d = 0; d < 3; ++d) {
+      bs[d] = bc[d] == 0 ? (nn[d] < 4 ? nn[d] : 4) : 0;
+      cs[d] = bc[d] == 0 ? (nn[d] > 4 ? nn[d] - 4 : 0) : nn[d];
+    }
+    nBand = bs[2] * nn[1] * nn[0] + cs[2] * bs[1] * nn[0] + cs[2] * cs[1] * bs[0];
+  }
   k_adj_flux<<<nb(nB1, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
   k_adj_face<<<nb(nFace, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
   k_adj_dnode<<<nb(nB1, 256), 256, 0, s>>>(A, Q, Wk);
-  k_adj_gather<<<nb(nPad, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
-  k_adj_fold<<<nb(nIn, 256), 256, 0, s>>>(A, Wk + (long long)W_G * L.fe, add, qout, acc, qb);
+  k_adj_gather<<<nb(nB, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, qb, fbar, i_f, fw, qfin);
+  if (nBand > 0) k_adj_fold<<<nb(nBand, 256), 256, 0, s>>>(A, Wk, qout, acc, fbar, i_f, fw, qfin);
   return hipGetLastError();
 }
 
@@ -644,7 +728,7 @@ size_t adjoint_work_elems(const Layout& L) { return (size_t)W_NF * (size_t)L.fe;
 hipError_t run_residual_vjp(hipStream_t s, const AdjArgs& a, const double* Q, const double* Rbar, double* Qbar,
                             double* work) {
   AdjK A{a.L, a.P, a.M, a.bc0, a.bc1, a.bc2};
-  return residual_vjp(s, A, Q, Rbar, 1.0, work, nullptr, Qbar);
+  return residual_vjp(s, A, Q, Rbar, 1.0, work, Qbar);
 }
 
 hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt, double dt, double* Qbar,
@@ -656,24 +740,24 @@ hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt,
   double* qcur = work + (long long)W_Q1 * fe;
   double* qnext = work + (long long)(W_Q1 + 5) * fe;
   double* acc = work + (long long)W_ACC * fe;
-  // qcur = Qbar, acc = 0 (interior)
-  k_axpy_interior<<<nb(nIn, 256), 256, 0, s>>>(L, Qbar, nullptr, qcur);
-  hipError_t e = hipMemsetAsync(acc, 0, (size_t)5 * fe * sizeof(double), s);
-  if (e != hipSuccess) return e;
+  // qcur = Qbar, acc = 0, fbar += alpha_5 dt Qbar (interior)
+  const bool want_f = fbar && a.i_f >= 0;
+  k_adj_init<<<nb(nIn, 256), 256, 0, s>>>(L, Qbar, qcur, acc, want_f ? fbar : nullptr, a.i_f, rk_alpha(4) * dt);
+  hipError_t e = hipSuccess;
   for (int l = 4; l >= 0; --l) {
     const double al = rk_alpha(l) * dt;
-    if (fbar && a.i_f >= 0)
-      k_fbar<<<nb((long long)L.nj * L.nk, 256), 256, 0, s>>>(L, a.i_f, al, qcur, fbar);
-    // qbar_{l-1} = (dR/dQ|Q^(l-1))^T (-alpha_l dt qbar_l), and acc += qbar_l
-    // (in the fold pass, which reads qbar_l after the gather is done with it)
+    // qbar_{l-1} = (dR/dQ|Q^(l-1))^T (-alpha_l dt qbar_l), acc += qbar_l,
+    // fbar += alpha_{l-1} dt qbar_{l-1}; after the last stage Qbar = acc +
+    // qbar_0
     const double* Ql = ckpt + (long long)l * 5 * fe;
-    e = residual_vjp(s, A, Ql, qcur, -al, work, nullptr, qnext, acc);
+    const bool f_next = want_f && l > 0;
+    e = residual_vjp(s, A, Ql, qcur, -al, work, qnext, acc, f_next ? fbar : nullptr, a.i_f,
+                     f_next ? rk_alpha(l - 1) * dt : 0.0, l == 0 ? Qbar : nullptr);
     if (e != hipSuccess) return e;
     double* tmp = qcur;
     qcur = qnext;
     qnext = tmp;
   }
-  k_axpy_interior<<<nb(nIn, 256), 256, 0, s>>>(L, acc, qcur, Qbar);
   return hipGetLastError();
 }
 

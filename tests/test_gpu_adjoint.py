@@ -71,7 +71,14 @@ def _cases():
     # difference); seeded noise on the momenta and the pressure moves it off
     # them, so that both linearisations take the same branches
     c3 = _with_momentum_noise(_with_pressure_noise(I.tgv_case(32), 19), 29)
-    return {"jet61x29x23": c1, "wavy47x33x19_alpha07": c2, "tgv32": c3}
+    # the smallest block the library takes, periodic in every direction:
+    # every interior node but six is within two nodes of a periodic seam, so
+    # the ghost-image fold carries most of the adjoint (axes of 5, 6 and 7
+    # nodes: seam bands with a core of 1, 2 and 3 nodes)
+    n = (5, 6, 7)
+    xyz = I.wavy_grid(*n, L=(1.0, 1.2, 1.4), amp=0.2)
+    c4 = I.periodic_case(*n, xyz, I.smooth_state(*n, seed=13, amp=0.1), mu_ref=3e-3, sgs=1)
+    return {"jet61x29x23": c1, "wavy47x33x19_alpha07": c2, "tgv32": c3, "wavy5x6x7": c4}
 
 
 CASES = _cases()
@@ -95,12 +102,17 @@ def test_residual_adjoint_dot_product(orc, lesmi, name):
     s.close()
 
 
-def test_rk_step_adjoint_dot_product(orc, lesmi):
+@pytest.mark.parametrize("name,i_f", [("jet61x29x23", 7), ("wavy5x6x7", 2)])
+def test_rk_step_adjoint_dot_product(orc, lesmi, name, i_f):
+    """One RK step with forcing on plane i_f: <w, dQ^{n+1}> against
+    <Qbar, v> + <fbar, df>.  On the 5 x 6 x 7 periodic box the forcing plane
+    i = 2 holds both nodes away from every seam and nodes next to one, so
+    the source-plane update and the final sum are taken on both paths."""
     import torch
-    case = CASES["jet61x29x23"]  # with resolved pressure differences
+    case = CASES[name]
+    print(f"[gpu] rk-step adjoint {name}", flush=True)
     m = orc.metrics(case)
     rng = np.random.default_rng(7)
-    i_f = 7
     f = 1e-3 * rng.uniform(-1, 1, size=(5, case["nk"], case["nj"]))
     df = rng.standard_normal(f.shape)
     v = _interior_rand(case, 8)
