@@ -216,9 +216,11 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
   }
   const size_t fe = (size_t)c->L.fe;
   c->kchunk = les::stage_kchunk(c->L);
-  c->part_n = les::ref_blocks(c->L);  // partials of the reference and the fused kernel
-  long long sb = les::stage_blocks(c->L, c->kchunk);
+  // partials of the reference kernel, the fused kernel and the CFL kernel
+  c->part_n = les::ref_blocks(c->L);
+  const long long sb = les::stage_blocks(c->L, c->kchunk), cb = les::cfl_blocks(c->L);
   if (sb > c->part_n) c->part_n = sb;
+  if (cb > c->part_n) c->part_n = cb;
   bool ok = hipMalloc(&c->M, 10 * fe * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->S[0], 5 * fe * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->S[1], 5 * fe * sizeof(double)) == hipSuccess &&

@@ -13,6 +13,7 @@
 // * k_norm_final: RMS / max norms of R from per-block partials (FP64).
 // * k_probe: pressure-fluctuation objective on a plane and its gradient.
 #include "les_common.hpp"
+#include "les_launch.hpp"
 
 namespace les {
 
@@ -198,16 +199,27 @@ __global__ void k_ghost_fill_f32(Layout L, int bc0, int bc1, int bc2, float* __r
 }
 
 // ---------------------------------------------------------------------------
-// CFL time step: per-block minima, then one block for the global minimum.
+// CFL time step: per-block minima, then one block of 1024 threads for the
+// global minimum.  A block covers 64 columns of 4 rows in kc consecutive
+// planes.  Its columns are a 64-element chunk of the row storage (chunks
+// start at the 128-byte-aligned row start, so node i sits in column
+// i + LEAD): every row segment is four whole 128-byte lines.  kc = 1 (many
+// small blocks keep the most loads in flight) unless that would leave more
+// than CFL_PARTS partials for the final block.  NaN wins every comparison,
+// so that a non-physical state is reported.
 // ---------------------------------------------------------------------------
+constexpr long long CFL_PARTS = 65536;
+
+__device__ __forceinline__ double min_nan(double a, double b) { return (b < a || b != b) ? b : a; }
+
 __global__ void __launch_bounds__(256) k_cfl_partial(Layout L, Phys P, const double* __restrict__ M,
-                                                     const double* __restrict__ Q, double* __restrict__ part) {
+                                                     const double* __restrict__ Q, int kc, double* __restrict__ part) {
   __shared__ double red[4];
-  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int i = blockIdx.x * 64 + threadIdx.x - LEAD;
   const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
+  const int k0 = blockIdx.z * kc, k1 = min(L.nk, k0 + kc);
   double loc = INFINITY;
-  if (i < L.ni && j < L.nj) {
+  for (int k = k0; k < k1 && i >= 0 && i < L.ni && j < L.nj; ++k) {
     long long n = L.at(i, j, k);
     double q0 = Q[n], q1 = Q[L.fe + n], q2 = Q[2 * L.fe + n], q3 = Q[3 * L.fe + n], q4 = Q[4 * L.fe + n];
     double u, v, w, p, tem;
@@ -225,8 +237,9 @@ __global__ void __launch_bounds__(256) k_cfl_partial(Layout L, Phys P, const dou
       lam += fabs(U) + c * sqrt(gg);
       g2 += gg;
     }
-    loc = 1.0 / (lam + 2.0 * nuv * g2);
-    if (!(loc > 0.0) || !(q0 > 0.0) || !(p > 0.0)) loc = NAN;
+    double l = 1.0 / (lam + 2.0 * nuv * g2);
+    if (!(l > 0.0) || !(q0 > 0.0) || !(p > 0.0)) l = NAN;
+    loc = min_nan(loc, l);
   }
   loc = wave_min(loc);
   const int tid = threadIdx.y * 64 + threadIdx.x;
@@ -234,26 +247,24 @@ __global__ void __launch_bounds__(256) k_cfl_partial(Layout L, Phys P, const dou
   __syncthreads();
   if (tid == 0) {
     double m = red[0];
-    for (int a = 1; a < 4; ++a) m = (red[a] < m || red[a] != red[a]) ? red[a] : m;
+    for (int a = 1; a < 4; ++a) m = min_nan(m, red[a]);
     part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = m;
   }
 }
 
 // scal[0] = dt; flag |= 1 when the minimum is not a positive finite number.
-__global__ void __launch_bounds__(256) k_cfl_final(const double* __restrict__ part, long long np, double cfl,
-                                                   double* __restrict__ scal, int* __restrict__ flag) {
-  __shared__ double red[4];
+__global__ void __launch_bounds__(1024) k_cfl_final(const double* __restrict__ part, long long np, double cfl,
+                                                    double* __restrict__ scal, int* __restrict__ flag) {
+  __shared__ double red[16];
   double m = INFINITY;
-  for (long long b = threadIdx.x; b < np; b += 256) {
-    double v = part[b];
-    m = (v < m || v != v) ? v : m;
-  }
+#pragma unroll 8
+  for (long long b = threadIdx.x; b < np; b += 1024) m = min_nan(m, part[b]);
   m = wave_min(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
     double r = red[0];
-    for (int a = 1; a < 4; ++a) r = (red[a] < r || red[a] != red[a]) ? red[a] : r;
+    for (int a = 1; a < 16; ++a) r = min_nan(r, red[a]);
     double dt = cfl * r;
     if (!(dt > 0.0) || !(dt < INFINITY)) *flag |= 1;
     scal[0] = dt;
@@ -567,11 +578,23 @@ hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3]
 
 long long ref_blocks(const Layout& L) { return (long long)nblk(L.ni, 64) * nblk(L.nj, 4) * L.nk; }
 
+// planes per CFL block
+static int cfl_kc(const Layout& L) {
+  const long long plane = (long long)nblk(L.ni + LEAD, 64) * nblk(L.nj, 4);
+  long long kc = (plane * L.nk + CFL_PARTS - 1) / CFL_PARTS;
+  return (int)(kc < 1 ? 1 : (kc > L.nk ? L.nk : kc));
+}
+
+long long cfl_blocks(const Layout& L) {
+  return (long long)nblk(L.ni + LEAD, 64) * nblk(L.nj, 4) * nblk(L.nk, cfl_kc(L));
+}
+
 hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
                       double* scal, int* flag) {
-  dim3 g(nblk(L.ni, 64), nblk(L.nj, 4), L.nk), b(64, 4);
-  k_cfl_partial<<<g, b, 0, s>>>(L, P, M, Q, part);
-  k_cfl_final<<<1, 256, 0, s>>>(part, ref_blocks(L), P.cfl, scal, flag);
+  const int kc = cfl_kc(L);
+  dim3 g(nblk(L.ni + LEAD, 64), nblk(L.nj, 4), nblk(L.nk, kc)), b(64, 4);
+  k_cfl_partial<<<g, b, 0, s>>>(L, P, M, Q, kc, part);
+  k_cfl_final<<<1, 1024, 0, s>>>(part, cfl_blocks(L), P.cfl, scal, flag);
   return hipGetLastError();
 }
 

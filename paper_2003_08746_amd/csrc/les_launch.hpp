@@ -12,6 +12,8 @@ long long ghost_count(const Layout& L);
 hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], double* q, const double* frozen, int nf);
 hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3], float* q, const double* frozen);
 long long ref_blocks(const Layout& L);
+// partials written by the CFL kernel
+long long cfl_blocks(const Layout& L);
 hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
                       double* scal, int* flag);
 hipError_t launch_residual_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q,
