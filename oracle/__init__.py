@@ -75,6 +75,8 @@ def _load():
     lib.orc_objective.restype = ctypes.c_double
     lib.orc_objective.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double]
+    lib.orc_stats.restype = None
+    lib.orc_stats.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
     lib.orc_rk_scalar.restype = None
     lib.orc_rk_scalar.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp]
     _lib = lib
@@ -214,3 +216,20 @@ def rk_scalar(lam: complex, dt: float, y0: complex = 1.0) -> complex:
     yi = ctypes.c_double(float(np.imag(y0)))
     lib.orc_rk_scalar(float(np.real(lam)), float(np.imag(lam)), float(dt), ctypes.byref(yr), ctypes.byref(yi))
     return complex(yr.value, yi.value)
+
+
+STATS_FIELDS = ("rho", "u", "v", "w", "p", "uu", "vv", "ww", "uv", "uw", "vw", "pp")
+
+
+def stats(case, Q, acc=None, prm=None) -> np.ndarray:
+    """Running statistics (Sec. 5 mean-flow and RMS profiles, averaged over
+    time and the periodic direction k): acc[s][j][i] += sum_k phi_s, phi in
+    STATS_FIELDS order.  Returns acc (a new zero array when acc is None)."""
+    lib = _load()
+    prm = case["params"] if prm is None else prm
+    if acc is None:
+        acc = np.zeros((len(STATS_FIELDS), case["nj"], case["ni"]))
+    assert acc.shape == (len(STATS_FIELDS), case["nj"], case["ni"]) and acc.dtype == np.float64
+    assert acc.flags.c_contiguous
+    lib.orc_stats(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(Q)), _ptr(acc))
+    return acc

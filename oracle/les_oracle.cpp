@@ -689,6 +689,27 @@ double orc_objective(const orc_dims* d, const orc_params* P, const double* m, do
 
 // Test hook for the scalar rules R11 and the RK driver on y' = lambda y
 // (complex lambda), used to check the amplification polynomial.
+// Running flow statistics (the time- and azimuth-averaged mean-flow and RMS
+// profiles of Sec. 5; the averaged periodic direction is k):
+//   acc[s][j][i] += sum over k = 0..nk-1 of phi_s(i, j, k),
+//   phi = (rho, u, v, w, p, uu, vv, ww, uv, uw, vw, pp),
+// with the primitives of Eq. 2: u_a = (rho u_a) / rho,
+// p = (gamma - 1)(e - rho (u^2 + v^2 + w^2) / 2).  acc: dense [12][nj][ni].
+void orc_stats(const orc_dims* d, const orc_params* P, const double* Q, double* acc) {
+  Box b(*d);
+  const size_t plane = (size_t)b.ni * b.nj;
+  for (int j = 0; j < b.nj; ++j)
+    for (int i = 0; i < b.ni; ++i)
+      for (int k = 0; k < b.nk; ++k) {
+        const size_t n = b.at(i, j, k);
+        const double rho = Q[n];
+        const double u = Q[b.N + n] / rho, v = Q[2 * b.N + n] / rho, w = Q[3 * b.N + n] / rho;
+        const double p = (P->gamma - 1.0) * (Q[4 * b.N + n] - 0.5 * rho * (u * u + v * v + w * w));
+        const double phi[12] = {rho, u, v, w, p, u * u, v * v, w * w, u * v, u * w, v * w, p * p};
+        for (int s = 0; s < 12; ++s) acc[s * plane + (size_t)j * b.ni + i] += phi[s];
+      }
+}
+
 void orc_rk_scalar(double lr, double li, double dt, double* yr, double* yi) {
   double y0r = *yr, y0i = *yi, cr = y0r, ci = y0i;
   for (int l = 0; l < 5; ++l) {

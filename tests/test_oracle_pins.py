@@ -451,3 +451,55 @@ def test_paper_constants():
     assert p["Pr_sgs"] == g["Pr_sgs"]["value"]
     assert abs(p["S_suth"] * 288.15 - g["S1_kelvin"]["value"]) < 1e-12
     assert abs(p["mu_ref"] - g["mach_jet"]["value"] / g["reynolds_jet"]["value"]) < 1e-20
+
+
+# ---------------------------------------------------------------------------
+# Running statistics (mean-flow and RMS profiles of Sec. 5): closed forms
+# ---------------------------------------------------------------------------
+def _harmonic_state(ni, nj, nk, gamma):
+    """Primitives that vary along k by whole harmonics of the period nk (and
+    along i, j through the means), and the conserved state Q of Eq. 2."""
+    i = np.arange(-2, ni + 2)[None, None, :]
+    j = np.arange(-2, nj + 2)[None, :, None]
+    k = np.arange(-2, nk + 2)[:, None, None]
+    th = 2.0 * np.pi * k / nk
+    U0, V0, p0 = 0.3 + 0.01 * i, -0.1 + 0.02 * j, 0.7 + 0.005 * (i + j)
+    A, B, C, eps = 0.05, 0.03, 0.02, 0.1
+    rho = 1.2 * (1.0 + eps * np.cos(2.0 * th)) + 0 * i * j
+    u = U0 + A * np.sin(th) + 0 * j
+    v = V0 + B * np.cos(th) + 0 * i
+    w = 0.0 * (i + j + k)
+    p = p0 + C * np.sin(th + 0.3)
+    e = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    Q = np.stack([rho, rho * u, rho * v, rho * w, e]).astype(np.float64)
+    means = dict(U0=U0[0, 0, 2:-2], V0=V0[0, 2:-2, 0], p0=p0[0, 2:-2, 2:-2], A=A, B=B, C=C)
+    return np.ascontiguousarray(Q), means
+
+
+@pytest.mark.parametrize("nk", [3, 7, 16])
+def test_stats_closed_forms(orc, nk):
+    """Sums over a full period of sin, cos and their products (N >= 3):
+    sum cos(m th) = sum sin(m th) = 0 (m = 1, 2), sum sin^2 = sum cos^2 = N/2,
+    sum sin cos = 0.  With the means varying in i and j a transposed index
+    fails, with rho varying in k a momentum taken for a velocity fails, and
+    the pressure variance pins p = (gamma - 1)(e - rho |u|^2 / 2)."""
+    ni, nj = 6, 5
+    case = I.periodic_case(ni, nj, nk, I.wavy_grid(ni, nj, nk), np.zeros((5, nk + 4, nj + 4, ni + 4)))
+    g = case["params"]["gamma"]
+    Q, mm = _harmonic_state(ni, nj, nk, g)
+    acc = orc.stats(case, Q)
+    N = nk
+    U0 = np.broadcast_to(mm["U0"][None, :], (nj, ni))
+    V0 = np.broadcast_to(mm["V0"][:, None], (nj, ni))
+    p0 = mm["p0"]
+    A, B, C = mm["A"], mm["B"], mm["C"]
+    want = {
+        "rho": np.full((nj, ni), N * 1.2), "u": N * U0, "v": N * V0, "w": np.zeros((nj, ni)), "p": N * p0,
+        "uu": N * (U0 ** 2 + A * A / 2), "vv": N * (V0 ** 2 + B * B / 2), "ww": np.zeros((nj, ni)),
+        "uv": N * U0 * V0, "uw": np.zeros((nj, ni)), "vw": np.zeros((nj, ni)), "pp": N * (p0 ** 2 + C * C / 2),
+    }
+    for s, name in enumerate(orc.STATS_FIELDS):
+        np.testing.assert_allclose(acc[s], want[name], rtol=1e-13, atol=1e-13 * N, err_msg=name)
+    # a second call adds the same sums (time accumulation)
+    acc2 = orc.stats(case, Q, acc.copy())
+    np.testing.assert_allclose(acc2, 2 * acc, rtol=1e-15, atol=0)
