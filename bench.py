@@ -16,8 +16,8 @@ Prints one JSON line:
              events around every stage launch, against 8 TB/s;
   cpu_baseline  the plain FP64 CPU oracle on a bounded sample of the same
              workload (rank 0, host cores of this machine).
-Extra keys report the mixed-precision path and the adjoint/forward cost
-when those paths are available.
+Extra keys report the mixed-precision path, the adjoint/forward cost and the
+running flow statistics when those paths are available.
 """
 import argparse
 import hashlib
@@ -135,6 +135,31 @@ def time_adjoint(ni=128, nj=64, nk=64, nsteps=50, i_f=8, i_p=16):
             "adjoint_over_plain_forward": round(res["backward_ms"] / plain, 3)}
 
 
+def time_stats(case, calls=50):
+    """Running flow statistics (les_stats_accumulate) on the benchmark shard:
+    mean time per call from HIP events on the solver's stream, against its
+    algorithmic bytes (Q read once, 40 B per point, plus the read-modify-write
+    of the 12 column sums, 192 B per (i, j) column)."""
+    import torch
+    from paper_2003_08746_amd import lesmi
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    acc = s.stats_accumulate(Q)  # warm-up (allocates acc)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(s.stream)
+    for _ in range(calls):
+        s.stats_accumulate(Q, acc)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / calls
+    ni, nj, nk = case["ni"], case["nj"], case["nk"]
+    byts = 40.0 * ni * nj * nk + 192.0 * ni * nj
+    s.close()
+    return {"us_per_call": round(us, 2), "algorithmic_GBps": round(byts / us / 1e3, 1),
+            "frac_of_hbm_peak": round(byts / us / 1e3 / HBM_PEAK_GBS, 4)}
+
+
 def time_large(steps, ni=800, nj=500, nk=500):
     """The 800 x 500 x 500 shard (2.0e8 points), generated on the device."""
     import torch
@@ -184,7 +209,7 @@ def main():
     ap.add_argument("--nj", type=int, default=128)
     ap.add_argument("--nk", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and adjoint legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision, adjoint and statistics legs")
     ap.add_argument("--large", action="store_true",
                     help="also time the 800 x 500 x 500 shard (FP64 and mixed, 20 steps each)")
     ap.add_argument("--large-steps", type=int, default=20)
@@ -260,6 +285,10 @@ def main():
             extra["adjoint"] = time_adjoint()
         except Exception as e:
             extra["adjoint"] = {"error": str(e)[:200]}
+        try:
+            extra["stats"] = time_stats(case)
+        except Exception as e:
+            extra["stats"] = {"error": str(e)[:200]}
         out["extra"] = extra
     if args.large:
         out.setdefault("extra", {})["large"] = time_large(args.large_steps)

@@ -182,7 +182,7 @@ int les_adjoint_step(les_ctx *ctx, const double *stage_ckpt, double dt, double *
  * Q: device, library layout, FP64; its ghost layers are filled in place.
  * Rbar: device, library layout; only interior values are read.
  * Qbar: device, library layout; interior written (must not alias Q or Rbar).
- * Allocates the adjoint work arrays on first use (51 fields of field_elems
+ * Allocates the adjoint work arrays on first use (84 fields of field_elems
  * doubles, kept by the context). */
 int les_residual_adjoint(les_ctx *ctx, double *Q, const double *Rbar, double *Qbar);
 
@@ -192,6 +192,20 @@ int les_residual_adjoint(les_ctx *ctx, double *Q, const double *Rbar, double *Qb
  * with p = (gamma - 1)(e - (m_1^2 + m_2^2 + m_3^2) / (2 rho)). */
 int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, double weight, double *J_accum,
                         double *Qbar);
+
+/* Running flow statistics for the time- and azimuth-averaged mean-flow and
+ * RMS profiles of Sec. 5 (the periodic k direction is the averaged one):
+ *   acc[s][j][i] += sum over k = 0..nk-1 of phi_s(i, j, k),
+ *   phi = (rho, u, v, w, p, u u, v v, w w, u v, u w, v w, p p),
+ * with the primitives of Eq. 2: u_a = (rho u_a) / rho and
+ * p = (gamma - 1)(e - rho |u|^2 / 2).  After N calls the Reynolds means are
+ * acc / (N nk); e.g. u_rms = sqrt(<u u> - <u>^2).
+ * Q: device, library layout, FP64 (interior read only).
+ * acc: device, dense [LES_STATS_NF][nj][ni], FP64, caller-owned; zero it
+ *    before the first call.  The sums over k are taken in a fixed order, so
+ *    repeated runs give identical results. */
+#define LES_STATS_NF 12
+int les_stats_accumulate(les_ctx *ctx, const double *Q, double *acc);
 
 const char *les_last_error(const les_ctx *ctx);
 const char *les_last_create_error(void);

@@ -410,6 +410,13 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
   return LES_OK;
 }
 
+int les_stats_accumulate(les_ctx* ctx, const double* Q, double* acc) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_stats_accumulate: null context");
+  if (!Q || !acc) return fail(ctx, LES_ERR_ARG, "les_stats_accumulate: Q and acc are required");
+  HIPCHK(ctx, les::launch_stats(ctx->s, ctx->L, ctx->P, Q, acc));
+  return LES_OK;
+}
+
 int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qbar) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual_adjoint: null context");
   if (!Q || !Rbar || !Qbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Q, Rbar and Qbar are required");

@@ -12,6 +12,8 @@
 //   cross-check the fused stage kernel.
 // * k_norm_final: RMS / max norms of R from per-block partials (FP64).
 // * k_probe: pressure-fluctuation objective on a plane and its gradient.
+// * k_stats: running sums of the primitives and their second moments over
+//   the periodic k direction (mean-flow and RMS profiles).
 #include "les_common.hpp"
 #include "les_launch.hpp"
 
@@ -540,6 +542,60 @@ __global__ void __launch_bounds__(64) k_probe_final(const double* __restrict__ p
 // ---------------------------------------------------------------------------
 namespace les {
 
+// ---------------------------------------------------------------------------
+// Running flow statistics (Sec. 5: time- and azimuth-averaged mean-flow and
+// RMS profiles; the periodic k direction is the averaged one):
+//   acc[s][j][i] += sum over k of phi_s(i, j, k),
+//   phi = (rho, u, v, w, p, uu, vv, ww, uv, uw, vw, pp).
+// A block of 64 x 4 threads covers 64 nodes of one row j; thread (x, y) sums
+// the y-th of four contiguous k ranges in ascending k, and the four partial
+// sums are added in a fixed order, so repeated runs give identical sums.
+// ---------------------------------------------------------------------------
+constexpr int STATS_NF = 12;
+
+__global__ void __launch_bounds__(256) k_stats(Layout L, Phys P, const double* __restrict__ Q,
+                                               double* __restrict__ acc) {
+  __shared__ double red[3][STATS_NF][64];
+  const int x = threadIdx.x, y = threadIdx.y;
+  const int i = blockIdx.x * 64 + x, j = blockIdx.y;
+  const int kper = (L.nk + 3) / 4;
+  const int k0 = y * kper, k1 = min(L.nk, k0 + kper);
+  double s[STATS_NF];
+#pragma unroll
+  for (int f = 0; f < STATS_NF; ++f) s[f] = 0.0;
+  if (i < L.ni) {
+#pragma unroll 2
+    for (int k = k0; k < k1; ++k) {
+      const long long n = L.at(i, j, k);
+      const double rho = Q[n];
+      double u, v, w, p, tem;
+      prim_from_q(rho, Q[L.fe + n], Q[2 * L.fe + n], Q[3 * L.fe + n], Q[4 * L.fe + n], P, u, v, w, p, tem);
+      s[0] += rho;
+      s[1] += u;
+      s[2] += v;
+      s[3] += w;
+      s[4] += p;
+      s[5] += u * u;
+      s[6] += v * v;
+      s[7] += w * w;
+      s[8] += u * v;
+      s[9] += u * w;
+      s[10] += v * w;
+      s[11] += p * p;
+    }
+  }
+  if (y > 0)
+#pragma unroll
+    for (int f = 0; f < STATS_NF; ++f) red[y - 1][f][x] = s[f];
+  __syncthreads();
+  if (y == 0 && i < L.ni) {
+    const long long plane = (long long)L.ni * L.nj;
+#pragma unroll
+    for (int f = 0; f < STATS_NF; ++f)
+      acc[f * plane + (long long)j * L.ni + i] += ((s[f] + red[0][f][x]) + red[1][f][x]) + red[2][f][x];
+  }
+}
+
 static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_metrics(hipStream_t s, const Layout& L, const int bc[3], const double* xyz, double* M) {
@@ -573,6 +629,12 @@ hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], do
 
 hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3], float* q, const double* frozen) {
   k_ghost_fill_f32<<<nblk(ghost_count(L), 256), 256, 0, s>>>(L, bc[0], bc[1], bc[2], q, frozen);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(hipStream_t s, const Layout& L, const Phys& P, const double* Q, double* acc) {
+  dim3 g(nblk(L.ni, 64), L.nj), b(64, 4);
+  k_stats<<<g, b, 0, s>>>(L, P, Q, acc);
   return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@ hipError_t launch_metrics_export(hipStream_t s, const Layout& L, const double* M
 long long ghost_count(const Layout& L);
 hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], double* q, const double* frozen, int nf);
 hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3], float* q, const double* frozen);
+// acc[12][nj][ni] += sums over k of the primitives and their second moments
+hipError_t launch_stats(hipStream_t s, const Layout& L, const Phys& P, const double* Q, double* acc);
 long long ref_blocks(const Layout& L);
 // partials written by the CFL kernel
 long long cfl_blocks(const Layout& L);

@@ -27,8 +27,12 @@ LES_BC_PERIODIC, LES_BC_DIRICHLET = 0, 1
 
 EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",
             "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_adjoint_step", "les_residual_adjoint",
-            "les_probe_objective",
+            "les_probe_objective", "les_stats_accumulate",
             "les_last_error", "les_last_create_error"]
+
+# fields of les_stats_accumulate, in its order (sums over k of each)
+LES_STATS_NF = 12
+STATS_FIELDS = ("rho", "u", "v", "w", "p", "uu", "vv", "ww", "uv", "uw", "vw", "pp")
 
 
 class LesError(RuntimeError):
@@ -89,6 +93,8 @@ def lib():
     L.les_residual_adjoint.argtypes = [_vp, _vp, _vp, _vp]
     L.les_probe_objective.restype = ctypes.c_int
     L.les_probe_objective.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp, _vp]
+    L.les_stats_accumulate.restype = ctypes.c_int
+    L.les_stats_accumulate.argtypes = [_vp, _vp, _vp]
     L.les_last_error.restype = ctypes.c_char_p
     L.les_last_error.argtypes = [_vp]
     L.les_last_create_error.restype = ctypes.c_char_p
@@ -202,6 +208,10 @@ def les_probe_objective(ctx, Q_ptr, i_p, p_inf, weight, J_ptr, Qbar_ptr=None):
            "les_probe_objective")
 
 
+def les_stats_accumulate(ctx, Q_ptr, acc_ptr):
+    _check(lib().les_stats_accumulate(ctx, Q_ptr, acc_ptr), ctx, "les_stats_accumulate")
+
+
 def les_debug_use_reference(ctx, on: bool):
     _check(lib().les_debug_use_reference(ctx, 1 if on else 0), ctx, "les_debug_use_reference")
 
@@ -312,5 +322,29 @@ class Solver:
     def probe_objective(self, Q, i_p, p_inf, weight, J, Qbar=None):
         les_probe_objective(self.ctx, Q.data_ptr(), i_p, p_inf, weight, J.data_ptr(), _ptr(Qbar))
 
+    def stats_accumulate(self, Q, acc=None):
+        """acc[s][j][i] += sums over k of STATS_FIELDS at the interior of Q;
+        acc: device float64 (LES_STATS_NF, nj, ni), allocated (zero) when None."""
+        t = self.torch
+        if acc is None:
+            acc = t.zeros((LES_STATS_NF, self.nj, self.ni), dtype=t.float64, device=self.device)
+        assert acc.shape == (LES_STATS_NF, self.nj, self.ni) and acc.dtype == t.float64 and acc.is_contiguous()
+        les_stats_accumulate(self.ctx, Q.data_ptr(), acc.data_ptr())
+        return acc
+
     def use_reference(self, on=True):
         les_debug_use_reference(self.ctx, on)
+
+
+def stats_profiles(acc, samples):
+    """Reynolds means and RMS fluctuations from les_stats_accumulate sums;
+    samples = number of calls times nk.  Returns a dict of (nj, ni) tensors:
+    the means of STATS_FIELDS[:5] and u_rms, v_rms, w_rms, p_rms, uv (the
+    covariance <u'v'>)."""
+    import torch
+    m = {name: acc[s] / samples for s, name in enumerate(STATS_FIELDS)}
+    out = {name: m[name] for name in STATS_FIELDS[:5]}
+    for a in ("u", "v", "w", "p"):
+        out[a + "_rms"] = torch.sqrt(torch.clamp(m[a + a] - m[a] * m[a], min=0.0))
+    out["uv"] = m["uv"] - m["u"] * m["v"]
+    return out
