@@ -29,7 +29,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 class OrcDims(ctypes.Structure):
     _fields_ = [("ni", ctypes.c_int), ("nj", ctypes.c_int), ("nk", ctypes.c_int),
-                ("bc", ctypes.c_int * 3)]
+                ("bc", ctypes.c_int * 3), ("face", ctypes.c_int * 6), ("p_exit", ctypes.c_double * 6),
+                ("outside", ctypes.c_void_p)]
 
 
 class OrcParams(ctypes.Structure):
@@ -75,6 +76,8 @@ def _load():
     lib.orc_objective.restype = ctypes.c_double
     lib.orc_objective.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double]
+    lib.orc_fill_ghosts_faces.restype = None
+    lib.orc_fill_ghosts_faces.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
     lib.orc_stats.restype = None
     lib.orc_stats.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
     lib.orc_rk_scalar.restype = None
@@ -109,8 +112,28 @@ def params(p: dict) -> OrcParams:
     return o
 
 
+# boundary-face types of a Dirichlet direction (faces i-lo, i-hi, j-lo, j-hi,
+# k-lo, k-hi): frozen ghosts, characteristic (entrance / far field), exit
+FACE_FROZEN, FACE_CHARACTERISTIC, FACE_EXIT = 0, 1, 2
+
+
 def _dims_of(case):
-    return dims(case["ni"], case["nj"], case["nk"], case["bc"])
+    """orc_dims of a case; case["faces"] (optional) = dict(types=[6],
+    p_exit=[6], outside=padded (5, ...) state whose ghost values are the
+    outside state of characteristic faces)."""
+    d = dims(case["ni"], case["nj"], case["nk"], case["bc"])
+    fc = case.get("faces")
+    if fc:
+        for f in range(6):
+            d.face[f] = int(fc["types"][f])
+            d.p_exit[f] = float(fc.get("p_exit", [0.0] * 6)[f])
+        out = fc.get("outside")
+        if out is not None:
+            out = _c(out)
+            assert out.shape == (5, case["nk"] + 4, case["nj"] + 4, case["ni"] + 4)
+            d._outside_ref = out  # keep alive while d is used
+            d.outside = out.ctypes.data
+    return d
 
 
 def _c(a):
@@ -132,6 +155,16 @@ def fill_ghosts(case, a: np.ndarray) -> np.ndarray:
     a = _c(a).copy()
     lib.orc_fill_ghosts(ctypes.byref(_dims_of(case)), _ptr(a), a.shape[0])
     return a
+
+
+def fill_ghosts_faces(case, m, Q, prm=None) -> np.ndarray:
+    """Copy of Q with its ghosts filled: periodic wrap, frozen Dirichlet
+    ghosts and the boundary faces of case["faces"]."""
+    lib = _load()
+    prm = case["params"] if prm is None else prm
+    q = _c(Q).copy()
+    lib.orc_fill_ghosts_faces(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(q))
+    return q
 
 
 def residual(case, m, Q, prm=None, f=None, i_f=-1) -> np.ndarray:

@@ -62,6 +62,8 @@
 // every reduction is a serial loop.
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstddef>
 #include <cstring>
 #include <vector>
@@ -123,6 +125,14 @@ extern "C" {
 typedef struct {
   int ni, nj, nk;  // interior points per direction
   int bc[3];       // per direction i, j, k: 0 = periodic, 1 = frozen Dirichlet ghosts
+  // Boundary faces of a Dirichlet direction (R13, R14), in the order i-lo,
+  // i-hi, j-lo, j-hi, k-lo, k-hi: 0 = frozen ghosts, 1 = characteristic
+  // (R13), 2 = subsonic exit with imposed pressure p_exit (R14).  outside:
+  // padded [5][N] state whose ghost-node values are the outside state of
+  // the characteristic faces (NULL when no face needs it).
+  int face[6];
+  double p_exit[6];
+  const double* outside;
 } orc_dims;
 
 typedef struct {
@@ -148,11 +158,26 @@ struct Box {
   int ni, nj, nk, bc[3];
   int pi, pj, pk;  // padded extents
   size_t N;        // padded node count
+  int face[6];     // boundary-face types (orc_dims.face)
+  double p_exit[6];
+  const double* outside;
+  const double* m = nullptr;  // metrics, for the face normals (set where faces are applied)
+  double gamma = 0.0;
   explicit Box(const orc_dims& d) {
     ni = d.ni; nj = d.nj; nk = d.nk;
     bc[0] = d.bc[0]; bc[1] = d.bc[1]; bc[2] = d.bc[2];
     pi = ni + 2 * G; pj = nj + 2 * G; pk = nk + 2 * G;
     N = (size_t)pi * pj * pk;
+    for (int f = 0; f < 6; ++f) {
+      face[f] = d.face[f];
+      p_exit[f] = d.p_exit[f];
+    }
+    outside = d.outside;
+  }
+  bool any_face() const {
+    for (int f = 0; f < 6; ++f)
+      if (face[f] != 0) return true;
+    return false;
   }
   // index of node (i, j, k) with interior range 0..n-1 and ghosts -2, -1, n, n+1
   size_t at(int i, int j, int k) const {
@@ -164,6 +189,127 @@ struct Box {
 // offset of the unit step in direction d
 static inline void step(int d, int& di, int& dj, int& dk) {
   di = (d == 0); dj = (d == 1); dk = (d == 2);
+}
+
+// ---------------------------------------------------------------------------
+// R13, R14: boundary faces of a Dirichlet direction (Sec. 3: entrance, far
+// field and exit conditions).  A ghost node that lies outside the interior
+// along exactly one Dirichlet direction d, on a face of type 1 or 2, takes a
+// state built from the boundary node r (the interior node next to the face
+// on the same line along d, periodic indices wrapped: zero-order
+// extrapolation for both ghost layers) and, for type 1, the outside state at
+// the ghost node.  Edge and corner ghosts of two Dirichlet directions stay
+// frozen.
+//   R14 exit (subsonic, imposed pressure): velocity and internal energy per
+//       unit mass eps = p / ((gamma - 1) rho) from r, p = p_exit, hence
+//       rho = p_exit / ((gamma - 1) eps) and e from Eq. 2.
+//   R13 characteristic (entrance and far field, locally one-dimensional along
+//       the outward unit normal n = -+grad(xi_d) / |grad(xi_d)| at r):
+//       supersonic outflow (u.n >= c at r): the state of r;
+//       supersonic inflow (u.n <= -c outside): the outside state;
+//       otherwise R+ = u.n + 2c/(gamma-1) from r, R- = u.n - 2c/(gamma-1)
+//       from outside, u.n = (R+ + R-)/2, c = (gamma-1)(R+ - R-)/4, entropy
+//       p/rho^gamma and the tangential velocity from r when u.n >= 0, else
+//       from outside; rho = (c^2/(gamma s))^(1/(gamma-1)), p = rho c^2/gamma.
+// ---------------------------------------------------------------------------
+template <class S>
+void face_state(int type, double gamma, double p_exit, const double nrm[3], const S qr[5], const double qo[5],
+                S out[5]) {
+  const double gm1 = gamma - 1.0;
+  const S rho = qr[0];
+  const S u[3] = {qr[1] / rho, qr[2] / rho, qr[3] / rho};
+  const S uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const S p = gm1 * (qr[4] - 0.5 * rho * uu);
+  if (type == 2) {
+    const S rg = rho * p_exit / p;
+    out[0] = rg;
+    for (int a = 0; a < 3; ++a) out[1 + a] = rg * u[a];
+    out[4] = p_exit / gm1 + 0.5 * rg * uu;
+    return;
+  }
+  const double ro = qo[0];
+  const double uo[3] = {qo[1] / ro, qo[2] / ro, qo[3] / ro};
+  const double po = gm1 * (qo[4] - 0.5 * ro * (uo[0] * uo[0] + uo[1] * uo[1] + uo[2] * uo[2]));
+  const S cr = s_sqrt(gamma * p / rho);
+  const double co = std::sqrt(gamma * po / ro);
+  const S unr = u[0] * nrm[0] + u[1] * nrm[1] + u[2] * nrm[2];
+  const double uno = uo[0] * nrm[0] + uo[1] * nrm[1] + uo[2] * nrm[2];
+  if (val(unr) >= val(cr)) {
+    for (int c = 0; c < 5; ++c) out[c] = qr[c];
+    return;
+  }
+  if (uno <= -co) {
+    for (int c = 0; c < 5; ++c) out[c] = S(qo[c]);
+    return;
+  }
+  const S Rp = unr + 2.0 * cr / gm1;
+  const S Rm = S(uno - 2.0 * co / gm1);
+  const S un = 0.5 * (Rp + Rm);
+  const S cb = 0.25 * gm1 * (Rp - Rm);
+  S ent, ut[3];
+  if (val(un) >= 0.0) {
+    ent = p / s_pow(rho, gamma);
+    for (int a = 0; a < 3; ++a) ut[a] = u[a] - unr * nrm[a];
+  } else {
+    ent = S(po / std::pow(ro, gamma));
+    for (int a = 0; a < 3; ++a) ut[a] = S(uo[a] - uno * nrm[a]);
+  }
+  const S rb = s_pow(cb * cb / (gamma * ent), 1.0 / gm1);
+  const S pb = rb * cb * cb / gamma;
+  S ub[3], ubb = S(0.0);
+  for (int a = 0; a < 3; ++a) {
+    ub[a] = ut[a] + un * nrm[a];
+    ubb = ubb + ub[a] * ub[a];
+  }
+  out[0] = rb;
+  for (int a = 0; a < 3; ++a) out[1 + a] = rb * ub[a];
+  out[4] = pb / gm1 + 0.5 * rb * ubb;
+}
+
+template <class S>
+void fill_faces(const Box& b, S* a) {
+  if (!b.m) {
+    std::fprintf(stderr, "oracle: boundary faces need the metrics (call through an entry point that has them)\n");
+    std::abort();
+  }
+  for (int k = -G; k < b.nk + G; ++k)
+    for (int j = -G; j < b.nj + G; ++j)
+      for (int i = -G; i < b.ni + G; ++i) {
+        const int idx[3] = {i, j, k};
+        int nd = 0, d = -1, w[3];
+        for (int e = 0; e < 3; ++e) {
+          const int n = b.n(e);
+          const bool g = idx[e] < 0 || idx[e] >= n;
+          if (g && b.bc[e] == 1) {
+            ++nd;
+            d = e;
+          }
+          w[e] = ((idx[e] % n) + n) % n;
+        }
+        if (nd != 1) continue;
+        const int hi = idx[d] >= b.n(d) ? 1 : 0;
+        const int f = 2 * d + hi;
+        if (b.face[f] == 0) continue;
+        w[d] = hi ? b.n(d) - 1 : 0;  // boundary node r
+        const size_t r = b.at(w[0], w[1], w[2]), g = b.at(i, j, k);
+        // outward unit normal from grad(xi_d) = J (xi_d/J)_x,y,z at r
+        const double J = b.m[9 * b.N + r];
+        double nrm[3], nn = 0.0;
+        for (int x = 0; x < 3; ++x) {
+          nrm[x] = J * b.m[(size_t)(3 * d + x) * b.N + r];
+          nn += nrm[x] * nrm[x];
+        }
+        nn = std::sqrt(nn);
+        for (int x = 0; x < 3; ++x) nrm[x] = (hi ? 1.0 : -1.0) * nrm[x] / nn;
+        S qr[5], out[5];
+        double qo[5] = {0, 0, 0, 0, 0};
+        for (int c = 0; c < 5; ++c) {
+          qr[c] = a[(size_t)c * b.N + r];
+          if (b.outside) qo[c] = b.outside[(size_t)c * b.N + g];
+        }
+        face_state(b.face[f], b.gamma, b.p_exit[f], nrm, qr, qo, out);
+        for (int c = 0; c < 5; ++c) a[(size_t)c * b.N + g] = out[c];
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -192,6 +338,7 @@ void fill_ghosts(const Box& b, S* a, int nfields) {
           q[b.at(i, j, k)] = q[b.at(w[0], w[1], w[2])];
         }
   }
+  if (nfields == 5 && b.any_face()) fill_faces(b, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -589,10 +736,20 @@ void orc_metrics(const orc_dims* d, const double* xyz, double* m) { metrics(Box(
 
 void orc_fill_ghosts(const orc_dims* d, double* a, int nfields) { fill_ghosts(Box(*d), a, nfields); }
 
+// Ghost fill of a state including the boundary faces of d (R13, R14).
+void orc_fill_ghosts_faces(const orc_dims* d, const orc_params* P, const double* m, double* Q) {
+  Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
+  fill_ghosts(b, Q, 5);
+}
+
 // R of a state (ghosts of a copy are filled first).  f: [5][nk][nj] or NULL.
 void orc_residual(const orc_dims* d, const orc_params* P, const double* m, const double* Q, const double* f, int i_f,
                   double* R) {
   Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
   std::vector<double> q(Q, Q + 5 * b.N);
   fill_ghosts(b, q.data(), 5);
   residual(b, *P, m, q.data(), f, i_f, R);
@@ -602,6 +759,8 @@ void orc_residual(const orc_dims* d, const orc_params* P, const double* m, const
 void orc_residual_tangent(const orc_dims* d, const orc_params* P, const double* m, const double* Q, const double* dQ,
                           const double* f, const double* df, int i_f, double* R, double* dR) {
   Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
   std::vector<Dual> q(5 * b.N), r(5 * b.N);
   for (size_t n = 0; n < 5 * b.N; ++n) q[n] = Dual(Q[n], dQ ? dQ[n] : 0.0);
   fill_ghosts(b, q.data(), 5);
@@ -626,6 +785,8 @@ double orc_cfl_dt(const orc_dims* d, const orc_params* P, const double* m, const
 double orc_rk_step(const orc_dims* d, const orc_params* P, const double* m, double* Q, double dt, const double* f,
                    int i_f, double* norms, double* stages) {
   Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
   if (!(dt > 0.0)) dt = cfl_dt(b, *P, m, Q);
   rk_step(b, *P, m, Q, dt, f, i_f, norms, stages);
   return dt;
@@ -636,6 +797,8 @@ double orc_rk_step(const orc_dims* d, const orc_params* P, const double* m, doub
 void orc_rk_step_tangent(const orc_dims* d, const orc_params* P, const double* m, double* Q, double* dQ, double dt,
                          const double* f, const double* df, int i_f) {
   Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
   std::vector<Dual> q(5 * b.N);
   for (size_t n = 0; n < 5 * b.N; ++n) q[n] = Dual(Q[n], dQ[n]);
   std::vector<Dual> fd;
@@ -660,6 +823,8 @@ double orc_objective_rollout(const orc_dims* d, const orc_params* P, const doubl
                              const double* f, const double* df, int i_f, int i_p, double p_inf, int nsteps, double dt,
                              double* dJ) {
   Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
   std::vector<Dual> q(5 * b.N);
   for (size_t n = 0; n < 5 * b.N; ++n) q[n] = Dual(Q0[n], dQ0 ? dQ0[n] : 0.0);
   size_t nf = (size_t)5 * b.nk * b.nj;
@@ -679,6 +844,8 @@ double orc_objective_rollout(const orc_dims* d, const orc_params* P, const doubl
 double orc_objective(const orc_dims* d, const orc_params* P, const double* m, double* Q0, const double* f, int i_f,
                      int i_p, double p_inf, int nsteps, double dt) {
   Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
   double J = 0.0;
   for (int s = 0; s < nsteps; ++s) {
     rk_step(b, *P, m, Q0, dt, f, i_f, nullptr, (double*)nullptr);

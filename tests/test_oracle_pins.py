@@ -503,3 +503,144 @@ def test_stats_closed_forms(orc, nk):
     # a second call adds the same sums (time accumulation)
     acc2 = orc.stats(case, Q, acc.copy())
     np.testing.assert_allclose(acc2, 2 * acc, rtol=1e-15, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Boundary faces (Sec. 3: entrance, far field, exit): properties of the
+# ghost states the oracle builds
+# ---------------------------------------------------------------------------
+def _prims(q, g):
+    rho = q[0]
+    u = q[1:4] / rho
+    p = (g - 1.0) * (q[4] - 0.5 * rho * (u * u).sum(0))
+    return rho, u, p
+
+
+def _face_case(seed=4):
+    """20 x 12 x 8 jet block, Dirichlet in i and j, periodic in k; the
+    interior is perturbed away from the outside state (the analytic profile
+    in the initial ghosts); entrance and far field characteristic, exit at
+    i-hi with the ambient pressure."""
+    c = I.jet_case(20, 12, 8, seed=seed)
+    c["bc"] = (1, 1, 0)
+    g = c["params"]["gamma"]
+    Q0 = c["Q"].copy()
+    rng = np.random.default_rng(seed)
+    Q = Q0.copy()
+    Q[1:4] += 0.05 * rng.uniform(-1, 1, size=Q[1:4].shape)
+    Q[4] *= 1.0 + 0.02 * rng.uniform(-1, 1, size=Q[4].shape)
+    c["Q"] = Q
+    c["faces"] = dict(types=[1, 2, 1, 1, 0, 0], p_exit=[0.0, 1.0 / g, 0, 0, 0, 0], outside=Q0)
+    return c, Q0
+
+
+def _normal(m, d, hi, i, j, k):
+    """Outward unit normal of face (d, hi) at padded node (i, j, k) from the
+    metrics: -+ grad xi_d / |grad xi_d|, grad xi_d = J (xi_d/J)."""
+    v = m[9, k, j, i] * m[3 * d:3 * d + 3, k, j, i]
+    return (1.0 if hi else -1.0) * v / np.linalg.norm(v)
+
+
+def test_face_exit_invariants(orc):
+    c, _ = _face_case()
+    g = c["params"]["gamma"]
+    m = orc.metrics(c)
+    q = orc.fill_ghosts_faces(c, m, c["Q"])
+    ni, nj, nk = c["ni"], c["nj"], c["nk"]
+    pe = c["faces"]["p_exit"][1]
+    count = 0
+    for gi in (ni, ni + 1):
+        for j in range(nj):
+            for kp in range(nk + 4):  # every k, ghosts in the periodic k included
+                kw = (kp - 2) % nk + 2
+                gq, rq = q[:, kp, j + 2, gi + 2], q[:, kw, j + 2, ni - 1 + 2]
+                rg, ug, pg = _prims(gq, g)
+                rr, ur, pr = _prims(rq, g)
+                assert abs(pg - pe) <= 1e-14 * pe
+                np.testing.assert_allclose(ug, ur, rtol=1e-14, atol=1e-15)
+                assert abs(pg / rg - pr / rr) <= 1e-14 * pr / rr  # internal energy per unit mass
+                count += 1
+    assert count == 2 * nj * (nk + 4)
+
+
+def test_face_characteristic_invariants(orc):
+    """Entrance (i-lo) and far field (j-lo, j-hi): supersonic outflow copies
+    the boundary node, supersonic inflow the outside state; otherwise the
+    outgoing invariant u.n + 2c/(g-1) is the boundary node's, the incoming
+    u.n - 2c/(g-1) the outside's, and entropy p/rho^g and tangential velocity
+    come from the upwind side."""
+    c, Q0 = _face_case()
+    g = c["params"]["gamma"]
+    m = orc.metrics(c)
+    q = orc.fill_ghosts_faces(c, m, c["Q"])
+    ni, nj, nk = c["ni"], c["nj"], c["nk"]
+    kinds = {"out": 0, "in": 0, "sub_out": 0, "sub_in": 0}
+    faces = [(0, 0), (1, 0), (1, 1)]  # (direction, hi)
+    for d, hi in faces:
+        n_d = ni if d == 0 else nj
+        ghosts = (n_d, n_d + 1) if hi else (-1, -2)
+        rb = n_d - 1 if hi else 0
+        tang = range(nj) if d == 0 else range(ni)
+        for gd in ghosts:
+            for t in tang:
+                for kp in range(nk + 4):
+                    kw = (kp - 2) % nk + 2
+                    if d == 0:
+                        G, R = (kp, t + 2, gd + 2), (kw, t + 2, rb + 2)
+                    else:
+                        G, R = (kp, gd + 2, t + 2), (kw, rb + 2, t + 2)
+                    n = _normal(m, d, hi, R[2], R[1], R[0])
+                    gq, rq, oq = q[(slice(None),) + G], q[(slice(None),) + R], Q0[(slice(None),) + G]
+                    rr, ur, pr = _prims(rq, g)
+                    ro, uo, po = _prims(oq, g)
+                    rg, ug, pg = _prims(gq, g)
+                    cr, co, cg = np.sqrt(g * pr / rr), np.sqrt(g * po / ro), np.sqrt(g * pg / rg)
+                    if ur @ n >= cr:
+                        np.testing.assert_array_equal(gq, rq)
+                        kinds["out"] += 1
+                    elif uo @ n <= -co:
+                        np.testing.assert_array_equal(gq, oq)
+                        kinds["in"] += 1
+                    else:
+                        scale = abs(ur @ n) + cr
+                        assert abs((ug @ n + 2 * cg / (g - 1)) - (ur @ n + 2 * cr / (g - 1))) <= 1e-13 * scale
+                        assert abs((ug @ n - 2 * cg / (g - 1)) - (uo @ n - 2 * co / (g - 1))) <= 1e-13 * scale
+                        src_r, src_u = (rr, ur) if ug @ n >= 0 else (ro, uo)
+                        src_p = pr if ug @ n >= 0 else po
+                        assert abs(pg / rg ** g - src_p / src_r ** g) <= 1e-13 * src_p / src_r ** g
+                        ut_g, ut_s = ug - (ug @ n) * n, src_u - (src_u @ n) * n
+                        np.testing.assert_allclose(ut_g, ut_s, rtol=0, atol=1e-13 * scale)
+                        kinds["sub_out" if ug @ n >= 0 else "sub_in"] += 1
+    # the block exercises every branch (jet core enters supersonically at i-lo)
+    assert kinds["in"] > 0 and kinds["sub_in"] > 0 and kinds["sub_out"] > 0, kinds
+
+
+def test_face_edges_stay_frozen(orc):
+    c, Q0 = _face_case()
+    m = orc.metrics(c)
+    q = orc.fill_ghosts_faces(c, m, c["Q"])
+    # ghosts in both i and j (two Dirichlet directions) keep the given values
+    for gi in (0, 1, c["ni"] + 2, c["ni"] + 3):
+        for gj in (0, 1, c["nj"] + 2, c["nj"] + 3):
+            np.testing.assert_array_equal(q[:, :, gj, gi], c["Q"][:, :, gj, gi])
+
+
+def test_face_uniform_flow_preserved(orc):
+    """A uniform subsonic flow whose outside state and exit pressure are its
+    own is reproduced in every face ghost, and its residual vanishes on the
+    curvilinear jet grid (free-stream preservation with the faces)."""
+    c = I.jet_case(20, 12, 8, seed=4)
+    c["bc"] = (1, 1, 0)
+    g = c["params"]["gamma"]
+    rho, u, p = 1.1, np.array([0.3, 0.08, -0.05]), 1.0 / g
+    Q = np.empty_like(c["Q"])
+    Q[0] = rho
+    Q[1:4] = rho * u[:, None, None, None]
+    Q[4] = p / (g - 1) + 0.5 * rho * (u @ u)
+    c["Q"] = Q
+    c["faces"] = dict(types=[1, 2, 1, 1, 0, 0], p_exit=[0.0, p, 0, 0, 0, 0], outside=Q.copy())
+    m = orc.metrics(c)
+    q = orc.fill_ghosts_faces(c, m, Q)
+    np.testing.assert_allclose(q, Q, rtol=1e-14, atol=1e-15)
+    R = I.interior(orc.residual(c, m, Q))
+    assert np.abs(R).max() <= 1e-12, np.abs(R).max()
