@@ -16,8 +16,9 @@ Prints one JSON line:
              events around every stage launch, against 8 TB/s;
   cpu_baseline  the plain FP64 CPU oracle on a bounded sample of the same
              workload (rank 0, host cores of this machine).
-Extra keys report the mixed-precision path, the adjoint/forward cost and the
-running flow statistics when those paths are available.
+Extra keys report the mixed-precision path, the adjoint/forward cost, the
+shard with boundary faces (entrance, exit, far field) and the running flow
+statistics when those paths are available.
 """
 import argparse
 import hashlib
@@ -60,11 +61,13 @@ def load_traffic(key):
     return None
 
 
-def time_gpu(case, prec, steps, warmup):
+def time_gpu(case, prec, steps, warmup, setup=None):
     import torch
     from paper_2003_08746_amd import lesmi
     s = lesmi.Solver(case, prec=prec)
     Q = s.upload(case["Q"])
+    if setup is not None:
+        setup(s, Q)
     for _ in range(warmup):
         s.rk_step(Q)
     dt0 = s.cfl_dt(Q)  # synchronises; also checks the warmed-up state is finite
@@ -133,6 +136,28 @@ def time_adjoint(ni=128, nj=64, nk=64, nsteps=50, i_f=8, i_p=16):
             "plain_forward_ms": round(plain, 3),
             "adjoint_over_forward": round(res["backward_ms"] / res["forward_ms"], 3),
             "adjoint_over_plain_forward": round(res["backward_ms"] / plain, 3)}
+
+
+def time_faces(case, steps, warmup):
+    """The benchmark shard with boundary faces instead of periodic i: a
+    characteristic entrance at i-lo (outside state: the initial profile), a
+    subsonic exit at i-hi (ambient pressure) and characteristic far-field
+    faces on both j sides; FP64, same steps as the main leg."""
+    from paper_2003_08746_amd import inputs, lesmi
+    c = dict(case)
+    c["bc"] = (1, 1, 0)
+
+    def setup(s, Q):
+        s.set_face(0, lesmi.LES_FACE_CHARACTERISTIC, Q)
+        s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=1.0 / inputs.GAMMA)
+        s.set_face(2, lesmi.LES_FACE_CHARACTERISTIC)
+        s.set_face(3, lesmi.LES_FACE_CHARACTERISTIC)
+
+    r = time_gpu(c, lesmi.LES_FP64, steps, warmup, setup)
+    npts = case["ni"] * case["nj"] * case["nk"]
+    return {"value": round(npts * 5 * steps / r["wall_s"] / 1e6, 2), "unit": "Mpoint-RK-stages/s",
+            "ms_per_step": round(r["wall_s"] * 1e3 / steps, 4),
+            "faces": "i-lo characteristic, i-hi exit, j-lo/j-hi characteristic, k periodic"}
 
 
 def time_stats(case, calls=50):
@@ -209,7 +234,7 @@ def main():
     ap.add_argument("--nj", type=int, default=128)
     ap.add_argument("--nk", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision, adjoint and statistics legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision, adjoint, boundary-face and statistics legs")
     ap.add_argument("--large", action="store_true",
                     help="also time the 800 x 500 x 500 shard (FP64 and mixed, 20 steps each)")
     ap.add_argument("--large-steps", type=int, default=20)
@@ -285,6 +310,11 @@ def main():
             extra["adjoint"] = time_adjoint()
         except Exception as e:
             extra["adjoint"] = {"error": str(e)[:200]}
+        try:
+            extra["faces"] = time_faces(case, args.steps, args.warmup)
+            extra["faces"]["vs_main"] = round(extra["faces"]["value"] / value, 3)
+        except Exception as e:
+            extra["faces"] = {"error": str(e)[:200]}
         try:
             extra["stats"] = time_stats(case)
         except Exception as e:

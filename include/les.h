@@ -56,12 +56,16 @@ typedef enum { LES_FP64 = 0, LES_MIXED = 1 } les_precision;
 
 typedef enum { LES_BC_PERIODIC = 0, LES_BC_DIRICHLET = 1 } les_bc;
 
+/* Treatment of one boundary face of a Dirichlet direction (les_set_face). */
+typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT = 2 } les_face_type;
+
 /* One structured block.  ni, nj, nk >= 5 interior points.
  * bc[d] for d = i, j, k:
  *   LES_BC_PERIODIC  -- period-wrap (Sec. 3: azimuthal periodicity); the
  *                       ghost coordinates must be the period-shifted images;
  *   LES_BC_DIRICHLET -- ghost nodes keep the values the caller stored in the
- *                       state's ghost layers (frozen far field).
+ *                       state's ghost layers (frozen far field), unless
+ *                       les_set_face gives a face another treatment.
  * xyz: device, dense padded layout [3][nk+4][nj+4][ni+4], coordinates on every
  * node including ghosts and edges (read during les_create only). */
 typedef struct {
@@ -192,6 +196,33 @@ int les_residual_adjoint(les_ctx *ctx, double *Q, const double *Rbar, double *Qb
  * with p = (gamma - 1)(e - (m_1^2 + m_2^2 + m_3^2) / (2 rho)). */
 int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, double weight, double *J_accum,
                         double *Qbar);
+
+/* Boundary face of a LES_BC_DIRICHLET direction (Sec. 3: entrance, far field
+ * and exit of the jet domain).  face: 0 = i-lo, 1 = i-hi, 2 = j-lo, 3 = j-hi,
+ * 4 = k-lo, 5 = k-hi.  The rule applies, at every ghost refresh, to the ghost
+ * nodes that lie outside the interior along that direction only (periodic
+ * indices wrapped); ghosts of two Dirichlet directions stay frozen.  Both
+ * ghost layers take the state built from the boundary node r next to the
+ * face (zero-order extrapolation):
+ *   LES_FACE_FROZEN          -- the ghosts keep the caller's values (default);
+ *   LES_FACE_CHARACTERISTIC  -- entrance and far field: locally
+ *      one-dimensional characteristics along the outward unit normal of the
+ *      face at r.  Supersonic outflow keeps r's state, supersonic inflow
+ *      takes the outside state; otherwise the outgoing Riemann invariant
+ *      u.n + 2c/(gamma-1) comes from r, the incoming u.n - 2c/(gamma-1) from
+ *      outside, and entropy p/rho^gamma and tangential velocity from the
+ *      upwind side (r when u.n >= 0);
+ *   LES_FACE_EXIT            -- subsonic exit: pressure p_exit imposed,
+ *      velocity and internal energy per unit mass of r kept; density and
+ *      total energy follow (Eq. 2).
+ * Q_outside: device, library layout, FP64, or NULL; when given, its ghost
+ *    values become the outside state of every characteristic face (copied
+ *    now; required before the first characteristic face).
+ * p_exit: imposed pressure (> 0) of an exit face; ignored otherwise.
+ * LES_ERR_ARG for a bad face, type or pressure, or a periodic direction.
+ * les_adjoint_step and les_residual_adjoint return LES_ERR_STATE while a
+ * face is not frozen (its ghost rule is not differentiated). */
+int les_set_face(les_ctx *ctx, int face, int type, const double *Q_outside, double p_exit);
 
 /* Running flow statistics for the time- and azimuth-averaged mean-flow and
  * RMS profiles of Sec. 5 (the periodic k direction is the averaged one):

@@ -31,6 +31,9 @@ struct les_ctx {
   int* flag = nullptr;               // bit 0: bad dt, bit 1: non-finite norm
   double* adj = nullptr;             // adjoint work arrays
   long long adj_n = 0;
+  int face[6] = {0, 0, 0, 0, 0, 0};  // boundary-face types (les_set_face)
+  double p_exit[6] = {0, 0, 0, 0, 0, 0};
+  double* outside = nullptr;         // [5][fe] outside state of characteristic faces
   int use_ref = 0;                   // 1: stage through the reference kernel
   int kchunk = 0;                    // k planes per block of the fused kernel
   // optional HIP-event timing of every stage-kernel launch
@@ -45,6 +48,20 @@ struct les_ctx {
 };
 
 static thread_local char g_create_err[512] = "";
+
+static les::Faces faces_of(const les_ctx* c) {
+  les::Faces F;
+  F.any = 0;
+  for (int f = 0; f < 6; ++f) {
+    F.type[f] = c->face[f];
+    F.p_exit[f] = c->p_exit[f];
+    if (c->face[f] != LES_FACE_FROZEN) F.any = 1;
+  }
+  F.outside = c->outside;
+  F.M = c->M;
+  F.gamma = c->P.gamma;
+  return F;
+}
 
 static int fail(les_ctx* c, int code, const char* fmt, ...) {
   char* buf = c ? c->err : g_create_err;
@@ -72,6 +89,7 @@ static void free_all(les_ctx* c) {
   (void)hipFree(c->Sf[1]);
   (void)hipFree(c->f);
   (void)hipFree(c->part);
+  (void)hipFree(c->outside);
   (void)hipFree(c->scal);
   (void)hipFree(c->flag);
   (void)hipFree(c->adj);
@@ -304,7 +322,7 @@ int les_residual(les_ctx* ctx, double* Q, double* R, double* norms) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual: null context");
   if (!Q || !R) return fail(ctx, LES_ERR_ARG, "les_residual: Q and R must be device pointers");
   if (Q == R) return fail(ctx, LES_ERR_ARG, "les_residual: Q and R must not alias");
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5));
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
   HIPCHK(ctx, les::launch_residual_ref(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->f, ctx->i_f, R,
                                        norms ? ctx->part : nullptr));
   if (!norms) return LES_OK;
@@ -344,7 +362,7 @@ int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norm
   les::Layout& L = ctx->L;
   const size_t fe = (size_t)L.fe;
   const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5));
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
   const double* dtp = nullptr;
   if (!(dt > 0.0)) {
     HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag));
@@ -357,7 +375,7 @@ int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norm
     les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
     for (int l = 0; l < 5; ++l) {
       const float* in32 = l == 0 ? nullptr : ctx->Sf[(l - 1) & 1];
-      if (l > 0) HIPCHK(ctx, les::launch_ghost_fill_f32(ctx->s, L, ctx->bc, (float*)in32, Q));
+      if (l > 0) HIPCHK(ctx, les::launch_ghost_fill_f32(ctx->s, L, ctx->bc, (float*)in32, Q, faces_of(ctx)));
       int trc = timing_begin(ctx);
       if (trc != LES_OK) return trc;
       HIPCHK(ctx, les::launch_stage_mixed(ctx->s, a, l == 0 ? Q : nullptr, in32, Q, l == 4 ? Q : nullptr,
@@ -372,7 +390,7 @@ int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norm
     const double* in = stage_ckpt ? stage_ckpt : Q;
     for (int l = 0; l < 5; ++l) {
       double* out = l == 4 ? Q : (stage_ckpt ? stage_ckpt + (size_t)(l + 1) * 5 * fe : ctx->S[l & 1]);
-      if (l > 0 || stage_ckpt) HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, (double*)in, Q, 5));
+      if (l > 0 || stage_ckpt) HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, (double*)in, Q, 5, faces_of(ctx)));
       // the residual norms of R(Q^n) are always reduced on the device (fused
       // into stage 1); only their copy to the host is optional
       double* part = l == 0 ? ctx->part : nullptr;
@@ -403,10 +421,36 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
   if (!stage_ckpt || !Qbar) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: stage_ckpt and Qbar are required");
   if (!(dt > 0.0)) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: dt must be > 0 (the step's fixed dt)");
   if (ctx->prec != LES_FP64) return fail(ctx, LES_ERR_STATE, "les_adjoint_step: needs an FP64 context");
+  if (faces_of(ctx).any)
+    return fail(ctx, LES_ERR_STATE, "les_adjoint_step: boundary faces other than frozen are not differentiated");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
   les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f};
   HIPCHK(ctx, les::run_adjoint_step(ctx->s, a, stage_ckpt, dt, Qbar, ctx->i_f >= 0 ? fbar : nullptr, ctx->adj));
+  return LES_OK;
+}
+
+int les_set_face(les_ctx* ctx, int face, int type, const double* Q_outside, double p_exit) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_set_face: null context");
+  if (face < 0 || face > 5) return fail(ctx, LES_ERR_ARG, "les_set_face: face %d outside [0, 6)", face);
+  if (ctx->bc[face / 2] != LES_BC_DIRICHLET)
+    return fail(ctx, LES_ERR_ARG, "les_set_face: face %d is on a periodic direction", face);
+  if (type != LES_FACE_FROZEN && type != LES_FACE_CHARACTERISTIC && type != LES_FACE_EXIT)
+    return fail(ctx, LES_ERR_ARG, "les_set_face: unknown face type %d", type);
+  if (type == LES_FACE_EXIT && !(p_exit > 0.0 && p_exit < INFINITY))
+    return fail(ctx, LES_ERR_ARG, "les_set_face: the exit pressure must be positive and finite");
+  if (type == LES_FACE_CHARACTERISTIC && !Q_outside && !ctx->outside)
+    return fail(ctx, LES_ERR_ARG, "les_set_face: a characteristic face needs an outside state");
+  if (Q_outside) {
+    const size_t bytes = (size_t)5 * ctx->L.fe * sizeof(double);
+    if (!ctx->outside && hipMalloc(&ctx->outside, bytes) != hipSuccess) {
+      ctx->outside = nullptr;
+      return fail(ctx, LES_ERR_NOMEM, "les_set_face: cannot allocate the outside state");
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->outside, Q_outside, bytes, hipMemcpyDeviceToDevice, ctx->s));
+  }
+  ctx->face[face] = type;
+  ctx->p_exit[face] = type == LES_FACE_EXIT ? p_exit : 0.0;
   return LES_OK;
 }
 
@@ -421,9 +465,11 @@ int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qb
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual_adjoint: null context");
   if (!Q || !Rbar || !Qbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Q, Rbar and Qbar are required");
   if (Qbar == Q || Qbar == Rbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Qbar must not alias Q or Rbar");
+  if (faces_of(ctx).any)
+    return fail(ctx, LES_ERR_STATE, "les_residual_adjoint: boundary faces other than frozen are not differentiated");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5));
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
   les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f};
   HIPCHK(ctx, les::run_residual_vjp(ctx->s, a, Q, Rbar, Qbar, ctx->adj));
   return LES_OK;

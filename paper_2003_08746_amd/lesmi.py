@@ -24,10 +24,11 @@ LIB_PATH = os.path.join(HERE, "liblesmi.so")
 LES_OK, LES_ERR_ARG, LES_ERR_HIP, LES_ERR_NOMEM, LES_ERR_NONFINITE, LES_ERR_STATE = 0, -1, -2, -3, -4, -5
 LES_FP64, LES_MIXED = 0, 1
 LES_BC_PERIODIC, LES_BC_DIRICHLET = 0, 1
+LES_FACE_FROZEN, LES_FACE_CHARACTERISTIC, LES_FACE_EXIT = 0, 1, 2
 
 EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",
             "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_adjoint_step", "les_residual_adjoint",
-            "les_probe_objective", "les_stats_accumulate",
+            "les_probe_objective", "les_set_face", "les_stats_accumulate",
             "les_last_error", "les_last_create_error"]
 
 # fields of les_stats_accumulate, in its order (sums over k of each)
@@ -93,6 +94,8 @@ def lib():
     L.les_residual_adjoint.argtypes = [_vp, _vp, _vp, _vp]
     L.les_probe_objective.restype = ctypes.c_int
     L.les_probe_objective.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _vp, _vp]
+    L.les_set_face.restype = ctypes.c_int
+    L.les_set_face.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double]
     L.les_stats_accumulate.restype = ctypes.c_int
     L.les_stats_accumulate.argtypes = [_vp, _vp, _vp]
     L.les_last_error.restype = ctypes.c_char_p
@@ -208,6 +211,10 @@ def les_probe_objective(ctx, Q_ptr, i_p, p_inf, weight, J_ptr, Qbar_ptr=None):
            "les_probe_objective")
 
 
+def les_set_face(ctx, face, type_, Q_outside_ptr=None, p_exit=0.0):
+    _check(lib().les_set_face(ctx, int(face), int(type_), Q_outside_ptr, float(p_exit)), ctx, "les_set_face")
+
+
 def les_stats_accumulate(ctx, Q_ptr, acc_ptr):
     _check(lib().les_stats_accumulate(ctx, Q_ptr, acc_ptr), ctx, "les_stats_accumulate")
 
@@ -321,6 +328,11 @@ class Solver:
 
     def probe_objective(self, Q, i_p, p_inf, weight, J, Qbar=None):
         les_probe_objective(self.ctx, Q.data_ptr(), i_p, p_inf, weight, J.data_ptr(), _ptr(Qbar))
+
+    def set_face(self, face, type_, Q_outside=None, p_exit=0.0):
+        """Boundary face treatment (les_set_face); Q_outside: library-layout
+        state whose ghost values are the outside state, or None."""
+        les_set_face(self.ctx, face, type_, _ptr(Q_outside), p_exit)
 
     def stats_accumulate(self, Q, acc=None):
         """acc[s][j][i] += sums over k of STATS_FIELDS at the interior of Q;

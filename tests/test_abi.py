@@ -76,4 +76,5 @@ def test_null_context_calls():
     assert L.les_adjoint_step(None, None, 1.0, None, None) == lesmi.LES_ERR_ARG
     assert L.les_set_forcing(None, None, 0) == lesmi.LES_ERR_ARG
     assert L.les_stats_accumulate(None, None, None) == lesmi.LES_ERR_ARG
+    assert L.les_set_face(None, 0, 1, None, 0.0) == lesmi.LES_ERR_ARG
     L.les_destroy(None)

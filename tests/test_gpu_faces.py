@@ -1,0 +1,142 @@
+"""Boundary faces of a Dirichlet direction (les_set_face: characteristic
+entrance / far field and subsonic exit, Sec. 3) against the oracle: the ghost
+states, the residual, two RK steps in FP64 and in FP32-mixed, and the
+argument and adjoint errors.  Tolerances: the FP64 bar of 1e-12 relative to
+each field's maximum; the mixed path's bound of 2e-6."""
+import numpy as np
+import pytest
+
+from paper_2003_08746_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+MIXED_BOUND = 2e-6
+
+
+@pytest.fixture(scope="module")
+def lesmi():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2003_08746_amd import lesmi as L
+    L.lib()
+    return L
+
+
+def _case(ni=61, nj=29, nk=23, seed=3):
+    """Jet block, Dirichlet in i (entrance at i-lo, exit at i-hi) and j (far
+    field on both sides), periodic in k; the interior is perturbed away from
+    the outside state (the analytic profile kept in the initial ghosts)."""
+    c = I.jet_case(ni, nj, nk, seed=seed)
+    c["bc"] = (1, 1, 0)
+    g = c["params"]["gamma"]
+    Q0 = c["Q"].copy()
+    rng = np.random.default_rng(seed)
+    Q = Q0.copy()
+    Q[1:4] += 0.05 * rng.uniform(-1, 1, size=Q[1:4].shape)
+    Q[4] *= 1.0 + 0.02 * rng.uniform(-1, 1, size=Q[4].shape)
+    c["Q"] = Q
+    c["faces"] = dict(types=[1, 2, 1, 1, 0, 0], p_exit=[0.0, 1.0 / g, 0, 0, 0, 0], outside=Q0)
+    return c, Q0
+
+
+def _solver(lesmi, case, Q0, prec=None):
+    s = lesmi.Solver(case, prec=lesmi.LES_FP64 if prec is None else prec)
+    fc = case["faces"]
+    s.set_face(0, lesmi.LES_FACE_CHARACTERISTIC, s.upload(Q0))
+    s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=fc["p_exit"][1])
+    s.set_face(2, lesmi.LES_FACE_CHARACTERISTIC)
+    s.set_face(3, lesmi.LES_FACE_CHARACTERISTIC)
+    return s
+
+
+def _rel(a, b):
+    ai, bi = I.interior(a), I.interior(b)
+    den = np.abs(bi).reshape(bi.shape[0], -1).max(1)
+    return np.abs(ai - bi).reshape(ai.shape[0], -1).max(1) / den
+
+
+def test_face_ghosts_and_residual(orc, lesmi):
+    import torch
+    case, Q0 = _case()
+    print("[gpu] faces: ghosts + residual 61x29x23", flush=True)
+    s = _solver(lesmi, case, Q0)
+    Q = s.upload(case["Q"])
+    R = s.residual(Q)  # fills Q's ghosts in place
+    torch.cuda.synchronize()
+    Qg = s.download(Q)
+    m = orc.metrics(case)
+    Qo = orc.fill_ghosts_faces(case, m, case["Q"])
+    scale = np.abs(Qo).reshape(5, -1).max(1)
+    err = np.abs(Qg - Qo).reshape(5, -1).max(1) / scale  # every node, ghosts included
+    assert (err <= 1e-13).all(), err
+    Ro = orc.residual(case, m, case["Q"])
+    assert (_rel(s.download(R), Ro) <= TOL).all(), _rel(s.download(R), Ro)
+    s.close()
+
+
+def test_face_rk_steps_fp64(orc, lesmi):
+    case, Q0 = _case()
+    print("[gpu] faces: 2 RK steps FP64", flush=True)
+    m = orc.metrics(case)
+    dt = 0.8 * orc.cfl_dt(case, m, case["Q"])
+    s = _solver(lesmi, case, Q0)
+    Q = s.upload(case["Q"])
+    Qo = case["Q"]
+    for _ in range(2):
+        s.rk_step(Q, dt)
+        Qo, _, _, _ = orc.rk_step(case, m, Qo, dt=dt)
+    err = _rel(s.download(Q), Qo)
+    assert (err <= TOL).all(), err
+    s.close()
+
+
+def test_face_rk_steps_mixed(orc, lesmi):
+    case, Q0 = _case()
+    print("[gpu] faces: 2 RK steps mixed", flush=True)
+    m = orc.metrics(case)
+    dt = 0.8 * orc.cfl_dt(case, m, case["Q"])
+    s = _solver(lesmi, case, Q0, prec=lesmi.LES_MIXED)
+    Q = s.upload(case["Q"])
+    Qo = case["Q"]
+    for _ in range(2):
+        s.rk_step(Q, dt)
+        Qo, _, _, _ = orc.rk_step(case, m, Qo, dt=dt)
+    q = I.interior(s.download(Q))
+    qo = I.interior(Qo)
+    sc = np.abs(qo).reshape(5, -1).max(1)
+    sc[1:4] = sc[1:4].max()
+    err = np.abs(q - qo).reshape(5, -1).max(1) / sc
+    assert (err <= MIXED_BOUND).all(), err
+    s.close()
+
+
+def test_face_errors(lesmi):
+    import torch
+    case, Q0 = _case(ni=16, nj=12, nk=8)
+    s = lesmi.Solver(case)
+    with pytest.raises(lesmi.LesError) as e:
+        s.set_face(4, lesmi.LES_FACE_EXIT, p_exit=0.7)  # k is periodic
+    assert e.value.code == lesmi.LES_ERR_ARG
+    with pytest.raises(lesmi.LesError):
+        s.set_face(6, lesmi.LES_FACE_EXIT, p_exit=0.7)
+    with pytest.raises(lesmi.LesError):
+        s.set_face(1, 7)
+    with pytest.raises(lesmi.LesError):
+        s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=0.0)
+    with pytest.raises(lesmi.LesError):
+        s.set_face(0, lesmi.LES_FACE_CHARACTERISTIC)  # no outside state yet
+    Q = s.upload(case["Q"])
+    s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=0.7)
+    with pytest.raises(lesmi.LesError) as e:
+        s.residual_adjoint(Q, s.upload(np.ones_like(case["Q"])))
+    assert e.value.code == lesmi.LES_ERR_STATE
+    ck = torch.empty(25 * s.fe, dtype=torch.float64, device="cuda")
+    s.rk_step(Q, 1e-4, ckpt=ck)
+    with pytest.raises(lesmi.LesError) as e:
+        s.adjoint_step(ck, 1e-4, s.upload(np.ones_like(case["Q"])))
+    assert e.value.code == lesmi.LES_ERR_STATE
+    # back to frozen: the adjoint is available again
+    s.set_face(1, lesmi.LES_FACE_FROZEN)
+    s.residual_adjoint(Q, s.upload(np.ones_like(case["Q"])))
+    s.close()
