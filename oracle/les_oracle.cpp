@@ -52,6 +52,10 @@
 //   R11 non-smooth derivatives (dual numbers): d|x|/dx = sign(x), 0 at 0;
 //       max(a, b) follows a when a >= b; d sqrt(x)/dx = 0 at x = 0.
 //   R12 an optional constant source f on the plane i = i_f: dQ/dt = -R + f.
+//   R13, R14 boundary faces of a Dirichlet direction: see fill_faces.
+//   R15 superposed periodic direction (Sec. 3: the first and last azimuthal
+//       points coincide): bc = 2, period n - 1; node n - 1 is node 0 again
+//       (it takes node 0's metrics), ghosts wrap with period n - 1.
 //
 // Data layout (all arrays): padded box [nk+4][nj+4][ni+4], i fastest, two
 // ghost layers per side; interior index 0..n-1 is stored at n+2.  Multi-field
@@ -124,7 +128,8 @@ static inline Dual s_max(Dual a, Dual b) { return a.v >= b.v ? a : b; }
 extern "C" {
 typedef struct {
   int ni, nj, nk;  // interior points per direction
-  int bc[3];       // per direction i, j, k: 0 = periodic, 1 = frozen Dirichlet ghosts
+  int bc[3];       // per direction i, j, k: 0 = periodic, 1 = frozen Dirichlet ghosts,
+                   // 2 = periodic with superposed first and last nodes (R15)
   // Boundary faces of a Dirichlet direction (R13, R14), in the order i-lo,
   // i-hi, j-lo, j-hi, k-lo, k-hi: 0 = frozen ghosts, 1 = characteristic
   // (R13), 2 = subsonic exit with imposed pressure p_exit (R14).  outside:
@@ -189,6 +194,13 @@ struct Box {
 // offset of the unit step in direction d
 static inline void step(int d, int& di, int& dj, int& dk) {
   di = (d == 0); dj = (d == 1); dk = (d == 2);
+}
+
+// Interior index of a periodic image: period n, or n - 1 when the first and
+// last nodes are superposed (R15).
+static inline int wrap(int x, int n, int bc) {
+  const int p = bc == 2 ? n - 1 : n;
+  return ((x % p) + p) % p;
 }
 
 // ---------------------------------------------------------------------------
@@ -284,7 +296,7 @@ void fill_faces(const Box& b, S* a) {
             ++nd;
             d = e;
           }
-          w[e] = ((idx[e] % n) + n) % n;
+          w[e] = wrap(idx[e], n, b.bc[e]);
         }
         if (nd != 1) continue;
         const int hi = idx[d] >= b.n(d) ? 1 : 0;
@@ -332,7 +344,7 @@ void fill_ghosts(const Box& b, S* a, int nfields) {
               ghost = true;
               if (b.bc[d] == 1) dirichlet = true;
             }
-            w[d] = ((idx[d] % n) + n) % n;
+            w[d] = wrap(idx[d], n, b.bc[d]);
           }
           if (!ghost || dirichlet) continue;
           q[b.at(i, j, k)] = q[b.at(w[0], w[1], w[2])];
@@ -406,7 +418,8 @@ void metrics(const Box& b, const double* xyz, double* m) {
         double vol = a11 * (a22 * a33 - a23 * a32) - a12 * (a21 * a33 - a23 * a31) + a13 * (a21 * a32 - a22 * a31);
         Jout[b.at(i, j, k)] = 1.0 / vol;
       }
-  // R2: periodic directions take wrapped interior metrics in their ghost layer.
+  // R2: periodic directions take wrapped interior metrics in their ghost
+  // layer; R15: along a superposed direction node n - 1 takes node 0's.
   for (int c = 0; c < 10; ++c) {
     double* q = m + (size_t)c * b.N;
     for (int k = -1; k <= b.nk; ++k)
@@ -417,8 +430,9 @@ void metrics(const Box& b, const double* xyz, double* m) {
           for (int d = 0; d < 3; ++d) {
             int n = b.n(d);
             w[d] = id[d];
-            if (b.bc[d] == 0 && (id[d] < 0 || id[d] >= n)) {
-              w[d] = ((id[d] % n) + n) % n;
+            const int top = b.bc[d] == 2 ? n - 1 : n;  // first index that is an image
+            if (b.bc[d] != 1 && (id[d] < 0 || id[d] >= top)) {
+              w[d] = wrap(id[d], n, b.bc[d]);
               any = true;
             }
           }

@@ -172,6 +172,35 @@ def wavy_grid(ni, nj, nk, L=(1.0, 1.0, 1.0), amp=0.15, m=1) -> np.ndarray:
     return np.ascontiguousarray(np.stack([x, y, z]), dtype=np.float64)
 
 
+def superposed_case(case: dict, axis: int) -> dict:
+    """The block of a case that is periodic along `axis` (0 = i, 1 = j,
+    2 = k), with one more node along it: node n is node 0 again (the first
+    and last nodes superposed, as the azimuthal direction of the paper's
+    O-grid), bc[axis] = 2.  Coordinates of node n and of the extra ghost
+    plane are the period-shifted images; the state of node n is node 0's."""
+    key = ("ni", "nj", "nk")[axis]
+    n = case[key]
+    ax = 3 - axis  # array axis of (c, k, j, i)
+
+    def plane(a, x):  # padded plane of index x along the axis
+        return np.take(a, x + 2, axis=ax)
+
+    xyz, Q = case["xyz"], case["Q"]
+    shift = plane(xyz, n) - plane(xyz, 0)  # one period
+    px = [plane(xyz, x) for x in range(-2, n + 2)] + [plane(xyz, 2) + shift]
+    pq = [plane(Q, x) for x in range(-2, n + 2)] + [plane(Q, 2)]
+    pq[n + 2] = plane(Q, 0)  # node n is node 0
+    out = dict(case)
+    out[key] = n + 1
+    out["xyz"] = np.ascontiguousarray(np.stack(px, axis=ax))
+    out["Q"] = np.ascontiguousarray(np.stack(pq, axis=ax))
+    bc = list(case["bc"])
+    bc[axis] = 2
+    out["bc"] = tuple(bc)
+    out["name"] = case.get("name", "case") + f"_superposed{axis}"
+    return out
+
+
 def uniform_state(shape3, rho=1.0, vel=(0.8, 0.6, 0.7), p=1.0 / GAMMA) -> np.ndarray:
     one = np.ones(shape3)
     return cons_from_prim(rho * one, vel[0] * one, vel[1] * one, vel[2] * one, p * one)

@@ -644,3 +644,41 @@ def test_face_uniform_flow_preserved(orc):
     np.testing.assert_allclose(q, Q, rtol=1e-14, atol=1e-15)
     R = I.interior(orc.residual(c, m, Q))
     assert np.abs(R).max() <= 1e-12, np.abs(R).max()
+
+
+# ---------------------------------------------------------------------------
+# Superposed periodic direction (Sec. 3: first and last azimuthal points
+# coincide): a block of n + 1 nodes whose last node is its first is the
+# plain periodic block of n nodes
+# ---------------------------------------------------------------------------
+def _periodic_base(n=(11, 9, 7)):
+    xyz = I.wavy_grid(*n, L=(1.3, 1.1, 0.9), amp=0.2)
+    return I.periodic_case(*n, xyz, I.smooth_state(*n, seed=9, amp=0.1), mu_ref=3e-3, sgs=1)
+
+
+def _along(a, axis, sl):
+    idx = [slice(None)] * 4
+    idx[3 - axis] = sl
+    return a[tuple(idx)]
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_superposed_equals_periodic(orc, axis):
+    c = _periodic_base()
+    cs = I.superposed_case(c, axis)
+    n = c[("ni", "nj", "nk")[axis]]
+    m, ms = orc.metrics(c), orc.metrics(cs)
+    R, Rs = orc.residual(c, m, c["Q"]), orc.residual(cs, ms, cs["Q"])
+    # nodes 0 .. n-1 along the axis: the periodic block's residual, exactly
+    np.testing.assert_array_equal(_along(I.interior(Rs), axis, slice(0, n)), I.interior(R))
+    # node n (superposed on node 0) has node 0's residual
+    np.testing.assert_array_equal(_along(I.interior(Rs), axis, slice(n, n + 1)),
+                                  _along(I.interior(Rs), axis, slice(0, 1)))
+    # one RK step and the CFL time step agree too
+    dt = orc.cfl_dt(c, m, c["Q"])
+    assert orc.cfl_dt(cs, ms, cs["Q"]) == dt
+    Q1, _, _, _ = orc.rk_step(c, m, c["Q"], dt=dt)
+    Qs1, _, _, _ = orc.rk_step(cs, ms, cs["Q"], dt=dt)
+    np.testing.assert_array_equal(_along(I.interior(Qs1), axis, slice(0, n)), I.interior(Q1))
+    np.testing.assert_array_equal(_along(I.interior(Qs1), axis, slice(n, n + 1)),
+                                  _along(I.interior(Qs1), axis, slice(0, 1)))
