@@ -54,7 +54,7 @@ typedef enum {
 
 typedef enum { LES_FP64 = 0, LES_MIXED = 1 } les_precision;
 
-typedef enum { LES_BC_PERIODIC = 0, LES_BC_DIRICHLET = 1 } les_bc;
+typedef enum { LES_BC_PERIODIC = 0, LES_BC_DIRICHLET = 1, LES_BC_PERIODIC_SUPERPOSED = 2 } les_bc;
 
 /* Treatment of one boundary face of a Dirichlet direction (les_set_face). */
 typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT = 2 } les_face_type;
@@ -66,6 +66,14 @@ typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT =
  *   LES_BC_DIRICHLET -- ghost nodes keep the values the caller stored in the
  *                       state's ghost layers (frozen far field), unless
  *                       les_set_face gives a face another treatment.
+ *   LES_BC_PERIODIC_SUPERPOSED -- periodic with the first and last nodes at
+ *                       the same place (Sec. 3: the azimuthal direction of
+ *                       the O-grid): period n - 1, node n - 1 takes node 0's
+ *                       metrics and the ghosts wrap with period n - 1; node
+ *                       n - 1 is updated like every interior node, so it stays
+ *                       equal to node 0 when it starts equal (it counts in the
+ *                       norms and the statistics).  Not differentiated: the
+ *                       adjoint entry points return LES_ERR_STATE.
  * xyz: device, dense padded layout [3][nk+4][nj+4][ni+4], coordinates on every
  * node including ghosts and edges (read during les_create only). */
 typedef struct {

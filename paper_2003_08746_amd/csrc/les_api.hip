@@ -49,6 +49,11 @@ struct les_ctx {
 
 static thread_local char g_create_err[512] = "";
 
+static bool has_superposed(const les_ctx* c) {
+  return c->bc[0] == LES_BC_PERIODIC_SUPERPOSED || c->bc[1] == LES_BC_PERIODIC_SUPERPOSED ||
+         c->bc[2] == LES_BC_PERIODIC_SUPERPOSED;
+}
+
 static les::Faces faces_of(const les_ctx* c) {
   les::Faces F;
   F.any = 0;
@@ -189,7 +194,7 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
       return fail(nullptr, LES_ERR_ARG, "les_create: block too large (%lld elements per field, limit 2^29)", Lc.fe);
   }
   for (int d = 0; d < 3; ++d)
-    if (grid->bc[d] != LES_BC_PERIODIC && grid->bc[d] != LES_BC_DIRICHLET)
+    if (grid->bc[d] != LES_BC_PERIODIC && grid->bc[d] != LES_BC_DIRICHLET && grid->bc[d] != LES_BC_PERIODIC_SUPERPOSED)
       return fail(nullptr, LES_ERR_ARG, "les_create: bc[%d] = %d is not a known boundary type", d, grid->bc[d]);
   if (!metrics_dense && !grid->xyz) return fail(nullptr, LES_ERR_ARG, "les_create: need xyz or metrics");
   if (!(prm->gamma > 1.0) || !(prm->R_gas > 0.0) || !(prm->Pr > 0.0) || !(prm->Pr_sgs > 0.0) ||
@@ -423,6 +428,8 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
   if (ctx->prec != LES_FP64) return fail(ctx, LES_ERR_STATE, "les_adjoint_step: needs an FP64 context");
   if (faces_of(ctx).any)
     return fail(ctx, LES_ERR_STATE, "les_adjoint_step: boundary faces other than frozen are not differentiated");
+  if (has_superposed(ctx))
+    return fail(ctx, LES_ERR_STATE, "les_adjoint_step: superposed periodic directions are not differentiated");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
   les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f};
@@ -467,6 +474,8 @@ int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qb
   if (Qbar == Q || Qbar == Rbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Qbar must not alias Q or Rbar");
   if (faces_of(ctx).any)
     return fail(ctx, LES_ERR_STATE, "les_residual_adjoint: boundary faces other than frozen are not differentiated");
+  if (has_superposed(ctx))
+    return fail(ctx, LES_ERR_STATE, "les_residual_adjoint: superposed periodic directions are not differentiated");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
   HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));

@@ -3,8 +3,9 @@
 // * k_metrics: Jacobian and metric terms (Alg. 2, "Calc(Jacob., Metric)")
 //   in the conservative central-difference form.
 // * k_ghost_fill: two ghost layers (Sec. 4, Fig. 3): periodic wrap (Sec. 3,
-//   azimuthal periodicity), frozen Dirichlet values, or the entrance / far
-//   field / exit conditions of a boundary face (Sec. 3).
+//   azimuthal periodicity; period n - 1 where the first and last nodes are
+//   superposed), frozen Dirichlet values, or the entrance / far field / exit
+//   conditions of a boundary face (Sec. 3).
 // * k_cfl_partial / k_cfl_final: global CFL time step (FP64 min reduction).
 // * k_residual_ref / k_stage_ref: one thread per interior node evaluating the
 //   residual (Eq. 12-15 with Turkel-Vatsa dissipation) directly from global
@@ -32,12 +33,15 @@ __global__ void k_metrics(Layout L, Dense D, int bc0, int bc1, int bc2, const do
   int i = (int)(t % ext_i) - 1;
   int j = (int)((t / ext_i) % ext_j) - 1;
   int k = (int)(t / ((long long)ext_i * ext_j)) - 1;
-  // a periodic ghost takes the metrics of its wrapped interior node
+  // a periodic ghost takes the metrics of its wrapped interior node; along a
+  // superposed direction (period n - 1) node n - 1 takes node 0's
   int id[3] = {i, j, k};
   const int nn[3] = {L.ni, L.nj, L.nk};
   const int bc[3] = {bc0, bc1, bc2};
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 3; ++d) {
     if (bc[d] == 0) id[d] = (id[d] + nn[d]) % nn[d];
+    if (bc[d] == 2) id[d] = (id[d] + nn[d] - 1) % (nn[d] - 1);
+  }
   const long long N = D.n();
   auto X = [&](int c, int a, int b, int e) { return xyz[c * N + D.at(a, b, e)]; };
   // central difference of coordinate c along direction d at node (a, b, e)
@@ -242,7 +246,8 @@ __global__ void k_ghost_fill(Layout L, int bc0, int bc1, int bc2, double* q, con
   for (int d = 0; d < 3; ++d) {
     bool g = id[d] < 0 || id[d] >= nn[d];
     if (g && bc[d] == 1) dir = true;
-    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d] : id[d];
+    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d]
+         : (g && bc[d] == 2) ? (id[d] + nn[d] - 1) % (nn[d] - 1) : id[d];
   }
   const long long dst = L.at(i, j, k);
   if (dir) {
@@ -296,7 +301,8 @@ __global__ void k_ghost_fill_f32(Layout L, int bc0, int bc1, int bc2, float* __r
   for (int d = 0; d < 3; ++d) {
     bool g = id[d] < 0 || id[d] >= nn[d];
     if (g && bc[d] == 1) dir = true;
-    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d] : id[d];
+    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d]
+         : (g && bc[d] == 2) ? (id[d] + nn[d] - 1) % (nn[d] - 1) : id[d];
   }
   const long long dst = L.at(i, j, k);
   if (dir) {

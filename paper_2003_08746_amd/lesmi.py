@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "liblesmi.so")
 
 LES_OK, LES_ERR_ARG, LES_ERR_HIP, LES_ERR_NOMEM, LES_ERR_NONFINITE, LES_ERR_STATE = 0, -1, -2, -3, -4, -5
 LES_FP64, LES_MIXED = 0, 1
-LES_BC_PERIODIC, LES_BC_DIRICHLET = 0, 1
+LES_BC_PERIODIC, LES_BC_DIRICHLET, LES_BC_PERIODIC_SUPERPOSED = 0, 1, 2
 LES_FACE_FROZEN, LES_FACE_CHARACTERISTIC, LES_FACE_EXIT = 0, 1, 2
 
 EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",

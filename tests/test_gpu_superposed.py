@@ -1,0 +1,111 @@
+"""Superposed periodic direction (LES_BC_PERIODIC_SUPERPOSED: the first and
+last nodes coincide, as the azimuthal direction of the paper's O-grid,
+Sec. 3) against the oracle, against the GPU's own plain periodic block of one
+node fewer, and the adjoint's refusal.  Tolerances: 1e-12 relative to each
+field's maximum (FP64), 2e-6 (mixed)."""
+import numpy as np
+import pytest
+
+from paper_2003_08746_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lesmi():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2003_08746_amd import lesmi as L
+    L.lib()
+    return L
+
+
+def _cases():
+    n = (47, 33, 19)
+    wavy = I.periodic_case(*n, I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3), I.smooth_state(*n, seed=21, amp=0.1),
+                           mu_ref=3e-3, sgs=1)
+    return {"wavy47x33x19_k": (wavy, 2), "jet61x29x23_i": (I.jet_case(61, 29, 23, seed=3), 0)}
+
+
+def _rel(a, b):
+    ai, bi = I.interior(a), I.interior(b)
+    den = np.abs(bi).reshape(bi.shape[0], -1).max(1)
+    return np.abs(ai - bi).reshape(ai.shape[0], -1).max(1) / den
+
+
+def _along(a, axis, sl):
+    idx = [slice(None)] * a.ndim
+    idx[a.ndim - 1 - axis] = sl
+    return a[tuple(idx)]
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_superposed_matches_oracle(orc, lesmi, name):
+    base, axis = _cases()[name]
+    case = I.superposed_case(base, axis)
+    print(f"[gpu] superposed {name}", flush=True)
+    m = orc.metrics(case)
+    s = lesmi.Solver(case)
+    mg = s.metrics_dense()
+    b1 = (slice(None), slice(1, -1), slice(1, -1), slice(1, -1))  # nodes of [-1, n]^3
+    err = np.abs(mg[b1] - m[b1]).reshape(10, -1).max(1) / np.abs(m[b1]).reshape(10, -1).max(1)
+    assert (err <= 1e-13).all(), err
+    Q = s.upload(case["Q"])
+    R = s.residual(Q)
+    Ro = orc.residual(case, m, case["Q"])
+    assert (_rel(s.download(R), Ro) <= TOL).all(), _rel(s.download(R), Ro)
+    dt = 0.8 * orc.cfl_dt(case, m, case["Q"])
+    Qo = case["Q"]
+    for _ in range(2):
+        s.rk_step(Q, dt)
+        Qo, _, _, _ = orc.rk_step(case, m, Qo, dt=dt)
+    Qg = s.download(Q)
+    assert (_rel(Qg, Qo) <= TOL).all(), _rel(Qg, Qo)
+    # the superposed node still equals node 0
+    n = case[("ni", "nj", "nk")[axis]]
+    qi = I.interior(Qg)
+    np.testing.assert_array_equal(_along(qi, axis, slice(n - 1, n)), _along(qi, axis, slice(0, 1)))
+    s.close()
+    # mixed precision on the same block
+    sm = lesmi.Solver(case, prec=lesmi.LES_MIXED)
+    Qm = sm.upload(case["Q"])
+    for _ in range(2):
+        sm.rk_step(Qm, dt)
+    qm, qo = I.interior(sm.download(Qm)), I.interior(Qo)
+    sc = np.abs(qo).reshape(5, -1).max(1)
+    sc[1:4] = sc[1:4].max()
+    assert (np.abs(qm - qo).reshape(5, -1).max(1) / sc <= 2e-6).all()
+    sm.close()
+
+
+def test_superposed_equals_periodic_on_gpu(lesmi):
+    """Two GPU steps of the superposed block reproduce, on nodes 0..n-1, two
+    GPU steps of the periodic block of n nodes."""
+    base, axis = _cases()["jet61x29x23_i"]
+    case = I.superposed_case(base, axis)
+    n = base["ni"]
+    a, b = lesmi.Solver(base), lesmi.Solver(case)
+    Qa, Qb = a.upload(base["Q"]), b.upload(case["Q"])
+    dt = a.cfl_dt(Qa)
+    assert b.cfl_dt(Qb) == dt
+    for _ in range(2):
+        a.rk_step(Qa, dt)
+        b.rk_step(Qb, dt)
+    qa, qb = I.interior(a.download(Qa)), I.interior(b.download(Qb))
+    d = np.abs(_along(qb, axis, slice(0, n)) - qa).reshape(5, -1).max(1) / np.abs(qa).reshape(5, -1).max(1)
+    assert (d <= 1e-14).all(), d
+    a.close()
+    b.close()
+
+
+def test_superposed_adjoint_refused(lesmi):
+    base, axis = _cases()["wavy47x33x19_k"]
+    case = I.superposed_case(base, axis)
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    with pytest.raises(lesmi.LesError) as e:
+        s.residual_adjoint(Q, s.upload(np.ones_like(case["Q"])))
+    assert e.value.code == lesmi.LES_ERR_STATE
+    s.close()
