@@ -55,7 +55,10 @@
 //   R13, R14 boundary faces of a Dirichlet direction: see fill_faces.
 //   R15 superposed periodic direction (Sec. 3: the first and last azimuthal
 //       points coincide): bc = 2, period n - 1; node n - 1 is node 0 again
-//       (it takes node 0's metrics), ghosts wrap with period n - 1.
+//       (it takes node 0's metrics), ghosts wrap with period n - 1.  A ghost
+//       takes the node reached by wrapping its ghost coordinates only; its
+//       interior coordinates are kept (a ghost next to node n - 1 is the
+//       image of a node of that plane, not of plane 0).
 //
 // Data layout (all arrays): padded box [nk+4][nj+4][ni+4], i fastest, two
 // ghost layers per side; interior index 0..n-1 is stored at n+2.  Multi-field
@@ -296,7 +299,7 @@ void fill_faces(const Box& b, S* a) {
             ++nd;
             d = e;
           }
-          w[e] = wrap(idx[e], n, b.bc[e]);
+          w[e] = g ? wrap(idx[e], n, b.bc[e]) : idx[e];  // R15: only ghost coordinates wrap
         }
         if (nd != 1) continue;
         const int hi = idx[d] >= b.n(d) ? 1 : 0;
@@ -344,7 +347,7 @@ void fill_ghosts(const Box& b, S* a, int nfields) {
               ghost = true;
               if (b.bc[d] == 1) dirichlet = true;
             }
-            w[d] = wrap(idx[d], n, b.bc[d]);
+            w[d] = g ? wrap(idx[d], n, b.bc[d]) : idx[d];  // R15: only ghost coordinates wrap
           }
           if (!ghost || dirichlet) continue;
           q[b.at(i, j, k)] = q[b.at(w[0], w[1], w[2])];

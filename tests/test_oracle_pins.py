@@ -682,3 +682,20 @@ def test_superposed_equals_periodic(orc, axis):
     np.testing.assert_array_equal(_along(I.interior(Qs1), axis, slice(0, n)), I.interior(Q1))
     np.testing.assert_array_equal(_along(I.interior(Qs1), axis, slice(n, n + 1)),
                                   _along(I.interior(Qs1), axis, slice(0, 1)))
+
+
+def test_superposed_stencil_reach(orc):
+    """Along a superposed axis the residual of plane x depends on the state
+    of planes x-2 .. x+2 through the ghosts: the duplicate plane n-1 reaches
+    rows n-3 .. n-1 only, plane 0 rows 0 .. 2 only (a ghost next to plane
+    n-1 in another direction is the image of a node of plane n-1)."""
+    c = _periodic_base(n=(12, 10, 8))
+    cs = I.superposed_case(c, 2)
+    ms = orc.metrics(cs)
+    nk = cs["nk"]
+    for src, want in ((nk - 1, {nk - 3, nk - 2, nk - 1}), (0, {0, 1, 2})):
+        v = np.zeros_like(cs["Q"])
+        v[:, src + 2, 2:-2, 2:-2] = np.random.default_rng(3).standard_normal(v[:, src + 2, 2:-2, 2:-2].shape)
+        _, dR = orc.residual_tangent(cs, ms, cs["Q"], v)
+        rows = np.abs(I.interior(dR)).max(axis=(0, 2, 3))
+        assert {k for k in range(nk) if rows[k] > 0} == want, (src, rows)
