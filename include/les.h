@@ -72,8 +72,8 @@ typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT =
  *                       metrics and the ghosts wrap with period n - 1; node
  *                       n - 1 is updated like every interior node, so it stays
  *                       equal to node 0 when it starts equal (it counts in the
- *                       norms and the statistics).  Not differentiated: the
- *                       adjoint entry points return LES_ERR_STATE.
+ *                       norms and the statistics).  A ghost takes the node
+ *                       reached by wrapping its ghost coordinates only.
  * xyz: device, dense padded layout [3][nk+4][nj+4][ni+4], coordinates on every
  * node including ghosts and edges (read during les_create only). */
 typedef struct {
@@ -175,8 +175,10 @@ int les_rk_step(les_ctx *ctx, double *Q, double dt, double *dt_out, double *norm
  *      fbar += alpha_l dt qbar[plane i_f];
  *      qbar = -alpha_l dt (dR/dQ |_{Q^(l-1)})^T qbar;
  *   Qbar <- acc + qbar.
- * dR/dQ includes the ghost fill (periodic ghost adjoints are folded onto the
- * interior; frozen Dirichlet ghosts carry no dependence).  Non-smooth points
+ * dR/dQ includes the ghost fill: periodic ghost adjoints are folded onto the
+ * interior, face ghosts (les_set_face) are pulled back to their boundary
+ * node through the face rule, frozen Dirichlet ghosts carry no dependence.
+ * Non-smooth points
  * take the derivative of the active branch: d|x|/dx = sign(x) (0 at 0),
  * max(a, b) follows a when a >= b.
  * stage_ckpt: device, as written by les_rk_step with the same dt.
@@ -228,8 +230,8 @@ int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, do
  *    now; required before the first characteristic face).
  * p_exit: imposed pressure (> 0) of an exit face; ignored otherwise.
  * LES_ERR_ARG for a bad face, type or pressure, or a periodic direction.
- * les_adjoint_step and les_residual_adjoint return LES_ERR_STATE while a
- * face is not frozen (its ghost rule is not differentiated). */
+ * The adjoint entry points differentiate the face rules (the outside state
+ * and p_exit are constants). */
 int les_set_face(les_ctx *ctx, int face, int type, const double *Q_outside, double p_exit);
 
 /* Running flow statistics for the time- and azimuth-averaged mean-flow and

@@ -20,9 +20,11 @@
 //      collects the gradient and sensor weights of its neighbours and the
 //      dissipation faces whose five-point stencil contains it, and maps the
 //      primitive adjoint back to conserved variables;
-//   pass 3 (fold, interior nodes next to a periodic seam): adds the adjoint
-//      of every periodic ghost image to its interior node (frozen Dirichlet
-//      ghosts carry no dependence).
+//   pass 3 (fold, interior nodes with ghost images): adds the adjoint of
+//      every periodic ghost image to its interior node and pulls the
+//      adjoint of a boundary face's ghosts back to the face's boundary node
+//      through the face rule's Jacobian (frozen Dirichlet ghosts carry no
+//      dependence).
 // Non-smooth points take the derivative of the active branch: d|x|/dx =
 // sign(x) with 0 at 0, max(a, b) follows a when a >= b, and the eddy
 // viscosity's |S| has derivative 0 at |S| = 0.
@@ -151,7 +153,32 @@ struct AdjK {
   Phys P;
   const double* M;
   int bc0, bc1, bc2;
+  int per[3];          // period of each axis: n (periodic), n - 1 (superposed), 0 (Dirichlet)
+  int lo[3], hi[3];    // pass-2 box: ghost layers of periodic axes and of active faces included
+  Faces F;             // boundary faces
+  int general;         // a superposed axis or an active face: pass 3 visits every interior node
 };
+
+AdjK make_adjk(const AdjArgs& a) {
+  AdjK A;
+  A.L = a.L;
+  A.P = a.P;
+  A.M = a.M;
+  A.bc0 = a.bc0;
+  A.bc1 = a.bc1;
+  A.bc2 = a.bc2;
+  A.F = a.F;
+  A.general = 0;
+  const int bc[3] = {a.bc0, a.bc1, a.bc2}, nn[3] = {a.L.ni, a.L.nj, a.L.nk};
+  for (int d = 0; d < 3; ++d) {
+    A.per[d] = bc[d] == 0 ? nn[d] : (bc[d] == 2 ? nn[d] - 1 : 0);
+    const bool flo = bc[d] == 1 && a.F.type[2 * d] != 0, fhi = bc[d] == 1 && a.F.type[2 * d + 1] != 0;
+    A.lo[d] = (bc[d] != 1 || flo) ? -2 : 0;
+    A.hi[d] = (bc[d] != 1 || fhi) ? nn[d] + 1 : nn[d] - 1;
+    if (bc[d] == 2 || flo || fhi) A.general = 1;
+  }
+  return A;
+}
 
 // ---------------------------------------------------------------------------
 // Pass 1
@@ -474,12 +501,20 @@ __device__ __forceinline__ bool in_b1(const Layout& L, int i, int j, int k) {
   return i >= -1 && i <= L.ni && j >= -1 && j <= L.nj && k >= -1 && k <= L.nk;
 }
 
-// Does interior node (i, j, k) have periodic ghost images (x <= 1 or
-// x >= n_d - 2 along a periodic axis)?
-__device__ __forceinline__ bool in_band(const AdjK& A, int i, int j, int k) {
-  const Layout& L = A.L;
-  return (A.bc0 == 0 && (i <= 1 || i >= L.ni - 2)) || (A.bc1 == 0 && (j <= 1 || j >= L.nj - 2)) ||
-         (A.bc2 == 0 && (k <= 1 || k >= L.nk - 2));
+// Does interior node (i, j, k) have ghost images: a periodic image along an
+// axis of period p (x + p in [n, n + 1] or x - p in [-2, -1]), or face ghosts
+// (x at an active boundary face of a Dirichlet axis)?
+__device__ __forceinline__ bool has_images(const AdjK& A, int i, int j, int k) {
+  const int id[3] = {i, j, k}, nn[3] = {A.L.ni, A.L.nj, A.L.nk}, bc[3] = {A.bc0, A.bc1, A.bc2};
+  for (int d = 0; d < 3; ++d) {
+    const int p = A.per[d];
+    if (p) {
+      if ((id[d] + p >= nn[d] && id[d] + p <= nn[d] + 1) || (id[d] - p <= -1 && id[d] - p >= -2)) return true;
+    } else if (bc[d] == 1) {
+      if ((id[d] == 0 && A.F.type[2 * d] != 0) || (id[d] == nn[d] - 1 && A.F.type[2 * d + 1] != 0)) return true;
+    }
+  }
+  return false;
 }
 
 // Last steps at an interior node whose adjoint q is complete: in the
@@ -494,10 +529,11 @@ __device__ __forceinline__ void finish_node(const Layout& L, long long n, int j,
     for (int c = 0; c < 5; ++c) qfin[c * L.fe + n] = acc[c * L.fe + n] + q[c];
 }
 
-// Pass 2 runs over B = R_i x R_j x R_k, R_d = [-2, n_d + 1] along a periodic
-// axis and [0, n_d) otherwise (frozen Dirichlet ghosts carry no dependence).
-// An interior node writes its gather to qout (and, in the Runge-Kutta
-// reverse, does acc += accsrc); a ghost node -- a periodic image of an
+// Pass 2 runs over B = R_i x R_j x R_k, R_d = [lo_d, hi_d]: the ghost layers
+// are included along a periodic axis and on the active faces of a Dirichlet
+// axis (frozen Dirichlet ghosts carry no dependence).  An interior node
+// writes its gather to qout (and, in the Runge-Kutta reverse, does
+// acc += accsrc); a ghost node -- a periodic image or a face ghost of an
 // interior node -- writes it to W_GG for pass 3.
 __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __restrict__ Q, double* __restrict__ Wk,
                                                     double* __restrict__ qout, double* __restrict__ acc,
@@ -506,13 +542,12 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
   const Layout& L = A.L;
   const Phys& P = A.P;
   const long long fe = L.fe;
-  const unsigned gi = A.bc0 == 0 ? 4 : 0, gj = A.bc1 == 0 ? 4 : 0, gk = A.bc2 == 0 ? 4 : 0;
-  const unsigned ri = L.ni + gi, rj = L.nj + gj;
+  const unsigned ri = A.hi[0] - A.lo[0] + 1, rj = A.hi[1] - A.lo[1] + 1, rk = A.hi[2] - A.lo[2] + 1;
   const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ri * rj * (unsigned)(L.nk + gk)) return;
-  const int i = (int)(t % ri) - (int)(gi >> 1);
-  const int j = (int)((t / ri) % rj) - (int)(gj >> 1);
-  const int k = (int)(t / (ri * rj)) - (int)(gk >> 1);
+  if (t >= ri * rj * rk) return;
+  const int i = (int)(t % ri) + A.lo[0];
+  const int j = (int)((t / ri) % rj) + A.lo[1];
+  const int k = (int)(t / (ri * rj)) + A.lo[2];
   const long long n = L.at(i, j, k);
   const bool b1 = in_b1(L, i, j, k);
 
@@ -587,7 +622,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
     if (acc)
       for (int c = 0; c < 5; ++c) acc[c * fe + n] += accsrc[c * fe + n];
     // nodes without periodic images are final here; pass 3 finishes the rest
-    if (!in_band(A, i, j, k)) finish_node(L, n, j, k, out, acc, fbar, i == i_f, fw, qfin);
+    if (!has_images(A, i, j, k)) finish_node(L, n, j, k, out, acc, fbar, i == i_f, fw, qfin);
   } else {
     for (int c = 0; c < 5; ++c) Wk[(W_GG + c) * fe + n] = out[c];
   }
@@ -668,6 +703,93 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restri
   finish_node(L, n0, j, k, q, acc, fbar, i == i_f, fw, qfin);
 }
 
+// Pass 3 when an axis is superposed or a boundary face is active: every
+// interior node with images adds, in a fixed order, the gathers of its
+// periodic images (period p along each periodic axis) and pulls back those
+// of its face ghosts through the face rule: qbar(r) += (dG/dq_r)^T Gbar for
+// each face ghost G = face_value(q_r) (both layers, and their periodic
+// images), the Jacobian column by column from forward-mode dual numbers.
+// Ghosts of two Dirichlet directions are frozen and carry nothing.
+__global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* __restrict__ Q,
+                                                          const double* __restrict__ Wk, double* __restrict__ qout,
+                                                          const double* __restrict__ acc, double* __restrict__ fbar,
+                                                          int i_f, double fw, double* __restrict__ qfin) {
+  const Layout& L = A.L;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
+  if (t >= nij * (unsigned)L.nk) return;
+  const int i = (int)(t % ni), j = (int)((t % nij) / ni), k = (int)(t / nij);
+  if (!has_images(A, i, j, k)) return;
+  const int id[3] = {i, j, k}, nn[3] = {L.ni, L.nj, L.nk}, bc[3] = {A.bc0, A.bc1, A.bc2};
+  int cand[3][3], kind[3][3], nc[3];  // kind: 0 own / periodic image, 1 lo-face ghost, 2 hi-face ghost
+  for (int d = 0; d < 3; ++d) {
+    nc[d] = 1;
+    cand[d][0] = id[d];
+    kind[d][0] = 0;
+    const int p = A.per[d];
+    if (p) {
+      if (id[d] + p >= nn[d] && id[d] + p <= nn[d] + 1) {
+        cand[d][nc[d]] = id[d] + p;
+        kind[d][nc[d]++] = 0;
+      }
+      if (id[d] - p <= -1 && id[d] - p >= -2) {
+        cand[d][nc[d]] = id[d] - p;
+        kind[d][nc[d]++] = 0;
+      }
+    } else if (bc[d] == 1) {
+      if (id[d] == 0 && A.F.type[2 * d] != 0) {
+        cand[d][nc[d]] = -1;
+        kind[d][nc[d]++] = 1;
+        cand[d][nc[d]] = -2;
+        kind[d][nc[d]++] = 1;
+      } else if (id[d] == nn[d] - 1 && A.F.type[2 * d + 1] != 0) {
+        cand[d][nc[d]] = nn[d];
+        kind[d][nc[d]++] = 2;
+        cand[d][nc[d]] = nn[d] + 1;
+        kind[d][nc[d]++] = 2;
+      }
+    }
+  }
+  const long long fe = L.fe, n0 = L.at(i, j, k);
+  const double* G = Wk + (long long)W_GG * fe;
+  double s[5], qr[5];
+  for (int c = 0; c < 5; ++c) {
+    s[c] = qout[c * fe + n0];
+    qr[c] = Q[c * fe + n0];
+  }
+  for (int a = 0; a < nc[0]; ++a)
+    for (int b = 0; b < nc[1]; ++b)
+      for (int e = 0; e < nc[2]; ++e) {
+        if (!(a | b | e)) continue;
+        const int kd[3] = {kind[0][a], kind[1][b], kind[2][e]};
+        const int nface = (kd[0] != 0) + (kd[1] != 0) + (kd[2] != 0);
+        if (nface > 1) continue;  // edge ghost: frozen
+        const long long g = L.at(cand[0][a], cand[1][b], cand[2][e]);
+        double gb[5];
+        for (int c = 0; c < 5; ++c) gb[c] = G[c * fe + g];
+        if (nface == 0) {
+          for (int c = 0; c < 5; ++c) s[c] += gb[c];
+          continue;
+        }
+        const int d = kd[0] ? 0 : (kd[1] ? 1 : 2), hi = kd[d] == 2;
+        const int type = A.F.type[2 * d + hi];
+        double nv[3], qo[5] = {0, 0, 0, 0, 0};
+        face_normal(L, A.F.M, d, hi, n0, nv);
+        if (A.F.outside)
+          for (int c = 0; c < 5; ++c) qo[c] = A.F.outside[c * fe + g];
+        for (int c = 0; c < 5; ++c) {  // column c of the face rule's Jacobian
+          DualD qd[5], od[5];
+          for (int m = 0; m < 5; ++m) qd[m] = DualD(qr[m], m == c ? 1.0 : 0.0);
+          face_value<DualD>(type, A.F.gamma, A.F.p_exit[2 * d + hi], nv, qd, qo, od);
+          double dot = 0.0;
+          for (int m = 0; m < 5; ++m) dot += od[m].d * gb[m];
+          s[c] += dot;
+        }
+      }
+  for (int c = 0; c < 5; ++c) qout[c * fe + n0] = s[c];
+  finish_node(L, n0, j, k, s, acc, fbar, i == i_f, fw, qfin);
+}
+
 // Start of the Runge-Kutta reverse (interior): qcur = Qbar, acc = 0, and
 // fbar[c][k][j] += w Qbar_c on the source plane (fbar non-null).
 __global__ void __launch_bounds__(256) k_adj_init(Layout L, const double* __restrict__ Qbar, double* __restrict__ qcur,
@@ -700,8 +822,8 @@ hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const dou
   const long long nB1 = (long long)(L.ni + 2) * (L.nj + 2) * (L.nk + 2);
   const long long nFace = (long long)(L.ni + 1) * L.nj * L.nk + (long long)L.ni * (L.nj + 1) * L.nk +
                          (long long)L.ni * L.nj * (L.nk + 1);
-  const long long gi = A.bc0 == 0 ? 4 : 0, gj = A.bc1 == 0 ? 4 : 0, gk = A.bc2 == 0 ? 4 : 0;
-  const long long nB = (L.ni + gi) * (L.nj + gj) * (L.nk + gk);
+  const long long nB = (long long)(A.hi[0] - A.lo[0] + 1) * (A.hi[1] - A.lo[1] + 1) * (A.hi[2] - A.lo[2] + 1);
+  const long long nIn = (long long)L.ni * L.nj * L.nk;
   long long nBand = 0;
   {
     const long long nn[3] = {L.ni, L.nj, L.nk};
@@ -717,7 +839,10 @@ hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const dou
   k_adj_face<<<nb(nFace, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
   k_adj_dnode<<<nb(nB1, 256), 256, 0, s>>>(A, Q, Wk);
   k_adj_gather<<<nb(nB, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, qb, fbar, i_f, fw, qfin);
-  if (nBand > 0) k_adj_fold<<<nb(nBand, 256), 256, 0, s>>>(A, Wk, qout, acc, fbar, i_f, fw, qfin);
+  if (A.general)
+    k_adj_fold_general<<<nb(nIn, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, fbar, i_f, fw, qfin);
+  else if (nBand > 0)
+    k_adj_fold<<<nb(nBand, 256), 256, 0, s>>>(A, Wk, qout, acc, fbar, i_f, fw, qfin);
   return hipGetLastError();
 }
 
@@ -727,13 +852,13 @@ size_t adjoint_work_elems(const Layout& L) { return (size_t)W_NF * (size_t)L.fe;
 
 hipError_t run_residual_vjp(hipStream_t s, const AdjArgs& a, const double* Q, const double* Rbar, double* Qbar,
                             double* work) {
-  AdjK A{a.L, a.P, a.M, a.bc0, a.bc1, a.bc2};
+  const AdjK A = make_adjk(a);
   return residual_vjp(s, A, Q, Rbar, 1.0, work, Qbar);
 }
 
 hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt, double dt, double* Qbar,
                             double* fbar, double* work) {
-  AdjK A{a.L, a.P, a.M, a.bc0, a.bc1, a.bc2};
+  const AdjK A = make_adjk(a);
   const Layout& L = a.L;
   const long long fe = L.fe;
   const long long nIn = (long long)L.ni * L.nj * L.nk;

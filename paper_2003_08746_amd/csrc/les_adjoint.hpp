@@ -1,6 +1,7 @@
 // les_adjoint.hpp -- reverse-mode (adjoint) of one Runge-Kutta step.
 #pragma once
 #include "les_common.hpp"
+#include "les_faces.hpp"
 
 namespace les {
 
@@ -8,8 +9,9 @@ struct AdjArgs {
   Layout L;
   Phys P;
   const double* M;
-  int bc0, bc1, bc2;
+  int bc0, bc1, bc2;  // 0 periodic, 1 Dirichlet, 2 periodic with superposed first and last nodes
   int i_f;
+  Faces F;            // boundary faces of the Dirichlet directions
 };
 
 // Device work elements (doubles) needed by run_adjoint_step.

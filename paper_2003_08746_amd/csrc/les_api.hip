@@ -49,11 +49,6 @@ struct les_ctx {
 
 static thread_local char g_create_err[512] = "";
 
-static bool has_superposed(const les_ctx* c) {
-  return c->bc[0] == LES_BC_PERIODIC_SUPERPOSED || c->bc[1] == LES_BC_PERIODIC_SUPERPOSED ||
-         c->bc[2] == LES_BC_PERIODIC_SUPERPOSED;
-}
-
 static les::Faces faces_of(const les_ctx* c) {
   les::Faces F;
   F.any = 0;
@@ -426,13 +421,9 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
   if (!stage_ckpt || !Qbar) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: stage_ckpt and Qbar are required");
   if (!(dt > 0.0)) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: dt must be > 0 (the step's fixed dt)");
   if (ctx->prec != LES_FP64) return fail(ctx, LES_ERR_STATE, "les_adjoint_step: needs an FP64 context");
-  if (faces_of(ctx).any)
-    return fail(ctx, LES_ERR_STATE, "les_adjoint_step: boundary faces other than frozen are not differentiated");
-  if (has_superposed(ctx))
-    return fail(ctx, LES_ERR_STATE, "les_adjoint_step: superposed periodic directions are not differentiated");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
-  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f};
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
   HIPCHK(ctx, les::run_adjoint_step(ctx->s, a, stage_ckpt, dt, Qbar, ctx->i_f >= 0 ? fbar : nullptr, ctx->adj));
   return LES_OK;
 }
@@ -472,14 +463,10 @@ int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qb
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual_adjoint: null context");
   if (!Q || !Rbar || !Qbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Q, Rbar and Qbar are required");
   if (Qbar == Q || Qbar == Rbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Qbar must not alias Q or Rbar");
-  if (faces_of(ctx).any)
-    return fail(ctx, LES_ERR_STATE, "les_residual_adjoint: boundary faces other than frozen are not differentiated");
-  if (has_superposed(ctx))
-    return fail(ctx, LES_ERR_STATE, "les_residual_adjoint: superposed periodic directions are not differentiated");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
   HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
-  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f};
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
   HIPCHK(ctx, les::run_residual_vjp(ctx->s, a, Q, Rbar, Qbar, ctx->adj));
   return LES_OK;
 }

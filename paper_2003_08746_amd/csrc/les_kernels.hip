@@ -97,70 +97,13 @@ __global__ void k_metrics_export(Layout L, Dense D, const double* __restrict__ M
 // ---------------------------------------------------------------------------
 // Boundary faces (Sec. 3: entrance, far field and exit of the jet domain).
 // A ghost node outside the interior along exactly one Dirichlet direction
-// d, on a face whose type is not frozen, takes a state built from the
-// boundary node r next to the face on its line along d (periodic indices
+// d, on a face whose type is not frozen, takes face_value (les_faces.hpp) of
+// the boundary node r next to the face on its line along d (periodic indices
 // wrapped; the same r for both ghost layers: zero-order extrapolation) and,
-// for the characteristic type, from the outside state stored at the ghost
-// node.  Ghosts of two Dirichlet directions (edges) stay frozen.
-//   exit (subsonic, imposed pressure pe): velocity and internal energy per
-//     unit mass p / ((gamma - 1) rho) of r are kept, p = pe, so
-//     rho = rho_r pe / p_r and e = pe / (gamma - 1) + rho |u|^2 / 2;
-//   characteristic (locally one-dimensional along the outward unit normal n
-//     of the face at r): supersonic outflow at r keeps r's state, supersonic
-//     inflow from outside takes the outside state; otherwise the outgoing
-//     Riemann invariant u.n + 2c/(gamma-1) comes from r and the incoming one
-//     u.n - 2c/(gamma-1) from outside, and the entropy p / rho^gamma and the
-//     tangential velocity from r (outflow, u.n >= 0) or from outside.
-// Computed in FP64 whatever the storage type of the state.
+// for the characteristic type, of the outside state stored at the ghost
+// node.  Ghosts of two Dirichlet directions (edges) stay frozen.  Computed
+// in FP64 whatever the storage type of the state.
 // ---------------------------------------------------------------------------
-__device__ void face_value(int type, double gamma, double pe, const double nv[3], const double qr[5],
-                           const double qo[5], double out[5]) {
-  const double gm1 = gamma - 1.0;
-  const double rr = qr[0];
-  const double ur[3] = {qr[1] / rr, qr[2] / rr, qr[3] / rr};
-  const double kr = ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2];
-  const double pr = gm1 * (qr[4] - 0.5 * rr * kr);
-  if (type == 2) {
-    const double rho = rr * pe / pr;
-    out[0] = rho;
-    for (int a = 0; a < 3; ++a) out[1 + a] = rho * ur[a];
-    out[4] = pe / gm1 + 0.5 * rho * kr;
-    return;
-  }
-  const double ro = qo[0];
-  const double uo[3] = {qo[1] / ro, qo[2] / ro, qo[3] / ro};
-  const double po = gm1 * (qo[4] - 0.5 * ro * (uo[0] * uo[0] + uo[1] * uo[1] + uo[2] * uo[2]));
-  const double cr = sqrt(gamma * pr / rr), co = sqrt(gamma * po / ro);
-  const double unr = ur[0] * nv[0] + ur[1] * nv[1] + ur[2] * nv[2];
-  const double uno = uo[0] * nv[0] + uo[1] * nv[1] + uo[2] * nv[2];
-  if (unr >= cr) {  // supersonic outflow
-    for (int c = 0; c < 5; ++c) out[c] = qr[c];
-    return;
-  }
-  if (uno <= -co) {  // supersonic inflow
-    for (int c = 0; c < 5; ++c) out[c] = qo[c];
-    return;
-  }
-  const double rplus = unr + 2.0 * cr / gm1;   // outgoing, from inside
-  const double rminus = uno - 2.0 * co / gm1;  // incoming, from outside
-  const double un = 0.5 * (rplus + rminus);
-  const double c = 0.25 * gm1 * (rplus - rminus);
-  const bool from_r = un >= 0.0;
-  const double ent = from_r ? pr / pow(rr, gamma) : po / pow(ro, gamma);
-  const double* us = from_r ? ur : uo;
-  const double uns = from_r ? unr : uno;
-  const double rho = pow(c * c / (gamma * ent), 1.0 / gm1);
-  const double p = rho * c * c / gamma;
-  double k = 0.0;
-  out[0] = rho;
-  for (int a = 0; a < 3; ++a) {
-    const double ub = us[a] - uns * nv[a] + un * nv[a];
-    out[1 + a] = rho * ub;
-    k += ub * ub;
-  }
-  out[4] = p / gm1 + 0.5 * rho * k;
-}
-
 // The face rule at ghost node dst of the state q (storage type T).  Returns
 // false when the node is not a face ghost (ghost along zero or several
 // Dirichlet directions, or a frozen face).
@@ -181,20 +124,14 @@ __device__ bool face_ghost(const Layout& L, const Faces& F, const int bc[3], con
   int r[3] = {w[0], w[1], w[2]};
   r[d] = hi ? nn[d] - 1 : 0;
   const long long rn = L.at(r[0], r[1], r[2]);
-  const double J = F.M[9 * L.fe + rn];
-  double nv[3], nrm = 0.0;
-  for (int x = 0; x < 3; ++x) {
-    nv[x] = J * F.M[(3 * d + x) * L.fe + rn];
-    nrm += nv[x] * nv[x];
-  }
-  const double sg = (hi ? 1.0 : -1.0) / sqrt(nrm);
-  for (int x = 0; x < 3; ++x) nv[x] *= sg;
+  double nv[3];
+  face_normal(L, F.M, d, hi, rn, nv);
   double qr[5], qo[5] = {0, 0, 0, 0, 0}, out[5];
   for (int c = 0; c < 5; ++c) {
     qr[c] = (double)q[c * L.fe + rn];
     if (F.outside) qo[c] = F.outside[c * L.fe + dst];
   }
-  face_value(type, F.gamma, F.p_exit[2 * d + hi], nv, qr, qo, out);
+  face_value<double>(type, F.gamma, F.p_exit[2 * d + hi], nv, qr, qo, out);
   for (int c = 0; c < 5; ++c) q[c * L.fe + dst] = (T)out[c];
   return true;
 }

@@ -2,6 +2,7 @@
 // unit per kernel family; the C-ABI implementation calls only these).
 #pragma once
 #include "les_common.hpp"
+#include "les_faces.hpp"
 
 namespace les {
 
@@ -9,17 +10,6 @@ hipError_t launch_metrics(hipStream_t s, const Layout& L, const int bc[3], const
 hipError_t launch_metrics_copy(hipStream_t s, const Layout& L, const double* src, double* M);
 hipError_t launch_metrics_export(hipStream_t s, const Layout& L, const double* M, double* dst);
 long long ghost_count(const Layout& L);
-// Boundary faces of Dirichlet directions, in the order i-lo, i-hi, j-lo,
-// j-hi, k-lo, k-hi (les_set_face): 0 = frozen ghosts, 1 = characteristic
-// entrance / far field, 2 = subsonic exit with imposed pressure.
-struct Faces {
-  int type[6];
-  double p_exit[6];
-  const double* outside;  // [5][fe] outside state at the ghost nodes (characteristic faces)
-  const double* M;        // metrics [10][fe] (face normals)
-  double gamma;
-  int any;                // some face is not frozen
-};
 hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], double* q, const double* frozen, int nf,
                              const Faces& F);
 hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3], float* q, const double* frozen,

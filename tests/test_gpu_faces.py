@@ -1,7 +1,8 @@
 """Boundary faces of a Dirichlet direction (les_set_face: characteristic
 entrance / far field and subsonic exit, Sec. 3) against the oracle: the ghost
-states, the residual, two RK steps in FP64 and in FP32-mixed, and the
-argument and adjoint errors.  Tolerances: the FP64 bar of 1e-12 relative to
+states, the residual, two RK steps in FP64 and in FP32-mixed, the argument
+errors, and the adjoint through the face rules (dot-product tests against the
+oracle's dual-number tangents).  Tolerances: the FP64 bar of 1e-12 relative to
 each field's maximum; the mixed path's bound of 2e-6."""
 import numpy as np
 import pytest
@@ -126,17 +127,59 @@ def test_face_errors(lesmi):
         s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=0.0)
     with pytest.raises(lesmi.LesError):
         s.set_face(0, lesmi.LES_FACE_CHARACTERISTIC)  # no outside state yet
+    s.close()
+
+
+def _interior_rand(case, seed, scale_by_field=True):
+    rng = np.random.default_rng(seed)
+    a = np.zeros_like(case["Q"])
+    sl = (slice(None), slice(2, -2), slice(2, -2), slice(2, -2))
+    a[sl] = rng.standard_normal(a[sl].shape)
+    if scale_by_field:
+        a *= np.abs(I.interior(case["Q"])).reshape(5, -1).max(1)[:, None, None, None]
+    return a
+
+
+def _dot(a, b):
+    return float((I.interior(a) * I.interior(b)).sum())
+
+
+def test_face_residual_adjoint_dot_product(orc, lesmi):
+    """<w, (dR/dQ) v> from the oracle's dual-number tangent (through the face
+    rules of the ghost fill) against <(dR/dQ)^T w, v> from the GPU adjoint,
+    which pulls the face ghosts' adjoint back to their boundary nodes."""
+    case, Q0 = _case(ni=40, nj=20, nk=12)
+    print("[gpu] faces: residual adjoint dot product", flush=True)
+    m = orc.metrics(case)
+    v = _interior_rand(case, 1)
+    w = _interior_rand(case, 2, scale_by_field=False)
+    _, dR = orc.residual_tangent(case, m, case["Q"], v)
+    lhs = _dot(w, dR)
+    s = _solver(lesmi, case, Q0)
+    Qbar = s.download(s.residual_adjoint(s.upload(case["Q"]), s.upload(w)))
+    rhs = _dot(Qbar, v)
+    scale = float(np.abs(I.interior(w) * I.interior(dR)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+    s.close()
+
+
+def test_face_rk_step_adjoint_dot_product(orc, lesmi):
+    import torch
+    case, Q0 = _case(ni=40, nj=20, nk=12)
+    print("[gpu] faces: RK-step adjoint dot product", flush=True)
+    m = orc.metrics(case)
+    v = _interior_rand(case, 8)
+    w = _interior_rand(case, 9, scale_by_field=False)
+    dt = 0.8 * orc.cfl_dt(case, m, case["Q"])
+    _, dQ1 = orc.rk_step_tangent(case, m, case["Q"], v, dt)
+    lhs = _dot(w, dQ1)
+    s = _solver(lesmi, case, Q0)
     Q = s.upload(case["Q"])
-    s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=0.7)
-    with pytest.raises(lesmi.LesError) as e:
-        s.residual_adjoint(Q, s.upload(np.ones_like(case["Q"])))
-    assert e.value.code == lesmi.LES_ERR_STATE
     ck = torch.empty(25 * s.fe, dtype=torch.float64, device="cuda")
-    s.rk_step(Q, 1e-4, ckpt=ck)
-    with pytest.raises(lesmi.LesError) as e:
-        s.adjoint_step(ck, 1e-4, s.upload(np.ones_like(case["Q"])))
-    assert e.value.code == lesmi.LES_ERR_STATE
-    # back to frozen: the adjoint is available again
-    s.set_face(1, lesmi.LES_FACE_FROZEN)
-    s.residual_adjoint(Q, s.upload(np.ones_like(case["Q"])))
+    s.rk_step(Q, dt, ckpt=ck)
+    Qbar = s.upload(w)
+    s.adjoint_step(ck, dt, Qbar)
+    rhs = _dot(s.download(Qbar), v)
+    scale = float(np.abs(I.interior(w) * I.interior(dQ1)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
     s.close()
