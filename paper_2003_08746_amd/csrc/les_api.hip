@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include "les.h"
+#include "les_debug.h"
 #include "les_launch.hpp"
 #include "les_stage.hpp"
 #include "les_adjoint.hpp"
@@ -480,16 +481,16 @@ int les_probe_objective(les_ctx* ctx, const double* Q, int i_p, double p_inf, do
   return LES_OK;
 }
 
-// Select the stage kernel: 0 = fused tiled kernel (default), 1 = reference
-// kernel.  Not declared in les.h: a testing switch used to cross-check the
-// two formulations.
+// Instrumentation (les_debug.h).  Select the stage kernel: 0 = fused tiled
+// kernel (default), 1 = reference kernel; a testing switch used to
+// cross-check the two formulations.
 int les_debug_use_reference(les_ctx* ctx, int on) {
   if (!ctx) return LES_ERR_ARG;
   ctx->use_ref = on ? 1 : 0;
   return LES_OK;
 }
 
-// Stage-kernel timing (not declared in les.h; used by the benchmark):
+// Stage-kernel timing (les_debug.h; used by the benchmark):
 // on != 0 starts recording a HIP event pair around every stage-kernel
 // launch on the context's stream; les_debug_stage_time synchronises and
 // returns the summed elapsed milliseconds and the launch count since

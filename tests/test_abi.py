@@ -11,10 +11,22 @@ from paper_2003_08746_amd import lesmi
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "les.h")).read()
+def _declared(header="les.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(les_[a-z_]+)\s*\(", src)))
+
+
+def _exported_by_library():
+    """Names of the les_* functions the shared library defines in its dynamic
+    symbol table (listed with binutils' nm)."""
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("binutils nm is not installed")
+    out = subprocess.run(["nm", "-D", "--defined-only", lesmi.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    return sorted({ln.split()[-1] for ln in out.splitlines() if " T les_" in ln})
 
 
 def test_header_symbols_exported():
@@ -24,6 +36,13 @@ def test_header_symbols_exported():
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
     assert set(lesmi.EXPORTED) == set(names)
+
+
+def test_every_export_is_declared():
+    """Every les_* symbol of the library is declared in include/les.h or, for
+    the instrumentation entry points, include/les_debug.h (and vice versa)."""
+    declared = set(_declared()) | set(_declared("les_debug.h"))
+    assert set(_exported_by_library()) == declared
 
 
 def test_layout_for():
