@@ -15,7 +15,8 @@
 // variables at t-2 .. t+1, primitives at t-1 and t+1, the zeta node flux and
 // the partial residual of the plane below), so the zeta direction needs no
 // LDS.  The in-plane (xi, eta) stencil goes through LDS in three phases per
-// plane, separated by barriers:
+// plane, separated by barriers (a third barrier closes the plane in the FP64
+// path; the FP32 path double-buffers the LDS Q plane instead, see below):
 //   B  fill:  every node of the patch (and a second halo ring along the
 //             axes, written by helper threads) stores Q, p, u, v, w, T;
 //   C  node:  every non-corner node of the patch computes its velocity and
@@ -28,12 +29,21 @@
 //             and finish the residual and stage update of the plane below
 //             (stage 1 also accumulates R^2 and max |R| per thread; the
 //             block reduces them once, after its last plane).
-// Memory.  Wave w owns patch rows 2w and 2w+1.  The ten metric fields and
+// Memory.  Wave w owns patch rows 2w and 2w+1 (rows 4w .. 4w+3 with the
+// 16-wide patch the shape constants also allow).  The ten metric fields and
 // Q^(0) of those rows are wave-private, so they travel as asynchronous
 // global->LDS copies (16 bytes per lane) into per-wave LDS blocks with no
-// barrier: the next plane's metrics are issued in phase C right after the
-// wave has read the current ones, and Q^(0) of the plane being finished is
-// issued in phase B; both land while the wave computes.  The flow constants
+// barrier: Q^(0) of the plane being finished is issued at the start of C
+// and read at the start of E; the next plane's metrics are issued right
+// after that read and land during E (E stores nothing to LDS, so no LDS
+// store has to wait for them).  The block barriers order LDS data only:
+// a full __syncthreads would also drain every outstanding global load,
+// store and copy of the wave, so each barrier would wait out the latency of
+// what was just issued.  Reads of copied blocks are preceded by counted
+// vmcnt waits instead.  The own-column loads are branch-free (threads past
+// the padded box load a clamped node), which lets the compiler see that
+// they have completed and keeps it from adding full vmcnt waits of its own.
+// The flow constants
 // are read from the kernel-argument segment where they are used, instead of
 // occupying scalar registers across the loop.  Divisions and square roots
 // use short Newton-refined sequences (valid for the positive, normal
@@ -45,7 +55,15 @@
 //
 // Work per thread is independent of the floating-point type T (double for
 // the FP64 path, float for the mixed path); metrics, Q^(0), the stage
-// update, J and all reductions stay in FP64.
+// update, J and all reductions stay in FP64.  The FP32 path has registers
+// and LDS to spare, and spends them on latency: it loads the helper ring one
+// plane ahead and its own column two planes ahead (in phase E, consumed in C
+// of the next plane), and it keeps two LDS Q planes, written at B of
+// alternate planes.  Phase E reads no other LDS array of the current plane
+// at other threads' nodes (p, u, v, w, T are read at neighbours only in C;
+// the node fluxes, radii and sensors are next written in C, after the next
+// plane's first barrier), so the barrier at the end of a plane is not needed
+// there.  The FP64 path has neither the registers nor the 24 KB of LDS.
 #include <stdlib.h>
 
 #include "les_stage.hpp"
@@ -55,11 +73,22 @@ namespace les {
 
 namespace {
 
-constexpr int BX = 32, BY = 16, NT = BX * BY;  // patch (threads)
+#ifndef LES_STAGE_BX
+#define LES_STAGE_BX 32
+#endif
+#ifndef LES_STAGE_BY
+#define LES_STAGE_BY 16
+#endif
+constexpr int BX = LES_STAGE_BX, BY = LES_STAGE_BY, NT = BX * BY;  // patch (threads)
 constexpr int TX = BX - 2, TY = BY - 2;        // output tile
 constexpr int EX = BX + 2, EY = BY + 2;        // patch + axis halo (LDS planes)
 constexpr int NH2 = 2 * TY + 2 * TX;           // second-ring helper nodes
 constexpr int NW = NT / 64;                    // waves per block
+constexpr int RPW = 64 / BX;                   // patch rows per wave
+constexpr int LPR = BX / 2;                    // lanes per row of a 16-byte row copy
+constexpr int BPC = 512 / NT;                  // resident blocks per CU (two waves per SIMD)
+static_assert(BX == 16 || BX == 32, "a wave covers whole patch rows");
+static_assert(BY % RPW == 0 && NT % 64 == 0 && NH2 <= NT && BPC >= 1, "tile shape");
 
 struct KArgs {
   Layout L;
@@ -74,9 +103,14 @@ struct KArgs {
   int per_xcd;          // blocks per XCD in the remapped order
 };
 
+// The FP32 path has the LDS for two Q planes (written at B of alternate
+// planes), which removes the barrier at the end of a plane: the only LDS
+// values that E reads at other threads' nodes are Q.
+template <class T>
+constexpr int kQBuf = sizeof(T) == 4 ? 2 : 1;
 template <class T>
 struct Smem {
-  T q[5][EY][EX];
+  T q[kQBuf<T>][5][EY][EX];
   T p[EY][EX];
   T u[EY][EX], v[EY][EX], w[EY][EX], tem[EY][EX];
   T hx[5][TY][BX];  // xi node flux, patch rows 1..TY
@@ -118,27 +152,27 @@ __device__ __forceinline__ void face_diss(const Phys& P, T La, T Lb, T na, T nb,
   }
 }
 
-// Per-wave reduction of the threads' R^2 sums and |R| maxima, accumulated in
-// the wave's row of `red` (all lanes of the wave must call it).
-__device__ __forceinline__ void norm_accumulate(const double s2[5], const double sm[5], double (*red)[10], int tid) {
+// Per-wave reduction of the threads' R^2 sums and |R| maxima into the ten
+// doubles at red (all lanes of the wave must call it; lane 0 writes).
+__device__ __forceinline__ void norm_wave(const double s2[5], const double sm[5], double* red, int lane) {
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
     const double sum = wave_sum(s2[c]);
     const double mx = wave_max(sm[c]);
-    if ((tid & 63) == 0) {
-      red[tid >> 6][c] += sum;
-      const double o = red[tid >> 6][5 + c];
-      red[tid >> 6][5 + c] = (mx > o || mx != mx) ? mx : o;
+    if (lane == 0) {
+      red[c] = sum;
+      red[5 + c] = mx;
     }
   }
 }
 
-// Per-wave row staging.  Wave w owns patch rows 2w and 2w+1 (the rows of its
-// own threads), so the metrics and Q^(0) of those rows can be copied into a
-// wave-private LDS block with no barrier.  One asynchronous global->LDS copy
-// moves 16 bytes (two doubles) per lane: lanes 0-15 the 32 columns of field f
-// row 2w, lanes 16-31 field f row 2w+1, lanes 32-63 the same for field f+1;
-// they land contiguously at [f][r][col] of the block.  src is the lane's
+// Per-wave row staging.  Wave w owns patch rows RPW w .. RPW w + RPW - 1 (the
+// rows of its own threads: two rows of 32 or four rows of 16), so the
+// metrics and Q^(0) of those rows can be copied into a wave-private LDS block
+// with no barrier.  One asynchronous global->LDS copy moves 16 bytes (two
+// doubles) per lane: lanes 0-31 the 64 nodes of field f (row after row),
+// lanes 32-63 the same for field f+1; they land contiguously at [f][r][col]
+// of the block.  src is the lane's
 // byte address for field (lane >> 5); fstep2 is two fields in bytes.  With
 // an odd field count the last copy uses lanes 0-31 only.
 template <int NF>
@@ -164,17 +198,31 @@ __device__ __forceinline__ void wait_vm() {
 // s_waitcnt lgkmcnt(0): this wave's LDS reads have returned
 __device__ __forceinline__ void wait_lgkm_all() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
+// Block barrier for LDS data only: release/acquire at workgroup scope for
+// the local address space, so the wave waits for its own LDS operations but
+// not for outstanding global loads, stores or global->LDS copies (which a
+// full __syncthreads drains).
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 template <class T, class QI, bool NORM>
-__global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qin, const double* Q0, double* Qout,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) k_stage(KArgs a, const QI* __restrict__ Qin, const double* Q0, double* Qout,
                                               float* Qsh, const double* __restrict__ dtp, double dt_host,
                                               double alpha, double* __restrict__ part) {
   // the FP32 path has the registers to prefetch the helper ring one plane
   // ahead; the FP64 path loads it at phase B (holding it would spill)
   constexpr bool kPrefetchRing = sizeof(T) == 4;
+  // the FP32 path also loads the own column two planes ahead (in E)
+  constexpr bool kPrefetchQ = sizeof(T) == 4;
+  constexpr bool kQ2 = kQBuf<T> == 2;
   __shared__ Smem<T> s;
-  __shared__ double mbw[NW][10][2][BX];  // per-wave metrics rows of the current plane
-  __shared__ double q0w[NW][5][2][BX];   // per-wave Q^(0) rows of the plane being finished
-  __shared__ double red[NW][10];         // per-wave norm partials (NORM only)
+  __shared__ double mbw[NW][10][RPW][BX];  // per-wave metrics rows of the current plane
+  __shared__ double q0w[NW][5][RPW][BX];   // per-wave Q^(0) rows of the plane being finished
+  static_assert(sizeof(Smem<T>) + sizeof(mbw) + sizeof(q0w) <= 163840 / BPC, "LDS of BPC blocks per CU");
   const Layout& L = a.L;
   // a (the first kernel argument) sits at the start of the kernel-argument
   // segment; the loop re-reads the flow constants through this pointer
@@ -195,10 +243,9 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
   const int tx = tid % BX, ty = tid / BX;
   const int ex = tx + 1, ey = ty + 1;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int fsel = lane >> 5, rsel = (lane >> 4) & 1, pr = lane & 15;  // row-copy lane geometry
-  const int ty1 = ty & 1;                                             // own row within the wave's pair
+  const int fsel = lane >> 5, rsel = (lane / LPR) % RPW, pr = lane % LPR;  // row-copy lane geometry
+  const int ty1 = ty % RPW;                                                // own row within the wave's rows
   const bool xh = (tx == 0 || tx == BX - 1), yh = (ty == 0 || ty == BY - 1);
-  if (NORM && tid < NW * 10) red[tid / 10][tid % 10] = 0.0;
   const unsigned sk = (unsigned)L.sk;
   const double adt = alpha * (dtp ? dtp[0] : dt_host);
 
@@ -222,6 +269,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
   // residual norms: per-thread running sums of R^2 and maxima of |R| over
   // all planes of the block (NORM only), reduced once at the end
   double n2[5] = {0, 0, 0, 0, 0}, nm[5] = {0, 0, 0, 0, 0};
+  int qbuf = 0;  // LDS Q plane written at the next B (alternates every plane)
   for (long long wq = w_begin; wq < w_end;) {
     // ---- one segment: planes [kb, ke) of one tile ----
     const int tile = (int)(wq / L.nk);
@@ -242,9 +290,14 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
     // padded box lies below 2^29 elements per field (checked at creation)
     const unsigned col = (unsigned)((long long)i + (long long)j * L.sj + L.o);
     const unsigned hcol = (unsigned)((long long)hi + (long long)hj * L.sj + L.o);
+    // own-column loads use the node clamped into the padded box, so that they
+    // and their uses need no branch (threads past the box load, and never
+    // publish, a copy of the box's edge node)
+    const unsigned qcol =
+        (unsigned)((long long)min(i, L.ni + 1) + (long long)min(j, L.nj + 1) * L.sj + L.o);
 
     // ---- column queues (own node) ----
-    T qw[5], qa[5];         // Q at t (written at B) and t+1
+    T qw[5], qa[5], qn[5];  // Q at t (written at B), t+1 and t+2 (prefetch)
     T qm1[5], qm2[5];       // Q at t-1, t-2
     T um1[4], up1[4];       // u, v, w, T at t-1; at t+1 (at B: plane t)
     T pm1 = 0, pp1 = 0;
@@ -253,7 +306,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
     T lz_prev = 0, nz_prev = 0;
     double J_prev = 0.0;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) qw[c] = qa[c] = qm1[c] = qm2[c] = hq[c] = hz_prev[c] = racc[c] = T(0);
+    for (int c = 0; c < 5; ++c) qw[c] = qa[c] = qn[c] = qm1[c] = qm2[c] = hq[c] = hz_prev[c] = racc[c] = T(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) um1[c] = up1[c] = T(0);
 
@@ -266,20 +319,19 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
     // column; helper Q(kb-1)
     //
     // element offset (plane 0) of this lane's row copy: field fsel, row
-    // 2 wave + rsel, column pair starting at i0-1+2pr (16-byte aligned);
+    // RPW wave + rsel, column pair starting at i0-1+2pr (16-byte aligned);
     // pairs past i = ni (ragged last tile) re-read the last pair within the row
     int icp = i0 - 1 + 2 * pr;
     if (icp > L.ni) icp = L.ni - ((LEAD + L.ni) & 1);
-    const int jcp = min(j0 - 1 + 2 * wave + rsel, L.nj);
+    const int jcp = min(j0 - 1 + RPW * wave + rsel, L.nj);
     const long long lane_el = (long long)fsel * fe + L.o + icp + (long long)jcp * L.sj;
     const long long fstep2 = 2 * fe * (long long)sizeof(double);
     dma_rows<10>((const char*)(kp->M + lane_el + (long long)(kb - 1) * L.sk), fstep2, &mbw[wave][0][0][0], lane);
-    if (load_ok) {
-      load_q<T>(Qin, fe, col + (unsigned)(kb - 2) * sk, qm1);
-      load_q<T>(Qin, fe, col + (unsigned)(kb - 1) * sk, qw);
-      prims(kp->P, qm1, um1, pm1);
-      prims(kp->P, qw, up1, pp1);  // plane kb-1, written at the first B
-    }
+    load_q<T>(Qin, fe, qcol + (unsigned)(kb - 2) * sk, qm1);
+    load_q<T>(Qin, fe, qcol + (unsigned)(kb - 1) * sk, qw);
+    if (kPrefetchQ) load_q<T>(Qin, fe, qcol + (unsigned)kb * sk, qa);
+    prims(kp->P, qm1, um1, pm1);
+    prims(kp->P, qw, up1, pp1);  // plane kb-1, written at the first B
     if (kPrefetchRing && h_ok) load_q<T>(Qin, fe, hcol + (unsigned)(kb - 1) * sk, hq);
 
     for (int t = kb - 1; t <= ke; ++t) {
@@ -293,35 +345,34 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
       const bool inner = t >= kb && t < ke;
       const bool nx_t = need_x && inner, ny_t = need_y && inner;
       const bool node_t = inner ? node_ok : out_ok;
+      T(*const sq)[EY][EX] = s.q[kQ2 ? qbuf : 0];
+      if (kQ2) qbuf ^= 1;
 
       // ---- B: fill LDS plane t ----
       if (load_ok) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) s.q[c][ey][ex] = qw[c];
+        for (int c = 0; c < 5; ++c) sq[c][ey][ex] = qw[c];
         s.p[ey][ex] = pp1;
         s.u[ey][ex] = up1[0]; s.v[ey][ex] = up1[1]; s.w[ey][ex] = up1[2]; s.tem[ey][ex] = up1[3];
-        load_q<T>(Qin, fe, nt + sk, qa);  // plane t+1 of the own column
       }
+      if (!kPrefetchQ) load_q<T>(Qin, fe, qcol + (unsigned)(t + 1) * sk, qa);  // plane t+1 of the own column
       if (h_ok) {
         T hu[4], hp;
         if (!kPrefetchRing) load_q<T>(Qin, fe, hcol + (unsigned)t * sk, hq);
         prims(P, hq, hu, hp);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) s.q[c][hy2][hx2] = hq[c];
+        for (int c = 0; c < 5; ++c) sq[c][hy2][hx2] = hq[c];
         s.p[hy2][hx2] = hp;
         s.u[hy2][hx2] = hu[0]; s.v[hy2][hx2] = hu[1]; s.w[hy2][hx2] = hu[2]; s.tem[hy2][hx2] = hu[3];
       }
-      // Q^(0) rows of the plane finished in this iteration (t-1), needed in E
-      if (t > kb) {
-        dma_rows<5>((const char*)(Q0 + lane_el + (long long)(t - 1) * L.sk), fstep2, &q0w[wave][0][0][0], lane);
-        wait_vm<3>();  // all but the three Q^(0) copies: metrics, helper ring, plane t+1
-      } else {
-        wait_vm<0>();
-      }
-      __syncthreads();
+      wait_vm<0>();  // metrics of plane t, helper ring, plane t+1 of the own column
+      lds_barrier();
 
       // ---- C: node work at plane t ----
-      if (load_ok) prims(P, qa, up1, pp1);  // plane t+1 of the own column
+      prims(P, qa, up1, pp1);  // plane t+1 of the own column
+      // Q^(0) rows of the plane finished in this iteration (t-1), needed in E
+      if (t > kb)
+        dma_rows<5>((const char*)(Q0 + lane_el + (long long)(t - 1) * L.sk), fstep2, &q0w[wave][0][0][0], lane);
       T hz[5] = {0, 0, 0, 0, 0};
       T lz = 0, nz = 0;
       double Jn = 0.0;
@@ -333,8 +384,6 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
       // issue the next plane's loads now so that they land during C and E:
       // helper ring (FP32 path), then the wave's metric rows (five copies)
       if (kPrefetchRing && h_ok && t < ke) load_q<T>(Qin, fe, hcol + (unsigned)(t + 1) * sk, hq);
-      if (t < ke)
-        dma_rows<10>((const char*)(kq->M + lane_el + (long long)(t + 1) * L.sk), fstep2, &mbw[wave][0][0][0], lane);
       if (node_t) {
         const T Jt = (T)Jn;
         T g[4][3];
@@ -356,7 +405,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
         const T s13 = T(0.5) * (g[0][2] + g[2][0]);
         const T s23 = T(0.5) * (g[1][2] + g[2][1]);
         const T skk3 = (s11 + s22 + s33) * T(1.0 / 3.0);
-        const T rho = s.q[0][ey][ex];
+        const T rho = sq[0][ey][ex];
         const T u = s.u[ey][ex], vv = s.v[ey][ex], w = s.w[ey][ex];
         const T tn = s.tem[ey][ex];
         const T mu = sutherland_fast(tn, P);
@@ -395,10 +444,10 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           const T mx = mt[3 * e], my = mt[3 * e + 1], mz = mt[3 * e + 2];
           const T Ue = U[e];
           H[0] = rho * Ue;
-          H[1] = s.q[1][ey][ex] * Ue + mx * p - (mx * t11 + my * t12 + mz * t13);
-          H[2] = s.q[2][ey][ex] * Ue + my * p - (mx * t12 + my * t22 + mz * t23);
-          H[3] = s.q[3][ey][ex] * Ue + mz * p - (mx * t13 + my * t23 + mz * t33);
-          H[4] = (s.q[4][ey][ex] + p) * Ue - (mx * th0 + my * th1 + mz * th2);
+          H[1] = sq[1][ey][ex] * Ue + mx * p - (mx * t11 + my * t12 + mz * t13);
+          H[2] = sq[2][ey][ex] * Ue + my * p - (mx * t12 + my * t22 + mz * t23);
+          H[3] = sq[3][ey][ex] * Ue + mz * p - (mx * t13 + my * t23 + mz * t33);
+          H[4] = (sq[4][ey][ex] + p) * Ue - (mx * th0 + my * th1 + mz * th2);
         };
         __builtin_amdgcn_sched_barrier(0);
         if (nx_t) {
@@ -427,16 +476,19 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           nz = fabs(pp1 - T(2) * p + pm1) * rcp_nr(pp1 + T(2) * p + pm1);
         }
       }
-      __syncthreads();
+      lds_barrier();
 
       double q0v[5] = {0, 0, 0, 0, 0};
       if (t > kb) {
-        // Q^(0) copies (issued at B) are older than the metric copies of this plane
-        if (t < ke) wait_vm<5>();
-        else wait_vm<0>();
+        wait_vm<0>();  // the Q^(0) copies (issued in C)
 #pragma unroll
         for (int c = 0; c < 5; ++c) q0v[c] = q0w[wave][c][ty1][tx];
       }
+      // the wave's metric rows of the next plane, landing during E (which
+      // stores nothing to LDS); read at C of the next plane
+      if (t < ke)
+        dma_rows<10>((const char*)(kq->M + lane_el + (long long)(t + 1) * L.sk), fstep2, &mbw[wave][0][0][0], lane);
+      if (kPrefetchQ && t < ke) load_q<T>(Qin, fe, qcol + (unsigned)(t + 2) * sk, qn);  // consumed at C of t+1
 
       // ---- E: residual (tile nodes) ----
       if (out_ok) {
@@ -452,8 +504,8 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           T q_a[5], q_b[5], q_c[5], q_d[5], q_e[5], D1[5], D0[5];
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
-            q_a[c] = s.q[c][ey][ex - 2]; q_b[c] = s.q[c][ey][ex - 1]; q_c[c] = s.q[c][ey][ex];
-            q_d[c] = s.q[c][ey][ex + 1]; q_e[c] = s.q[c][ey][ex + 2];
+            q_a[c] = sq[c][ey][ex - 2]; q_b[c] = sq[c][ey][ex - 1]; q_c[c] = sq[c][ey][ex];
+            q_d[c] = sq[c][ey][ex + 1]; q_e[c] = sq[c][ey][ex + 2];
           }
           face_diss(P, s.lx[cy][tx], s.lx[cy][tx + 1], s.nx[cy][tx], s.nx[cy][tx + 1], q_b, q_c, q_d, q_e, D1);
           face_diss(P, s.lx[cy][tx - 1], s.lx[cy][tx], s.nx[cy][tx - 1], s.nx[cy][tx], q_a, q_b, q_c, q_d, D0);
@@ -462,8 +514,8 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
-            q_a[c] = s.q[c][ey - 2][ex]; q_b[c] = s.q[c][ey - 1][ex];
-            q_d[c] = s.q[c][ey + 1][ex]; q_e[c] = s.q[c][ey + 2][ex];
+            q_a[c] = sq[c][ey - 2][ex]; q_b[c] = sq[c][ey - 1][ex];
+            q_d[c] = sq[c][ey + 1][ex]; q_e[c] = sq[c][ey + 2][ex];
           }
           face_diss(P, s.ly[ty][cx], s.ly[ty + 1][cx], s.ny[ty][cx], s.ny[ty + 1][cx], q_b, q_c, q_d, q_e, D1);
           face_diss(P, s.ly[ty - 1][cx], s.ly[ty][cx], s.ny[ty - 1][cx], s.ny[ty][cx], q_a, q_b, q_c, q_d, D0);
@@ -475,7 +527,7 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
           // zeta face t - 1/2 between plane t-1 and plane t
           T qc[5], D[5], fz[5];
 #pragma unroll
-          for (int c = 0; c < 5; ++c) qc[c] = s.q[c][ey][ex];
+          for (int c = 0; c < 5; ++c) qc[c] = sq[c][ey][ex];
           face_diss(P, lz_prev, lz, nz_prev, nz, qm2, qm1, qc, qa, D);
 #pragma unroll
           for (int c = 0; c < 5; ++c) fz[c] = T(0.5) * (hz_prev[c] + hz[c]) - D[c];
@@ -511,28 +563,30 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a, const QI* __restrict__ Qi
         J_prev = Jn;
       }
       // ---- shift the column queues (plane t values from LDS) ----
-      if (load_ok) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          qm2[c] = qm1[c];
-          qm1[c] = s.q[c][ey][ex];
-          qw[c] = qa[c];
-        }
-        um1[0] = s.u[ey][ex]; um1[1] = s.v[ey][ex]; um1[2] = s.w[ey][ex]; um1[3] = s.tem[ey][ex];
-        pm1 = s.p[ey][ex];
+      for (int c = 0; c < 5; ++c) {
+        qm2[c] = qm1[c];
+        qm1[c] = sq[c][ey][ex];
+        qw[c] = qa[c];
+        if (kPrefetchQ) qa[c] = qn[c];
       }
-      __syncthreads();
+      um1[0] = s.u[ey][ex]; um1[1] = s.v[ey][ex]; um1[2] = s.w[ey][ex]; um1[3] = s.tem[ey][ex];
+      pm1 = s.p[ey][ex];
+      if (!kQ2) lds_barrier();
     }
   }
 
-  if (NORM) norm_accumulate(n2, nm, red, tid);
   // ---- block partial norms ----
+  // (the wave's Q^(0) block is free: its last copy was waited for and read)
   if (NORM) {
+    constexpr int QW = 5 * RPW * BX;  // doubles per wave in q0w
+    norm_wave(n2, nm, &q0w[wave][0][0][0], lane);
     __syncthreads();
     if (tid < 10) {
-      double r = red[0][tid];
+      const double* red = &q0w[0][0][0][0];
+      double r = red[tid];
       for (int w = 1; w < NW; ++w) {
-        const double o = red[w][tid];
+        const double o = red[w * QW + tid];
         r = tid < 5 ? r + o : ((o > r || o != o) ? o : r);
       }
       part[(long long)v * 10 + tid] = r;
@@ -549,8 +603,8 @@ struct Config {
 long long auto_per_block(const Layout& L) {
   const long long tiles = (long long)((L.ni + TX - 1) / TX) * ((L.nj + TY - 1) / TY);
   const long long total = tiles * L.nk;
-  // one persistent block per CU, at least 8 planes each
-  long long pb = (total + 255) / 256;
+  // one persistent block per resident slot (BPC per CU), at least 8 planes each
+  long long pb = (total + 256 * BPC - 1) / (256 * BPC);
   return pb < 8 ? 8 : pb;
 }
 
