@@ -13,7 +13,7 @@ struct StageArgs {
   int kchunk;       // k planes per block (from stage_kchunk, fixed per context)
 };
 
-// k planes per block of the fused kernel for this layout (LES_KCHUNK in
+// k planes per block of the fused kernel for this layout (LES_SEG in
 // the environment overrides the automatic choice; read once per context).
 int stage_kchunk(const Layout& L);
 
