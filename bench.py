@@ -17,8 +17,9 @@ Prints one JSON line:
   cpu_baseline  the plain FP64 CPU oracle on a bounded sample of the same
              workload (rank 0, host cores of this machine).
 Extra keys report the mixed-precision path, the adjoint/forward cost, the
-shard with boundary faces (entrance, exit, far field) and the running flow
-statistics when those paths are available.
+shard with boundary faces (entrance, exit, far field), the running flow
+statistics and the restart file (write and read rates) when those paths are
+available.
 """
 import argparse
 import hashlib
@@ -185,6 +186,33 @@ def time_stats(case, calls=50):
             "frac_of_hbm_peak": round(byts / us / 1e3 / HBM_PEAK_GBS, 4)}
 
 
+def time_restart(case):
+    """Restart file of the benchmark shard (state with ghosts, 5 padded FP64
+    fields, plus the statistics sums): wall time to write it (device to file)
+    and to read it back (file to device), in a temporary directory."""
+    import tempfile
+    import torch
+    from paper_2003_08746_amd import lesmi, restart
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    acc = s.stats_accumulate(Q)
+    nbytes = 5 * 8 * (case["ni"] + 4) * (case["nj"] + 4) * (case["nk"] + 4) + acc.numel() * 8
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "run.safetensors")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        restart.save(p, s, Q, case, step=1, time=0.0, stats=acc, samples=case["nk"])
+        tw = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = restart.load(p, s, case)
+        torch.cuda.synchronize()
+        tr = time.perf_counter() - t0
+        same = bool(torch.equal(s.view(r["Q"]), s.view(Q)) and torch.equal(r["stats"], acc))
+    s.close()
+    return {"bytes": int(nbytes), "write_s": round(tw, 3), "read_s": round(tr, 3),
+            "write_GBps": round(nbytes / tw / 1e9, 2), "read_GBps": round(nbytes / tr / 1e9, 2), "bitwise": same}
+
+
 def time_large(steps, ni=800, nj=500, nk=500):
     """The 800 x 500 x 500 shard (2.0e8 points), generated on the device."""
     import torch
@@ -234,7 +262,7 @@ def main():
     ap.add_argument("--nj", type=int, default=128)
     ap.add_argument("--nk", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision, adjoint, boundary-face and statistics legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision, adjoint, boundary-face, statistics and restart legs")
     ap.add_argument("--large", action="store_true",
                     help="also time the 800 x 500 x 500 shard (FP64 and mixed, 20 steps each)")
     ap.add_argument("--large-steps", type=int, default=20)
@@ -319,6 +347,10 @@ def main():
             extra["stats"] = time_stats(case)
         except Exception as e:
             extra["stats"] = {"error": str(e)[:200]}
+        try:
+            extra["restart"] = time_restart(case)
+        except Exception as e:
+            extra["restart"] = {"error": str(e)[:200]}
         out["extra"] = extra
     if args.large:
         out.setdefault("extra", {})["large"] = time_large(args.large_steps)

@@ -235,7 +235,7 @@ int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, do
 int les_set_face(les_ctx *ctx, int face, int type, const double *Q_outside, double p_exit);
 
 /* Running flow statistics for the time- and azimuth-averaged mean-flow and
- * RMS profiles of Sec. 5 (the periodic k direction is the averaged one):
+ * RMS profiles of Sec. 6 (the periodic k direction is the averaged one):
  *   acc[s][j][i] += sum over k = 0..nk-1 of phi_s(i, j, k),
  *   phi = (rho, u, v, w, p, u u, v v, w w, u v, u w, v w, p p),
  * with the primitives of Eq. 2: u_a = (rho u_a) / rho and

@@ -255,7 +255,7 @@ STATS_FIELDS = ("rho", "u", "v", "w", "p", "uu", "vv", "ww", "uv", "uw", "vw", "
 
 
 def stats(case, Q, acc=None, prm=None) -> np.ndarray:
-    """Running statistics (Sec. 5 mean-flow and RMS profiles, averaged over
+    """Running statistics (Sec. 6 mean-flow and RMS profiles, averaged over
     time and the periodic direction k): acc[s][j][i] += sum_k phi_s, phi in
     STATS_FIELDS order.  Returns acc (a new zero array when acc is None)."""
     lib = _load()

@@ -874,7 +874,7 @@ double orc_objective(const orc_dims* d, const orc_params* P, const double* m, do
 // Test hook for the scalar rules R11 and the RK driver on y' = lambda y
 // (complex lambda), used to check the amplification polynomial.
 // Running flow statistics (the time- and azimuth-averaged mean-flow and RMS
-// profiles of Sec. 5; the averaged periodic direction is k):
+// profiles of Sec. 6; the averaged periodic direction is k):
 //   acc[s][j][i] += sum over k = 0..nk-1 of phi_s(i, j, k),
 //   phi = (rho, u, v, w, p, uu, vv, ww, uv, uw, vw, pp),
 // with the primitives of Eq. 2: u_a = (rho u_a) / rho,

@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(64) k_probe_final(const double* __restrict__ p
 namespace les {
 
 // ---------------------------------------------------------------------------
-// Running flow statistics (Sec. 5: time- and azimuth-averaged mean-flow and
+// Running flow statistics (Sec. 6: time- and azimuth-averaged mean-flow and
 // RMS profiles; the periodic k direction is the averaged one):
 //   acc[s][j][i] += sum over k of phi_s(i, j, k),
 //   phi = (rho, u, v, w, p, uu, vv, ww, uv, uw, vw, pp).

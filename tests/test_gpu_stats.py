@@ -1,6 +1,6 @@
 """Running flow statistics (les_stats_accumulate) against the oracle: sums
 over the periodic k direction of the primitives and their second moments
-(the mean-flow and RMS profiles of Sec. 5), accumulated over two states."""
+(the mean-flow and RMS profiles of Sec. 6), accumulated over two states."""
 import numpy as np
 import pytest
 

@@ -454,7 +454,7 @@ def test_paper_constants():
 
 
 # ---------------------------------------------------------------------------
-# Running statistics (mean-flow and RMS profiles of Sec. 5): closed forms
+# Running statistics (mean-flow and RMS profiles of Sec. 6): closed forms
 # ---------------------------------------------------------------------------
 def _harmonic_state(ni, nj, nk, gamma):
     """Primitives that vary along k by whole harmonics of the period nk (and
