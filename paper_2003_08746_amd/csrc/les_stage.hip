@@ -8,9 +8,11 @@
 // Decomposition.  A block of 32 x 16 threads owns the nodes of a 32 x 16
 // patch of one k-plane: the 30 x 14 output tile and a one-node halo ring.
 // Blocks are persistent (one per CU): block v marches a contiguous range of
-// (tile, k) planes, tile-major, so neighbouring tiles -- which share halo
-// lines -- run on the same XCD and the per-tile start-up cost (two extra
-// planes) is paid once per range, not once per k chunk.  Each thread keeps
+// (tile, k) planes in chunk-major order (k chunks as long as one block's
+// range, tiles within a chunk, planes within a tile), so the blocks that
+// run together on one XCD start on neighbouring tiles at the same plane and
+// read the halo lines they share while those are still in the XCD's L2, and
+// the per-tile start-up cost (two extra planes) is paid about once per block.  Each thread keeps
 // the k-direction stencil of its own column in registers (conserved
 // variables at t-2 .. t+1, primitives at t-1 and t+1, the zeta node flux and
 // the partial residual of the plane below), so the zeta direction needs no
@@ -99,6 +101,7 @@ struct KArgs {
   int ntx, nty;         // tiles in i, j
   long long total;      // tile-planes = ntx * nty * nk
   long long per_block;  // tile-planes per block (contiguous range)
+  int kc;               // planes per k chunk of the chunk-major order
   int nblocks;          // blocks with work
   int per_xcd;          // blocks per XCD in the remapped order
 };
@@ -272,9 +275,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
   int qbuf = 0;  // LDS Q plane written at the next B (alternates every plane)
   for (long long wq = w_begin; wq < w_end;) {
     // ---- one segment: planes [kb, ke) of one tile ----
-    const int tile = (int)(wq / L.nk);
-    const int kb = (int)(wq % L.nk);
-    const int ke = (int)min((long long)L.nk, (long long)kb + (w_end - wq));
+    // tile-planes are ordered k chunk by k chunk (kc planes; the last chunk
+    // may be shorter), tile by tile within a chunk, plane by plane within a
+    // tile: the blocks that run at the same time on one XCD start on
+    // neighbouring tiles at the same plane, so the halo lines they share
+    // are read while they are still in that XCD's L2
+    const long long cfull = (long long)a.ntx * a.nty * a.kc;
+    const int ch = (int)(wq / cfull);
+    const int k0 = ch * a.kc;
+    const int kcc = min(a.kc, L.nk - k0);
+    const long long rr = wq - (long long)ch * cfull;
+    const int tile = (int)(rr / kcc);
+    const int kb = k0 + (int)(rr % kcc);
+    const int ke = (int)min((long long)(k0 + kcc), (long long)kb + (w_end - wq));
     wq += ke - kb;
     const int tix = tile % a.ntx, tiy = tile / a.ntx;
     const int i0 = tix * TX, j0 = tiy * TY;
@@ -624,7 +637,8 @@ template <class T, class QI>
 hipError_t launch(hipStream_t st, const StageArgs& sa, const QI* Qin, const double* Q0, double* Qout, float* Qsh,
                   const double* dtp, double dt, double alpha, double* part) {
   Config c = config(sa.L, sa.kchunk);
-  KArgs a{sa.L, sa.P, sa.M, sa.f, sa.i_f, c.ntx, c.nty, c.total, c.per_block, c.nblocks, c.per_xcd};
+  const int kc = (int)min((long long)sa.L.nk, c.per_block);
+  KArgs a{sa.L, sa.P, sa.M, sa.f, sa.i_f, c.ntx, c.nty, c.total, c.per_block, kc, c.nblocks, c.per_xcd};
   if (part)
     k_stage<T, QI, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part);
   else
