@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -37,12 +38,21 @@ BYTES_FP64 = 192.0  # algorithmic bytes per point-stage, FP64 path
 BYTES_MIXED = 168.0
 
 
+def _code_only(text):
+    """C++ source without comments and with whitespace collapsed: edits to
+    comments or layout do not change what the stage kernel is."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash():
+    """Hash of the stage kernel's code (the sources it is built from)."""
     h = hashlib.sha256()
     for f in ["les_stage.hip", "les_stage.hpp", "les_common.hpp"]:
         p = os.path.join(ROOT, "paper_2003_08746_amd", "csrc", f)
         if os.path.exists(p):
-            h.update(open(p, "rb").read())
+            h.update(_code_only(open(p).read()).encode())
     return h.hexdigest()[:16]
 
 

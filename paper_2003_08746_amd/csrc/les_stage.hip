@@ -12,13 +12,14 @@
 // range, tiles within a chunk, planes within a tile), so the blocks that
 // run together on one XCD start on neighbouring tiles at the same plane and
 // read the halo lines they share while those are still in the XCD's L2, and
-// the per-tile start-up cost (two extra planes) is paid about once per block.  Each thread keeps
-// the k-direction stencil of its own column in registers (conserved
-// variables at t-2 .. t+1, primitives at t-1 and t+1, the zeta node flux and
-// the partial residual of the plane below), so the zeta direction needs no
-// LDS.  The in-plane (xi, eta) stencil goes through LDS in three phases per
-// plane, separated by barriers (a third barrier closes the plane in the FP64
-// path; the FP32 path double-buffers the LDS Q plane instead, see below):
+// the per-tile start-up cost (two extra planes) is paid about once per
+// block.  Each thread keeps the k-direction stencil of its own column in
+// registers (conserved variables at t-2 .. t+1, primitives at t-1 and t+1,
+// the zeta node flux and the partial residual of the plane below), so the
+// zeta direction needs no LDS.  The in-plane (xi, eta) stencil goes
+// through LDS in three phases per plane, separated by barriers (a third
+// barrier closes the plane in the FP64 path; the FP32 path double-buffers
+// the LDS Q plane instead, see below):
 //   B  fill:  every node of the patch (and a second halo ring along the
 //             axes, written by helper threads) stores Q, p, u, v, w, T;
 //   C  node:  every non-corner node of the patch computes its velocity and
@@ -45,9 +46,8 @@
 // vmcnt waits instead.  The own-column loads are branch-free (threads past
 // the padded box load a clamped node), which lets the compiler see that
 // they have completed and keeps it from adding full vmcnt waits of its own.
-// The flow constants
-// are read from the kernel-argument segment where they are used, instead of
-// occupying scalar registers across the loop.  Divisions and square roots
+// The flow constants are read from the kernel-argument segment where they
+// are used, instead of occupying scalar registers across the loop.  Divisions and square roots
 // use short Newton-refined sequences (valid for the positive, normal
 // arguments met here).  Scheduling fences split phases C and E into short
 // regions (gradient / stress / spectral radii / each node flux; each
