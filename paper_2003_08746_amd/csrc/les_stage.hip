@@ -102,6 +102,8 @@ struct KArgs {
   long long total;      // tile-planes = ntx * nty * nk
   long long per_block;  // tile-planes per block (contiguous range)
   int kc;               // planes per k chunk of the chunk-major order
+  int rr;               // 1: blocks take (chunk, tile) segments round robin
+  long long nseg;       // segments in round-robin mode
   int nblocks;          // blocks with work
   int per_xcd;          // blocks per XCD in the remapped order
 };
@@ -239,8 +241,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
   const int hb = blockIdx.x;
   const int v = (hb & 7) * a.per_xcd + (hb >> 3);
   if (v >= a.nblocks) return;
-  const long long w_begin = (long long)v * a.per_block;
-  const long long w_end = min(a.total, w_begin + a.per_block);
+  // contiguous mode: tile-planes [w_begin, w_end) of the chunk-major order;
+  // round-robin mode: segments v, v + nblocks, v + 2 nblocks, ...
+  const long long w_begin = a.rr ? (long long)v : (long long)v * a.per_block;
+  const long long w_end = a.rr ? a.nseg : min(a.total, w_begin + a.per_block);
 
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
@@ -279,16 +283,29 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // may be shorter), tile by tile within a chunk, plane by plane within a
     // tile: the blocks that run at the same time on one XCD start on
     // neighbouring tiles at the same plane, so the halo lines they share
-    // are read while they are still in that XCD's L2
-    const long long cfull = (long long)a.ntx * a.nty * a.kc;
-    const int ch = (int)(wq / cfull);
-    const int k0 = ch * a.kc;
-    const int kcc = min(a.kc, L.nk - k0);
-    const long long rr = wq - (long long)ch * cfull;
-    const int tile = (int)(rr / kcc);
-    const int kb = k0 + (int)(rr % kcc);
-    const int ke = (int)min((long long)(k0 + kcc), (long long)kb + (w_end - wq));
-    wq += ke - kb;
+    // are read while they are still in that XCD's L2.  A block takes a
+    // contiguous range of that order when its share is at most one chunk;
+    // with larger shares it takes whole (chunk, tile) segments round robin,
+    // which keeps the blocks of an XCD on neighbouring tiles throughout.
+    int tile, kb, ke;
+    if (a.rr) {
+      const long long ntiles = (long long)a.ntx * a.nty;
+      const int ch = (int)(wq / ntiles);
+      tile = (int)(wq % ntiles);
+      kb = ch * a.kc;
+      ke = min(L.nk, kb + a.kc);
+      wq += a.nblocks;
+    } else {
+      const long long cfull = (long long)a.ntx * a.nty * a.kc;
+      const int ch = (int)(wq / cfull);
+      const int k0 = ch * a.kc;
+      const int kcc = min(a.kc, L.nk - k0);
+      const long long rr = wq - (long long)ch * cfull;
+      tile = (int)(rr / kcc);
+      kb = k0 + (int)(rr % kcc);
+      ke = (int)min((long long)(k0 + kcc), (long long)kb + (w_end - wq));
+      wq += ke - kb;
+    }
     const int tix = tile % a.ntx, tiy = tile / a.ntx;
     const int i0 = tix * TX, j0 = tiy * TY;
     const int i = i0 - 1 + tx, j = j0 - 1 + ty;
@@ -609,8 +626,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 
 // Stage kernel configuration for a layout.
 struct Config {
-  int ntx, nty, nblocks, grid, per_xcd;
-  long long total, per_block;
+  int ntx, nty, nblocks, grid, per_xcd, kc, rr;
+  long long total, per_block, nseg;
 };
 
 long long auto_per_block(const Layout& L) {
@@ -627,7 +644,33 @@ Config config(const Layout& L, long long per_block) {
   c.nty = (L.nj + TY - 1) / TY;
   c.total = (long long)c.ntx * c.nty * L.nk;
   c.per_block = per_block < 1 ? 1 : per_block;
-  c.nblocks = (int)((c.total + c.per_block - 1) / c.per_block);
+  c.rr = c.per_block > L.nk;
+  c.nseg = 0;
+  if (!c.rr) {
+    c.kc = (int)c.per_block;
+    c.nblocks = (int)((c.total + c.per_block - 1) / c.per_block);
+  } else {
+    // the number of k chunks (at most 16, chunks of at least 32 planes when
+    // nk allows) that best fills whole rounds of the blocks there are
+    // slots for; fewer chunks on ties (fewer segment start-ups)
+    const long long ntiles = (long long)c.ntx * c.nty;
+    const long long slots = (c.total + c.per_block - 1) / c.per_block;
+    double best = -1.0;
+    for (int n = 1; n <= 16; ++n) {
+      const int kc = (L.nk + n - 1) / n;
+      if (n > 1 && kc < 32) break;
+      const long long nseg = ntiles * ((L.nk + kc - 1) / kc);
+      const long long nb = nseg < slots ? nseg : slots;
+      const long long rounds = (nseg + nb - 1) / nb;
+      const double eff = (double)nseg / (double)(rounds * nb);
+      if (eff > best + 1e-9) {
+        best = eff;
+        c.kc = kc;
+        c.nseg = nseg;
+        c.nblocks = (int)nb;
+      }
+    }
+  }
   c.per_xcd = (c.nblocks + 7) / 8;
   c.grid = c.per_xcd * 8;
   return c;
@@ -637,8 +680,8 @@ template <class T, class QI>
 hipError_t launch(hipStream_t st, const StageArgs& sa, const QI* Qin, const double* Q0, double* Qout, float* Qsh,
                   const double* dtp, double dt, double alpha, double* part) {
   Config c = config(sa.L, sa.kchunk);
-  const int kc = (int)min((long long)sa.L.nk, c.per_block);
-  KArgs a{sa.L, sa.P, sa.M, sa.f, sa.i_f, c.ntx, c.nty, c.total, c.per_block, kc, c.nblocks, c.per_xcd};
+  KArgs a{sa.L,        sa.P,   sa.M,   sa.f,      sa.i_f,    c.ntx,    c.nty,
+          c.total,     c.per_block, c.kc, c.rr, c.nseg, c.nblocks, c.per_xcd};
   if (part)
     k_stage<T, QI, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part);
   else

@@ -29,11 +29,13 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("shape,seg", [((61, 29, 23), "5"), ((31, 15, 9), "4"), ((93, 43, 17), ""),
-                                       ((40, 20, 12), "7")])
+                                       ((40, 20, 12), "7"), ((61, 29, 23), "40"), ((93, 43, 37), "200")])
 def test_fused_matches_reference_kernel(lesmi, shape, seg, monkeypatch):
     """tiles 30 x 14 in (i, j): every shape leaves a ragged last tile; the
     segment sizes (tile-planes per persistent block) put segment starts and
-    ends inside k and segments that span two tiles."""
+    ends inside k and segments that span two tiles.  A share larger than nk
+    (the last two cases) switches the blocks to round-robin (chunk, tile)
+    segments, the schedule of the largest shards."""
     if seg:
         monkeypatch.setenv("LES_SEG", seg)
     else:
