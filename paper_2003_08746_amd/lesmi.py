@@ -360,3 +360,11 @@ def stats_profiles(acc, samples):
         out[a + "_rms"] = torch.sqrt(torch.clamp(m[a + a] - m[a] * m[a], min=0.0))
     out["uv"] = m["uv"] - m["u"] * m["v"]
     return out
+
+
+def potential_core(profiles, u_jet, frac=0.95):
+    """The jet's potential core as Sec. 6 defines it: the nodes whose
+    time-averaged axial velocity is at least frac (95 %) of the inlet jet
+    velocity u_jet.  profiles: the dict of stats_profiles (its "u" entry,
+    (nj, ni)); returns a boolean (nj, ni) tensor."""
+    return profiles["u"] >= frac * u_jet

@@ -51,3 +51,4 @@ def test_refuses_other_runs(tmp_path):
     save_file({"Q": Q}, q, metadata={"format": "something-else"})
     with pytest.raises(ValueError):
         restart.read(q, case)
+
