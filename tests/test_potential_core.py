@@ -1,6 +1,8 @@
 """The potential-core helper on the host (no GPU): the region of Sec. 6
 where the time-averaged axial velocity is at least 95 % of the inlet jet
 velocity."""
+
+
 def test_potential_core_mask():
     """Sec. 6: the potential core is where <U> >= 0.95 U_jet (host tensors;
     the helper only reads the mean axial velocity of stats_profiles)."""
