@@ -18,8 +18,9 @@ Prints one JSON line:
              workload (rank 0, host cores of this machine).
 Extra keys report the mixed-precision path, the adjoint/forward cost, the
 shard with boundary faces (entrance, exit, far field), the running flow
-statistics and the restart file (write and read rates) when those paths are
-available.
+statistics, the restart file (write and read rates) and the bandwidth a
+plain device copy reaches (the achievable stream rate beside the 8 TB/s
+peak) when those paths are available.
 """
 import argparse
 import hashlib
@@ -196,6 +197,36 @@ def time_stats(case, calls=50):
             "frac_of_hbm_peak": round(byts / us / 1e3 / HBM_PEAK_GBS, 4)}
 
 
+def time_copy(mib=1024, reps=10):
+    """Achievable stream bandwidth on this GPU: a plain device-to-device copy
+    of mib MiB, read + write bytes over the mean copy time (HIP events on the
+    copy's stream), by the library's copy kernel and by torch's."""
+    import torch
+    from paper_2003_08746_amd import lesmi
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    out = {"bytes_moved": 2 * n * 8}
+    for name, run in (("GBps", lambda: lesmi.les_debug_stream_copy(src.data_ptr(), dst.data_ptr(), n * 8,
+                                                                    stream.cuda_stream)),
+                      ("torch_copy_GBps", lambda: dst.copy_(src))):
+        run()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            run()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        s = ev0.elapsed_time(ev1) / 1e3 / reps
+        out[name] = round(2 * n * 8 / s / 1e9, 1)
+    out["frac_of_hbm_peak"] = round(out["GBps"] / HBM_PEAK_GBS, 4)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_restart(case):
     """Restart file of the benchmark shard (state with ghosts, 5 padded FP64
     fields, plus the statistics sums): wall time to write it (device to file)
@@ -272,7 +303,7 @@ def main():
     ap.add_argument("--nj", type=int, default=128)
     ap.add_argument("--nk", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision, adjoint, boundary-face, statistics and restart legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision, adjoint, boundary-face, statistics, restart and copy legs")
     ap.add_argument("--large", action="store_true",
                     help="also time the 800 x 500 x 500 shard (FP64 and mixed, 20 steps each)")
     ap.add_argument("--large-steps", type=int, default=20)
@@ -361,6 +392,11 @@ def main():
             extra["restart"] = time_restart(case)
         except Exception as e:
             extra["restart"] = {"error": str(e)[:200]}
+        try:
+            extra["copy"] = time_copy()
+            extra["copy"]["stage_frac_of_copy"] = round(achieved / extra["copy"]["GBps"], 4)
+        except Exception as e:
+            extra["copy"] = {"error": str(e)[:200]}
         out["extra"] = extra
     if args.large:
         out.setdefault("extra", {})["large"] = time_large(args.large_steps)

@@ -1,8 +1,9 @@
 /* les_debug.h -- instrumentation entry points of liblesmi.so.
  *
  * Not part of the method: these are for the benchmark (per-launch timing of
- * the stage kernel) and for the tests (switching the RK step to the
- * one-thread-per-node reference kernel to cross-check the fused kernel).
+ * the stage kernel, a plain copy for the achievable stream bandwidth) and
+ * for the tests (switching the RK step to the one-thread-per-node reference
+ * kernel to cross-check the fused kernel).
  * Same conventions as les.h: status codes, never abort. */
 #ifndef LES_DEBUG_H
 #define LES_DEBUG_H
@@ -27,6 +28,13 @@ int les_debug_stage_timing(les_ctx *ctx, int on);
  * on or last read; synchronises with the recorded events, then resets the
  * totals.  LES_ERR_ARG for a null argument. */
 int les_debug_stage_time(les_ctx *ctx, double *total_ms, long long *launches);
+
+/* Plain device-to-device copy of nbytes from src to dst (device pointers,
+ * both 16-byte aligned, nbytes a positive multiple of 16), enqueued on
+ * hip_stream (NULL: the default stream); the benchmark times it as the
+ * achievable stream bandwidth.  LES_ERR_ARG for bad arguments, LES_ERR_HIP
+ * when the launch fails.  Needs no context. */
+int les_debug_stream_copy(const void *src, void *dst, long long nbytes, void *hip_stream);
 
 #ifdef __cplusplus
 }

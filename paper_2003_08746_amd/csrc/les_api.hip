@@ -514,4 +514,14 @@ int les_debug_stage_time(les_ctx* ctx, double* total_ms, long long* launches) {
   return rc;
 }
 
+// Plain device copy of nbytes (a multiple of 16, both pointers 16-byte
+// aligned) on the given HIP stream (les_debug.h; the benchmark's achievable
+// stream bandwidth).
+int les_debug_stream_copy(const void* src, void* dst, long long nbytes, void* hip_stream) {
+  if (!src || !dst || nbytes <= 0 || (nbytes & 15) || (((uintptr_t)src | (uintptr_t)dst) & 15))
+    return LES_ERR_ARG;
+  if (les::launch_stream_copy((hipStream_t)hip_stream, src, dst, nbytes / 16) != hipSuccess) return LES_ERR_HIP;
+  return LES_OK;
+}
+
 }  // extern "C"

@@ -685,6 +685,27 @@ hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3]
   return hipGetLastError();
 }
 
+// Stream copy (instrumentation): the bandwidth a plain, coalesced copy
+// reaches, as the achievable counterpart of the HBM peak.  Each thread
+// moves four 16-byte words, 256 words apart, loaded before any is stored.
+__global__ void __launch_bounds__(256) k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                     long long n16) {
+  const long long i = (long long)blockIdx.x * 1024 + threadIdx.x;
+  uint4 v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (i + 256 * u < n16) v[u] = src[i + 256 * u];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (i + 256 * u < n16) dst[i + 256 * u] = v[u];
+}
+
+hipError_t launch_stream_copy(hipStream_t s, const void* src, void* dst, long long n16) {
+  const long long blocks = (n16 + 1023) / 1024;
+  k_stream_copy<<<(unsigned)blocks, 256, 0, s>>>((const uint4*)src, (uint4*)dst, n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_stats(hipStream_t s, const Layout& L, const Phys& P, const double* Q, double* acc) {
   dim3 g(nblk(L.ni, 64), L.nj), b(64, 4);
   k_stats<<<g, b, 0, s>>>(L, P, Q, acc);

@@ -16,6 +16,8 @@ hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3]
                                  const Faces& F);
 // acc[12][nj][ni] += sums over k of the primitives and their second moments
 hipError_t launch_stats(hipStream_t s, const Layout& L, const Phys& P, const double* Q, double* acc);
+// Plain copy of n16 16-byte words (instrumentation: achievable stream rate).
+hipError_t launch_stream_copy(hipStream_t s, const void* src, void* dst, long long n16);
 long long ref_blocks(const Layout& L);
 // partials written by the CFL kernel
 long long cfl_blocks(const Layout& L);

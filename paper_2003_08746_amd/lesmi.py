@@ -108,6 +108,8 @@ def lib():
     L.les_debug_stage_timing.argtypes = [_vp, ctypes.c_int]
     L.les_debug_stage_time.restype = ctypes.c_int
     L.les_debug_stage_time.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.les_debug_stream_copy.restype = ctypes.c_int
+    L.les_debug_stream_copy.argtypes = [_vp, _vp, ctypes.c_longlong, _vp]
     _lib = L
     return L
 
@@ -232,6 +234,10 @@ def les_debug_stage_time(ctx):
     n = ctypes.c_longlong()
     _check(lib().les_debug_stage_time(ctx, ctypes.byref(ms), ctypes.byref(n)), ctx, "les_debug_stage_time")
     return ms.value, n.value
+
+
+def les_debug_stream_copy(src_ptr, dst_ptr, nbytes, stream_ptr=None):
+    _check(lib().les_debug_stream_copy(src_ptr, dst_ptr, int(nbytes), stream_ptr), None, "les_debug_stream_copy")
 
 
 # ---------------------------------------------------------------------------

@@ -96,4 +96,6 @@ def test_null_context_calls():
     assert L.les_set_forcing(None, None, 0) == lesmi.LES_ERR_ARG
     assert L.les_stats_accumulate(None, None, None) == lesmi.LES_ERR_ARG
     assert L.les_set_face(None, 0, 1, None, 0.0) == lesmi.LES_ERR_ARG
+    assert L.les_debug_stream_copy(None, None, 16, None) == lesmi.LES_ERR_ARG
+    assert L.les_debug_stream_copy(16, 32, 24, None) == lesmi.LES_ERR_ARG  # not a multiple of 16 (no launch)
     L.les_destroy(None)
