@@ -144,7 +144,10 @@ int les_get_metrics(les_ctx *ctx, double *dense_out);
  * Q: device, library layout [5][field_elems], FP64; its ghost layers are
  *    filled in place (periodic wrap; Dirichlet ghosts untouched); interior
  *    values are not modified.
- * R: device, library layout [5][field_elems]; interior nodes written.
+ * R: device, library layout [5][field_elems]; interior nodes written (when
+ *    R is 16-byte aligned the fused stage kernel computes it and the ghost
+ *    layers of R are set to 0; otherwise the one-node-per-thread reference
+ *    kernel computes it and leaves them as they were).
  * norms: host double[10] or NULL: RMS of R per variable (5) then max |R| (5)
  *    over the interior. */
 int les_residual(les_ctx *ctx, double *Q, double *R, double *norms);

@@ -324,11 +324,24 @@ int les_residual(les_ctx* ctx, double* Q, double* R, double* norms) {
   if (!Q || !R) return fail(ctx, LES_ERR_ARG, "les_residual: Q and R must be device pointers");
   if (Q == R) return fail(ctx, LES_ERR_ARG, "les_residual: Q and R must not alias");
   HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
-  HIPCHK(ctx, les::launch_residual_ref(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->f, ctx->i_f, R,
-                                       norms ? ctx->part : nullptr));
+  const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
+  double* part = norms ? ctx->part : nullptr;
+  long long nb;
+  if (!ctx->use_ref && !(((uintptr_t)R) & 15)) {
+    // the fused stage kernel with Q^(0) = R = 0 and alpha dt = -1 writes
+    // 0 + R(Q) at every interior node (and reduces the norms of R)
+    const les::Layout& L = ctx->L;
+    HIPCHK(ctx, les::launch_zero(ctx->s, R, 5 * L.fe));
+    const les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
+    HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, Q, R, R, nullptr, 1.0, -1.0, part));
+    nb = les::stage_blocks(L, ctx->kchunk);
+  } else {
+    HIPCHK(ctx, les::launch_residual_ref(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->f, ctx->i_f, R, part));
+    nb = les::ref_blocks(ctx->L);
+  }
   if (!norms) return LES_OK;
   const double cnt = (double)ctx->L.ni * ctx->L.nj * ctx->L.nk;
-  HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::ref_blocks(ctx->L), cnt, ctx->scal + 1, ctx->flag));
+  HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
   return sync_outputs(ctx, nullptr, norms);
 }
 

@@ -685,6 +685,18 @@ hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3]
   return hipGetLastError();
 }
 
+// p[0 .. n) = 0 (a kernel, not a memset, so that a captured call records
+// only kernel nodes).
+__global__ void __launch_bounds__(256) k_zero(double* __restrict__ p, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+hipError_t launch_zero(hipStream_t s, double* p, long long n) {
+  k_zero<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
 // Stream copy (instrumentation): the bandwidth a plain, coalesced copy
 // reaches, as the achievable counterpart of the HBM peak.  Each thread
 // moves four 16-byte words, 256 words apart, loaded before any is stored.
