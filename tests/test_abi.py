@@ -99,3 +99,22 @@ def test_null_context_calls():
     assert L.les_debug_stream_copy(None, None, 16, None) == lesmi.LES_ERR_ARG
     assert L.les_debug_stream_copy(16, 32, 24, None) == lesmi.LES_ERR_ARG  # not a multiple of 16 (no launch)
     L.les_destroy(None)
+
+
+def test_create_size_limit():
+    """The stage kernels address a field with 32-bit byte offsets: a padded
+    field of 2^29 elements or more is refused before anything is allocated.
+    800 x 800 x 812 pads to 99.7 % of the limit (it passes the size check and
+    fails on the missing coordinates instead); 800 x 800 x 815 pads to 100.1 %."""
+    L = lesmi.lib()
+    ctx = ctypes.c_void_p()
+    p = lesmi.flow_params_struct(__import__("paper_2003_08746_amd.inputs", fromlist=["x"]).flow_params())
+    g = lesmi.LesGrid()
+    g.ni, g.nj, g.nk = 800, 800, 815
+    assert L.les_create(ctypes.byref(ctx), ctypes.byref(g), None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
+    assert b"too large" in L.les_last_create_error()
+    g.nk = 812
+    assert L.les_create(ctypes.byref(ctx), ctypes.byref(g), None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
+    assert b"too large" not in L.les_last_create_error()
+    assert lesmi.les_layout_for(800, 800, 812)[2] < (1 << 29) <= lesmi.les_layout_for(800, 800, 815)[2]
+    assert ctx.value is None
