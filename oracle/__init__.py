@@ -80,6 +80,8 @@ def _load():
     lib.orc_fill_ghosts_faces.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
     lib.orc_stats.restype = None
     lib.orc_stats.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
+    lib.orc_threads.restype = ctypes.c_int
+    lib.orc_threads.argtypes = [ctypes.c_int]
     lib.orc_rk_scalar.restype = None
     lib.orc_rk_scalar.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp]
     _lib = lib
@@ -91,6 +93,12 @@ def _ptr(a):
         return None
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(_dp)
+
+
+def threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP thread count (n > 0) and return the count its
+    loops use."""
+    return int(_load().orc_threads(int(n)))
 
 
 def dims(ni, nj, nk, bc=(0, 0, 0)) -> OrcDims:
@@ -113,14 +121,14 @@ def params(p: dict) -> OrcParams:
 
 
 # boundary-face types of a Dirichlet direction (faces i-lo, i-hi, j-lo, j-hi,
-# k-lo, k-hi): frozen ghosts, characteristic (entrance / far field), exit
-FACE_FROZEN, FACE_CHARACTERISTIC, FACE_EXIT = 0, 1, 2
+# k-lo, k-hi): frozen ghosts, characteristic entrance, exit, far field
+FACE_FROZEN, FACE_CHARACTERISTIC, FACE_EXIT, FACE_FARFIELD = 0, 1, 2, 3
 
 
 def _dims_of(case):
     """orc_dims of a case; case["faces"] (optional) = dict(types=[6],
     p_exit=[6], outside=padded (5, ...) state whose ghost values are the
-    outside state of characteristic faces)."""
+    outside state of characteristic and far-field faces)."""
     d = dims(case["ni"], case["nj"], case["nk"], case["bc"])
     fc = case.get("faces")
     if fc:

@@ -52,7 +52,7 @@
 //   R11 non-smooth derivatives (dual numbers): d|x|/dx = sign(x), 0 at 0;
 //       max(a, b) follows a when a >= b; d sqrt(x)/dx = 0 at x = 0.
 //   R12 an optional constant source f on the plane i = i_f: dQ/dt = -R + f.
-//   R13, R14 boundary faces of a Dirichlet direction: see fill_faces.
+//   R13, R14, R16 boundary faces of a Dirichlet direction: see fill_faces.
 //   R15 superposed periodic direction (Sec. 3: the first and last azimuthal
 //       points coincide): bc = 2, period n - 1; node n - 1 is node 0 again
 //       (it takes node 0's metrics), ghosts wrap with period n - 1.  A ghost
@@ -70,6 +70,9 @@
 
 #include <cmath>
 #include <cstdio>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <cstdlib>
 #include <cstddef>
 #include <cstring>
@@ -133,11 +136,12 @@ typedef struct {
   int ni, nj, nk;  // interior points per direction
   int bc[3];       // per direction i, j, k: 0 = periodic, 1 = frozen Dirichlet ghosts,
                    // 2 = periodic with superposed first and last nodes (R15)
-  // Boundary faces of a Dirichlet direction (R13, R14), in the order i-lo,
+  // Boundary faces of a Dirichlet direction (R13, R14, R16), in the order i-lo,
   // i-hi, j-lo, j-hi, k-lo, k-hi: 0 = frozen ghosts, 1 = characteristic
-  // (R13), 2 = subsonic exit with imposed pressure p_exit (R14).  outside:
-  // padded [5][N] state whose ghost-node values are the outside state of
-  // the characteristic faces (NULL when no face needs it).
+  // entrance (R13), 2 = subsonic exit with imposed pressure p_exit (R14),
+  // 3 = far field (R16).  outside: padded [5][N] state whose ghost-node
+  // values are the outside state of the characteristic and far-field faces
+  // (NULL when no face needs it).
   int face[6];
   double p_exit[6];
   const double* outside;
@@ -207,18 +211,18 @@ static inline int wrap(int x, int n, int bc) {
 }
 
 // ---------------------------------------------------------------------------
-// R13, R14: boundary faces of a Dirichlet direction (Sec. 3: entrance, far
+// R13, R14, R16: boundary faces of a Dirichlet direction (Sec. 3: entrance, far
 // field and exit conditions).  A ghost node that lies outside the interior
-// along exactly one Dirichlet direction d, on a face of type 1 or 2, takes a
+// along exactly one Dirichlet direction d, on a face of type 1, 2 or 3, takes a
 // state built from the boundary node r (the interior node next to the face
 // on the same line along d, periodic indices wrapped: zero-order
-// extrapolation for both ghost layers) and, for type 1, the outside state at
-// the ghost node.  Edge and corner ghosts of two Dirichlet directions stay
+// extrapolation for both ghost layers) and, for types 1 and 3, the outside
+// state at the ghost node.  Edge and corner ghosts of two Dirichlet directions stay
 // frozen.
 //   R14 exit (subsonic, imposed pressure): velocity and internal energy per
 //       unit mass eps = p / ((gamma - 1) rho) from r, p = p_exit, hence
 //       rho = p_exit / ((gamma - 1) eps) and e from Eq. 2.
-//   R13 characteristic (entrance and far field, locally one-dimensional along
+//   R13 characteristic (entrance, locally one-dimensional along
 //       the outward unit normal n = -+grad(xi_d) / |grad(xi_d)| at r):
 //       supersonic outflow (u.n >= c at r): the state of r;
 //       supersonic inflow (u.n <= -c outside): the outside state;
@@ -226,6 +230,18 @@ static inline int wrap(int x, int n, int bc) {
 //       from outside, u.n = (R+ + R-)/2, c = (gamma-1)(R+ - R-)/4, entropy
 //       p/rho^gamma and the tangential velocity from r when u.n >= 0, else
 //       from outside; rho = (c^2/(gamma s))^(1/(gamma-1)), p = rho c^2/gamma.
+//       This rule serves the entrance (the flat-hat profile is the outside
+//       state).
+//   R16 far field (Sec. 3: Riemann invariants, normal velocity extrapolated
+//       at zero order from inside, flow angle fixed, the rest from the jet
+//       Mach number through the outside state): u.n = u_r.n; tangential
+//       velocity = the outside state's (its direction, the flow angle, does
+//       not follow the interior); the incoming invariant
+//       R- = u_o.n - 2c_o/(gamma-1) of the outside state is kept, so
+//       c = (gamma-1)(u.n - R-)/2; entropy p/rho^gamma from outside when
+//       u.n < 0 (inflow), from r otherwise; rho and p from c and entropy.
+//       The outside state carries the jet-Mach-number-dependent far-field
+//       values (ambient density and pressure, co-flow velocity).
 // ---------------------------------------------------------------------------
 template <class S>
 void face_state(int type, double gamma, double p_exit, const double nrm[3], const S qr[5], const double qo[5],
@@ -249,6 +265,28 @@ void face_state(int type, double gamma, double p_exit, const double nrm[3], cons
   const double co = std::sqrt(gamma * po / ro);
   const S unr = u[0] * nrm[0] + u[1] * nrm[1] + u[2] * nrm[2];
   const double uno = uo[0] * nrm[0] + uo[1] * nrm[1] + uo[2] * nrm[2];
+  if (type == 3) {
+    // R16 far field, in the order of the Sec. 3 sentence: normal velocity
+    // from r (zero order); tangential velocity of the outside state (the
+    // fixed flow angle); the incoming Riemann invariant of the outside
+    // state at that normal velocity gives c; entropy from outside on
+    // inflow (u.n < 0), from r otherwise.
+    const S un = unr;
+    const double Rm = uno - 2.0 * co / gm1;
+    const S cb = 0.5 * gm1 * (un - Rm);
+    const S ent = val(un) >= 0.0 ? p / s_pow(rho, gamma) : S(po / std::pow(ro, gamma));
+    const S rb = s_pow(cb * cb / (gamma * ent), 1.0 / gm1);
+    const S pb = rb * cb * cb / gamma;
+    S ubb = S(0.0);
+    out[0] = rb;
+    for (int a = 0; a < 3; ++a) {
+      const S ub = (uo[a] - uno * nrm[a]) + un * nrm[a];
+      out[1 + a] = rb * ub;
+      ubb = ubb + ub * ub;
+    }
+    out[4] = pb / gm1 + 0.5 * rb * ubb;
+    return;
+  }
   if (val(unr) >= val(cr)) {
     for (int c = 0; c < 5; ++c) out[c] = qr[c];
     return;
@@ -749,11 +787,23 @@ extern "C" {
 
 size_t orc_box_nodes(const orc_dims* d) { return Box(*d).N; }
 
+// Threads of the OpenMP loops (n <= 0: leave unchanged); returns the number
+// the next parallel loop will use (1 without OpenMP).
+int orc_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 void orc_metrics(const orc_dims* d, const double* xyz, double* m) { metrics(Box(*d), xyz, m); }
 
 void orc_fill_ghosts(const orc_dims* d, double* a, int nfields) { fill_ghosts(Box(*d), a, nfields); }
 
-// Ghost fill of a state including the boundary faces of d (R13, R14).
+// Ghost fill of a state including the boundary faces of d (R13, R14, R16).
 void orc_fill_ghosts_faces(const orc_dims* d, const orc_params* P, const double* m, double* Q) {
   Box b(*d);
   b.m = m;

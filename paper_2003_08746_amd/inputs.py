@@ -144,6 +144,24 @@ def jet_state(xyz: np.ndarray, ni, nj, nk, seed=0, mach=1.4, R=0.5, theta=0.05, 
     return cons_from_prim(rho, vel[0], vel[1], vel[2], p)
 
 
+def outside_state(case: dict, mach=1.4, R=0.5, theta=0.05, coflow=0.0, cross=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Outside state of the jet block's boundary faces on every node of the
+    padded box: the unperturbed jet profile (the flat-hat-like tanh profile
+    that the entrance imposes) with ambient pressure p_inf = 1/gamma, plus
+    an optional uniform co-flow coflow * M_j along x and cross-flow
+    cross * M_j.  Far from the jet this is the far-field state, whose
+    velocity scale and temperature follow from the jet Mach number M_j."""
+    y = case["xyz"][1]
+    Uj = mach
+    u = 0.5 * Uj * (np.tanh((R + y) / (2 * theta)) + np.tanh((R - y) / (2 * theta)))
+    s = u / Uj
+    T = 1.0 + 0.5 * (GAMMA - 1.0) * mach * mach * s * (1.0 - s)
+    p = np.full_like(u, 1.0 / GAMMA)
+    rho = p / ((1.0 / GAMMA) * T)
+    vel = [u + (coflow + cross[0]) * Uj, np.full_like(u, cross[1] * Uj), np.full_like(u, cross[2] * Uj)]
+    return cons_from_prim(rho, vel[0], vel[1], vel[2], p)
+
+
 def jet_case(ni=256, nj=128, nk=128, seed=0, **kw) -> dict:
     scale = dict(Lx=7.5 * ni / 256, Ly=10.0, Lz=2.5 * nk / 128)
     scale.update({k: kw.pop(k) for k in list(kw) if k in ("Lx", "Ly", "Lz")})

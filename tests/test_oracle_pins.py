@@ -518,19 +518,21 @@ def _prims(q, g):
 
 def _face_case(seed=4):
     """20 x 12 x 8 jet block, Dirichlet in i and j, periodic in k; the
-    interior is perturbed away from the outside state (the analytic profile
-    in the initial ghosts); entrance and far field characteristic, exit at
-    i-hi with the ambient pressure."""
+    interior is perturbed away from the outside state; characteristic
+    entrance at i-lo, exit at i-hi with the ambient pressure, far field at
+    j-lo and j-hi.  The outside state is the analytic jet profile plus a
+    small spanwise cross-flow, so that the far-field flow angle is not the
+    normal's."""
     c = I.jet_case(20, 12, 8, seed=seed)
     c["bc"] = (1, 1, 0)
     g = c["params"]["gamma"]
-    Q0 = c["Q"].copy()
+    Q0 = I.outside_state(c, cross=(0.0, 0.0, 0.03))
     rng = np.random.default_rng(seed)
-    Q = Q0.copy()
+    Q = c["Q"].copy()
     Q[1:4] += 0.05 * rng.uniform(-1, 1, size=Q[1:4].shape)
     Q[4] *= 1.0 + 0.02 * rng.uniform(-1, 1, size=Q[4].shape)
     c["Q"] = Q
-    c["faces"] = dict(types=[1, 2, 1, 1, 0, 0], p_exit=[0.0, 1.0 / g, 0, 0, 0, 0], outside=Q0)
+    c["faces"] = dict(types=[1, 2, 3, 3, 0, 0], p_exit=[0.0, 1.0 / g, 0, 0, 0, 0], outside=Q0)
     return c, Q0
 
 
@@ -563,56 +565,128 @@ def test_face_exit_invariants(orc):
     assert count == 2 * nj * (nk + 4)
 
 
+def _face_ghosts(c, d, hi):
+    """(ghost index, boundary index) tuples (k, j, i) of the padded box for
+    face (d, hi) of the face case (d = 0 or 1), every periodic k included."""
+    ni, nj, nk = c["ni"], c["nj"], c["nk"]
+    n_d = ni if d == 0 else nj
+    ghosts = (n_d, n_d + 1) if hi else (-1, -2)
+    rb = n_d - 1 if hi else 0
+    for gd in ghosts:
+        for t in (range(nj) if d == 0 else range(ni)):
+            for kp in range(nk + 4):
+                kw = (kp - 2) % nk + 2
+                if d == 0:
+                    yield (kp, t + 2, gd + 2), (kw, t + 2, rb + 2)
+                else:
+                    yield (kp, gd + 2, t + 2), (kw, rb + 2, t + 2)
+
+
 def test_face_characteristic_invariants(orc):
-    """Entrance (i-lo) and far field (j-lo, j-hi): supersonic outflow copies
-    the boundary node, supersonic inflow the outside state; otherwise the
-    outgoing invariant u.n + 2c/(g-1) is the boundary node's, the incoming
-    u.n - 2c/(g-1) the outside's, and entropy p/rho^g and tangential velocity
-    come from the upwind side."""
+    """Entrance (i-lo): supersonic outflow copies the boundary node,
+    supersonic inflow the outside state; otherwise the outgoing invariant
+    u.n + 2c/(g-1) is the boundary node's, the incoming u.n - 2c/(g-1) the
+    outside's, and entropy p/rho^g and tangential velocity come from the
+    upwind side."""
     c, Q0 = _face_case()
     g = c["params"]["gamma"]
     m = orc.metrics(c)
     q = orc.fill_ghosts_faces(c, m, c["Q"])
     ni, nj, nk = c["ni"], c["nj"], c["nk"]
     kinds = {"out": 0, "in": 0, "sub_out": 0, "sub_in": 0}
-    faces = [(0, 0), (1, 0), (1, 1)]  # (direction, hi)
-    for d, hi in faces:
-        n_d = ni if d == 0 else nj
-        ghosts = (n_d, n_d + 1) if hi else (-1, -2)
-        rb = n_d - 1 if hi else 0
-        tang = range(nj) if d == 0 else range(ni)
-        for gd in ghosts:
-            for t in tang:
-                for kp in range(nk + 4):
-                    kw = (kp - 2) % nk + 2
-                    if d == 0:
-                        G, R = (kp, t + 2, gd + 2), (kw, t + 2, rb + 2)
-                    else:
-                        G, R = (kp, gd + 2, t + 2), (kw, rb + 2, t + 2)
-                    n = _normal(m, d, hi, R[2], R[1], R[0])
-                    gq, rq, oq = q[(slice(None),) + G], q[(slice(None),) + R], Q0[(slice(None),) + G]
-                    rr, ur, pr = _prims(rq, g)
-                    ro, uo, po = _prims(oq, g)
-                    rg, ug, pg = _prims(gq, g)
-                    cr, co, cg = np.sqrt(g * pr / rr), np.sqrt(g * po / ro), np.sqrt(g * pg / rg)
-                    if ur @ n >= cr:
-                        np.testing.assert_array_equal(gq, rq)
-                        kinds["out"] += 1
-                    elif uo @ n <= -co:
-                        np.testing.assert_array_equal(gq, oq)
-                        kinds["in"] += 1
-                    else:
-                        scale = abs(ur @ n) + cr
-                        assert abs((ug @ n + 2 * cg / (g - 1)) - (ur @ n + 2 * cr / (g - 1))) <= 1e-13 * scale
-                        assert abs((ug @ n - 2 * cg / (g - 1)) - (uo @ n - 2 * co / (g - 1))) <= 1e-13 * scale
-                        src_r, src_u = (rr, ur) if ug @ n >= 0 else (ro, uo)
-                        src_p = pr if ug @ n >= 0 else po
-                        assert abs(pg / rg ** g - src_p / src_r ** g) <= 1e-13 * src_p / src_r ** g
-                        ut_g, ut_s = ug - (ug @ n) * n, src_u - (src_u @ n) * n
-                        np.testing.assert_allclose(ut_g, ut_s, rtol=0, atol=1e-13 * scale)
-                        kinds["sub_out" if ug @ n >= 0 else "sub_in"] += 1
+    for G, R in _face_ghosts(c, 0, 0):
+        n = _normal(m, 0, 0, R[2], R[1], R[0])
+        gq, rq, oq = q[(slice(None),) + G], q[(slice(None),) + R], Q0[(slice(None),) + G]
+        rr, ur, pr = _prims(rq, g)
+        ro, uo, po = _prims(oq, g)
+        rg, ug, pg = _prims(gq, g)
+        cr, co, cg = np.sqrt(g * pr / rr), np.sqrt(g * po / ro), np.sqrt(g * pg / rg)
+        if ur @ n >= cr:
+            np.testing.assert_array_equal(gq, rq)
+            kinds["out"] += 1
+        elif uo @ n <= -co:
+            np.testing.assert_array_equal(gq, oq)
+            kinds["in"] += 1
+        else:
+            scale = abs(ur @ n) + cr
+            assert abs((ug @ n + 2 * cg / (g - 1)) - (ur @ n + 2 * cr / (g - 1))) <= 1e-13 * scale
+            assert abs((ug @ n - 2 * cg / (g - 1)) - (uo @ n - 2 * co / (g - 1))) <= 1e-13 * scale
+            src_r, src_u = (rr, ur) if ug @ n >= 0 else (ro, uo)
+            src_p = pr if ug @ n >= 0 else po
+            assert abs(pg / rg ** g - src_p / src_r ** g) <= 1e-13 * src_p / src_r ** g
+            ut_g, ut_s = ug - (ug @ n) * n, src_u - (src_u @ n) * n
+            np.testing.assert_allclose(ut_g, ut_s, rtol=0, atol=1e-13 * scale)
+            kinds["sub_out" if ug @ n >= 0 else "sub_in"] += 1
     # the block exercises every branch (jet core enters supersonically at i-lo)
     assert kinds["in"] > 0 and kinds["sub_in"] > 0 and kinds["sub_out"] > 0, kinds
+
+
+def test_face_farfield_rule(orc):
+    """Far field (j-lo, j-hi; Sec. 3): the ghost's normal velocity is the
+    boundary node's (zero-order extrapolation); its tangential velocity is
+    the outside state's whatever the interior does (fixed flow angle); its
+    incoming Riemann invariant u.n - 2c/(g-1) is the outside state's; its
+    entropy p/rho^g is the outside state's on inflow (u.n < 0) and the
+    boundary node's on outflow.  Both directions occur on the block."""
+    c, Q0 = _face_case()
+    g = c["params"]["gamma"]
+    m = orc.metrics(c)
+    q = orc.fill_ghosts_faces(c, m, c["Q"])
+    kinds = {"in": 0, "out": 0}
+    for hi in (0, 1):
+        for G, R in _face_ghosts(c, 1, hi):
+            n = _normal(m, 1, hi, R[2], R[1], R[0])
+            gq, rq, oq = q[(slice(None),) + G], q[(slice(None),) + R], Q0[(slice(None),) + G]
+            rr, ur, pr = _prims(rq, g)
+            ro, uo, po = _prims(oq, g)
+            rg, ug, pg = _prims(gq, g)
+            cr, co, cg = np.sqrt(g * pr / rr), np.sqrt(g * po / ro), np.sqrt(g * pg / rg)
+            scale = np.linalg.norm(ur) + cr
+            assert abs(ug @ n - ur @ n) <= 1e-14 * scale
+            np.testing.assert_allclose(ug - (ug @ n) * n, uo - (uo @ n) * n, rtol=0, atol=1e-14 * scale)
+            assert abs((ug @ n - 2 * cg / (g - 1)) - (uo @ n - 2 * co / (g - 1))) <= 1e-13 * scale
+            src = (ro, po) if ug @ n < 0 else (rr, pr)
+            assert abs(pg / rg ** g - src[1] / src[0] ** g) <= 1e-13 * src[1] / src[0] ** g
+            kinds["in" if ug @ n < 0 else "out"] += 1
+    assert kinds["in"] > 0 and kinds["out"] > 0, kinds
+
+
+def test_face_farfield_ignores_interior_tangential_velocity(orc):
+    """Changing the boundary nodes' tangential velocity (keeping their normal
+    velocity, density and pressure) leaves every far-field ghost unchanged;
+    changing their normal velocity does not (it is extrapolated)."""
+    c, Q0 = _face_case()
+    g = c["params"]["gamma"]
+    m = orc.metrics(c)
+    q = orc.fill_ghosts_faces(c, m, c["Q"])
+    Q2 = c["Q"].copy()
+    nj = c["nj"]
+    for jr, hi in ((0, 0), (nj - 1, 1)):
+        for kk in range(c["nk"]):
+            for ii in range(c["ni"]):
+                idx = (slice(None), kk + 2, jr + 2, ii + 2)
+                rho, u, p = _prims(Q2[idx], g)
+                n = _normal(m, 1, hi, ii + 2, jr + 2, kk + 2)
+                t = np.cross(n, [0.3, 0.1, 1.0])
+                u2 = u + 0.2 * t / np.linalg.norm(t)
+                Q2[idx] = [rho, *(rho * u2), p / (g - 1) + 0.5 * rho * (u2 @ u2)]
+    q2 = orc.fill_ghosts_faces(c, m, Q2)
+    tol = 1e-13 * np.abs(q).reshape(5, -1).max(1)
+    for hi in (0, 1):
+        for G, _ in _face_ghosts(c, 1, hi):
+            assert (np.abs(q2[(slice(None),) + G] - q[(slice(None),) + G]) <= tol).all()
+    # a change of the normal velocity moves the ghosts' normal velocity with it
+    Q3 = c["Q"].copy()
+    idx = (slice(None), 5, 2, 9)  # boundary node j = 0 at i = 7, k = 3
+    rho, u, p = _prims(Q3[idx], g)
+    n = _normal(m, 1, 0, 9, 2, 5)
+    u3 = u + 0.01 * n
+    Q3[idx] = [rho, *(rho * u3), p / (g - 1) + 0.5 * rho * (u3 @ u3)]
+    q3 = orc.fill_ghosts_faces(c, m, Q3)
+    for gj in (0, 1):
+        _, ug, _ = _prims(q3[:, 5, gj, 9], g)
+        _, ug0, _ = _prims(q[:, 5, gj, 9], g)
+        assert abs((ug - ug0) @ n - 0.01) <= 1e-13
 
 
 def test_face_edges_stay_frozen(orc):
@@ -638,7 +712,7 @@ def test_face_uniform_flow_preserved(orc):
     Q[1:4] = rho * u[:, None, None, None]
     Q[4] = p / (g - 1) + 0.5 * rho * (u @ u)
     c["Q"] = Q
-    c["faces"] = dict(types=[1, 2, 1, 1, 0, 0], p_exit=[0.0, p, 0, 0, 0, 0], outside=Q.copy())
+    c["faces"] = dict(types=[1, 2, 3, 3, 0, 0], p_exit=[0.0, p, 0, 0, 0, 0], outside=Q.copy())
     m = orc.metrics(c)
     q = orc.fill_ghosts_faces(c, m, Q)
     np.testing.assert_allclose(q, Q, rtol=1e-14, atol=1e-15)
@@ -699,3 +773,148 @@ def test_superposed_stencil_reach(orc):
         _, dR = orc.residual_tangent(cs, ms, cs["Q"], v)
         rows = np.abs(I.interior(dR)).max(axis=(0, 2, 3))
         assert {k for k in range(nk) if rows[k] > 0} == want, (src, rows)
+
+
+# ---------------------------------------------------------------------------
+# CFL time step (reading R9) against its closed form on grids whose metrics
+# are known exactly: an anisotropic Cartesian box and a sheared affine grid
+# (central differences are exact on linear maps, so the physical gradients
+# of xi, eta, zeta are the rows of the inverse of the map).  A metric taken
+# without its J factor, a dropped factor 2 on the viscous term, or a max in
+# place of the sum over directions changes dt by O(1) here.
+# ---------------------------------------------------------------------------
+def _affine_case(n, A, Q_fn, **prm):
+    ni, nj, nk = n
+    sh = (nk + 4, nj + 4, ni + 4)
+    idx = np.stack(np.broadcast_arrays(I.padded_indices(ni)[None, None, :], I.padded_indices(nj)[None, :, None],
+                                       I.padded_indices(nk)[:, None, None]))
+    xyz = np.ascontiguousarray(np.einsum("ab,b...->a...", np.asarray(A, float), idx))
+    Q = Q_fn(sh, idx)
+    return _case(ni, nj, nk, xyz, Q, bc=(1, 1, 1), **prm)
+
+
+def _sutherland(T, prm):
+    th = T / prm["T_ref"]
+    return prm["mu_ref"] * th ** 1.5 * (1.0 + prm["S_suth"]) / (th + prm["S_suth"])
+
+
+def _cfl_closed_form(A, rho, u, p, prm):
+    g = prm["gamma"]
+    T = p / (rho * prm["R_gas"])
+    c = math.sqrt(g * p / rho)
+    nu = max(4.0 / 3.0, g / prm["Pr"]) * _sutherland(T, prm) / rho
+    G = np.linalg.inv(np.asarray(A, float))  # row d = grad of coordinate d
+    conv = sum(abs(G[d] @ u) + c * np.linalg.norm(G[d]) for d in range(3))
+    visc = 2.0 * nu * sum(G[d] @ G[d] for d in range(3))
+    return prm["cfl"] / (conv + visc)
+
+
+@pytest.mark.parametrize("A", [np.diag([0.7, 1.3, 0.45]),
+                               [[0.8, 0.3, 0.1], [0.2, 1.1, -0.25], [0.05, 0.4, 0.6]]])
+def test_cfl_closed_form_uniform(orc, A):
+    rho, u, p = 1.2, np.array([0.3, -0.5, 0.2]), 0.9 / I.GAMMA
+    case = _affine_case((7, 6, 5), A, lambda sh, idx: I.uniform_state(sh, rho=rho, vel=tuple(u), p=p),
+                        mu_ref=0.2, cfl=0.7)
+    m = orc.metrics(case)
+    prm = case["params"]
+    want = _cfl_closed_form(A, rho, u, p, prm)
+    assert orc.cfl_dt(case, m, case["Q"]) == pytest.approx(want, rel=1e-13)
+    # the viscous term is a sizeable part of the bound here (so it is pinned)
+    inviscid_only = _cfl_closed_form(A, rho, u, p, dict(prm, mu_ref=0.0))
+    assert inviscid_only > 1.3 * want
+
+
+def test_cfl_closed_form_varying(orc):
+    """A state varying node by node on the sheared grid: dt is the smallest
+    of the nodes' closed-form bounds (the node with the largest speed and
+    temperature sets it), interior nodes only."""
+    A = [[0.8, 0.3, 0.1], [0.2, 1.1, -0.25], [0.05, 0.4, 0.6]]
+    rng = np.random.default_rng(21)
+    n = (6, 5, 4)
+    sh = (n[2] + 4, n[1] + 4, n[0] + 4)
+    rho = 1.0 + 0.2 * rng.uniform(-1, 1, sh)
+    vel = 0.6 * rng.uniform(-1, 1, (3,) + sh)
+    p = (1.0 + 0.3 * rng.uniform(-1, 1, sh)) / I.GAMMA
+    # ghost nodes carry a much faster flow that must not count
+    vel[:, :2] = vel[:, -2:] = 5.0
+    case = _affine_case(n, A, lambda s_, idx: I.cons_from_prim(rho, vel[0], vel[1], vel[2], p), mu_ref=0.05, cfl=0.5)
+    m = orc.metrics(case)
+    best = min(_cfl_closed_form(A, rho[k, j, i], vel[:, k, j, i], p[k, j, i], case["params"])
+               for k in range(2, n[2] + 2) for j in range(2, n[1] + 2) for i in range(2, n[0] + 2))
+    assert orc.cfl_dt(case, m, case["Q"]) == pytest.approx(best, rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Probe objective of the forcing workload (reading R12/A18):
+#   J = sum_{n=1..N} dt sum_{j,k} (p(Q^n)_{i_p,j,k} - p_inf)^2.
+# (a) a uniform state at rest is steady, so J = N dt nj nk (p - p_inf)^2;
+# (b) a state at rest with p = p_inf and a constant energy source f_e on the
+#     probe plane heats that plane linearly: p^n - p_inf = (gamma-1) n dt f_e
+#     up to O(dt^2), so J = dt^3 (gamma-1)^2 f_e^2 nj nk N(N+1)(2N+1)/6 and
+#     dJ/df_e = 2 J / f_e.  A wrong plane gives J ~ 0; summing the steps
+#     0..N-1 gives (N-1)N(2N-1)/6 instead.
+# ---------------------------------------------------------------------------
+def test_probe_objective_uniform(orc):
+    n = (9, 6, 5)
+    xyz = I.wavy_grid(*n, amp=0.2)
+    p, pinf = 1.3 / I.GAMMA, 1.0 / I.GAMMA
+    Q = I.uniform_state((n[2] + 4, n[1] + 4, n[0] + 4), rho=1.1, vel=(0.0, 0.0, 0.0), p=p)
+    case = _case(*n, xyz, Q, mu_ref=1e-3)
+    m = orc.metrics(case)
+    f = np.zeros((5, n[2], n[1]))
+    for N, dt in ((1, 0.01), (4, 0.003)):
+        J = orc.objective(case, m, Q, f, 3, 5, pinf, N, dt)
+        assert J == pytest.approx(N * dt * n[1] * n[2] * (p - pinf) ** 2, rel=1e-12)
+
+
+@pytest.mark.parametrize("i_p", [2, 6])
+def test_probe_objective_heated_plane(orc, i_p):
+    n = (9, 6, 5)
+    xyz = I.wavy_grid(*n, amp=0.2)
+    pinf = 1.0 / I.GAMMA
+    g = I.GAMMA
+    Q = I.uniform_state((n[2] + 4, n[1] + 4, n[0] + 4), rho=1.0, vel=(0.0, 0.0, 0.0), p=pinf)
+    case = _case(*n, xyz, Q, mu_ref=1e-3)
+    m = orc.metrics(case)
+    fe = 0.7
+    f = np.zeros((5, n[2], n[1]))
+    f[4] = fe
+    N, dt = 5, 1e-7
+    S = N * (N + 1) * (2 * N + 1) / 6.0
+    want = dt ** 3 * (g - 1) ** 2 * fe ** 2 * n[1] * n[2] * S
+    J = orc.objective(case, m, Q, f, i_p, i_p, pinf, N, dt)
+    assert J == pytest.approx(want, rel=1e-5)
+    # the neighbouring plane sees only what the fluxes carry over, O(dt) smaller
+    assert orc.objective(case, m, Q, f, i_p, i_p + 1, pinf, N, dt) < 1e-3 * want
+    df = np.zeros_like(f)
+    df[4] = 1.0
+    J2, dJ = orc.objective_rollout(case, m, Q, f, df, i_p, i_p, pinf, N, dt)
+    assert J2 == pytest.approx(want, rel=1e-5)
+    assert dJ == pytest.approx(2.0 * want / fe, rel=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# Superposed seam (R15) along physical directions: a perturbation that moves
+# plane 0 and its duplicate plane n together keeps the block a periodic one,
+# so the superposed block's tangent must equal the periodic block's whatever
+# rule the ghosts use to break the tie between the two copies.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("axis", [0, 2])
+def test_superposed_tangent_along_physical_directions(orc, axis):
+    c = _periodic_base()
+    cs = I.superposed_case(c, axis)
+    n = c[("ni", "nj", "nk")[axis]]
+    m, ms = orc.metrics(c), orc.metrics(cs)
+    v = np.random.default_rng(5).standard_normal(c["Q"].shape) * np.abs(c["Q"]).mean(axis=(1, 2, 3))[:, None, None, None]
+    vs = I.superposed_case(dict(c, Q=v), axis)["Q"]
+    _, dR = orc.residual_tangent(c, m, c["Q"], v)
+    _, dRs = orc.residual_tangent(cs, ms, cs["Q"], vs)
+    scale = np.abs(I.interior(dR)).max()
+    assert np.abs(_along(I.interior(dRs), axis, slice(0, n)) - I.interior(dR)).max() <= 1e-13 * scale
+    assert np.abs(_along(I.interior(dRs), axis, slice(n, n + 1)) - _along(I.interior(dR), axis, slice(0, 1))).max() \
+        <= 1e-13 * scale
+    dt = orc.cfl_dt(c, m, c["Q"])
+    _, dQ = orc.rk_step_tangent(c, m, c["Q"], v, dt)
+    _, dQs = orc.rk_step_tangent(cs, ms, cs["Q"], vs, dt)
+    sc = np.abs(I.interior(dQ)).max()
+    assert np.abs(_along(I.interior(dQs), axis, slice(0, n)) - I.interior(dQ)).max() <= 1e-13 * sc
