@@ -1,11 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of the LES Runge-Kutta hot path on one MI355X.
 
-Workload: the 256 x 128 x 128 curvilinear jet shard (one GPU's share of the
-paper's Mach 1.4, Re_D = 1.57e6 jet, Sec. 5.1), FP64, CFL 0.5.  One "step" is
-one five-stage Runge-Kutta step: ghost fill, the device-side CFL time step,
-five fused residual + stage-update launches, and the residual-norm
-reduction (no host synchronisation inside the timed region).
+Workload (headline): the 800 x 500 x 500 curvilinear jet shard (2.0e8
+points, about 1e9 unknowns; the largest of the benchmark shapes, one GPU's
+share of the paper's Mach 1.4, Re_D = 1.57e6 jet, Sec. 5.1), FP64, CFL 0.5,
+generated on the device.  One "step" is one five-stage Runge-Kutta step:
+ghost fill, five fused residual + stage-update launches (the last one also
+reduces the next step's CFL time step) and the norm / time-step
+reductions; the timed region is one les_advance call of K steps (no host
+synchronisation inside it).
 
 Prints one JSON line:
   value      Mpoint-RK-stages/s = N * 5 * steps / wall time / 1e6 (inputs
@@ -13,14 +16,17 @@ Prints one JSON line:
   roofline   the stage kernel's algorithmic HBM bytes per launch
              (192 B per point: mean of 160 B for stage 1 and 200 B for
              stages 2-5) over its mean launch time, measured with HIP
-             events around every stage launch, against 8 TB/s;
+             events recorded on the library's stream around every stage
+             launch, against 8 TB/s; traffic = HBM bytes per launch from the
+             committed rocprofv3 counter runs of the same kernel source;
   cpu_baseline  the plain FP64 CPU oracle on a bounded sample of the same
-             workload (rank 0, host cores of this machine).
-Extra keys report the mixed-precision path, the adjoint/forward cost, the
-shard with boundary faces (entrance, exit, far field), the running flow
-statistics, the restart file (write and read rates) and the bandwidth a
-plain device copy reaches (the achievable stream rate beside the 8 TB/s
-peak) when those paths are available.
+             workload family (all host cores, and one thread).
+Extra keys: the FP32-mixed path on the same shard (speedup and its per-field
+error against the FP64 GPU path after the same steps), the 256 x 128 x 128
+jet shard in FP64 and mixed, the adjoint/forward cost on the forcing
+workload, the shard with boundary faces (entrance, exit, far field), the
+running flow statistics, the restart file and a plain device copy (the
+achievable stream rate beside the 8 TB/s peak).
 """
 import argparse
 import hashlib
@@ -36,7 +42,11 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpoint-RK-stages/s & % HBM peak; FP32-mixed vs FP64; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
 BYTES_FP64 = 192.0  # algorithmic bytes per point-stage, FP64 path
-BYTES_MIXED = 168.0
+# mixed path: stage 1 reads FP64 Q^n (stencil and Q^(0), one array) 40 +
+# metrics 80 + writes the FP32 stage state 20 = 140; stages 2-4: FP32 state
+# 20 + Q^(0) 40 + metrics 80 + FP32 write 20 = 160; stage 5: 20 + 40 + 80 +
+# FP64 write 40 = 180; mean 160
+BYTES_MIXED = 160.0
 
 
 def _code_only(text):
@@ -73,38 +83,57 @@ def load_traffic(key):
     return None
 
 
-def time_gpu(case, prec, steps, warmup, setup=None):
+def time_gpu(case, prec, steps, warmup, setup=None, keep_state=False):
+    """Warm-up, then `steps` CFL steps in one les_advance call between two
+    device synchronisations; stage-kernel launches timed with HIP events on
+    the library's stream."""
     import torch
     from paper_2003_08746_amd import lesmi
     s = lesmi.Solver(case, prec=prec)
     Q = s.upload(case["Q"])
     if setup is not None:
         setup(s, Q)
-    for _ in range(warmup):
-        s.rk_step(Q)
+    if warmup:
+        s.advance(Q, warmup)
     dt0 = s.cfl_dt(Q)  # synchronises; also checks the warmed-up state is finite
-    timing = True
-    if timing:
-        lesmi.les_debug_stage_timing(s.ctx, True)
+    lesmi.les_debug_stage_timing(s.ctx, True)
     stream = s.stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(steps):
-        s.rk_step(Q)
+    s.advance(Q, steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    stage_ms, launches = (lesmi.les_debug_stage_time(s.ctx) if timing else (None, 0))
-    if timing:
-        lesmi.les_debug_stage_timing(s.ctx, False)
+    stage_ms, launches = lesmi.les_debug_stage_time(s.ctx)
+    lesmi.les_debug_stage_timing(s.ctx, False)
+    out = dict(wall_s=wall, gpu_ms=gpu_ms, stage_ms=stage_ms, launches=launches, dt0=dt0)
+    if keep_state:
+        out["state"] = s.view(Q).clone()
     _, norms = s.rk_step(Q, 0.0, want_norms=True)  # raises on a non-finite state
-    out = dict(wall_s=wall, gpu_ms=gpu_ms, stage_ms=stage_ms, launches=launches, dt0=dt0, norms=list(norms))
+    out["norms"] = list(norms)
     s.close()
+    del Q
+    torch.cuda.empty_cache()
     return out
+
+
+def field_errors(a, b):
+    """Per-field Linf and L2 of a - b over the interior (dense padded torch
+    arrays), relative to the field's max |b| (the three momenta share the
+    largest momentum's scale)."""
+    import torch
+    d = (a - b)[:, 2:-2, 2:-2, 2:-2].reshape(5, -1)
+    sc = b[:, 2:-2, 2:-2, 2:-2].abs().reshape(5, -1).amax(1)
+    sc[1:4] = sc[1:4].max()
+    linf = (d.abs().amax(1) / sc).cpu().tolist()
+    l2 = (torch.sqrt((d * d).mean(1)) / sc).cpu().tolist()
+    names = ("rho", "rho_u", "rho_v", "rho_w", "e")
+    return {"linf": {n: float(f"{x:.3e}") for n, x in zip(names, linf)},
+            "l2": {n: float(f"{x:.3e}") for n, x in zip(names, l2)}}
 
 
 def time_adjoint(ni=128, nj=64, nk=64, nsteps=50, i_f=8, i_p=16):
@@ -151,10 +180,10 @@ def time_adjoint(ni=128, nj=64, nk=64, nsteps=50, i_f=8, i_p=16):
 
 
 def time_faces(case, steps, warmup):
-    """The benchmark shard with boundary faces instead of periodic i: a
+    """The jet shard with boundary faces instead of periodic i: a
     characteristic entrance at i-lo (outside state: the initial profile), a
-    subsonic exit at i-hi (ambient pressure) and characteristic far-field
-    faces on both j sides; FP64, same steps as the main leg."""
+    subsonic exit at i-hi (ambient pressure) and far-field faces on both j
+    sides; FP64, same steps as the shard's own leg."""
     from paper_2003_08746_amd import inputs, lesmi
     c = dict(case)
     c["bc"] = (1, 1, 0)
@@ -162,14 +191,14 @@ def time_faces(case, steps, warmup):
     def setup(s, Q):
         s.set_face(0, lesmi.LES_FACE_CHARACTERISTIC, Q)
         s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=1.0 / inputs.GAMMA)
-        s.set_face(2, lesmi.LES_FACE_CHARACTERISTIC)
-        s.set_face(3, lesmi.LES_FACE_CHARACTERISTIC)
+        s.set_face(2, lesmi.LES_FACE_FARFIELD)
+        s.set_face(3, lesmi.LES_FACE_FARFIELD)
 
     r = time_gpu(c, lesmi.LES_FP64, steps, warmup, setup)
     npts = case["ni"] * case["nj"] * case["nk"]
     return {"value": round(npts * 5 * steps / r["wall_s"] / 1e6, 2), "unit": "Mpoint-RK-stages/s",
             "ms_per_step": round(r["wall_s"] * 1e3 / steps, 4),
-            "faces": "i-lo characteristic, i-hi exit, j-lo/j-hi characteristic, k periodic"}
+            "faces": "i-lo characteristic entrance, i-hi exit, j-lo/j-hi far field, k periodic"}
 
 
 def time_stats(case, calls=50):
@@ -254,69 +283,90 @@ def time_restart(case):
             "write_GBps": round(nbytes / tw / 1e9, 2), "read_GBps": round(nbytes / tr / 1e9, 2), "bitwise": same}
 
 
-def time_large(steps, ni=800, nj=500, nk=500):
-    """The 800 x 500 x 500 shard (2.0e8 points), generated on the device."""
-    import torch
-    from paper_2003_08746_amd import inputs, lesmi
-    case = inputs.jet_case_device(ni, nj, nk, seed=0)
-    npts = ni * nj * nk
-    out = {"workload": f"jet shard {ni}x{nj}x{nk} ({npts:.3g} points)"}
+def time_shard(case, steps, warmup, label):
+    """FP64 and mixed legs of one jet shard: throughput, stage-kernel launch
+    time and algorithmic bandwidth, mixed speedup and the mixed path's
+    per-field error against the FP64 path after the same steps."""
+    from paper_2003_08746_amd import lesmi
+    npts = case["ni"] * case["nj"] * case["nk"]
+    out = {"workload": label}
+    states = {}
     for name, prec, byts in (("fp64", lesmi.LES_FP64, BYTES_FP64), ("mixed", lesmi.LES_MIXED, BYTES_MIXED)):
-        r = time_gpu(case, prec, steps, 1)
+        print(f"[bench] {label}: {name}, warmup {warmup}, steps {steps}", file=sys.stderr, flush=True)
+        r = time_gpu(case, prec, steps, warmup, keep_state=True)
+        states[name] = r.pop("state")
         v = npts * 5 * steps / r["wall_s"] / 1e6
-        o = {"value": round(v, 2), "unit": "Mpoint-RK-stages/s", "ms_per_step": round(r["wall_s"] * 1e3 / steps, 3),
-             "algorithmic_GBps": round(byts * npts * 5 * steps / r["wall_s"] / 1e9, 1)}
-        if r["stage_ms"]:
-            o["avg_stage_launch_us"] = round(r["stage_ms"] / r["launches"] * 1e3, 1)
-        out[name] = o
-        torch.cuda.empty_cache()
-    del case
-    torch.cuda.empty_cache()
+        launch_s = r["stage_ms"] / r["launches"] / 1e3
+        out[name] = {"value": round(v, 2), "unit": "Mpoint-RK-stages/s",
+                     "ms_per_step": round(r["wall_s"] * 1e3 / steps, 4),
+                     "gpu_event_ms_per_step": round(r["gpu_ms"] / steps, 4),
+                     "avg_stage_launch_us": round(launch_s * 1e6, 2),
+                     "stage_algorithmic_GBps": round(byts * npts / launch_s / 1e9, 1),
+                     "stage_frac_of_hbm_peak": round(byts * npts / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "_wall_s": r["wall_s"], "_launch_s": launch_s}
+    out["mixed"]["speedup_vs_fp64"] = round(out["mixed"]["value"] / out["fp64"]["value"], 3)
+    out["mixed"]["error_vs_fp64_after_steps"] = field_errors(states["mixed"], states["fp64"])
+    del states
     return out
 
 
-def cpu_baseline(case, target_s=10.0, max_steps=3):
+def cpu_baseline(label, n_omp=(160, 100, 100), n_one=(64, 40, 40), target_s=10.0, max_steps=5):
+    """The plain FP64 oracle on bounded samples of the workload family: all
+    host cores (OpenMP over k) on an n_omp block and one thread on an n_one
+    block, whole RK steps until target_s."""
     import oracle
-    m = oracle.metrics(case)
-    Q = case["Q"]
-    n = case["ni"] * case["nj"] * case["nk"]
-    t0 = time.perf_counter()
-    done = 0
-    while done < max_steps:
-        Q, _, _, _ = oracle.rk_step(case, m, Q)
-        done += 1
-        if time.perf_counter() - t0 >= target_s:
-            break
-    el = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    return dict(value=n * 5 * done / el / 1e6, unit="Mpoint-RK-stages/s", cores=cores, kind="oracle",
-                sample=f"{done} RK step(s) ({done * 5} stages) of the {case['ni']}x{case['nj']}x{case['nk']} "
-                       f"jet shard, FP64, {el:.1f} s")
+    from paper_2003_08746_amd import inputs
+    avail = len(os.sched_getaffinity(0))
+    legs = {}
+    for name, n, threads in (("omp", n_omp, avail), ("one", n_one, 1)):
+        case = inputs.jet_case(*n, seed=0)
+        m = oracle.metrics(case)
+        used = oracle.threads(threads)
+        Q = case["Q"]
+        npts = n[0] * n[1] * n[2]
+        t0 = time.perf_counter()
+        done = 0
+        while done < max_steps:
+            Q, _, _, _ = oracle.rk_step(case, m, Q)
+            done += 1
+            if time.perf_counter() - t0 >= target_s:
+                break
+        el = time.perf_counter() - t0
+        legs[name] = dict(value=npts * 5 * done / el / 1e6, cores=used,
+                          sample=f"{done} RK step(s) of a {n[0]}x{n[1]}x{n[2]} block of the jet grid family, "
+                                 f"FP64, {el:.1f} s, {used} thread(s)")
+    oracle.threads(avail)
+    o = legs["omp"]
+    return dict(value=round(o["value"], 4), unit="Mpoint-RK-stages/s", cores=o["cores"], kind="oracle",
+                sample=o["sample"] + f" (same per-point work as the {label})",
+                single_thread={"value": round(legs["one"]["value"], 4), "unit": "Mpoint-RK-stages/s",
+                               "cores": 1, "sample": legs["one"]["sample"]})
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--ni", type=int, default=256)
-    ap.add_argument("--nj", type=int, default=128)
-    ap.add_argument("--nk", type=int, default=128)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ni", type=int, default=800)
+    ap.add_argument("--nj", type=int, default=500)
+    ap.add_argument("--nk", type=int, default=500)
+    ap.add_argument("--small-steps", type=int, default=100, help="steps of the 256 x 128 x 128 shard legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision, adjoint, boundary-face, statistics, restart and copy legs")
-    ap.add_argument("--large", action="store_true",
-                    help="also time the 800 x 500 x 500 shard (FP64 and mixed, 20 steps each)")
-    ap.add_argument("--large-steps", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip every leg but the headline (mixed, small shard, adjoint, faces, statistics, "
+                         "restart, copy)")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.copy_kernel:
         import torch
+        from paper_2003_08746_amd import lesmi
         n = args.copy_kernel * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
-            dst.copy_(src)
+            lesmi.les_debug_stream_copy(src.data_ptr(), dst.data_ptr(), n * 8, torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
         print(json.dumps({"copy_kernel_bytes_read": n * 8, "copy_kernel_bytes_written": n * 8, "launches": 5}))
         return
@@ -330,17 +380,27 @@ def main():
     from paper_2003_08746_amd import inputs, lesmi
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    case = inputs.jet_case(args.ni, args.nj, args.nk, seed=0)
-    npts = args.ni * args.nj * args.nk
-    print(f"[bench] workload jet {args.ni}x{args.nj}x{args.nk} FP64 warmup {args.warmup} steps {args.steps}",
-          file=sys.stderr, flush=True)
-    r = time_gpu(case, lesmi.LES_FP64, args.steps, args.warmup)
-    value = npts * 5 * args.steps / r["wall_s"] / 1e6
-    ms_per_step = r["wall_s"] * 1e3 / args.steps
-    avg_launch_s = r["stage_ms"] / r["launches"] / 1e3
+    ni, nj, nk = args.ni, args.nj, args.nk
+    npts = ni * nj * nk
+    label = f"jet shard {ni}x{nj}x{nk}"
+    print(f"[bench] generating {label} on the device", file=sys.stderr, flush=True)
+    case = inputs.jet_case_device(ni, nj, nk, seed=0)
+    do_extra = not args.no_extra
+    if do_extra:
+        big = time_shard(case, args.steps, args.warmup, label)
+        main_r = big["fp64"]
+        wall_s, launch_s, gpu_ms = main_r.pop("_wall_s"), main_r.pop("_launch_s"), main_r["gpu_event_ms_per_step"]
+        big["mixed"].pop("_wall_s"), big["mixed"].pop("_launch_s")
+    else:
+        print(f"[bench] {label}: fp64, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+        r = time_gpu(case, lesmi.LES_FP64, args.steps, args.warmup)
+        wall_s, launch_s, gpu_ms = r["wall_s"], r["stage_ms"] / r["launches"] / 1e3, r["gpu_ms"] / args.steps
+    del case
+    torch.cuda.empty_cache()
+    value = npts * 5 * args.steps / wall_s / 1e6
     bytes_per_launch = BYTES_FP64 * npts
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = load_traffic("jet_fp64")
+    achieved = bytes_per_launch / launch_s / 1e9
+    traffic = load_traffic(f"jet{ni}x{nj}x{nk}_fp64")
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -348,61 +408,55 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(wall_s * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"jet shard {args.ni}x{args.nj}x{args.nk}, curvilinear (tanh-clustered, wavy), "
-                               "Mach 1.4, Re_D 1.57e6, Smagorinsky SGS on, CFL 0.5, FP64",
+        "config": {"workload": f"{label}, curvilinear (tanh-clustered, wavy), Mach 1.4, Re_D 1.57e6, "
+                               "Smagorinsky SGS on, CFL 0.5, FP64",
                    "points": npts, "stages_per_step": 5},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic / avg_launch_s / 1e9, 1),
+                     "traffic": None if traffic is None else round(traffic / launch_s / 1e9, 1),
                      "kernel": "stage (fused residual + RK update)",
-                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "avg_launch_us": round(launch_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": int(bytes_per_launch)},
-        "gpu_event_ms_per_step": round(r["gpu_ms"] / args.steps, 4),
+        "gpu_event_ms_per_step": round(gpu_ms, 4),
     }
-    if not args.no_extra:
-        extra = {}
+    if do_extra:
+        extra = {"mixed": big["mixed"]}
+        small = inputs.jet_case(256, 128, 128, seed=0)
         try:
-            rm = time_gpu(case, lesmi.LES_MIXED, args.steps, args.warmup)
-            vm = npts * 5 * args.steps / rm["wall_s"] / 1e6
-            extra["mixed"] = {"value": round(vm, 2), "unit": "Mpoint-RK-stages/s",
-                              "speedup_vs_fp64": round(vm / value, 3),
-                              "algorithmic_GBps": round(BYTES_MIXED * npts * 5 * args.steps / rm["wall_s"] / 1e9, 1)}
-        except Exception as e:  # the path reports its own error; the FP64 line stands
-            extra["mixed"] = {"error": str(e)[:200]}
-        try:
-            extra["adjoint"] = time_adjoint()
-        except Exception as e:
-            extra["adjoint"] = {"error": str(e)[:200]}
-        try:
-            extra["faces"] = time_faces(case, args.steps, args.warmup)
-            extra["faces"]["vs_main"] = round(extra["faces"]["value"] / value, 3)
-        except Exception as e:
-            extra["faces"] = {"error": str(e)[:200]}
-        try:
-            extra["stats"] = time_stats(case)
-        except Exception as e:
-            extra["stats"] = {"error": str(e)[:200]}
-        try:
-            extra["restart"] = time_restart(case)
-        except Exception as e:
-            extra["restart"] = {"error": str(e)[:200]}
-        try:
-            extra["copy"] = time_copy()
+            extra["jet256x128x128"] = time_shard(small, args.small_steps, 5, "jet shard 256x128x128")
+            for k in ("fp64", "mixed"):
+                extra["jet256x128x128"][k].pop("_wall_s"), extra["jet256x128x128"][k].pop("_launch_s")
+            t_small = load_traffic("jet256x128x128_fp64")
+            if t_small is not None:
+                ls = extra["jet256x128x128"]["fp64"]["avg_stage_launch_us"] / 1e6
+                extra["jet256x128x128"]["fp64"]["traffic_GBps"] = round(t_small / ls / 1e9, 1)
+        except Exception as e:  # the leg reports its own error; the headline stands
+            extra["jet256x128x128"] = {"error": str(e)[:200]}
+        for key, fn in (("adjoint", time_adjoint),
+                        ("faces", lambda: time_faces(small, args.small_steps, 5)),
+                        ("stats", lambda: time_stats(small)),
+                        ("restart", lambda: time_restart(small)),
+                        ("copy", time_copy)):
+            print(f"[bench] extra: {key}", file=sys.stderr, flush=True)
+            try:
+                extra[key] = fn()
+            except Exception as e:
+                extra[key] = {"error": str(e)[:200]}
+        if "value" in extra.get("faces", {}) and "fp64" in extra.get("jet256x128x128", {}):
+            extra["faces"]["vs_periodic_shard"] = round(extra["faces"]["value"] /
+                                                        extra["jet256x128x128"]["fp64"]["value"], 3)
+        if "GBps" in extra.get("copy", {}):
             extra["copy"]["stage_frac_of_copy"] = round(achieved / extra["copy"]["GBps"], 4)
-        except Exception as e:
-            extra["copy"] = {"error": str(e)[:200]}
         out["extra"] = extra
-    if args.large:
-        out.setdefault("extra", {})["large"] = time_large(args.large_steps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(case)
+        out["cpu_baseline"] = cpu_baseline(label)
     print(json.dumps(out), flush=True)
 
 

@@ -57,7 +57,7 @@ typedef enum { LES_FP64 = 0, LES_MIXED = 1 } les_precision;
 typedef enum { LES_BC_PERIODIC = 0, LES_BC_DIRICHLET = 1, LES_BC_PERIODIC_SUPERPOSED = 2 } les_bc;
 
 /* Treatment of one boundary face of a Dirichlet direction (les_set_face). */
-typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT = 2 } les_face_type;
+typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT = 2, LES_FACE_FARFIELD = 3 } les_face_type;
 
 /* One structured block.  ni, nj, nk >= 5 interior points.
  * bc[d] for d = i, j, k:
@@ -173,6 +173,24 @@ int les_set_forcing(les_ctx *ctx, const double *f, int i_f);
  *    receives the stage inputs Q^(0..4) (ghosts filled) for les_adjoint_step. */
 int les_rk_step(les_ctx *ctx, double *Q, double dt, double *dt_out, double *norms, double *stage_ckpt);
 
+/* nsteps steps of the five-stage scheme, each at the CFL time step of its
+ * own Q^n (Sec. 4, Alg. 2: the time loop; the same result as nsteps calls of
+ * les_rk_step with dt <= 0).  The dt rule is pointwise in the state, so the
+ * last stage of each step reduces the next step's dt while Q^{n+1} is in
+ * registers (the first step's dt takes a pass of its own): no separate pass
+ * over Q and the metrics per step.
+ * Q: device, library layout, FP64, 16-byte aligned (LES_ERR_ARG otherwise),
+ *    in/out as for les_rk_step; the caller must not touch it until the call's
+ *    work on the stream is done.
+ * nsteps >= 1 (LES_ERR_ARG otherwise).
+ * dt_out: host double[nsteps] or NULL: the time step of every step (then
+ *    nsteps <= LES_ADVANCE_DT_MAX, else LES_ERR_ARG).
+ * norms: host double[10] or NULL: norms of R(Q^n) of the last step.
+ * A non-finite dt or norm found on the way is reported as LES_ERR_NONFINITE
+ * when dt_out or norms is given (the call then synchronises). */
+#define LES_ADVANCE_DT_MAX 4096
+int les_advance(les_ctx *ctx, double *Q, int nsteps, double *dt_out, double *norms);
+
 /* Reverse (adjoint) of one les_rk_step at fixed dt, from its stage inputs:
  *   qbar <- Qbar;  acc = 0;  for l = 5..1:  acc += qbar;
  *      fbar += alpha_l dt qbar[plane i_f];
@@ -218,19 +236,27 @@ int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, do
  * ghost layers take the state built from the boundary node r next to the
  * face (zero-order extrapolation):
  *   LES_FACE_FROZEN          -- the ghosts keep the caller's values (default);
- *   LES_FACE_CHARACTERISTIC  -- entrance and far field: locally
- *      one-dimensional characteristics along the outward unit normal of the
- *      face at r.  Supersonic outflow keeps r's state, supersonic inflow
- *      takes the outside state; otherwise the outgoing Riemann invariant
- *      u.n + 2c/(gamma-1) comes from r, the incoming u.n - 2c/(gamma-1) from
- *      outside, and entropy p/rho^gamma and tangential velocity from the
- *      upwind side (r when u.n >= 0);
+ *   LES_FACE_CHARACTERISTIC  -- entrance (flat-hat profile through 1-D
+ *      characteristic relations): locally one-dimensional characteristics
+ *      along the outward unit normal n of the face at r.  Supersonic outflow
+ *      keeps r's state, supersonic inflow takes the outside state; otherwise
+ *      the outgoing Riemann invariant u.n + 2c/(gamma-1) comes from r, the
+ *      incoming u.n - 2c/(gamma-1) from outside, and entropy p/rho^gamma and
+ *      tangential velocity from the upwind side (r when u.n >= 0);
  *   LES_FACE_EXIT            -- subsonic exit: pressure p_exit imposed,
  *      velocity and internal energy per unit mass of r kept; density and
- *      total energy follow (Eq. 2).
+ *      total energy follow (Eq. 2);
+ *   LES_FACE_FARFIELD        -- far field (Riemann invariants, normal
+ *      velocity extrapolated at zero order, fixed flow angle, the remaining
+ *      properties from the jet Mach number): u.n = r's u.n; tangential
+ *      velocity = the outside state's; c from the outside state's incoming
+ *      invariant, c = (gamma-1)(u.n - (u_o.n - 2c_o/(gamma-1)))/2; entropy
+ *      from outside when u.n < 0, from r otherwise.  A state with
+ *      c <= 0 (an inflow faster than about 5 c_o) gives NaN, reported by the
+ *      next synchronising call as LES_ERR_NONFINITE.
  * Q_outside: device, library layout, FP64, or NULL; when given, its ghost
- *    values become the outside state of every characteristic face (copied
- *    now; required before the first characteristic face).
+ *    values become the outside state of every characteristic and far-field
+ *    face (copied now; required before the first such face).
  * p_exit: imposed pressure (> 0) of an exit face; ignored otherwise.
  * LES_ERR_ARG for a bad face, type or pressure, or a periodic direction.
  * The adjoint entry points differentiate the face rules (the outside state

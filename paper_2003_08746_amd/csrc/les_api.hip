@@ -28,7 +28,9 @@ struct les_ctx {
   int i_f = -1;
   double* part = nullptr;            // per-block reduction partials
   long long part_n = 0;              // capacity in blocks (10 doubles each)
-  double* scal = nullptr;            // [0] dt, [1..10] norms, [11..15] spare
+  double* cpart = nullptr;           // per-block CFL bounds from the last stage (stage_blocks doubles)
+  double* dthist = nullptr;          // time steps of one les_advance call (LES_ADVANCE_DT_MAX doubles)
+  double* scal = nullptr;            // [0] dt, [1..10] norms, [12] dt of the next step (les_advance)
   int* flag = nullptr;               // bit 0: bad dt, bit 1: non-finite norm
   double* adj = nullptr;             // adjoint work arrays
   long long adj_n = 0;
@@ -90,6 +92,8 @@ static void free_all(les_ctx* c) {
   (void)hipFree(c->Sf[1]);
   (void)hipFree(c->f);
   (void)hipFree(c->part);
+  (void)hipFree(c->cpart);
+  (void)hipFree(c->dthist);
   (void)hipFree(c->outside);
   (void)hipFree(c->scal);
   (void)hipFree(c->flag);
@@ -244,6 +248,8 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
             hipMalloc(&c->S[0], 5 * fe * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->S[1], 5 * fe * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->part, (size_t)c->part_n * 10 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->cpart, (size_t)sb * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->dthist, (size_t)LES_ADVANCE_DT_MAX * sizeof(double)) == hipSuccess &&
             hipMalloc(&c->scal, 16 * sizeof(double)) == hipSuccess && hipMalloc(&c->flag, sizeof(int)) == hipSuccess;
   if (ok && c->prec == LES_MIXED)
     ok = hipMalloc(&c->Sf[0], 5 * fe * sizeof(float)) == hipSuccess &&
@@ -333,7 +339,7 @@ int les_residual(les_ctx* ctx, double* Q, double* R, double* norms) {
     const les::Layout& L = ctx->L;
     HIPCHK(ctx, les::launch_zero(ctx->s, R, 5 * L.fe));
     const les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
-    HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, Q, R, R, nullptr, 1.0, -1.0, part));
+    HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, Q, R, R, nullptr, 1.0, -1.0, part, nullptr));
     nb = les::stage_blocks(L, ctx->kchunk);
   } else {
     HIPCHK(ctx, les::launch_residual_ref(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->f, ctx->i_f, R, part));
@@ -366,24 +372,14 @@ int les_set_forcing(les_ctx* ctx, const double* f, int i_f) {
   return LES_OK;
 }
 
-int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norms, double* stage_ckpt) {
-  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_rk_step: null context");
-  if (!Q) return fail(ctx, LES_ERR_ARG, "les_rk_step: Q is NULL");
-  if (((uintptr_t)Q) & 15) return fail(ctx, LES_ERR_ARG, "les_rk_step: Q must be 16-byte aligned");
-  if (dt != dt) return fail(ctx, LES_ERR_ARG, "les_rk_step: dt is NaN");
-  if (stage_ckpt && ctx->prec != LES_FP64)
-    return fail(ctx, LES_ERR_STATE, "les_rk_step: stage checkpoints need an FP64 context");
+// One Runge-Kutta step on the context's stream: ghost fill of Q^n, five
+// stages (time step read from dtp on the device when not null, else dt),
+// norm reduction of R(Q^n).  cpart (or null): the last stage also reduces
+// the per-block CFL bounds of Q^{n+1} into it (fused kernel only).
+static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, double* stage_ckpt, double* cpart) {
   les::Layout& L = ctx->L;
   const size_t fe = (size_t)L.fe;
   const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
-  const double* dtp = nullptr;
-  if (!(dt > 0.0)) {
-    HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag));
-    dtp = ctx->scal;
-  } else {
-    dtp = nullptr;
-  }
   const double cnt = (double)L.ni * L.nj * L.nk;
   if (ctx->prec == LES_MIXED) {
     les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
@@ -394,7 +390,7 @@ int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norm
       if (trc != LES_OK) return trc;
       HIPCHK(ctx, les::launch_stage_mixed(ctx->s, a, l == 0 ? Q : nullptr, in32, Q, l == 4 ? Q : nullptr,
                                           l == 4 ? nullptr : ctx->Sf[l & 1], dtp, dt, les::rk_alpha(l),
-                                          l == 0 ? ctx->part : nullptr));
+                                          l == 0 ? ctx->part : nullptr, l == 4 ? cpart : nullptr));
       trc = timing_end(ctx);
       if (trc != LES_OK) return trc;
     }
@@ -415,7 +411,8 @@ int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norm
                                           ctx->i_f, part));
       } else {
         les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
-        HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, in, Q, out, dtp, dt, les::rk_alpha(l), part));
+        HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, in, Q, out, dtp, dt, les::rk_alpha(l), part,
+                                           l == 4 ? cpart : nullptr));
       }
       trc = timing_end(ctx);
       if (trc != LES_OK) return trc;
@@ -424,10 +421,63 @@ int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norm
     long long nb = ctx->use_ref ? les::ref_blocks(L) : les::stage_blocks(L, ctx->kchunk);
     HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
   }
+  return LES_OK;
+}
+
+int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norms, double* stage_ckpt) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_rk_step: null context");
+  if (!Q) return fail(ctx, LES_ERR_ARG, "les_rk_step: Q is NULL");
+  if (((uintptr_t)Q) & 15) return fail(ctx, LES_ERR_ARG, "les_rk_step: Q must be 16-byte aligned");
+  if (dt != dt) return fail(ctx, LES_ERR_ARG, "les_rk_step: dt is NaN");
+  if (stage_ckpt && ctx->prec != LES_FP64)
+    return fail(ctx, LES_ERR_STATE, "les_rk_step: stage checkpoints need an FP64 context");
+  les::Layout& L = ctx->L;
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+  const double* dtp = nullptr;
+  if (!(dt > 0.0)) {
+    HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag));
+    dtp = ctx->scal;
+  }
+  int rc = step_core(ctx, Q, dtp, dt, stage_ckpt, nullptr);
+  if (rc != LES_OK) return rc;
   if (!dt_out && !norms) return LES_OK;
-  int rc = sync_outputs(ctx, dt_out, norms);
+  rc = sync_outputs(ctx, dt_out, norms);
   if (dt_out && dtp == nullptr) *dt_out = dt;
   return rc;
+}
+
+int les_advance(les_ctx* ctx, double* Q, int nsteps, double* dt_out, double* norms) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_advance: null context");
+  if (!Q) return fail(ctx, LES_ERR_ARG, "les_advance: Q is NULL");
+  if (((uintptr_t)Q) & 15) return fail(ctx, LES_ERR_ARG, "les_advance: Q must be 16-byte aligned");
+  if (nsteps < 1) return fail(ctx, LES_ERR_ARG, "les_advance: nsteps must be >= 1 (got %d)", nsteps);
+  if (dt_out && nsteps > LES_ADVANCE_DT_MAX)
+    return fail(ctx, LES_ERR_ARG, "les_advance: dt_out holds at most %d steps (got %d)", LES_ADVANCE_DT_MAX, nsteps);
+  les::Layout& L = ctx->L;
+  const long long nb = les::stage_blocks(L, ctx->kchunk);
+  // the first step's dt by a pass of its own; each later one was reduced by
+  // the last stage of the step before (the state it reads is that stage's
+  // output, untouched since)
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+  HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag,
+                              dt_out ? ctx->dthist : nullptr));
+  for (int n = 0; n < nsteps; ++n) {
+    double* dtp = ctx->scal + ((n & 1) ? 12 : 0);
+    double* dnext = ctx->scal + ((n & 1) ? 0 : 12);
+    const bool more = n + 1 < nsteps;
+    if (n > 0) HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+    int rc = step_core(ctx, Q, dtp, 0.0, nullptr, (more && !ctx->use_ref) ? ctx->cpart : nullptr);
+    if (rc != LES_OK) return rc;
+    if (!more) break;
+    double* rec = dt_out ? ctx->dthist + n + 1 : nullptr;
+    if (ctx->use_ref)
+      HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, dnext, ctx->flag, rec));
+    else
+      HIPCHK(ctx, les::launch_cfl_final(ctx->s, ctx->cpart, nb, ctx->P.cfl, dnext, rec, ctx->flag));
+  }
+  if (!dt_out && !norms) return LES_OK;
+  if (dt_out) HIPCHK(ctx, hipMemcpyAsync(dt_out, ctx->dthist, (size_t)nsteps * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+  return sync_outputs(ctx, nullptr, norms);
 }
 
 int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* Qbar, double* fbar) {
@@ -447,12 +497,13 @@ int les_set_face(les_ctx* ctx, int face, int type, const double* Q_outside, doub
   if (face < 0 || face > 5) return fail(ctx, LES_ERR_ARG, "les_set_face: face %d outside [0, 6)", face);
   if (ctx->bc[face / 2] != LES_BC_DIRICHLET)
     return fail(ctx, LES_ERR_ARG, "les_set_face: face %d is on a periodic direction", face);
-  if (type != LES_FACE_FROZEN && type != LES_FACE_CHARACTERISTIC && type != LES_FACE_EXIT)
+  if (type != LES_FACE_FROZEN && type != LES_FACE_CHARACTERISTIC && type != LES_FACE_EXIT &&
+      type != LES_FACE_FARFIELD)
     return fail(ctx, LES_ERR_ARG, "les_set_face: unknown face type %d", type);
   if (type == LES_FACE_EXIT && !(p_exit > 0.0 && p_exit < INFINITY))
     return fail(ctx, LES_ERR_ARG, "les_set_face: the exit pressure must be positive and finite");
-  if (type == LES_FACE_CHARACTERISTIC && !Q_outside && !ctx->outside)
-    return fail(ctx, LES_ERR_ARG, "les_set_face: a characteristic face needs an outside state");
+  if ((type == LES_FACE_CHARACTERISTIC || type == LES_FACE_FARFIELD) && !Q_outside && !ctx->outside)
+    return fail(ctx, LES_ERR_ARG, "les_set_face: a characteristic or far-field face needs an outside state");
   if (Q_outside) {
     const size_t bytes = (size_t)5 * ctx->L.fe * sizeof(double);
     if (!ctx->outside && hipMalloc(&ctx->outside, bytes) != hipSuccess) {

@@ -7,12 +7,12 @@
 namespace les {
 
 // Faces in the order i-lo, i-hi, j-lo, j-hi, k-lo, k-hi (les_set_face):
-// 0 = frozen ghosts, 1 = characteristic entrance / far field, 2 = subsonic
-// exit with imposed pressure.
+// 0 = frozen ghosts, 1 = characteristic entrance, 2 = subsonic exit with
+// imposed pressure, 3 = far field.
 struct Faces {
   int type[6];
   double p_exit[6];
-  const double* outside;  // [5][fe] outside state at the ghost nodes (characteristic faces)
+  const double* outside;  // [5][fe] outside state at the ghost nodes (characteristic and far-field faces)
   const double* M;        // metrics [10][fe] (face normals)
   double gamma;
   int any;                // some face is not frozen
@@ -50,7 +50,13 @@ __device__ inline DualD fpow(DualD a, double e) {
 //     energy per unit mass p / ((gamma - 1) rho) of the boundary node are
 //     kept, p = pe, so rho = rho_r pe / p_r and e = pe / (gamma - 1) +
 //     rho |u|^2 / 2;
-//   characteristic (type 1, locally one-dimensional along nv): supersonic
+//   far field (type 3; Sec. 3: Riemann invariants, normal velocity
+//     extrapolated at zero order, fixed flow angle, the rest from the jet
+//     Mach number carried by the outside state): u.n of the boundary node;
+//     tangential velocity of the outside state; the outside state's incoming
+//     invariant u.n - 2c/(gamma-1) gives c; entropy p / rho^gamma from
+//     outside when u.n < 0, from the boundary node otherwise;
+//   characteristic (type 1, the entrance; locally one-dimensional along nv): supersonic
 //     outflow at the boundary node keeps its state, supersonic inflow from
 //     outside takes the outside state; otherwise the outgoing Riemann
 //     invariant u.n + 2c/(gamma-1) comes from the boundary node and the
@@ -81,6 +87,25 @@ __device__ void face_value(int type, double gamma, double pe, const double nv[3]
   const double co = sqrt(gamma * po / ro);
   const T unr = ur[0] * T(nv[0]) + ur[1] * T(nv[1]) + ur[2] * T(nv[2]);
   const double uno = uo[0] * nv[0] + uo[1] * nv[1] + uo[2] * nv[2];
+  if (type == 3) {
+    // far field: u.n kept from the boundary node, tangential velocity (the
+    // fixed flow angle) and incoming invariant u.n - 2c/(gamma-1) from
+    // outside, entropy from outside on inflow and from the node otherwise
+    const double rm = uno - 2.0 * co / gm1;
+    const T c = T(0.5 * gm1) * (unr - T(rm));
+    const T ent = fval(unr) >= 0.0 ? pr / fpow(rr, gamma) : T(po / pow(ro, gamma));
+    const T rho = fpow(c * c / (T(gamma) * ent), 1.0 / gm1);
+    const T p = rho * c * c / T(gamma);
+    T k = T(0.0);
+    out[0] = rho;
+    for (int a = 0; a < 3; ++a) {
+      const T ub = T(uo[a] - uno * nv[a]) + unr * T(nv[a]);
+      out[1 + a] = rho * ub;
+      k = k + ub * ub;
+    }
+    out[4] = p / T(gm1) + T(0.5) * rho * k;
+    return;
+  }
   if (fval(unr) >= fval(cr)) {  // supersonic outflow
     for (int c = 0; c < 5; ++c) out[c] = qr[c];
     return;

@@ -263,8 +263,6 @@ __global__ void k_ghost_fill_f32(Layout L, int bc0, int bc1, int bc2, float* __r
 // ---------------------------------------------------------------------------
 constexpr long long CFL_PARTS = 65536;
 
-__device__ __forceinline__ double min_nan(double a, double b) { return (b < a || b != b) ? b : a; }
-
 __global__ void __launch_bounds__(256) k_cfl_partial(Layout L, Phys P, const double* __restrict__ M,
                                                      const double* __restrict__ Q, int kc, double* __restrict__ part) {
   __shared__ double red[4];
@@ -274,25 +272,11 @@ __global__ void __launch_bounds__(256) k_cfl_partial(Layout L, Phys P, const dou
   double loc = INFINITY;
   for (int k = k0; k < k1 && i >= 0 && i < L.ni && j < L.nj; ++k) {
     long long n = L.at(i, j, k);
-    double q0 = Q[n], q1 = Q[L.fe + n], q2 = Q[2 * L.fe + n], q3 = Q[3 * L.fe + n], q4 = Q[4 * L.fe + n];
-    double u, v, w, p, tem;
-    prim_from_q(q0, q1, q2, q3, q4, P, u, v, w, p, tem);
-    double c = sqrt(P.gamma * p / q0);
-    double mu = sutherland(tem, P);
-    double nuv = P.nu_fac * mu / q0;
-    double J = M[9 * L.fe + n];
-    double lam = 0.0, g2 = 0.0;
+    double m9[9];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double gx = J * M[(3 * d) * L.fe + n], gy = J * M[(3 * d + 1) * L.fe + n], gz = J * M[(3 * d + 2) * L.fe + n];
-      double U = gx * u + gy * v + gz * w;
-      double gg = gx * gx + gy * gy + gz * gz;
-      lam += fabs(U) + c * sqrt(gg);
-      g2 += gg;
-    }
-    double l = 1.0 / (lam + 2.0 * nuv * g2);
-    if (!(l > 0.0) || !(q0 > 0.0) || !(p > 0.0)) l = NAN;
-    loc = min_nan(loc, l);
+    for (int c = 0; c < 9; ++c) m9[c] = M[c * L.fe + n];
+    loc = min_nan(loc, cfl_local(Q[n], Q[L.fe + n], Q[2 * L.fe + n], Q[3 * L.fe + n], Q[4 * L.fe + n],
+                                 M[9 * L.fe + n], m9, P));
   }
   loc = wave_min(loc);
   const int tid = threadIdx.y * 64 + threadIdx.x;
@@ -305,9 +289,11 @@ __global__ void __launch_bounds__(256) k_cfl_partial(Layout L, Phys P, const dou
   }
 }
 
-// scal[0] = dt; flag |= 1 when the minimum is not a positive finite number.
+// *dt_out = dt (and *also = dt when also is not null); flag |= 1 when the
+// minimum is not a positive finite number.
 __global__ void __launch_bounds__(1024) k_cfl_final(const double* __restrict__ part, long long np, double cfl,
-                                                    double* __restrict__ scal, int* __restrict__ flag) {
+                                                    double* __restrict__ dt_out, double* __restrict__ also,
+                                                    int* __restrict__ flag) {
   __shared__ double red[16];
   double m = INFINITY;
 #pragma unroll 8
@@ -320,7 +306,8 @@ __global__ void __launch_bounds__(1024) k_cfl_final(const double* __restrict__ p
     for (int a = 1; a < 16; ++a) r = min_nan(r, red[a]);
     double dt = cfl * r;
     if (!(dt > 0.0) || !(dt < INFINITY)) *flag |= 1;
-    scal[0] = dt;
+    *dt_out = dt;
+    if (also) *also = dt;
   }
 }
 
@@ -738,11 +725,17 @@ long long cfl_blocks(const Layout& L) {
 }
 
 hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
-                      double* scal, int* flag) {
+                      double* dt_out, int* flag, double* also) {
   const int kc = cfl_kc(L);
   dim3 g(nblk(L.ni + LEAD, 64), nblk(L.nj, 4), nblk(L.nk, kc)), b(64, 4);
   k_cfl_partial<<<g, b, 0, s>>>(L, P, M, Q, kc, part);
-  k_cfl_final<<<1, 1024, 0, s>>>(part, cfl_blocks(L), P.cfl, scal, flag);
+  k_cfl_final<<<1, 1024, 0, s>>>(part, cfl_blocks(L), P.cfl, dt_out, also, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_final(hipStream_t s, const double* part, long long np, double cfl, double* dt_out,
+                            double* also, int* flag) {
+  k_cfl_final<<<1, 1024, 0, s>>>(part, np, cfl, dt_out, also, flag);
   return hipGetLastError();
 }
 

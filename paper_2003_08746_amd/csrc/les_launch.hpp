@@ -23,8 +23,12 @@ hipError_t launch_stream_copy(hipStream_t s, const void* src, void* dst, long lo
 long long ref_blocks(const Layout& L);
 // partials written by the CFL kernel
 long long cfl_blocks(const Layout& L);
+// dt of the interior of Q into *dt_out (and *also when not null)
 hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
-                      double* scal, int* flag);
+                      double* dt_out, int* flag, double* also = nullptr);
+// dt = cfl * min of np per-block CFL bounds (e.g. the stage kernel's)
+hipError_t launch_cfl_final(hipStream_t s, const double* part, long long np, double cfl, double* dt_out,
+                            double* also, int* flag);
 hipError_t launch_residual_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q,
                                const double* f, int i_f, double* R, double* part);
 hipError_t launch_stage_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Qin,

@@ -3,7 +3,10 @@
 // One launch evaluates R(Q^(l-1)) at every interior node and writes
 // Q^(l) = Q^(0) - alpha_l dt R (Sec. 4, Alg. 2: inviscid flux, artificial
 // dissipation, viscous flux, RHS and the stage update of one RK stage,
-// fused), plus per-block partial norms of R.
+// fused), plus per-block partial norms of R (first stage) or per-block
+// minima of the local CFL bound of the updated state (last stage: the time
+// step of the next step is pointwise in Q^{n+1}, so it is reduced while the
+// state is in registers instead of by a pass of its own).
 //
 // Decomposition.  A block of 32 x 16 threads owns the nodes of a 32 x 16
 // patch of one k-plane: the 30 x 14 output tile and a one-node halo ring.
@@ -214,10 +217,10 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <class T, class QI, bool NORM>
+template <class T, class QI, bool NORM, bool CFL>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) k_stage(KArgs a, const QI* __restrict__ Qin, const double* Q0, double* Qout,
                                               float* Qsh, const double* __restrict__ dtp, double dt_host,
-                                              double alpha, double* __restrict__ part) {
+                                              double alpha, double* __restrict__ part, double* __restrict__ cpart) {
   // the FP32 path has the registers to prefetch the helper ring one plane
   // ahead; the FP64 path loads it at phase B (holding it would spill)
   constexpr bool kPrefetchRing = sizeof(T) == 4;
@@ -276,6 +279,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
   // residual norms: per-thread running sums of R^2 and maxima of |R| over
   // all planes of the block (NORM only), reduced once at the end
   double n2[5] = {0, 0, 0, 0, 0}, nm[5] = {0, 0, 0, 0, 0};
+  // CFL only (the last stage): running minimum of the local CFL bound of the
+  // updated state Q^(l) = Q^{n+1} over the block's nodes
+  double cmin = INFINITY;
   int qbuf = 0;  // LDS Q plane written at the next B (alternates every plane)
   for (long long wq = w_begin; wq < w_end;) {
     // ---- one segment: planes [kb, ke) of one tile ----
@@ -553,6 +559,15 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
           for (int c = 0; c < 5; ++c) r[c] -= D1[c] - D0[c];
         }
         __builtin_amdgcn_sched_barrier(0);
+        // CFL only: the nine metric terms of the node finished in this
+        // iteration (plane t-1), read back through the caches (they were
+        // copied to LDS two planes ago); consumed after the update
+        double cm[9];
+        if (CFL) {
+          const unsigned n = (out_ok && t > kb) ? nt - sk : qcol;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) cm[c] = ldo(kq->M + c * fe, n);
+        }
         if (t >= kb) {
           // zeta face t - 1/2 between plane t-1 and plane t
           T qc[5], D[5], fz[5];
@@ -566,11 +581,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
             // residual of plane t-1 and its stage update
             const int k = t - 1;
             const unsigned n = nt - sk;
+            double qnv[5];
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
               double R = J_prev * (double)(racc[c] + fz[c]);
               if (kq->f && i == kq->i_f) R -= kq->f[((long long)c * kq->L.nk + k) * kq->L.nj + j];
               const double qn = q0v[c] - adt * R;
+              qnv[c] = qn;
               if (Qout) sto(Qout + c * fe, n, qn);
               if (Qsh) sto(Qsh + c * fe, n, (float)qn);
               if (NORM) {
@@ -579,6 +596,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
                 nm[c] = (a > nm[c] || a != a) ? a : nm[c];  // NaN wins so that it is reported
               }
             }
+            if (CFL) cmin = min_nan(cmin, cfl_local(qnv[0], qnv[1], qnv[2], qnv[3], qnv[4], J_prev, cm, kq->P));
           }
 #pragma unroll
           for (int c = 0; c < 5; ++c) racc[c] = r[c] - fz[c];
@@ -620,6 +638,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
         r = tid < 5 ? r + o : ((o > r || o != o) ? o : r);
       }
       part[(long long)v * 10 + tid] = r;
+    }
+  }
+  // ---- block partial of the CFL bound (CFL only) ----
+  if (CFL) {
+    const double m = wave_min(cmin);
+    double* red = &q0w[0][0][0][0];
+    __syncthreads();  // every wave is past its last read of q0w
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    if (tid == 0) {
+      double r = red[0];
+      for (int w = 1; w < NW; ++w) r = min_nan(r, red[w]);
+      cpart[v] = r;
     }
   }
 }
@@ -678,14 +709,17 @@ Config config(const Layout& L, long long per_block) {
 
 template <class T, class QI>
 hipError_t launch(hipStream_t st, const StageArgs& sa, const QI* Qin, const double* Q0, double* Qout, float* Qsh,
-                  const double* dtp, double dt, double alpha, double* part) {
+                  const double* dtp, double dt, double alpha, double* part, double* cpart) {
+  if (part && cpart) return hipErrorInvalidValue;  // norms belong to stage 1, the CFL bound to stage 5
   Config c = config(sa.L, sa.kchunk);
   KArgs a{sa.L,        sa.P,   sa.M,   sa.f,      sa.i_f,    c.ntx,    c.nty,
           c.total,     c.per_block, c.kc, c.rr, c.nseg, c.nblocks, c.per_xcd};
   if (part)
-    k_stage<T, QI, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part);
+    k_stage<T, QI, true, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  else if (cpart)
+    k_stage<T, QI, false, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
   else
-    k_stage<T, QI, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part);
+    k_stage<T, QI, false, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
   return hipGetLastError();
 }
 
@@ -700,15 +734,15 @@ int stage_kchunk(const Layout& L) {
 long long stage_blocks(const Layout& L, int kchunk) { return config(L, kchunk).nblocks; }
 
 hipError_t launch_stage_fp64(hipStream_t s, const StageArgs& a, const double* Qin, const double* Q0, double* Qout,
-                             const double* dtp, double dt, double alpha, double* part) {
-  return launch<double, double>(s, a, Qin, Q0, Qout, nullptr, dtp, dt, alpha, part);
+                             const double* dtp, double dt, double alpha, double* part, double* cpart) {
+  return launch<double, double>(s, a, Qin, Q0, Qout, nullptr, dtp, dt, alpha, part, cpart);
 }
 
 hipError_t launch_stage_mixed(hipStream_t s, const StageArgs& a, const double* Qin64, const float* Qin32,
                               const double* Q0, double* Qout, float* Qsh, const double* dtp, double dt, double alpha,
-                              double* part) {
-  if (Qin64) return launch<float, double>(s, a, Qin64, Q0, Qout, Qsh, dtp, dt, alpha, part);
-  return launch<float, float>(s, a, Qin32, Q0, Qout, Qsh, dtp, dt, alpha, part);
+                              double* part, double* cpart) {
+  if (Qin64) return launch<float, double>(s, a, Qin64, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  return launch<float, float>(s, a, Qin32, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
 }
 
 }  // namespace les

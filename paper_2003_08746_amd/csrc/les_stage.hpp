@@ -22,15 +22,17 @@ long long stage_blocks(const Layout& L, int kchunk);
 
 // One FP64 stage: Qout = Q0 - alpha dt R(Qin) on the interior (Qin's ghosts
 // already filled).  dtp (device) overrides dt when non-null.  part: norm
-// partials (or null).  Q0 and Qout may alias.
+// partials (or null).  cpart (or null): per-block minima of the local CFL
+// bound of the updated state (stage_blocks doubles; not together with part).
+// Q0 and Qout may alias.
 hipError_t launch_stage_fp64(hipStream_t s, const StageArgs& a, const double* Qin, const double* Q0, double* Qout,
-                             const double* dtp, double dt, double alpha, double* part);
+                             const double* dtp, double dt, double alpha, double* part, double* cpart);
 
 // One mixed-precision stage: the stencil input is FP64 (Qin64, stage 1) or
 // FP32 (Qin32); fluxes and dissipation in FP32; the update Q0 - alpha dt R
 // in FP64, written as FP64 (Qout) and/or as an FP32 stage state (Qsh).
 hipError_t launch_stage_mixed(hipStream_t s, const StageArgs& a, const double* Qin64, const float* Qin32,
                               const double* Q0, double* Qout, float* Qsh, const double* dtp, double dt, double alpha,
-                              double* part);
+                              double* part, double* cpart);
 
 }  // namespace les

@@ -24,10 +24,10 @@ LIB_PATH = os.path.join(HERE, "liblesmi.so")
 LES_OK, LES_ERR_ARG, LES_ERR_HIP, LES_ERR_NOMEM, LES_ERR_NONFINITE, LES_ERR_STATE = 0, -1, -2, -3, -4, -5
 LES_FP64, LES_MIXED = 0, 1
 LES_BC_PERIODIC, LES_BC_DIRICHLET, LES_BC_PERIODIC_SUPERPOSED = 0, 1, 2
-LES_FACE_FROZEN, LES_FACE_CHARACTERISTIC, LES_FACE_EXIT = 0, 1, 2
+LES_FACE_FROZEN, LES_FACE_CHARACTERISTIC, LES_FACE_EXIT, LES_FACE_FARFIELD = 0, 1, 2, 3
 
 EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",
-            "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_adjoint_step", "les_residual_adjoint",
+            "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_advance", "les_adjoint_step", "les_residual_adjoint",
             "les_probe_objective", "les_set_face", "les_stats_accumulate",
             "les_last_error", "les_last_create_error"]
 
@@ -88,6 +88,8 @@ def lib():
     L.les_set_forcing.argtypes = [_vp, _vp, ctypes.c_int]
     L.les_rk_step.restype = ctypes.c_int
     L.les_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _dp, _dp, _vp]
+    L.les_advance.restype = ctypes.c_int
+    L.les_advance.argtypes = [_vp, _vp, ctypes.c_int, _dp, _dp]
     L.les_adjoint_step.restype = ctypes.c_int
     L.les_adjoint_step.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp]
     L.les_residual_adjoint.restype = ctypes.c_int
@@ -198,6 +200,14 @@ def les_rk_step(ctx, Q_ptr, dt=0.0, want_dt=False, want_norms=False, ckpt_ptr=No
     rc = lib().les_rk_step(ctx, Q_ptr, float(dt), ctypes.byref(dto) if want_dt else None, norms, ckpt_ptr)
     _check(rc, ctx, "les_rk_step")
     return (dto.value if want_dt else None), (np.array(norms[:]) if want_norms else None)
+
+
+def les_advance(ctx, Q_ptr, nsteps, want_dt=False, want_norms=False):
+    dts = (ctypes.c_double * int(nsteps))() if want_dt else None
+    norms = (ctypes.c_double * 10)() if want_norms else None
+    rc = lib().les_advance(ctx, Q_ptr, int(nsteps), dts, norms)
+    _check(rc, ctx, "les_advance")
+    return (np.array(dts[:]) if want_dt else None), (np.array(norms[:]) if want_norms else None)
 
 
 def les_adjoint_step(ctx, ckpt_ptr, dt, Qbar_ptr, fbar_ptr=None):
@@ -320,6 +330,10 @@ class Solver:
 
     def rk_step(self, Q, dt=0.0, want_dt=False, want_norms=False, ckpt=None):
         return les_rk_step(self.ctx, Q.data_ptr(), dt, want_dt, want_norms, _ptr(ckpt))
+
+    def advance(self, Q, nsteps, want_dt=False, want_norms=False):
+        """nsteps CFL steps in one call (les_advance); returns (dts, norms)."""
+        return les_advance(self.ctx, Q.data_ptr(), nsteps, want_dt, want_norms)
 
     def set_forcing(self, f, i_f):
         les_set_forcing(self.ctx, None if f is None else f.data_ptr(), i_f)

@@ -1,0 +1,183 @@
+"""The benchmark configurations against the oracle, through the C ABI.
+
+* les_advance (nsteps CFL steps in one call, the next step's dt reduced by
+  the last stage of each step) against the oracle stepping with the CFL
+  time step of each Q^n, and against repeated les_rk_step calls;
+* the 256 x 128 x 128 jet shard: its first five steps, element by element
+  (FP64 bar: 1e-12 of each field's maximum; dt to 1e-14);
+* the FP32-mixed form on that shard against the FP64 oracle (two steps,
+  bound 2e-6 of each field's scale) and against the FP64 GPU path over 100
+  steps (bound 3e-5: the per-step FP32 error of the 10-step bound, 2e-7,
+  accumulated linearly over 100 steps, with a factor 1.5 of margin); the
+  per-field L2 and Linf errors are printed.
+"""
+import numpy as np
+import pytest
+
+from paper_2003_08746_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+MIXED_BOUND = 2e-6
+MIXED_100_BOUND = 3e-5
+
+
+@pytest.fixture(scope="module")
+def lesmi():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a device"
+    from paper_2003_08746_amd import lesmi as L
+    L.lib()
+    return L
+
+
+def _rel(a, b):
+    ai, bi = I.interior(a), I.interior(b)
+    den = np.abs(bi).reshape(bi.shape[0], -1).max(1)
+    den = np.where(den == 0, 1.0, den)
+    return np.abs(ai - bi).reshape(ai.shape[0], -1).max(1) / den
+
+
+def _field_scale(Q):
+    sc = np.abs(I.interior(Q)).reshape(5, -1).max(1)
+    sc[1:4] = sc[1:4].max()  # a momentum component may start at zero
+    return sc
+
+
+def _small_cases():
+    n = (70, 37, 21)
+    xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
+    return {"tgv32": (I.tgv_case(32), 6),
+            "jet150x40x20": (I.jet_case(150, 40, 20, seed=4), 3),
+            "wavy70x37x21": (I.periodic_case(*n, xyz, I.smooth_state(*n, seed=9, amp=0.1), mu_ref=3e-3,
+                                             alpha=0.7, sgs=1), 3)}
+
+
+SMALL = _small_cases()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_advance_parity(orc, lesmi, name):
+    case, steps = SMALL[name]
+    print(f"[gpu] advance {name} x{steps}", flush=True)
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    dts, norms = s.advance(Q, steps, want_dt=True, want_norms=True)
+    m = orc.metrics(case)
+    Qo = case["Q"]
+    for n in range(steps):
+        Qo, dto, no, _ = orc.rk_step(case, m, Qo)
+        assert abs(dts[n] - dto) <= 1e-14 * dto, (n, dts[n], dto)
+    assert np.allclose(norms, no, rtol=1e-11, atol=0), (norms, no)
+    Qg = s.download(Q)
+    assert (_rel(Qg, Qo) <= TOL).all(), _rel(Qg, Qo)
+    # the same steps one call at a time (CFL pass of its own every step)
+    Q2 = s.upload(case["Q"])
+    for n in range(steps):
+        dt, _ = s.rk_step(Q2, 0.0, want_dt=True)
+        assert abs(dt - dts[n]) <= 1e-15 * dt, (n, dt, dts[n])
+    assert (_rel(s.download(Q2), Qg) <= 1e-15).all()
+    s.close()
+
+
+def test_advance_arguments(lesmi):
+    case, _ = SMALL["tgv32"]
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    for bad in (0, -3):
+        with pytest.raises(lesmi.LesError) as e:
+            s.advance(Q, bad)
+        assert e.value.code == lesmi.LES_ERR_ARG
+    with pytest.raises(lesmi.LesError) as e:
+        lesmi.les_advance(s.ctx, Q.data_ptr() + 8, 1)
+    assert e.value.code == lesmi.LES_ERR_ARG
+    with pytest.raises(lesmi.LesError) as e:
+        s.advance(Q, 4097, want_dt=True)
+    assert e.value.code == lesmi.LES_ERR_ARG
+    s.close()
+
+
+def test_advance_mixed_matches_rk_steps(lesmi):
+    """Mixed precision: les_advance and one les_rk_step per step agree."""
+    case, _ = SMALL["jet150x40x20"]
+    s = lesmi.Solver(case, prec=lesmi.LES_MIXED)
+    Q = s.upload(case["Q"])
+    dts, _ = s.advance(Q, 3, want_dt=True)
+    Q2 = s.upload(case["Q"])
+    for n in range(3):
+        dt, _ = s.rk_step(Q2, 0.0, want_dt=True)
+        assert abs(dt - dts[n]) <= 1e-15 * dt
+    assert (_rel(s.download(Q2), s.download(Q)) <= 1e-15).all()
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def jet_shard():
+    return I.jet_case(256, 128, 128, seed=0)
+
+
+def test_jet_shard_five_steps(orc, lesmi, jet_shard):
+    """The first five steps of the 256 x 128 x 128 jet shard (the
+    benchmark's smaller workload) through les_advance."""
+    case = jet_shard
+    print("[gpu] jet shard 256x128x128: 5 steps", flush=True)
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    dts, norms = s.advance(Q, 5, want_dt=True, want_norms=True)
+    Qg = s.download(Q)
+    s.close()
+    m = orc.metrics(case)
+    Qo = case["Q"]
+    for n in range(5):
+        Qo, dto, no, _ = orc.rk_step(case, m, Qo)
+        assert abs(dts[n] - dto) <= 1e-14 * dto, (n, dts[n], dto)
+    assert np.allclose(norms, no, rtol=1e-11, atol=0)
+    err = _rel(Qg, Qo)
+    print(f"[gpu] jet shard 5 steps: per-field rel {err}", flush=True)
+    assert (err <= TOL).all(), err
+    assert (_rel(Qg - case["Q"], Qo - case["Q"]) <= 1e-9).all()
+
+
+def test_mixed_jet_shard_vs_oracle(orc, lesmi, jet_shard):
+    """FP32-mixed form of the jet shard against the FP64 oracle, two steps."""
+    case = jet_shard
+    print("[gpu] jet shard 256x128x128 mixed: 2 steps", flush=True)
+    s = lesmi.Solver(case, prec=lesmi.LES_MIXED)
+    Q = s.upload(case["Q"])
+    dts, _ = s.advance(Q, 2, want_dt=True)
+    Qg = s.download(Q)
+    s.close()
+    m = orc.metrics(case)
+    Qo = case["Q"]
+    for n in range(2):
+        Qo, _, _, _ = orc.rk_step(case, m, Qo, dt=dts[n])
+    d = I.interior(Qg) - I.interior(Qo)
+    sc = _field_scale(Qo)
+    linf = np.abs(d).reshape(5, -1).max(1) / sc
+    l2 = np.sqrt((d ** 2).reshape(5, -1).mean(1)) / sc
+    print(f"[gpu] mixed vs oracle, jet shard 2 steps: Linf {linf} L2 {l2}", flush=True)
+    assert (linf <= MIXED_BOUND).all(), linf
+
+
+def test_mixed_vs_fp64_100_steps(lesmi, jet_shard):
+    """100 steps of the jet shard, FP32-mixed against FP64 on the GPU."""
+    import torch
+    case = jet_shard
+    print("[gpu] jet shard 256x128x128: 100 steps FP64 and mixed", flush=True)
+    out = {}
+    for name, prec in (("fp64", lesmi.LES_FP64), ("mixed", lesmi.LES_MIXED)):
+        s = lesmi.Solver(case, prec=prec)
+        Q = s.upload(case["Q"])
+        s.advance(Q, 100)
+        out[name] = s.view(Q).clone()
+        s.close()
+    a, b = out["mixed"], out["fp64"]
+    d = (a - b)[:, 2:-2, 2:-2, 2:-2].reshape(5, -1)
+    sc = b[:, 2:-2, 2:-2, 2:-2].abs().reshape(5, -1).amax(1)
+    sc[1:4] = sc[1:4].max()
+    linf = (d.abs().amax(1) / sc).cpu().numpy()
+    l2 = (torch.sqrt((d ** 2).mean(1)) / sc).cpu().numpy()
+    print(f"[gpu] mixed vs FP64, jet shard 100 steps: Linf {linf} L2 {l2}", flush=True)
+    assert np.isfinite(linf).all()
+    assert (linf <= MIXED_100_BOUND).all(), linf

@@ -1,5 +1,5 @@
 """Boundary faces of a Dirichlet direction (les_set_face: characteristic
-entrance / far field and subsonic exit, Sec. 3) against the oracle: the ghost
+entrance, subsonic exit and far field, Sec. 3) against the oracle: the ghost
 states, the residual, two RK steps in FP64 and in FP32-mixed, the argument
 errors, and the adjoint through the face rules (dot-product tests against the
 oracle's dual-number tangents).  Tolerances: the FP64 bar of 1e-12 relative to
@@ -27,17 +27,18 @@ def lesmi():
 def _case(ni=61, nj=29, nk=23, seed=3):
     """Jet block, Dirichlet in i (entrance at i-lo, exit at i-hi) and j (far
     field on both sides), periodic in k; the interior is perturbed away from
-    the outside state (the analytic profile kept in the initial ghosts)."""
+    the outside state (the analytic jet profile with a small spanwise
+    cross-flow, so that the far-field flow angle is not the normal's)."""
     c = I.jet_case(ni, nj, nk, seed=seed)
     c["bc"] = (1, 1, 0)
     g = c["params"]["gamma"]
-    Q0 = c["Q"].copy()
+    Q0 = I.outside_state(c, cross=(0.0, 0.0, 0.03))
     rng = np.random.default_rng(seed)
-    Q = Q0.copy()
+    Q = c["Q"].copy()
     Q[1:4] += 0.05 * rng.uniform(-1, 1, size=Q[1:4].shape)
     Q[4] *= 1.0 + 0.02 * rng.uniform(-1, 1, size=Q[4].shape)
     c["Q"] = Q
-    c["faces"] = dict(types=[1, 2, 1, 1, 0, 0], p_exit=[0.0, 1.0 / g, 0, 0, 0, 0], outside=Q0)
+    c["faces"] = dict(types=[1, 2, 3, 3, 0, 0], p_exit=[0.0, 1.0 / g, 0, 0, 0, 0], outside=Q0)
     return c, Q0
 
 
@@ -46,8 +47,8 @@ def _solver(lesmi, case, Q0, prec=None):
     fc = case["faces"]
     s.set_face(0, lesmi.LES_FACE_CHARACTERISTIC, s.upload(Q0))
     s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=fc["p_exit"][1])
-    s.set_face(2, lesmi.LES_FACE_CHARACTERISTIC)
-    s.set_face(3, lesmi.LES_FACE_CHARACTERISTIC)
+    s.set_face(2, lesmi.LES_FACE_FARFIELD)
+    s.set_face(3, lesmi.LES_FACE_FARFIELD)
     return s
 
 

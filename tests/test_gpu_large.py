@@ -147,3 +147,30 @@ def test_large_shard_mixed_windows(orc, lesmi, shard):
     s.close()
     del Q, Qv
     torch.cuda.empty_cache()
+
+
+def test_large_shard_advance_matches_rk_steps(lesmi, shard):
+    """The benchmark's timed call on the full shard: les_advance over two
+    steps (the second step's dt reduced by the first step's last stage)
+    equals two les_rk_step calls that take that dt from a pass of their own
+    (the windows above check les_rk_step against the oracle)."""
+    import torch
+    case = shard
+    print("[gpu] large shard: les_advance x2 against two les_rk_step calls", flush=True)
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    dts, norms = s.advance(Q, 2, want_dt=True, want_norms=True)
+    Q2 = s.upload(case["Q"])
+    dt0, _ = s.rk_step(Q2, 0.0, want_dt=True)
+    assert abs(dt0 - dts[0]) <= 1e-15 * dt0, (dt0, dts[0])
+    dt1 = s.cfl_dt(Q2)
+    assert abs(dt1 - dts[1]) <= 1e-15 * dt1, (dt1, dts[1])
+    _, norms2 = s.rk_step(Q2, float(dts[1]), want_norms=True)
+    assert np.allclose(norms, norms2, rtol=1e-13, atol=0)
+    a, b = s.view(Q)[:, 2:-2, 2:-2, 2:-2], s.view(Q2)[:, 2:-2, 2:-2, 2:-2]
+    d = ((a - b).abs().reshape(5, -1).amax(1) / b.abs().reshape(5, -1).amax(1)).cpu().numpy()
+    print(f"[gpu] large shard advance vs rk_step: dt {dts}, rel {d}", flush=True)
+    assert (d <= 1e-15).all(), d
+    s.close()
+    del Q, Q2, a, b
+    torch.cuda.empty_cache()

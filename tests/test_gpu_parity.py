@@ -1,8 +1,11 @@
 """GPU path (through the C ABI) against the FP64 CPU oracle, element by
 element, on seeded inputs: metrics, residual, CFL time step, norms and RK
-steps; sizes span several kernel tiles with ragged tails, plus the C0 TGV
-box and one full-size step of the 256x128x128 jet shard.  Tolerance: the
-FP64 bar of 1e-12 relative to each field's maximum."""
+steps; sizes span several kernel tiles with ragged tails, plus the 32^3
+Taylor-Green box (the full-size jet shard is in test_gpu_configs.py).
+Tolerance: the FP64 bar of 1e-12 relative to each field's maximum; for the
+Taylor-Green residual (Mach 0.1, every component a small difference of much
+larger flux terms) relative to the largest component of the whole residual
+vector, the reading the test states."""
 import numpy as np
 import pytest
 
@@ -139,23 +142,6 @@ def test_rk_fixed_dt_and_checkpoints(orc, lesmi):
     for l in range(5):
         st = s.download(ck[l * 5 * s.fe:(l + 1) * 5 * s.fe])
         assert (_rel(st, stages[l]) <= TOL).all(), l
-    s.close()
-
-
-def test_rk_parity_full_jet_shard(orc, lesmi):
-    """One step of the full 256x128x128 jet shard (the benchmark workload)."""
-    case = I.jet_case(256, 128, 128, seed=0)
-    print("[gpu] rk full jet shard 256x128x128", flush=True)
-    s = lesmi.Solver(case)
-    Q = s.upload(case["Q"])
-    dt, norms = s.rk_step(Q, 0.0, want_dt=True, want_norms=True)
-    m = orc.metrics(case)
-    Qo, dto, no, _ = orc.rk_step(case, m, case["Q"])
-    assert abs(dt - dto) <= 1e-14 * dto
-    assert np.allclose(norms, no, rtol=1e-11, atol=0)
-    Qg = s.download(Q)
-    assert (_rel(Qg, Qo) <= TOL).all()
-    assert (_rel(Qg - case["Q"], Qo - case["Q"]) <= 1e-9).all()
     s.close()
 
 

@@ -149,3 +149,38 @@ def test_superposed_adjoint_dot_products(orc, lesmi, name):
     scale = float(np.abs(I.interior(w) * I.interior(dQ1)).sum())
     assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
     s.close()
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_superposed_adjoint_physical_directions(orc, lesmi, name):
+    """The superposed block's residual adjoint along perturbations that move
+    node 0 and its duplicate node n together (the directions that keep the
+    block a periodic one) against the plain periodic block's oracle tangent:
+    <Js^T w, v_s> = <w', Jp v>, w' = w with its plane n added onto plane 0.
+    Neither side depends on how the ghosts break the tie between the two
+    copies of the seam."""
+    base, axis = _cases()[name]
+    if name.startswith("jet"):
+        base = dict(base)
+        Qn = base["Q"].copy()
+        Qn[4] += 1e-4 * (1.0 / I.GAMMA) / (I.GAMMA - 1.0) * np.random.default_rng(17).uniform(-1, 1, Qn[4].shape)
+        base["Q"] = Qn
+    case = I.superposed_case(base, axis)
+    n = base[("ni", "nj", "nk")[axis]]
+    print(f"[gpu] superposed adjoint, physical directions {name}", flush=True)
+    v = _interior_rand(base, 3)
+    vs = I.superposed_case(dict(base, Q=v), axis)["Q"]
+    w = _interior_rand(case, 4, scale_by_field=False)
+    wf = np.zeros_like(base["Q"])
+    wi = I.interior(w)
+    wfi = _along(wi, axis, slice(0, n)).copy()
+    _along(wfi, axis, slice(0, 1))[...] += _along(wi, axis, slice(n, n + 1))
+    wf[:, 2:-2, 2:-2, 2:-2] = wfi
+    _, dRp = orc.residual_tangent(base, orc.metrics(base), base["Q"], v)
+    s = lesmi.Solver(case)
+    Qbar = s.download(s.residual_adjoint(s.upload(case["Q"]), s.upload(w)))
+    s.close()
+    lhs = _dot(Qbar, vs)
+    rhs = _dot(wf, dRp)
+    scale = float(np.abs(I.interior(wf) * I.interior(dRp)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
