@@ -38,7 +38,7 @@ class OrcParams(ctypes.Structure):
                 ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("S_suth", ctypes.c_double),
                 ("R_gas", ctypes.c_double), ("sgs", ctypes.c_int), ("Cs", ctypes.c_double),
                 ("k2", ctypes.c_double), ("k4", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("cfl", ctypes.c_double)]
+                ("cfl", ctypes.c_double), ("CI", ctypes.c_double)]
 
 
 def _load():
@@ -80,6 +80,8 @@ def _load():
     lib.orc_fill_ghosts_faces.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
     lib.orc_stats.restype = None
     lib.orc_stats.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
+    lib.orc_dynamic_coefficients.restype = None
+    lib.orc_dynamic_coefficients.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp, _dp]
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_threads.argtypes = [ctypes.c_int]
     lib.orc_rk_scalar.restype = None
@@ -110,7 +112,7 @@ def dims(ni, nj, nk, bc=(0, 0, 0)) -> OrcDims:
 
 
 _PARAM_KEYS = ["gamma", "Pr", "Pr_sgs", "mu_ref", "T_ref", "S_suth", "R_gas", "sgs", "Cs", "k2", "k4",
-               "alpha", "cfl"]
+               "alpha", "cfl", "CI"]
 
 
 def params(p: dict) -> OrcParams:
@@ -198,6 +200,18 @@ def residual_tangent(case, m, Q, dQ, prm=None, f=None, df=None, i_f=-1):
                              _ptr(None if dQ is None else _c(dQ)), _ptr(None if f is None else _c(f)),
                              _ptr(None if df is None else _c(df)), int(i_f), _ptr(R), _ptr(dR))
     return R, dR
+
+
+def dynamic_coefficients(case, m, Q, prm=None):
+    """(C, D_T): the dynamic closure's coefficients per padded column, arrays
+    (nj+4, ni+4) (mu_sgs = C rho D^2 |S|, kappa_sgs = Cp D_T rho D^2 |S|)."""
+    lib = _load()
+    prm = case["params"] if prm is None else prm
+    C = np.zeros((case["nj"] + 4, case["ni"] + 4))
+    D = np.zeros_like(C)
+    lib.orc_dynamic_coefficients(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)),
+                                 _ptr(_c(Q)), _ptr(C), _ptr(D))
+    return C, D
 
 
 def cfl_dt(case, m, Q, prm=None) -> float:

@@ -53,6 +53,27 @@
 //       max(a, b) follows a when a >= b; d sqrt(x)/dx = 0 at x = 0.
 //   R12 an optional constant source f on the plane i = i_f: dQ/dt = -R + f.
 //   R13, R14, R16 boundary faces of a Dirichlet direction: see fill_faces.
+//   R17 dynamic SGS closure (sgs = 2; the paper fixes Pr_sgs = 0.9 only for
+//       static closures): the coefficients of mu_sgs = C rho D^2 |S| and
+//       kappa_sgs = Cp D_T rho D^2 |S| (D_T = C / Pr_sgs) come from Germano's
+//       identity between the grid filter and a test filter of width 2D, in
+//       the compressible (Favre) form of Moin, Squires, Cabot and Lee (1991),
+//       by Lilly's least squares averaged over the periodic k direction:
+//         C(i,j) = max(0, <L^d : M> / <M : M>),  D_T(i,j) = max(0, <K . N> / <N . N>),
+//       with <.> the sum over interior k and, at one node (^ = test filter,
+//       the index-space tensor product of the weights (1/4, 1/2, 1/4)):
+//         L_ij = (rho u_i u_j)^ - (rho u_i)^ (rho u_j)^ / rho^,
+//         M_ij = 2 (D^2 rho |S| S^d_ij)^ - 2 (2D)^2 rho^ |S~| S~^d_ij,
+//         K_j  = (rho u_j T)^ - (rho u_j)^ (rho T)^ / rho^,
+//         N_j  = (D^2 rho |S| dT/dx_j)^ - (2D)^2 rho^ |S~| dT~/dx_j,
+//       where S~ and T~ are the strain rate and gradient (central
+//       differences, chain rule) of u~ = (rho u)^ / rho^ and T~ = (rho T)^ /
+//       rho^, D = (1/J)^(1/3) at the node.  Ghost columns take the wrapped
+//       (periodic) or nearest interior (Dirichlet) column's coefficients.
+//       Re-evaluated with every residual, as the viscosity is.
+//   R18 isotropic part of the SGS stress (Eq. 11), Yoshizawa's model:
+//       sigma_kk = 2 CI rho D^2 |S|^2 (sgs >= 1).  By Eq. 1 it acts as an
+//       added pressure sigma_kk / 3 in the momentum and energy fluxes.
 //   R15 superposed periodic direction (Sec. 3: the first and last azimuthal
 //       points coincide): bc = 2, period n - 1; node n - 1 is node 0 again
 //       (it takes node 0's metrics), ghosts wrap with period n - 1.  A ghost
@@ -155,10 +176,12 @@ typedef struct {
   double T_ref;   // Sutherland reference temperature (nondimensional)
   double S_suth;  // S1 / T_ref (Eq. 6, reading R5)
   double R_gas;   // gas constant (Eq. 7-8)
-  int sgs;        // 0: mu_sgs = 0 (the paper's runs), 1: static Smagorinsky (R6)
+  int sgs;        // 0: mu_sgs = 0 (the paper's runs), 1: static Smagorinsky (R6),
+                  // 2: dynamic closure (R17)
   double Cs;      // Smagorinsky constant
   double k2, k4, alpha;  // Turkel-Vatsa constants (R7)
   double cfl;     // CFL number (R9)
+  double CI;      // isotropic SGS constant of the sigma_kk model (R18); 0 = sigma_kk off
 } orc_params;
 }
 
@@ -483,6 +506,151 @@ void metrics(const Box& b, const double* xyz, double* m) {
 }
 
 // ---------------------------------------------------------------------------
+// R17: dynamic coefficients C(i,j), D_T(i,j) on every padded column
+// (index (j + G) * pi + (i + G)), from Q with its ghosts filled.
+// ---------------------------------------------------------------------------
+template <class S>
+void dynamic_coefficients(const Box& b, const orc_params& P, const double* m, const S* Q, std::vector<S>& Cc,
+                          std::vector<S>& Dc) {
+  const size_t N = b.N;
+  const double g = P.gamma;
+  const S* Qv[5] = {Q, Q + N, Q + 2 * N, Q + 3 * N, Q + 4 * N};
+  const double* M[10];
+  for (int c = 0; c < 10; ++c) M[c] = m + (size_t)c * N;
+  // primitives on the padded box
+  std::vector<S> u(3 * N), T(N);
+  for (size_t n = 0; n < N; ++n) {
+    for (int a = 0; a < 3; ++a) u[(size_t)a * N + n] = Qv[1 + a][n] / Qv[0][n];
+    S uu = u[n] * u[n] + u[N + n] * u[N + n] + u[2 * N + n] * u[2 * N + n];
+    S p = (g - 1.0) * (Qv[4][n] - 0.5 * Qv[0][n] * uu);
+    T[n] = p / (Qv[0][n] * P.R_gas);
+  }
+  // gradient (central differences, chain rule) of field F at node (i,j,k)
+  auto gradient = [&](const S* F, int i, int j, int k, S out[3]) {
+    const size_t n = b.at(i, j, k);
+    const double Jn = M[9][n];
+    S dxi = 0.5 * (F[b.at(i + 1, j, k)] - F[b.at(i - 1, j, k)]);
+    S deta = 0.5 * (F[b.at(i, j + 1, k)] - F[b.at(i, j - 1, k)]);
+    S dzeta = 0.5 * (F[b.at(i, j, k + 1)] - F[b.at(i, j, k - 1)]);
+    for (int x = 0; x < 3; ++x) out[x] = Jn * (M[0 + x][n] * dxi + M[3 + x][n] * deta + M[6 + x][n] * dzeta);
+  };
+  // strain rate, its deviatoric part and |S| = sqrt(2 S:S) from the
+  // velocity gradient du[a][x]
+  auto strain = [&](S du[3][3], S Sd[3][3], S& mag) {
+    S Sij[3][3], SS = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int x = 0; x < 3; ++x) {
+        Sij[a][x] = 0.5 * (du[a][x] + du[x][a]);
+        SS = SS + Sij[a][x] * Sij[a][x];
+      }
+    S tr = (Sij[0][0] + Sij[1][1] + Sij[2][2]) / 3.0;
+    for (int a = 0; a < 3; ++a)
+      for (int x = 0; x < 3; ++x) Sd[a][x] = Sij[a][x] - (a == x ? tr : S(0.0));
+    mag = s_sqrt(2.0 * SS);
+  };
+  // grid-level fields: F0 = rho, F1..3 = rho u_a, F4 = rho T, F5..10 = rho u_i u_j
+  // (i <= j), F11..13 = rho u_j T (whole box); F14..19 = D^2 rho |S| S^d_ij
+  // (i <= j), F20..22 = D^2 rho |S| dT/dx_j (on [-1, n]^3)
+  const int NF = 23;
+  const int pair[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+  std::vector<S> F((size_t)NF * N, S(0.0));
+  for (size_t n = 0; n < N; ++n) {
+    const S r = Qv[0][n];
+    F[n] = r;
+    for (int a = 0; a < 3; ++a) F[(size_t)(1 + a) * N + n] = Qv[1 + a][n];
+    F[4 * N + n] = r * T[n];
+    for (int q = 0; q < 6; ++q) F[(size_t)(5 + q) * N + n] = r * u[(size_t)pair[q][0] * N + n] * u[(size_t)pair[q][1] * N + n];
+    for (int a = 0; a < 3; ++a) F[(size_t)(11 + a) * N + n] = r * u[(size_t)a * N + n] * T[n];
+  }
+  for (int k = -1; k <= b.nk; ++k)
+    for (int j = -1; j <= b.nj; ++j)
+      for (int i = -1; i <= b.ni; ++i) {
+        const size_t n = b.at(i, j, k);
+        S du[3][3], dT[3], Sd[3][3], mag;
+        for (int a = 0; a < 3; ++a) gradient(&u[(size_t)a * N], i, j, k, du[a]);
+        gradient(T.data(), i, j, k, dT);
+        strain(du, Sd, mag);
+        const double D2 = std::pow(std::cbrt(1.0 / M[9][n]), 2);
+        const S w = D2 * Qv[0][n] * mag;
+        for (int q = 0; q < 6; ++q) F[(size_t)(14 + q) * N + n] = w * Sd[pair[q][0]][pair[q][1]];
+        for (int a = 0; a < 3; ++a) F[(size_t)(20 + a) * N + n] = w * dT[a];
+      }
+  // test filter at node (i,j,k): weights (1/4, 1/2, 1/4) along each index
+  const double wt[3] = {0.25, 0.5, 0.25};
+  auto filt = [&](int f, int i, int j, int k) {
+    S acc = 0.0;
+    for (int c = -1; c <= 1; ++c)
+      for (int bb = -1; bb <= 1; ++bb)
+        for (int a = -1; a <= 1; ++a)
+          acc = acc + (wt[a + 1] * wt[bb + 1] * wt[c + 1]) * F[(size_t)f * N + b.at(i + a, j + bb, k + c)];
+    return acc;
+  };
+  // test-filtered velocity and temperature on [-1, n]^3
+  std::vector<S> ut(3 * N, S(0.0)), Tt(N, S(0.0));
+  for (int k = -1; k <= b.nk; ++k)
+    for (int j = -1; j <= b.nj; ++j)
+      for (int i = -1; i <= b.ni; ++i) {
+        const size_t n = b.at(i, j, k);
+        const S rh = filt(0, i, j, k);
+        for (int a = 0; a < 3; ++a) ut[(size_t)a * N + n] = filt(1 + a, i, j, k) / rh;
+        Tt[n] = filt(4, i, j, k) / rh;
+      }
+  // per-column sums over interior k (ascending) of L^d:M, M:M, K.N, N.N
+  const size_t cols = (size_t)b.pj * b.pi;
+  std::vector<S> nC(cols, S(0.0)), dC(cols, S(0.0)), nD(cols, S(0.0)), dD(cols, S(0.0));
+  for (int j = 0; j < b.nj; ++j)
+    for (int i = 0; i < b.ni; ++i) {
+      const size_t col = (size_t)(j + G) * b.pi + (size_t)(i + G);
+      for (int k = 0; k < b.nk; ++k) {
+        const size_t n = b.at(i, j, k);
+        S fv[NF];
+        for (int f = 0; f < NF; ++f) fv[f] = filt(f, i, j, k);
+        S du[3][3], dT[3], Sd[3][3], mag;
+        for (int a = 0; a < 3; ++a) gradient(&ut[(size_t)a * N], i, j, k, du[a]);
+        gradient(Tt.data(), i, j, k, dT);
+        strain(du, Sd, mag);
+        const double Dt2 = 4.0 * std::pow(std::cbrt(1.0 / M[9][n]), 2);  // (2 D)^2
+        S L[3][3], Mm[3][3];
+        for (int q = 0; q < 6; ++q) {
+          const int a = pair[q][0], c = pair[q][1];
+          L[a][c] = L[c][a] = fv[5 + q] - fv[1 + a] * fv[1 + c] / fv[0];
+          Mm[a][c] = Mm[c][a] = 2.0 * fv[14 + q] - 2.0 * Dt2 * fv[0] * mag * Sd[a][c];
+        }
+        const S tr = (L[0][0] + L[1][1] + L[2][2]) / 3.0;
+        for (int a = 0; a < 3; ++a) L[a][a] = L[a][a] - tr;
+        S lm = 0.0, mm = 0.0, kn = 0.0, nn = 0.0;
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) {
+            lm = lm + L[a][c] * Mm[a][c];
+            mm = mm + Mm[a][c] * Mm[a][c];
+          }
+        for (int a = 0; a < 3; ++a) {
+          const S K = fv[11 + a] - fv[1 + a] * fv[4] / fv[0];
+          const S Nj = fv[20 + a] - Dt2 * fv[0] * mag * dT[a];
+          kn = kn + K * Nj;
+          nn = nn + Nj * Nj;
+        }
+        nC[col] = nC[col] + lm;
+        dC[col] = dC[col] + mm;
+        nD[col] = nD[col] + kn;
+        dD[col] = dD[col] + nn;
+      }
+    }
+  Cc.assign(cols, S(0.0));
+  Dc.assign(cols, S(0.0));
+  for (int j = -G; j < b.nj + G; ++j)
+    for (int i = -G; i < b.ni + G; ++i) {
+      // ghost columns: wrapped (periodic) or nearest interior (Dirichlet) column
+      int ii = i, jj = j;
+      if (i < 0 || i >= b.ni) ii = b.bc[0] == 1 ? std::min(std::max(i, 0), b.ni - 1) : wrap(i, b.ni, b.bc[0]);
+      if (j < 0 || j >= b.nj) jj = b.bc[1] == 1 ? std::min(std::max(j, 0), b.nj - 1) : wrap(j, b.nj, b.bc[1]);
+      const size_t src = (size_t)(jj + G) * b.pi + (size_t)(ii + G), dst = (size_t)(j + G) * b.pi + (size_t)(i + G);
+      Cc[dst] = val(dC[src]) > 0.0 ? s_max(S(0.0), nC[src] / dC[src]) : S(0.0);
+      Dc[dst] = val(dD[src]) > 0.0 ? s_max(S(0.0), nD[src] / dD[src]) : S(0.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Residual R(Q) at interior nodes (R1-R7, R12).  Q must have its ghosts
 // filled.  Everything is computed on the box B1 = [-1, n]^3 with separate
 // arrays for every intermediate.
@@ -535,8 +703,11 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
       }
 
   // --- stress, SGS viscosity and the energy-flux vector Theta on B1 ---
-  // tau[3*a+b] (symmetric), Theta[x] = u_i tau_ix + (kappa + kappa_sgs) dT/dx
-  std::vector<S> tau(9 * N), Theta(3 * N);
+  // tau[3*a+b] (symmetric), Theta[x] = u_i tau_ix + (kappa + kappa_sgs) dT/dx,
+  // pis = sigma_kk / 3 (R18)
+  std::vector<S> Cdyn, Ddyn;
+  if (P.sgs == 2) dynamic_coefficients(b, P, m, Q, Cdyn, Ddyn);
+  std::vector<S> tau(9 * N), Theta(3 * N), pis(N, S(0.0));
 #pragma omp parallel for
   for (int k = -1; k <= b.nk; ++k)
     for (int j = -1; j <= b.nj; ++j)
@@ -549,20 +720,29 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
         for (int a = 0; a < 3; ++a)
           for (int x = 0; x < 3; ++x) Sij[a][x] = 0.5 * (du[a][x] + du[x][a]);
         S Skk = Sij[0][0] + Sij[1][1] + Sij[2][2];
-        S mu_sgs = 0.0;
+        S mu_sgs = 0.0, kap_sgs = 0.0;
         if (P.sgs) {
           S SS = 0.0;
           for (int a = 0; a < 3; ++a)
             for (int x = 0; x < 3; ++x) SS = SS + Sij[a][x] * Sij[a][x];
           S Smag = s_sqrt(2.0 * SS);
           double Delta = std::cbrt(1.0 / M[9][n]);
-          mu_sgs = rho[n] * (P.Cs * Delta) * (P.Cs * Delta) * Smag;
+          if (P.sgs == 1) {
+            mu_sgs = rho[n] * (P.Cs * Delta) * (P.Cs * Delta) * Smag;
+            kap_sgs = mu_sgs * Cp / P.Pr_sgs;
+          } else {  // R17
+            const size_t col = (size_t)(j + G) * b.pi + (size_t)(i + G);
+            mu_sgs = Cdyn[col] * rho[n] * (Delta * Delta) * Smag;
+            kap_sgs = Cp * Ddyn[col] * rho[n] * (Delta * Delta) * Smag;
+          }
+          // R18: sigma_kk / 3 = (2/3) CI rho D^2 |S|^2, |S|^2 = 2 S:S
+          if (P.CI > 0.0) pis[n] = (2.0 / 3.0) * P.CI * rho[n] * (Delta * Delta) * (2.0 * SS);
         }
         S mut = mu[n] + mu_sgs;
         for (int a = 0; a < 3; ++a)
           for (int x = 0; x < 3; ++x)
             tau[(size_t)(3 * a + x) * N + n] = 2.0 * mut * (Sij[a][x] - (a == x ? Skk / 3.0 : S(0.0)));
-        S kap = mu[n] * Cp / P.Pr + mu_sgs * Cp / P.Pr_sgs;
+        S kap = mu[n] * Cp / P.Pr + kap_sgs;
         S uu[3] = {u[n], v[n], w[n]};
         for (int x = 0; x < 3; ++x) {
           S t = 0.0;
@@ -581,12 +761,14 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
         for (int d = 0; d < 3; ++d) {
           double mx = M[3 * d][n], my = M[3 * d + 1][n], mz = M[3 * d + 2][n];
           S U = mx * u[n] + my * v[n] + mz * w[n];
+          // the isotropic SGS stress enters like a pressure (Eq. 1, R18)
+          const S pe = p[n] + pis[n];
           S E[5];
           E[0] = rho[n] * U;
-          E[1] = rho[n] * u[n] * U + mx * p[n];
-          E[2] = rho[n] * v[n] * U + my * p[n];
-          E[3] = rho[n] * w[n] * U + mz * p[n];
-          E[4] = (Qv[4][n] + p[n]) * U;
+          E[1] = rho[n] * u[n] * U + mx * pe;
+          E[2] = rho[n] * v[n] * U + my * pe;
+          E[3] = rho[n] * w[n] * U + mz * pe;
+          E[4] = (Qv[4][n] + pe) * U;
           S Ev[5];
           Ev[0] = 0.0;
           for (int a = 0; a < 3; ++a)
@@ -842,6 +1024,21 @@ void orc_residual_tangent(const orc_dims* d, const orc_params* P, const double* 
     R[n] = r[n].v;
     dR[n] = r[n].d;
   }
+}
+
+// R17: dynamic coefficients of a state (ghosts of a copy filled first);
+// C, D: [(nj+4)(ni+4)] per padded column (i fastest).
+void orc_dynamic_coefficients(const orc_dims* d, const orc_params* P, const double* m, const double* Q, double* C,
+                              double* D) {
+  Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
+  std::vector<double> q(Q, Q + 5 * b.N);
+  fill_ghosts(b, q.data(), 5);
+  std::vector<double> Cc, Dc;
+  dynamic_coefficients(b, *P, m, q.data(), Cc, Dc);
+  std::copy(Cc.begin(), Cc.end(), C);
+  std::copy(Dc.begin(), Dc.end(), D);
 }
 
 double orc_cfl_dt(const orc_dims* d, const orc_params* P, const double* m, const double* Q) {

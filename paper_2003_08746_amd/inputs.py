@@ -47,6 +47,7 @@ def flow_params(**over) -> dict:
         k4=1.0 / 64.0,
         alpha=0.5,
         cfl=0.5,
+        CI=0.0,                # isotropic SGS constant (sigma_kk model); 0 = off
     )
     p.update(over)
     return p

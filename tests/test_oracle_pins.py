@@ -113,11 +113,11 @@ def test_conservation_wavy_smooth(orc):
 # dropped viscous or SGS term, a transposed metric or a wrong chain rule all
 # give an O(1) error that does not converge.
 # ---------------------------------------------------------------------------
-def _mms_errors(orc, grid, ns, prm_over, ls=0.0, exact_over=None):
+def _mms_errors(orc, grid, ns, prm_over, ls=0.0, exact_over=None, cl=0.0, cl_exact=None):
     from tests import mms
     prm = I.flow_params(**(prm_over if exact_over is None else exact_over))
     prim_fn, rhs_fn = mms.exact_rhs(prm["gamma"], prm["R_gas"], prm["mu_ref"], prm["T_ref"], prm["S_suth"],
-                                    prm["Pr"], prm["Pr_sgs"], ls)
+                                    prm["Pr"], prm["Pr_sgs"], ls, cl if cl_exact is None else cl_exact)
     errs = []
     for n in ns:
         if grid == "cart":
@@ -134,6 +134,9 @@ def _mms_errors(orc, grid, ns, prm_over, ls=0.0, exact_over=None):
         over = dict(prm_over)
         if ls > 0:
             over["Cs"] = ls / (2 * math.pi / n)
+            over["sgs"] = 1
+        if cl > 0:  # CI D^2 = cl^2 with D = h on the Cartesian grid
+            over["CI"] = (cl / (2 * math.pi / n)) ** 2
             over["sgs"] = 1
         case = _case(n, n, n, xyz, Q, **over)
         m = orc.metrics(case)
@@ -167,6 +170,28 @@ def test_mms_second_order_sgs(orc):
     errs = _mms_errors(orc, "cart", [16, 32, 64], over, ls=0.3)
     orders = _orders(errs)
     assert (orders[-1] > 1.85).all() and (orders[-1] < 2.2).all(), (errs, orders)
+
+
+@pytest.mark.parametrize("ls", [0.0, 0.3])
+def test_mms_second_order_sigma_kk(orc, ls):
+    """The isotropic SGS stress sigma_kk = 2 CI rho D^2 |S|^2 (Eq. 11, R18)
+    with CI D^2 held at cl^2: an O(1) term of the momentum and energy
+    equations (alone, and with the eddy viscosity) that must converge at
+    second order like the rest; a wrong sign, a lost factor 1/3 or a dropped
+    energy term stalls at O(1)."""
+    over = dict(mu_ref=0.01, sgs=1, Cs=0.0)
+    errs = _mms_errors(orc, "cart", [16, 32, 64], over, ls=ls, cl=0.35)
+    orders = _orders(errs)
+    assert (orders[-1] > 1.85).all() and (orders[-1] < 2.2).all(), (errs, orders)
+
+
+def test_mms_sigma_kk_term_matters(orc):
+    """Control for the test above: the oracle with the sigma_kk term against
+    an exact right-hand side without it stalls at O(1) in the momentum and
+    energy equations while continuity still converges."""
+    errs = _mms_errors(orc, "cart", [32, 64], dict(mu_ref=0.01, sgs=1, Cs=0.0), cl=0.35, cl_exact=0.0)
+    assert (errs[-1][1:] > 0.75 * errs[0][1:]).all(), errs  # second order would give 0.25
+    assert _orders(errs)[0][0] > 1.85, errs
 
 
 def test_mms_heat_flux_sign_matters(orc):
@@ -918,3 +943,99 @@ def test_superposed_tangent_along_physical_directions(orc, axis):
     _, dQs = orc.rk_step_tangent(cs, ms, cs["Q"], vs, dt)
     sc = np.abs(I.interior(dQ)).max()
     assert np.abs(_along(I.interior(dQs), axis, slice(0, n)) - I.interior(dQ)).max() <= 1e-13 * sc
+
+
+# ---------------------------------------------------------------------------
+# Dynamic closure (R17): closed forms on a linear field, invariants
+# ---------------------------------------------------------------------------
+def _linear_field_case(A, b, g, T0, n=(9, 8, 7), rho=1.1):
+    """Unit Cartesian block (x = i, y = j, z = k; D = 1), Dirichlet in every
+    direction with exact ghost values, uniform density, velocity A x + b and
+    temperature g . x + T0."""
+    sh = (n[2] + 4, n[1] + 4, n[0] + 4)
+    xyz = _aniso_grid(*n, 1.0, 1.0, 1.0)
+    x = xyz.reshape(3, -1)
+    u = (np.asarray(A) @ x + np.asarray(b)[:, None]).reshape((3,) + sh)
+    T = (np.asarray(g) @ x + T0).reshape(sh)
+    r = np.full(sh, rho)
+    Q = I.cons_from_prim(r, u[0], u[1], u[2], r * T / I.GAMMA)
+    return _case(*n, xyz, Q, bc=(1, 1, 1), sgs=2, mu_ref=1e-3)
+
+
+_A_LIN = [[-0.351, 0.473, 0.39], [0.322, -0.02, -0.268], [0.302, 0.424, -0.234]]
+_G_LIN = [0.004, -0.006, 0.043]
+
+
+def test_dynamic_closed_form_linear_field(orc):
+    """On a linear velocity and temperature field with uniform density the
+    test filter (weights 1/4, 1/2, 1/4) leaves linear functions unchanged and
+    adds 1/2 per direction to a square, so (D = 1, test width 2):
+      L = (rho/2) A A^T,  M = -6 rho |S| S^d  =>  C = -(A A^T)^d : S^d / (12 |S| S^d : S^d),
+      K = (rho/2) A g,    N = -3 rho |S| g    =>  D_T = -(A g) . g / (6 |S| |g|^2),
+    the same at every column (ghost columns included)."""
+    A, g = np.array(_A_LIN), np.array(_G_LIN)
+    case = _linear_field_case(A, [0.3, -0.1, 0.2], g, 1.0)
+    m = orc.metrics(case)
+    C, D = orc.dynamic_coefficients(case, m, case["Q"])
+    S = 0.5 * (A + A.T)
+    Sd = S - np.trace(S) / 3 * np.eye(3)
+    mag = math.sqrt(2.0 * (S * S).sum())
+    AA = A @ A.T
+    AAd = AA - np.trace(AA) / 3 * np.eye(3)
+    c_want = -(AAd * Sd).sum() / (12.0 * mag * (Sd * Sd).sum())
+    d_want = -(A @ g) @ g / (6.0 * mag * (g @ g))
+    assert c_want > 0.02 and d_want > 0.02  # not the clipped branch
+    np.testing.assert_allclose(C[1:-1, 1:-1], c_want, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(D[1:-1, 1:-1], d_want, rtol=1e-10, atol=0)
+
+
+def test_dynamic_uniform_flow_and_clipping(orc):
+    """A uniform flow has M = N = 0: both coefficients are 0 and the residual
+    vanishes (free stream preserved with the dynamic closure on a curvilinear
+    grid); a linear field whose closed form is negative is clipped to 0."""
+    n = (12, 10, 8)
+    xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
+    Q = I.uniform_state((n[2] + 4, n[1] + 4, n[0] + 4), vel=(0.8, 0.3, -0.2))
+    case = _case(*n, xyz, Q, sgs=2, CI=0.01, mu_ref=1e-3)
+    m = orc.metrics(case)
+    C, D = orc.dynamic_coefficients(case, m, Q)
+    assert np.abs(C).max() == 0.0 and np.abs(D).max() == 0.0
+    R = orc.residual(case, m, Q)
+    assert np.abs(I.interior(R)).max() <= 1e-13 * _inviscid_scale(m, Q)
+    # -A flips the sign of both closed forms (L, K are even in A; M, N odd)
+    neg = _linear_field_case(-np.array(_A_LIN), [0.0, 0.0, 0.0], np.array(_G_LIN), 1.0)
+    C, D = orc.dynamic_coefficients(neg, orc.metrics(neg), neg["Q"])
+    assert np.abs(C).max() == 0.0 and np.abs(D).max() == 0.0
+
+
+def test_dynamic_galilean_invariance(orc):
+    """Germano's identity terms do not change when a uniform velocity is added
+    to the flow (density and temperature kept), so neither do C and D_T; on a
+    periodic box the ghost columns carry the wrapped interior columns."""
+    n = (12, 10, 8)
+    xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
+    Q = I.smooth_state(*n, seed=4, amp=0.15)
+    case = _case(*n, xyz, Q, sgs=2, mu_ref=1e-3)
+    m = orc.metrics(case)
+    C, D = orc.dynamic_coefficients(case, m, Q)
+    assert C[2:-2, 2:-2].max() > 0 and D[2:-2, 2:-2].max() > 0
+    rho = Q[0]
+    u = Q[1:4] / rho
+    p = (I.GAMMA - 1) * (Q[4] - 0.5 * rho * (u * u).sum(0))
+    V = np.array([0.7, -0.4, 0.25])[:, None, None, None]
+    Q2 = I.cons_from_prim(rho, *(u + V), p)
+    C2, D2 = orc.dynamic_coefficients(case, m, Q2)
+    np.testing.assert_allclose(C2, C, rtol=1e-9, atol=1e-12 * np.abs(C).max())
+    np.testing.assert_allclose(D2, D, rtol=1e-9, atol=1e-12 * np.abs(D).max())
+    # ghost columns: periodic wrap in i and j
+    np.testing.assert_array_equal(C[2:-2, 0:2], C[2:-2, -4:-2])
+    np.testing.assert_array_equal(C[0:2, 2:-2], C[-4:-2, 2:-2])
+
+
+def test_dynamic_conservation(orc):
+    """The dynamic closure keeps the telescoping face form: discrete
+    conservation on a periodic curvilinear box, with sigma_kk on."""
+    n = (14, 12, 10)
+    xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
+    Q = I.smooth_state(*n, seed=6, amp=0.15)
+    _conservation(orc, _case(*n, xyz, Q, sgs=2, CI=0.05, mu_ref=1e-3), steps=3)
