@@ -82,6 +82,8 @@ def _load():
     lib.orc_stats.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
     lib.orc_dynamic_coefficients.restype = None
     lib.orc_dynamic_coefficients.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp, _dp]
+    lib.orc_residual_nofill.restype = None
+    lib.orc_residual_nofill.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp]
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_threads.argtypes = [ctypes.c_int]
     lib.orc_rk_scalar.restype = None
@@ -186,6 +188,16 @@ def residual(case, m, Q, prm=None, f=None, i_f=-1) -> np.ndarray:
     fa = None if f is None else _c(f)
     lib.orc_residual(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q), _ptr(fa),
                      int(i_f), _ptr(R))
+    return R
+
+
+def residual_nofill(case, m, Q, prm=None) -> np.ndarray:
+    """R(Q) with Q's ghost layers and axis nodes taken as given (no fill)."""
+    lib = _load()
+    prm = case["params"] if prm is None else prm
+    Q = _c(Q)
+    R = np.zeros_like(Q)
+    lib.orc_residual_nofill(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q), _ptr(R))
     return R
 
 

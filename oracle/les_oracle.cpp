@@ -74,6 +74,23 @@
 //   R18 isotropic part of the SGS stress (Eq. 11), Yoshizawa's model:
 //       sigma_kk = 2 CI rho D^2 |S|^2 (sgs >= 1).  By Eq. 1 it acts as an
 //       added pressure sigma_kk / 3 in the momentum and energy fluxes.
+//   R19 centerline of the O-grid (Sec. 3: a singularity of the coordinate
+//       transformation), bc[1] = 3: node j = 0 lies on the polar axis (every
+//       k there is the same point); the j-hi side is Dirichlet.  k must be
+//       superposed periodic with nk - 1 even.  Ghost (i, -m, k) is the node
+//       across the axis, (i, m, k + (nk - 1)/2).  The axis nodes are not
+//       advanced by the residual (R = 0 there): before every residual
+//       evaluation and after every stage update each takes the conserved
+//       variables of the adjacent ring j = 1 extrapolated at zero order and
+//       averaged over the nk - 1 distinct azimuths.  The metrics give
+//       xi/J = eta/J = 0 on the axis, so the eta node flux and the eta
+//       spectral radius there are 0 (their limits; J itself is infinite).
+//       The fourth difference of the face between the axis and j = 1 takes
+//       the cross-axis value by linear extrapolation, Q(-1) = 2 Q(0) - Q(1),
+//       i.e. d3 = Q(2) - 2 Q(1) + Q(0), so no five-point stencil reaches
+//       across the axis (the pressure sensor, a three-point stencil, keeps
+//       its cross-axis neighbour).  The CFL bound skips the axis nodes.  The
+//       dynamic closure (R17) is not defined there (sgs = 2 refused).
 //   R15 superposed periodic direction (Sec. 3: the first and last azimuthal
 //       points coincide): bc = 2, period n - 1; node n - 1 is node 0 again
 //       (it takes node 0's metrics), ghosts wrap with period n - 1.  A ghost
@@ -156,7 +173,8 @@ extern "C" {
 typedef struct {
   int ni, nj, nk;  // interior points per direction
   int bc[3];       // per direction i, j, k: 0 = periodic, 1 = frozen Dirichlet ghosts,
-                   // 2 = periodic with superposed first and last nodes (R15)
+                   // 2 = periodic with superposed first and last nodes (R15),
+                   // 3 (j only) = polar axis at j = 0, Dirichlet at j-hi (R19)
   // Boundary faces of a Dirichlet direction (R13, R14, R16), in the order i-lo,
   // i-hi, j-lo, j-hi, k-lo, k-hi: 0 = frozen ghosts, 1 = characteristic
   // entrance (R13), 2 = subsonic exit with imposed pressure p_exit (R14),
@@ -198,6 +216,7 @@ struct Box {
   const double* outside;
   const double* m = nullptr;  // metrics, for the face normals (set where faces are applied)
   double gamma = 0.0;
+  bool axis = false;          // R19: j = 0 is the polar axis
   explicit Box(const orc_dims& d) {
     ni = d.ni; nj = d.nj; nk = d.nk;
     bc[0] = d.bc[0]; bc[1] = d.bc[1]; bc[2] = d.bc[2];
@@ -208,7 +227,14 @@ struct Box {
       p_exit[f] = d.p_exit[f];
     }
     outside = d.outside;
+    axis = bc[1] == 3;
+    if (bc[0] == 3 || bc[2] == 3 || (axis && (bc[2] != 2 || (nk - 1) % 2 != 0))) {
+      std::fprintf(stderr, "oracle: the axis (bc 3) is for j only, with k superposed periodic and nk - 1 even\n");
+      std::abort();
+    }
   }
+  // ghost index x along d lies on a Dirichlet side (frozen, or a face rule)
+  bool dirichlet_side(int d, int x) const { return bc[d] == 1 || (bc[d] == 3 && x >= n(d)); }
   bool any_face() const {
     for (int f = 0; f < 6; ++f)
       if (face[f] != 0) return true;
@@ -352,11 +378,12 @@ void fill_faces(const Box& b, S* a) {
     for (int j = -G; j < b.nj + G; ++j)
       for (int i = -G; i < b.ni + G; ++i) {
         const int idx[3] = {i, j, k};
+        if (b.axis && j < 0) continue;  // across the axis: filled from its image (R19)
         int nd = 0, d = -1, w[3];
         for (int e = 0; e < 3; ++e) {
           const int n = b.n(e);
           const bool g = idx[e] < 0 || idx[e] >= n;
-          if (g && b.bc[e] == 1) {
+          if (g && b.dirichlet_side(e, idx[e])) {
             ++nd;
             d = e;
           }
@@ -406,15 +433,43 @@ void fill_ghosts(const Box& b, S* a, int nfields) {
             bool g = idx[d] < 0 || idx[d] >= n;
             if (g) {
               ghost = true;
-              if (b.bc[d] == 1) dirichlet = true;
+              if (b.dirichlet_side(d, idx[d])) dirichlet = true;
             }
             w[d] = g ? wrap(idx[d], n, b.bc[d]) : idx[d];  // R15: only ghost coordinates wrap
           }
-          if (!ghost || dirichlet) continue;
+          if (!ghost || dirichlet || (b.axis && j < 0)) continue;
           q[b.at(i, j, k)] = q[b.at(w[0], w[1], w[2])];
         }
   }
   if (nfields == 5 && b.any_face()) fill_faces(b, a);
+  // R19: a ghost across the axis is the node diametrically opposite
+  if (b.axis) {
+    const int half = (b.nk - 1) / 2;
+    for (int f = 0; f < nfields; ++f) {
+      S* q = a + (size_t)f * b.N;
+      for (int k = -G; k < b.nk + G; ++k)
+        for (int j = -G; j < 0; ++j)
+          for (int i = -G; i < b.ni + G; ++i)
+            q[b.at(i, j, k)] = q[b.at(i, -j, wrap(k + half, b.nk, 2))];
+    }
+  }
+}
+
+// R19: centerline condition on the axis nodes of the interior columns: the
+// azimuthal mean of the adjacent ring j = 1 (zero-order extrapolation, then
+// the average over the nk - 1 distinct azimuths), for every k.
+template <class S>
+void apply_axis(const Box& b, S* a) {
+  if (!b.axis) return;
+  for (int f = 0; f < 5; ++f) {
+    S* q = a + (size_t)f * b.N;
+    for (int i = 0; i < b.ni; ++i) {
+      S sum = 0.0;
+      for (int k = 0; k < b.nk - 1; ++k) sum = sum + q[b.at(i, 1, k)];
+      const S mean = sum / double(b.nk - 1);
+      for (int k = 0; k < b.nk; ++k) q[b.at(i, 0, k)] = mean;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -495,7 +550,7 @@ void metrics(const Box& b, const double* xyz, double* m) {
             int n = b.n(d);
             w[d] = id[d];
             const int top = b.bc[d] == 2 ? n - 1 : n;  // first index that is an image
-            if (b.bc[d] != 1 && (id[d] < 0 || id[d] >= top)) {
+            if (b.bc[d] != 1 && b.bc[d] != 3 && (id[d] < 0 || id[d] >= top)) {
               w[d] = wrap(id[d], n, b.bc[d]);
               any = true;
             }
@@ -706,6 +761,10 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
   // tau[3*a+b] (symmetric), Theta[x] = u_i tau_ix + (kappa + kappa_sgs) dT/dx,
   // pis = sigma_kk / 3 (R18)
   std::vector<S> Cdyn, Ddyn;
+  if (P.sgs == 2 && b.axis) {
+    std::fprintf(stderr, "oracle: the dynamic closure is not defined on the axis (R19)\n");
+    std::abort();
+  }
   if (P.sgs == 2) dynamic_coefficients(b, P, m, Q, Cdyn, Ddyn);
   std::vector<S> tau(9 * N), Theta(3 * N), pis(N, S(0.0));
 #pragma omp parallel for
@@ -776,6 +835,11 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
                         mz * tau[(size_t)(3 * a + 2) * N + n];
           Ev[4] = mx * Theta[n] + my * Theta[N + n] + mz * Theta[2 * N + n];
           for (int q = 0; q < 5; ++q) H[(size_t)(5 * d + q) * N + n] = E[q] - Ev[q];
+          // R19: on the axis xi/J = eta/J = 0 and J is infinite; the node
+          // fluxes are taken as their limits there (0 for eta, the only one an
+          // off-axis residual uses)
+          if (b.axis && j == 0)
+            for (int q = 0; q < 5; ++q) H[(size_t)(5 * d + q) * N + n] = 0.0;
         }
       }
 
@@ -802,6 +866,7 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
           S le = lam[(size_t)((d + 1) % 3) * N + n];
           S lf = lam[(size_t)((d + 2) % 3) * N + n];
           Lam[(size_t)d * N + n] = ld * (1.0 + s_pow(le / ld, P.alpha) + s_pow(lf / ld, P.alpha));
+          if (b.axis && j == 0) Lam[(size_t)d * N + n] = 0.0;  // R19: lam_eta = 0 on the axis
           int di, dj, dk;
           step(d, di, dj, dk);
           S pp = p[b.at(i + di, j + dj, k + dk)], pm = p[b.at(i - di, j - dj, k - dk)];
@@ -831,9 +896,13 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
           S eps2 = P.k2 * s_max(nu[(size_t)d * N + a], nu[(size_t)d * N + bb]);
           S eps4 = s_max(S(0.0), P.k4 - eps2);
           S Lf = 0.5 * (Lam[(size_t)d * N + a] + Lam[(size_t)d * N + bb]);
+          // R19: the face between the axis and j = 1 takes the cross-axis value
+          // by linear extrapolation (no five-point stencil across the axis)
+          const bool axis_face = b.axis && d == 1 && j == 0;
           for (int q = 0; q < 5; ++q) {
             S d1 = Qv[q][bb] - Qv[q][a];
-            S d3 = Qv[q][bp] - 3.0 * Qv[q][bb] + 3.0 * Qv[q][a] - Qv[q][am];
+            S d3 = axis_face ? Qv[q][bp] - 2.0 * Qv[q][bb] + Qv[q][a]
+                             : Qv[q][bp] - 3.0 * Qv[q][bb] + 3.0 * Qv[q][a] - Qv[q][am];
             S D = Lf * (eps2 * d1 - eps4 * d3);
             F[(size_t)(5 * d + q) * N + a] = 0.5 * (H[(size_t)(5 * d + q) * N + a] + H[(size_t)(5 * d + q) * N + bb]) - D;
           }
@@ -854,6 +923,7 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
           s = s + (F[(size_t)(10 + q) * N + n] - F[(size_t)(10 + q) * N + b.at(i, j, k - 1)]);
           S r = M[9][n] * s;
           if (f && i == i_f) r = r - f[((size_t)q * b.nk + k) * b.nj + j];
+          if (b.axis && j == 0) r = 0.0;  // R19: the axis follows the centerline condition
           R[(size_t)q * N + n] = r;
         }
       }
@@ -867,7 +937,7 @@ double cfl_dt(const Box& b, const orc_params& P, const double* m, const double* 
   const double g = P.gamma;
   double best = INFINITY;
   for (int k = 0; k < b.nk; ++k)
-    for (int j = 0; j < b.nj; ++j)
+    for (int j = b.axis ? 1 : 0; j < b.nj; ++j)  // R19: not on the axis
       for (int i = 0; i < b.ni; ++i) {
         size_t n = b.at(i, j, k);
         double rho = Q[n], u = Q[N + n] / rho, v = Q[2 * N + n] / rho, w = Q[3 * N + n] / rho;
@@ -904,9 +974,11 @@ template <class S>
 void rk_step(const Box& b, const orc_params& P, const double* m, S* Q, double dt, const S* f, int i_f,
              double* norms, S* stages) {
   const size_t N = b.N;
+  apply_axis(b, Q);
   fill_ghosts(b, Q, 5);
   std::vector<S> Q0(Q, Q + 5 * N), cur(Q, Q + 5 * N), R(5 * N);
   for (int l = 0; l < 5; ++l) {
+    apply_axis(b, cur.data());
     fill_ghosts(b, cur.data(), 5);
     if (stages) std::copy(cur.begin(), cur.end(), stages + (size_t)l * 5 * N);
     residual(b, P, m, cur.data(), f, i_f, R.data());
@@ -934,6 +1006,7 @@ void rk_step(const Box& b, const orc_params& P, const double* m, S* Q, double dt
           for (int q = 0; q < 5; ++q)
             nxt[(size_t)q * N + n] = Q0[(size_t)q * N + n] - (RK_ALPHA[l] * dt) * R[(size_t)q * N + n];
         }
+    apply_axis(b, nxt.data());  // boundary update after the stage (Alg. 2)
     cur.swap(nxt);
   }
   for (int k = 0; k < b.nk; ++k)
@@ -990,7 +1063,17 @@ void orc_fill_ghosts_faces(const orc_dims* d, const orc_params* P, const double*
   Box b(*d);
   b.m = m;
   b.gamma = P->gamma;
+  apply_axis(b, Q);
   fill_ghosts(b, Q, 5);
+}
+
+// The residual of a state whose ghost layers (and axis nodes) are taken as
+// given, without the ghost fill: for tests of what a stencil reads.
+void orc_residual_nofill(const orc_dims* d, const orc_params* P, const double* m, const double* Q, double* R) {
+  Box b(*d);
+  b.m = m;
+  b.gamma = P->gamma;
+  residual(b, *P, m, Q, (const double*)nullptr, -1, R);
 }
 
 // R of a state (ghosts of a copy are filled first).  f: [5][nk][nj] or NULL.
@@ -1000,6 +1083,7 @@ void orc_residual(const orc_dims* d, const orc_params* P, const double* m, const
   b.m = m;
   b.gamma = P->gamma;
   std::vector<double> q(Q, Q + 5 * b.N);
+  apply_axis(b, q.data());
   fill_ghosts(b, q.data(), 5);
   residual(b, *P, m, q.data(), f, i_f, R);
 }
@@ -1012,6 +1096,7 @@ void orc_residual_tangent(const orc_dims* d, const orc_params* P, const double* 
   b.gamma = P->gamma;
   std::vector<Dual> q(5 * b.N), r(5 * b.N);
   for (size_t n = 0; n < 5 * b.N; ++n) q[n] = Dual(Q[n], dQ ? dQ[n] : 0.0);
+  apply_axis(b, q.data());
   fill_ghosts(b, q.data(), 5);
   std::vector<Dual> fd;
   if (f) {

@@ -174,6 +174,59 @@ def jet_case(ni=256, nj=128, nk=128, seed=0, **kw) -> dict:
 
 
 # ---------------------------------------------------------------------------
+# The paper's cylindrical O-grid (Sec. 3, Fig. 1; Tab. 2: 361 azimuthal
+# points): i axial, j radial from the jet axis (j = 0 on the axis) to the far
+# field, k azimuthal with the first and last points superposed.
+# ---------------------------------------------------------------------------
+def ogrid(ni, nj, nk=361, Lx=7.5, R_far=5.0) -> np.ndarray:
+    """Coordinates (3, nk+4, nj+4, ni+4): x = Lx i / ni, y = r cos(th),
+    z = r sin(th), th = 2 pi k / (nk - 1), with r(j) = R_far s(j / (nj - 1)),
+    s the (odd) tanh-clustered map of the jet grid scaled to s(1) = 1, fine
+    across the shear layer at r = 0.5 D.  Because s is odd, the ghost nodes
+    j = -1, -2 are the points across the axis: (i, -m, k) coincides with
+    (i, m, k + (nk - 1)/2)."""
+    I, J, K = _mesh(ni, nj, nk)
+    t = J / (nj - 1)
+    r = R_far * _cluster(t) / _cluster(np.array([1.0]))[0]
+    th = 2.0 * math.pi * K / (nk - 1)
+    shape = (nk + 4, nj + 4, ni + 4)
+    x = np.broadcast_to(Lx * I / ni, shape)
+    y = np.broadcast_to(r * np.cos(th), shape)
+    z = np.broadcast_to(r * np.sin(th), shape)
+    return np.ascontiguousarray(np.stack([x, y, z]), dtype=np.float64)
+
+
+def ogrid_case(ni=64, nj=48, nk=361, seed=0, Lx=None, R_far=5.0, mach=1.4, R=0.5, theta=0.05, pert=0.01,
+               **kw) -> dict:
+    """A round jet on the O-grid: the tanh profile in r, Crocco-Busemann T,
+    uniform p, 1 % seeded velocity perturbations off the axis (shear-layer
+    envelope).  Axis nodes hold the azimuthal mean of the ring j = 1, the
+    duplicate azimuth k = nk - 1 equals k = 0.  i periodic (an axial shard),
+    j: axis (bc 3) with frozen far-field ghosts at j-hi, k superposed."""
+    Lx = 7.5 * ni / 256 if Lx is None else Lx
+    xyz = ogrid(ni, nj, nk, Lx=Lx, R_far=R_far)
+    r = np.sqrt(xyz[1] ** 2 + xyz[2] ** 2)
+    Uj = mach
+    u = 0.5 * Uj * (np.tanh((R + r) / (2 * theta)) + np.tanh((R - r) / (2 * theta)))
+    sh = u / Uj
+    T = 1.0 + 0.5 * (GAMMA - 1.0) * mach * mach * sh * (1.0 - sh)
+    p = np.full_like(u, 1.0 / GAMMA)
+    rho = p / ((1.0 / GAMMA) * T)
+    env = 4.0 * sh * (1.0 - sh)
+    rng = np.random.default_rng(seed)
+    vel = [u.copy(), np.zeros_like(u), np.zeros_like(u)]
+    inner = (slice(2, nk + 2), slice(3, nj + 2), slice(2, ni + 2))  # j >= 1
+    for c in range(3):
+        vel[c][inner] += pert * Uj * rng.uniform(-1.0, 1.0, size=(nk, nj - 1, ni)) * env[inner]
+    Q = cons_from_prim(rho, vel[0], vel[1], vel[2], p)
+    Q[:, nk + 1] = Q[:, 2]                                # duplicate azimuth
+    Q[:, 2:nk + 2, 2] = Q[:, 2:nk + 1, 3].mean(axis=1)[:, None, :]  # axis: mean of ring j = 1
+    prm = flow_params(**kw)
+    return dict(name=f"ogrid{ni}x{nj}x{nk}", ni=ni, nj=nj, nk=nk, bc=(0, 3, 2), xyz=xyz, Q=Q, params=prm,
+                p_inf=1.0 / GAMMA, period=(Lx, None, None))
+
+
+# ---------------------------------------------------------------------------
 # Generic test grids and states
 # ---------------------------------------------------------------------------
 def wavy_grid(ni, nj, nk, L=(1.0, 1.0, 1.0), amp=0.15, m=1) -> np.ndarray:

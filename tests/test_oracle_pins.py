@@ -1039,3 +1039,103 @@ def test_dynamic_conservation(orc):
     xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
     Q = I.smooth_state(*n, seed=6, amp=0.15)
     _conservation(orc, _case(*n, xyz, Q, sgs=2, CI=0.05, mu_ref=1e-3), steps=3)
+
+
+# ---------------------------------------------------------------------------
+# Centerline of the O-grid (R19; Sec. 3): uniform flow, the azimuthal
+# average, no five-point stencil across the axis, convergence next to it
+# ---------------------------------------------------------------------------
+def test_axis_uniform_flow_preserved(orc):
+    """A uniform flow (with a component across the axis) on the O-grid:
+    the residual vanishes off the axis and steps leave the state unchanged
+    (the azimuthal mean of a uniform ring is the uniform state)."""
+    c = I.ogrid_case(12, 10, 25, seed=1)
+    sh = c["Q"].shape[1:]
+    Q = I.uniform_state(sh, vel=(1.2, 0.3, -0.2))
+    c["Q"] = Q
+    m = orc.metrics(c)
+    R = I.interior(orc.residual(c, m, Q))
+    scale = float(np.nanmax(np.where(np.isfinite(m[9]), np.abs(m[9]), 0)[2:-2, 3:-2, 2:-2]))
+    assert np.abs(R).max() <= 1e-12 * scale, (np.abs(R).max(), scale)
+    Qn = Q
+    for _ in range(3):
+        Qn, _, _, _ = orc.rk_step(c, m, Qn)
+    rel = np.abs(I.interior(Qn) - I.interior(Q)).reshape(5, -1).max(1) / np.abs(I.interior(Q)).reshape(5, -1).max(1)
+    assert rel.max() <= 1e-13, rel
+
+
+def test_axis_centerline_average(orc):
+    """After a step every axis node holds, for each conserved variable, the
+    mean over the nk - 1 distinct azimuths of the ring j = 1 (so that mean is
+    conserved by the condition), the same at every k."""
+    c = I.ogrid_case(10, 8, 21, seed=2)
+    m = orc.metrics(c)
+    Qn, dt, _, _ = orc.rk_step(c, m, c["Q"])
+    Qi = I.interior(Qn)  # (5, nk, nj, ni)
+    nk = c["nk"]
+    ring_mean = Qi[:, :nk - 1, 1, :].mean(axis=1)
+    for k in range(nk):
+        np.testing.assert_allclose(Qi[:, k, 0, :], ring_mean, rtol=1e-14, atol=0)
+        np.testing.assert_array_equal(Qi[:, k, 0, :], Qi[:, 0, 0, :])
+    # the ring itself moved (the test is not vacuous)
+    assert np.abs(Qi[:, :, 1, :] - I.interior(c["Q"])[:, :, 1, :]).max() > 0
+
+
+def _axis_filled(orc, c, m):
+    return orc.fill_ghosts_faces(c, m, c["Q"])
+
+
+@pytest.mark.parametrize("k2", [0.0, 0.25])
+def test_axis_no_five_point_stencil_across(orc, k2):
+    """The residual off the axis does not read the ghost rows across the axis
+    (j = -1, -2) except through the three-point pressure sensor at the axis:
+    with k2 = 0 any change of those rows leaves it bit for bit unchanged; with
+    k2 > 0 a change that keeps their pressure (up to the rounding of
+    rebuilding the state from it) leaves it unchanged to rounding; a pressure
+    change there does reach it (control)."""
+    c = I.ogrid_case(10, 8, 21, seed=3, k2=k2)
+    m = orc.metrics(c)
+    Q = _axis_filled(orc, c, m)
+    R0 = orc.residual_nofill(c, m, Q)
+    rng = np.random.default_rng(7)
+    Q2 = Q.copy()
+    g = (slice(None), slice(None), slice(0, 2), slice(None))  # rows j = -2, -1
+    rho, u, p = Q2[0][g[1:]], Q2[1:4][g] / Q2[0][g[1:]], None
+    g2 = I.GAMMA
+    pr = (g2 - 1) * (Q2[4][g[1:]] - 0.5 * rho * (u * u).sum(0))
+    u2 = u + 0.3 * rng.uniform(-1, 1, u.shape)
+    rho2 = rho * (1 + 0.2 * rng.uniform(-1, 1, rho.shape))
+    p2 = pr if k2 > 0 else pr * (1 + 0.2 * rng.uniform(-1, 1, pr.shape))
+    Q2[g] = I.cons_from_prim(rho2, u2[0], u2[1], u2[2], p2)
+    R2 = orc.residual_nofill(c, m, Q2)
+    off0, off2 = I.interior(R0)[:, :, 1:, :], I.interior(R2)[:, :, 1:, :]
+    if k2 == 0.0:
+        np.testing.assert_array_equal(off2, off0)
+    else:
+        assert np.abs(off2 - off0).max() <= 1e-14 * np.abs(off0).max()
+        Q3 = Q.copy()
+        Q3[4][g[1:]] *= 1.3
+        R3 = orc.residual_nofill(c, m, Q3)
+        assert np.abs(I.interior(R3 - R0)[:, :, 1, :]).max() > 1e-6 * np.abs(off0).max()
+
+
+def test_axis_mms_second_order(orc):
+    """Manufactured solution on the O-grid (periodic axial shard, axis,
+    superposed azimuth; nj x nj x (2 nj + 1)): the residual converges to the
+    exact right-hand side at second order on every ring off the axis,
+    including the ring next to it, with the centerline condition applied."""
+    from tests import mms
+    prm = I.flow_params(mu_ref=0.01, sgs=0)
+    prim_fn, rhs_fn = mms.exact_rhs(prm["gamma"], prm["R_gas"], prm["mu_ref"], prm["T_ref"], prm["S_suth"],
+                                    prm["Pr"], prm["Pr_sgs"], 0.0)
+    errs = []
+    for n in (8, 16, 32):
+        xyz = I.ogrid(n, n, 2 * n + 1, Lx=2 * math.pi, R_far=2.0)
+        Q = I.cons_from_prim(*mms.evaluate(prim_fn, xyz))
+        case = dict(ni=n, nj=n, nk=2 * n + 1, bc=(0, 3, 2), xyz=xyz, Q=Q, params=prm)
+        m = orc.metrics(case)
+        d = np.abs(I.interior(orc.residual(case, m, Q)) - I.interior(mms.evaluate(rhs_fn, xyz)))
+        errs.append([d[:, :, 1:, :].max(), d[:, :, 1, :].max()])
+    errs = np.array(errs)
+    orders = np.log2(errs[:-1] / errs[1:])
+    assert (orders[-1] > 1.7).all() and (orders[0] > 1.2).all(), (errs, orders)
