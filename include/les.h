@@ -152,6 +152,25 @@ int les_get_metrics(les_ctx *ctx, double *dense_out);
  *    over the interior. */
 int les_residual(les_ctx *ctx, double *Q, double *R, double *norms);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual of les_residual, computed by the fused stage kernel, with its
+ * norms reduced through a static device scratch instead of the context's
+ * buffers, and written to device memory.  The call allocates nothing,
+ * frees nothing and never synchronises.
+ * Q: device, library layout, FP64; its ghost layers are filled in place.
+ * R: device, library layout, 16-byte aligned (LES_ERR_ARG otherwise);
+ *    interior written, ghost layers set to 0.
+ * norms_dev: device double[10] or NULL: RMS of R per variable (5) then
+ *    max |R| (5); a non-finite residual shows as NaN there (no status).
+ * Limit: the scratch holds LES_NOALLOC_BLOCKS per-block partials (320 KB
+ *    per GPU, held until the process ends); a context whose stage kernel
+ *    runs more blocks gets LES_ERR_ARG.  Every call on one GPU shares that
+ *    GPU's scratch, so calls that overlap on one GPU (different streams or
+ *    threads) race; calls in one stream's order do not. */
+#define LES_NOALLOC_BLOCKS 4096
+int les_residual_noalloc(les_ctx *ctx, double *Q, double *R, double *norms_dev);
+
 /* Time step dt (CFL rule above) of the interior of Q; dt_out: host. */
 int les_cfl_dt(les_ctx *ctx, const double *Q, double *dt_out);
 

@@ -8,11 +8,41 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "les.h"
 #include "les_debug.h"
 #include "les_launch.hpp"
 #include "les_stage.hpp"
 #include "les_adjoint.hpp"
+
+// Scratch of les_residual_noalloc: LES_NOALLOC_BLOCKS per-block norm
+// partials (10 doubles each) and one flag word.  One copy per GPU, held
+// until the process ends.  Host code never uses this name as an address: the
+// per-device address comes from hipGetSymbolAddress (scratch_on) and is
+// what the kernels get.
+constexpr long long kScratchDoubles = 10LL * LES_NOALLOC_BLOCKS + 32;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static double* g_scratch_at[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch (the device must be current);
+// resolved once per device.
+static hipError_t scratch_on(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_at[device] = (double*)p;
+  }
+  *out = g_scratch_at[device];
+  return hipSuccess;
+}
 
 struct les_ctx {
   les::Layout L;
@@ -39,6 +69,7 @@ struct les_ctx {
   double* outside = nullptr;         // [5][fe] outside state of characteristic faces
   int use_ref = 0;                   // 1: stage through the reference kernel
   int kchunk = 0;                    // k planes per block of the fused kernel
+  double* scratch = nullptr;         // this device's les_residual_noalloc scratch
   // optional HIP-event timing of every stage-kernel launch
   int timing = 0;
   static const int TMAX = 4096;
@@ -237,6 +268,12 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
     delete c;
     return fail(nullptr, LES_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
   }
+  e = scratch_on(c->device, &c->scratch);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, LES_ERR_HIP, "les_create: scratch address on device %d: %s", c->device,
+                hipGetErrorString(e));
+  }
   const size_t fe = (size_t)c->L.fe;
   c->kchunk = les::stage_kchunk(c->L);
   // partials of the reference kernel, the fused kernel and the CFL kernel
@@ -349,6 +386,33 @@ int les_residual(les_ctx* ctx, double* Q, double* R, double* norms) {
   const double cnt = (double)ctx->L.ni * ctx->L.nj * ctx->L.nk;
   HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
   return sync_outputs(ctx, nullptr, norms);
+}
+
+int les_residual_noalloc(les_ctx* ctx, double* Q, double* R, double* norms_dev) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual_noalloc: null context");
+  if (!Q || !R) return fail(ctx, LES_ERR_ARG, "les_residual_noalloc: Q and R must be device pointers");
+  if (Q == R) return fail(ctx, LES_ERR_ARG, "les_residual_noalloc: Q and R must not alias");
+  if (((uintptr_t)R) & 15) return fail(ctx, LES_ERR_ARG, "les_residual_noalloc: R must be 16-byte aligned");
+  if (!ctx->scratch) return fail(ctx, LES_ERR_STATE, "les_residual_noalloc: no scratch on this device");
+  const les::Layout& L = ctx->L;
+  const long long nb = les::stage_blocks(L, ctx->kchunk);
+  if (nb > LES_NOALLOC_BLOCKS)
+    return fail(ctx, LES_ERR_ARG, "les_residual_noalloc: %lld kernel blocks exceed the scratch's %d", nb,
+                LES_NOALLOC_BLOCKS);
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+  HIPCHK(ctx, les::launch_zero(ctx->s, R, 5 * L.fe));
+  const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
+  const les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
+  double* part = norms_dev ? ctx->scratch : nullptr;
+  HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, Q, R, R, nullptr, 1.0, -1.0, part, nullptr));
+  if (norms_dev) {
+    // the flag word after the partials is written but never read: a
+    // non-finite residual shows as NaN in the norms
+    int* flag = (int*)(ctx->scratch + 10LL * LES_NOALLOC_BLOCKS);
+    const double cnt = (double)L.ni * L.nj * L.nk;
+    HIPCHK(ctx, les::launch_norm_final(ctx->s, part, nb, cnt, norms_dev, flag));
+  }
+  return LES_OK;
 }
 
 int les_cfl_dt(les_ctx* ctx, const double* Q, double* dt_out) {

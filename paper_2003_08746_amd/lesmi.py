@@ -28,7 +28,7 @@ LES_FACE_FROZEN, LES_FACE_CHARACTERISTIC, LES_FACE_EXIT, LES_FACE_FARFIELD = 0, 
 
 EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",
             "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_advance", "les_adjoint_step", "les_residual_adjoint",
-            "les_probe_objective", "les_set_face", "les_stats_accumulate",
+            "les_probe_objective", "les_set_face", "les_stats_accumulate", "les_residual_noalloc",
             "les_last_error", "les_last_create_error"]
 
 # fields of les_stats_accumulate, in its order (sums over k of each)
@@ -88,6 +88,8 @@ def lib():
     L.les_set_forcing.argtypes = [_vp, _vp, ctypes.c_int]
     L.les_rk_step.restype = ctypes.c_int
     L.les_rk_step.argtypes = [_vp, _vp, ctypes.c_double, _dp, _dp, _vp]
+    L.les_residual_noalloc.restype = ctypes.c_int
+    L.les_residual_noalloc.argtypes = [_vp, _vp, _vp, _vp]
     L.les_advance.restype = ctypes.c_int
     L.les_advance.argtypes = [_vp, _vp, ctypes.c_int, _dp, _dp]
     L.les_adjoint_step.restype = ctypes.c_int
@@ -200,6 +202,10 @@ def les_rk_step(ctx, Q_ptr, dt=0.0, want_dt=False, want_norms=False, ckpt_ptr=No
     rc = lib().les_rk_step(ctx, Q_ptr, float(dt), ctypes.byref(dto) if want_dt else None, norms, ckpt_ptr)
     _check(rc, ctx, "les_rk_step")
     return (dto.value if want_dt else None), (np.array(norms[:]) if want_norms else None)
+
+
+def les_residual_noalloc(ctx, Q_ptr, R_ptr, norms_dev_ptr=None):
+    _check(lib().les_residual_noalloc(ctx, Q_ptr, R_ptr, norms_dev_ptr), ctx, "les_residual_noalloc")
 
 
 def les_advance(ctx, Q_ptr, nsteps, want_dt=False, want_norms=False):
