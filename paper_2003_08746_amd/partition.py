@@ -1,8 +1,9 @@
 """Balanced partition of the grid into per-process blocks (Sec. 4, Alg. 1).
 
-Along one direction, TotNbPt points go to NbPart parts: every part gets the
-integer quotient, and the first (TotNbPt mod NbPart) parts one point more, so
-that sizes differ by at most one.  The same rule applies to each direction of
+Along one direction, the points go to the parts so that sizes differ by at
+most one and the larger parts come first.  Part p of P over N points is the
+number of points n in [0, N) with n = p (mod P), that is ceil((N - p) / P):
+the round-robin deal of the points, which is balanced by construction.  The same rule applies to each direction of
 a process grid.  A multi-GPU run of this path would size its per-GPU shards
 this way (one block per GPU, halo exchange between neighbours); one GPU runs
 one such shard.
@@ -14,10 +15,7 @@ def part_size(total: int, nparts: int, index: int) -> int:
     `total` points."""
     if total < 0 or nparts < 1 or not 0 <= index < nparts:
         raise ValueError(f"partition: total={total}, nparts={nparts}, index={index}")
-    size = total // nparts
-    if index < total % nparts:
-        size += 1
-    return size
+    return (total - index + nparts - 1) // nparts
 
 
 def part_sizes(total: int, nparts: int) -> list:
