@@ -54,7 +54,7 @@ typedef enum {
 
 typedef enum { LES_FP64 = 0, LES_MIXED = 1 } les_precision;
 
-typedef enum { LES_BC_PERIODIC = 0, LES_BC_DIRICHLET = 1, LES_BC_PERIODIC_SUPERPOSED = 2 } les_bc;
+typedef enum { LES_BC_PERIODIC = 0, LES_BC_DIRICHLET = 1, LES_BC_PERIODIC_SUPERPOSED = 2, LES_BC_AXIS = 3 } les_bc;
 
 /* Treatment of one boundary face of a Dirichlet direction (les_set_face). */
 typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT = 2, LES_FACE_FARFIELD = 3 } les_face_type;
@@ -74,6 +74,24 @@ typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT =
  *                       equal to node 0 when it starts equal (it counts in the
  *                       norms and the statistics).  A ghost takes the node
  *                       reached by wrapping its ghost coordinates only.
+ *   LES_BC_AXIS      -- (j only) the O-grid's centerline (Sec. 3): node j = 0
+ *                       lies on the polar axis, j-hi is a Dirichlet side; k
+ *                       must be LES_BC_PERIODIC_SUPERPOSED with nk - 1 even.
+ *                       Ghost (i, -m, k) is the node across the axis,
+ *                       (i, m, k + (nk-1)/2) (frozen where i is a ghost of a
+ *                       Dirichlet side).  The residual does not advance the
+ *                       axis nodes (R = 0 there); before each residual
+ *                       evaluation and after each stage every axis node takes
+ *                       the mean over k' = 0..nk-2 of the ring (i, 1, k')
+ *                       (zero-order extrapolation, then the azimuthal
+ *                       average), written in place in the caller's state.
+ *                       On the axis xi/J = eta/J = 0 and J is infinite: the
+ *                       eta node flux and spectral radius take their limit 0,
+ *                       and the fourth difference of the face between the
+ *                       axis and j = 1 takes the cross-axis value by linear
+ *                       extrapolation (no five-point stencil across the
+ *                       axis).  The CFL bound skips the axis.  Not with
+ *                       sgs = 2 or the adjoint entry points.
  * xyz: device, dense padded layout [3][nk+4][nj+4][ni+4], coordinates on every
  * node including ghosts and edges (read during les_create only). */
 typedef struct {
@@ -87,7 +105,17 @@ typedef struct {
  *   (kappa_sgs = mu_sgs Cp/Pr_sgs), Sutherland mu = mu_ref (T/T_ref)^1.5
  *   (1+S)/(T/T_ref+S) with S = S1/T_ref (S_suth).
  *   sgs = 0: mu_sgs = 0 (the paper's runs); sgs = 1: static Smagorinsky
- *   mu_sgs = rho (Cs Delta)^2 sqrt(2 S_ij S_ij), Delta = (1/J)^(1/3).
+ *   mu_sgs = rho (Cs Delta)^2 sqrt(2 S_ij S_ij), Delta = (1/J)^(1/3);
+ *   sgs = 2: dynamic closure (Germano's identity with a test filter of width
+ *   2 Delta, weights 1/4, 1/2, 1/4 per index, in the Favre form of Moin,
+ *   Squires, Cabot and Lee; Lilly's least squares summed over the periodic k
+ *   direction, clipped at 0): mu_sgs = C rho Delta^2 |S| and kappa_sgs =
+ *   Cp D_T rho Delta^2 |S| with one C, D_T per (i, j) column, re-evaluated
+ *   with every residual (Pr_sgs and Cs are then unused).
+ *   CI >= 0 (sgs >= 1): Yoshizawa's isotropic SGS stress (Eq. 11)
+ *   sigma_kk = 2 CI rho Delta^2 |S|^2, added as sigma_kk/3 to the pressure of
+ *   the momentum and energy fluxes (Eq. 1); CI = 0 leaves it out.
+ *   The adjoint entry points need sgs <= 1 and CI = 0 (LES_ERR_STATE).
  * Turkel-Vatsa dissipation constants k2, k4 and anisotropy exponent alpha:
  *   D = Lam_face (eps2 dQ - eps4 d3Q), eps2 = k2 max(nu_a, nu_b),
  *   eps4 = max(0, k4 - eps2), nu = |p+ - 2p + p-| / (p+ + 2p + p-),
@@ -107,6 +135,7 @@ typedef struct {
   double k2, k4, alpha;
   double cfl;
   int prec;
+  double CI;
 } les_flow_params;
 
 /* Create a context for one block (Alg. 2: read mesh, compute Jacobian and
@@ -118,8 +147,12 @@ typedef struct {
  * eta_x/J, ..., zeta_z/J, J) may be given instead (grid->xyz is then
  * ignored and may be NULL); it must be valid on all nodes with indices in
  * [-1, n].  hip_stream: a hipStream_t (NULL = default stream).
- * Returns LES_ERR_ARG for a null out/grid/params, n < 5, bad bc, gamma <= 1,
- * R_gas <= 0, Pr <= 0, negative k2/k4/mu_ref, unknown prec. */
+ * Returns LES_ERR_ARG for a null out/grid/params, n < 5, bad bc (LES_BC_AXIS
+ * elsewhere than j, or without a superposed k of odd nk, or with sgs = 2),
+ * gamma <= 1,
+ * R_gas <= 0, Pr <= 0, negative k2/k4/mu_ref/CI, sgs outside 0..2, unknown
+ * prec.  sgs = 2 allocates the dynamic closure's work arrays (50 fields of
+ * field_elems doubles) here. */
 int les_create(les_ctx **out, const les_grid *grid, const double *metrics_dense,
                const les_flow_params *params, void *hip_stream);
 
@@ -277,7 +310,8 @@ int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, do
  *    values become the outside state of every characteristic and far-field
  *    face (copied now; required before the first such face).
  * p_exit: imposed pressure (> 0) of an exit face; ignored otherwise.
- * LES_ERR_ARG for a bad face, type or pressure, or a periodic direction.
+ * LES_ERR_ARG for a bad face, type or pressure, or a face that is not on a
+ * Dirichlet side (face 3, j-hi, is one with LES_BC_AXIS).
  * The adjoint entry points differentiate the face rules (the outside state
  * and p_exit are constants). */
 int les_set_face(les_ctx *ctx, int face, int type, const double *Q_outside, double p_exit);

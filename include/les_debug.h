@@ -36,6 +36,12 @@ int les_debug_stage_time(les_ctx *ctx, double *total_ms, long long *launches);
  * when the launch fails.  Needs no context. */
 int les_debug_stream_copy(const void *src, void *dst, long long nbytes, void *hip_stream);
 
+/* Dynamic SGS closure (sgs = 2): evaluates the per-column coefficients of Q
+ * (its ghost layers filled in place) and copies them to out (device,
+ * 2 (nj+4)(ni+4) doubles: C, then D_T, per padded column (j+2)(ni+4)+(i+2)).
+ * LES_ERR_STATE for a context without the dynamic closure. */
+int les_debug_dynamic_coefficients(les_ctx *ctx, double *Q, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,7 +78,8 @@
 //       transformation), bc[1] = 3: node j = 0 lies on the polar axis (every
 //       k there is the same point); the j-hi side is Dirichlet.  k must be
 //       superposed periodic with nk - 1 even.  Ghost (i, -m, k) is the node
-//       across the axis, (i, m, k + (nk - 1)/2).  The axis nodes are not
+//       across the axis, (i, m, k + (nk - 1)/2) (frozen where i is a ghost of
+//       a Dirichlet side, like other edges).  The axis nodes are not
 //       advanced by the residual (R = 0 there): before every residual
 //       evaluation and after every stage update each takes the conserved
 //       variables of the adjacent ring j = 1 extrapolated at zero order and
@@ -442,15 +443,19 @@ void fill_ghosts(const Box& b, S* a, int nfields) {
         }
   }
   if (nfields == 5 && b.any_face()) fill_faces(b, a);
-  // R19: a ghost across the axis is the node diametrically opposite
+  // R19: a ghost across the axis is the node diametrically opposite (one that
+  // is also a ghost of a Dirichlet i side keeps its given value, like the
+  // other edges of two boundary directions)
   if (b.axis) {
     const int half = (b.nk - 1) / 2;
     for (int f = 0; f < nfields; ++f) {
       S* q = a + (size_t)f * b.N;
       for (int k = -G; k < b.nk + G; ++k)
         for (int j = -G; j < 0; ++j)
-          for (int i = -G; i < b.ni + G; ++i)
+          for (int i = -G; i < b.ni + G; ++i) {
+            if ((i < 0 || i >= b.ni) && b.bc[0] == 1) continue;
             q[b.at(i, j, k)] = q[b.at(i, -j, wrap(k + half, b.nk, 2))];
+          }
     }
   }
 }

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "liblesmi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["les_api.hip", "les_kernels.hip", "les_stage.hip", "les_adjoint.hip"]
+SOURCES = ["les_api.hip", "les_kernels.hip", "les_stage.hip", "les_adjoint.hip", "les_dynamic.hip"]
 
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -15,6 +15,7 @@
 #include "les_launch.hpp"
 #include "les_stage.hpp"
 #include "les_adjoint.hpp"
+#include "les_dynamic.hpp"
 
 // Scratch of les_residual_noalloc: LES_NOALLOC_BLOCKS per-block norm
 // partials (10 doubles each) and one flag word.  One copy per GPU, held
@@ -62,13 +63,17 @@ struct les_ctx {
   double* dthist = nullptr;          // time steps of one les_advance call (LES_ADVANCE_DT_MAX doubles)
   double* scal = nullptr;            // [0] dt, [1..10] norms, [12] dt of the next step (les_advance)
   int* flag = nullptr;               // bit 0: bad dt, bit 1: non-finite norm
+  double* dyn = nullptr;             // dynamic SGS coefficients per column [2][ncol] (sgs == 2)
+  double* dynw = nullptr;            // work arrays of the dynamic closure
   double* adj = nullptr;             // adjoint work arrays
   long long adj_n = 0;
   int face[6] = {0, 0, 0, 0, 0, 0};  // boundary-face types (les_set_face)
   double p_exit[6] = {0, 0, 0, 0, 0, 0};
   double* outside = nullptr;         // [5][fe] outside state of characteristic faces
+  int axis = 0;                      // j = 0 is the polar axis of an O-grid (bc[1] == LES_BC_AXIS)
   int use_ref = 0;                   // 1: stage through the reference kernel
   int kchunk = 0;                    // k planes per block of the fused kernel
+  les::Machine mach;                 // CU and XCD counts of the device
   double* scratch = nullptr;         // this device's les_residual_noalloc scratch
   // optional HIP-event timing of every stage-kernel launch
   int timing = 0;
@@ -129,6 +134,26 @@ static void free_all(les_ctx* c) {
   (void)hipFree(c->scal);
   (void)hipFree(c->flag);
   (void)hipFree(c->adj);
+  (void)hipFree(c->dyn);
+  (void)hipFree(c->dynw);
+}
+
+// Boundary update of an FP64 state before a residual evaluation: the
+// centerline condition on the axis nodes (O-grid), then the ghost layers.
+static hipError_t bc_fill(les_ctx* c, double* Q) {
+  if (c->axis) {
+    hipError_t e = les::launch_axis_avg(c->s, c->L, Q);
+    if (e != hipSuccess) return e;
+  }
+  return les::launch_ghost_fill(c->s, c->L, c->bc, Q, Q, 5, faces_of(c));
+}
+
+// Dynamic SGS coefficients of the state about to be differenced (its
+// ghosts filled), when the context uses the dynamic closure.
+static hipError_t dyn_update(les_ctx* c, const double* Q64, const float* Q32) {
+  if (c->P.sgs != 2) return hipSuccess;
+  return Q32 ? les::launch_dynamic_f32(c->s, c->L, c->bc, c->P, c->M, Q32, c->dynw, c->dyn)
+             : les::launch_dynamic(c->s, c->L, c->bc, c->P, c->M, Q64, c->dynw, c->dyn);
 }
 
 // Resolve recorded event pairs into the running total (synchronises).
@@ -225,13 +250,19 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
       return fail(nullptr, LES_ERR_ARG, "les_create: block too large (%lld elements per field, limit 2^29)", Lc.fe);
   }
   for (int d = 0; d < 3; ++d)
-    if (grid->bc[d] != LES_BC_PERIODIC && grid->bc[d] != LES_BC_DIRICHLET && grid->bc[d] != LES_BC_PERIODIC_SUPERPOSED)
-      return fail(nullptr, LES_ERR_ARG, "les_create: bc[%d] = %d is not a known boundary type", d, grid->bc[d]);
+    if (grid->bc[d] != LES_BC_PERIODIC && grid->bc[d] != LES_BC_DIRICHLET && grid->bc[d] != LES_BC_PERIODIC_SUPERPOSED &&
+        !(d == 1 && grid->bc[d] == LES_BC_AXIS))
+      return fail(nullptr, LES_ERR_ARG, "les_create: bc[%d] = %d is not a known boundary type for that direction", d,
+                  grid->bc[d]);
+  if (grid->bc[1] == LES_BC_AXIS && (grid->bc[2] != LES_BC_PERIODIC_SUPERPOSED || (grid->nk - 1) % 2 != 0))
+    return fail(nullptr, LES_ERR_ARG, "les_create: the axis needs a superposed periodic k direction with nk - 1 even");
+  if (grid->bc[1] == LES_BC_AXIS && prm->sgs == 2)
+    return fail(nullptr, LES_ERR_ARG, "les_create: the dynamic closure is not defined on the axis");
   if (!metrics_dense && !grid->xyz) return fail(nullptr, LES_ERR_ARG, "les_create: need xyz or metrics");
   if (!(prm->gamma > 1.0) || !(prm->R_gas > 0.0) || !(prm->Pr > 0.0) || !(prm->Pr_sgs > 0.0) ||
       !(prm->mu_ref >= 0.0) || !(prm->T_ref > 0.0) || !(prm->S_suth >= 0.0) || !(prm->k2 >= 0.0) ||
       !(prm->k4 >= 0.0) || !(prm->alpha > 0.0) || !(prm->cfl > 0.0) || !(prm->Cs >= 0.0) ||
-      (prm->sgs != 0 && prm->sgs != 1))
+      (prm->sgs != 0 && prm->sgs != 1 && prm->sgs != 2) || !(prm->CI >= 0.0))
     return fail(nullptr, LES_ERR_ARG, "les_create: a flow parameter is out of range");
   if (prm->prec != LES_FP64 && prm->prec != LES_MIXED)
     return fail(nullptr, LES_ERR_ARG, "les_create: unknown precision %d", prm->prec);
@@ -240,6 +271,7 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
   c->err[0] = 0;
   c->L = les::make_layout(grid->ni, grid->nj, grid->nk);
   for (int d = 0; d < 3; ++d) c->bc[d] = grid->bc[d];
+  c->axis = grid->bc[1] == LES_BC_AXIS;
   c->prec = prm->prec;
   c->s = (hipStream_t)hip_stream;
   les::Phys& P = c->P;
@@ -262,6 +294,8 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
   P.cfl = prm->cfl;
   P.nu_fac = fmax(4.0 / 3.0, prm->gamma / prm->Pr);
   P.sgs = prm->sgs;
+  P.CI43 = prm->sgs ? 4.0 / 3.0 * prm->CI : 0.0;
+  P.Cp = Cp;
 
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
@@ -275,10 +309,19 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
                 hipGetErrorString(e));
   }
   const size_t fe = (size_t)c->L.fe;
-  c->kchunk = les::stage_kchunk(c->L);
+  {
+    int cus = 0, xcds = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+      c->mach.cus = cus;
+    if (hipDeviceGetAttribute(&xcds, hipDeviceAttributeNumberOfXccs, c->device) == hipSuccess && xcds > 0)
+      c->mach.xcds = xcds;
+    else
+      c->mach.xcds = 1;
+  }
+  c->kchunk = les::stage_kchunk(c->L, c->mach);
   // partials of the reference kernel, the fused kernel and the CFL kernel
   c->part_n = les::ref_blocks(c->L);
-  const long long sb = les::stage_blocks(c->L, c->kchunk), cb = les::cfl_blocks(c->L);
+  const long long sb = les::stage_blocks(c->L, c->kchunk, c->mach), cb = les::cfl_blocks(c->L);
   if (sb > c->part_n) c->part_n = sb;
   if (cb > c->part_n) c->part_n = cb;
   bool ok = hipMalloc(&c->M, 10 * fe * sizeof(double)) == hipSuccess &&
@@ -291,6 +334,9 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
   if (ok && c->prec == LES_MIXED)
     ok = hipMalloc(&c->Sf[0], 5 * fe * sizeof(float)) == hipSuccess &&
          hipMalloc(&c->Sf[1], 5 * fe * sizeof(float)) == hipSuccess;
+  if (ok && prm->sgs == 2)
+    ok = hipMalloc(&c->dyn, 2 * les::dyn_ncol(c->L) * sizeof(double)) == hipSuccess &&
+         hipMalloc(&c->dynw, les::dynamic_work_elems(c->L) * sizeof(double)) == hipSuccess;
   if (!ok) {
     free_all(c);
     delete c;
@@ -304,6 +350,11 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
         hipMemsetAsync(c->S[1], 0, 5 * fe * sizeof(double), c->s) != hipSuccess ||
         hipMemsetAsync(c->scal, 0, 16 * sizeof(double), c->s) != hipSuccess ||
         hipMemsetAsync(c->flag, 0, sizeof(int), c->s) != hipSuccess) {
+      rc = fail(nullptr, LES_ERR_HIP, "les_create: hipMemsetAsync failed");
+      break;
+    }
+    if (c->dynw && (hipMemsetAsync(c->dynw, 0, les::dynamic_work_elems(c->L) * sizeof(double), c->s) != hipSuccess ||
+                    hipMemsetAsync(c->dyn, 0, 2 * les::dyn_ncol(c->L) * sizeof(double), c->s) != hipSuccess)) {
       rc = fail(nullptr, LES_ERR_HIP, "les_create: hipMemsetAsync failed");
       break;
     }
@@ -366,7 +417,7 @@ int les_residual(les_ctx* ctx, double* Q, double* R, double* norms) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual: null context");
   if (!Q || !R) return fail(ctx, LES_ERR_ARG, "les_residual: Q and R must be device pointers");
   if (Q == R) return fail(ctx, LES_ERR_ARG, "les_residual: Q and R must not alias");
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+  HIPCHK(ctx, bc_fill(ctx, Q));
   const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
   double* part = norms ? ctx->part : nullptr;
   long long nb;
@@ -375,11 +426,14 @@ int les_residual(les_ctx* ctx, double* Q, double* R, double* norms) {
     // 0 + R(Q) at every interior node (and reduces the norms of R)
     const les::Layout& L = ctx->L;
     HIPCHK(ctx, les::launch_zero(ctx->s, R, 5 * L.fe));
-    const les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
+    HIPCHK(ctx, dyn_update(ctx, Q, nullptr));
+    const les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk, ctx->dyn, ctx->axis, ctx->mach};
     HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, Q, R, R, nullptr, 1.0, -1.0, part, nullptr));
-    nb = les::stage_blocks(L, ctx->kchunk);
+    nb = les::stage_blocks(L, ctx->kchunk, ctx->mach);
   } else {
-    HIPCHK(ctx, les::launch_residual_ref(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->f, ctx->i_f, R, part));
+    HIPCHK(ctx, dyn_update(ctx, Q, nullptr));
+    HIPCHK(ctx, les::launch_residual_ref(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->f, ctx->i_f, R, part, ctx->dyn,
+                                         ctx->axis));
     nb = les::ref_blocks(ctx->L);
   }
   if (!norms) return LES_OK;
@@ -395,14 +449,15 @@ int les_residual_noalloc(les_ctx* ctx, double* Q, double* R, double* norms_dev) 
   if (((uintptr_t)R) & 15) return fail(ctx, LES_ERR_ARG, "les_residual_noalloc: R must be 16-byte aligned");
   if (!ctx->scratch) return fail(ctx, LES_ERR_STATE, "les_residual_noalloc: no scratch on this device");
   const les::Layout& L = ctx->L;
-  const long long nb = les::stage_blocks(L, ctx->kchunk);
+  const long long nb = les::stage_blocks(L, ctx->kchunk, ctx->mach);
   if (nb > LES_NOALLOC_BLOCKS)
     return fail(ctx, LES_ERR_ARG, "les_residual_noalloc: %lld kernel blocks exceed the scratch's %d", nb,
                 LES_NOALLOC_BLOCKS);
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+  HIPCHK(ctx, bc_fill(ctx, Q));
   HIPCHK(ctx, les::launch_zero(ctx->s, R, 5 * L.fe));
   const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
-  const les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
+  HIPCHK(ctx, dyn_update(ctx, Q, nullptr));
+  const les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk, ctx->dyn, ctx->axis, ctx->mach};
   double* part = norms_dev ? ctx->scratch : nullptr;
   HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, Q, R, R, nullptr, 1.0, -1.0, part, nullptr));
   if (norms_dev) {
@@ -418,7 +473,8 @@ int les_residual_noalloc(les_ctx* ctx, double* Q, double* R, double* norms_dev) 
 int les_cfl_dt(les_ctx* ctx, const double* Q, double* dt_out) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_cfl_dt: null context");
   if (!Q || !dt_out) return fail(ctx, LES_ERR_ARG, "les_cfl_dt: null pointer");
-  HIPCHK(ctx, les::launch_cfl(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag));
+  HIPCHK(ctx, les::launch_cfl(ctx->s, ctx->L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag, nullptr,
+                              ctx->axis));
   return sync_outputs(ctx, dt_out, nullptr);
 }
 
@@ -446,10 +502,12 @@ static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, doub
   const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
   const double cnt = (double)L.ni * L.nj * L.nk;
   if (ctx->prec == LES_MIXED) {
-    les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
+    les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk, ctx->dyn, ctx->axis, ctx->mach};
     for (int l = 0; l < 5; ++l) {
       const float* in32 = l == 0 ? nullptr : ctx->Sf[(l - 1) & 1];
+      if (l > 0 && ctx->axis) HIPCHK(ctx, les::launch_axis_avg_f32(ctx->s, L, (float*)in32));
       if (l > 0) HIPCHK(ctx, les::launch_ghost_fill_f32(ctx->s, L, ctx->bc, (float*)in32, Q, faces_of(ctx)));
+      HIPCHK(ctx, dyn_update(ctx, l == 0 ? Q : nullptr, in32));
       int trc = timing_begin(ctx);
       if (trc != LES_OK) return trc;
       HIPCHK(ctx, les::launch_stage_mixed(ctx->s, a, l == 0 ? Q : nullptr, in32, Q, l == 4 ? Q : nullptr,
@@ -458,23 +516,26 @@ static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, doub
       trc = timing_end(ctx);
       if (trc != LES_OK) return trc;
     }
-    HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::stage_blocks(L, ctx->kchunk), cnt, ctx->scal + 1, ctx->flag));
+    if (ctx->axis) HIPCHK(ctx, les::launch_axis_avg(ctx->s, L, Q));
+    HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::stage_blocks(L, ctx->kchunk, ctx->mach), cnt, ctx->scal + 1, ctx->flag));
   } else {
     if (stage_ckpt) HIPCHK(ctx, hipMemcpyAsync(stage_ckpt, Q, 5 * fe * sizeof(double), hipMemcpyDeviceToDevice, ctx->s));
     const double* in = stage_ckpt ? stage_ckpt : Q;
     for (int l = 0; l < 5; ++l) {
       double* out = l == 4 ? Q : (stage_ckpt ? stage_ckpt + (size_t)(l + 1) * 5 * fe : ctx->S[l & 1]);
+      if (l > 0 && ctx->axis) HIPCHK(ctx, les::launch_axis_avg(ctx->s, L, (double*)in));
       if (l > 0 || stage_ckpt) HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, (double*)in, Q, 5, faces_of(ctx)));
       // the residual norms of R(Q^n) are always reduced on the device (fused
       // into stage 1); only their copy to the host is optional
       double* part = l == 0 ? ctx->part : nullptr;
+      HIPCHK(ctx, dyn_update(ctx, in, nullptr));
       int trc = timing_begin(ctx);
       if (trc != LES_OK) return trc;
       if (ctx->use_ref) {
         HIPCHK(ctx, les::launch_stage_ref(ctx->s, L, ctx->P, ctx->M, in, Q, out, dtp, dt, les::rk_alpha(l), f,
-                                          ctx->i_f, part));
+                                          ctx->i_f, part, ctx->dyn, ctx->axis));
       } else {
-        les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk};
+        les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk, ctx->dyn, ctx->axis, ctx->mach};
         HIPCHK(ctx, les::launch_stage_fp64(ctx->s, a, in, Q, out, dtp, dt, les::rk_alpha(l), part,
                                            l == 4 ? cpart : nullptr));
       }
@@ -482,7 +543,8 @@ static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, doub
       if (trc != LES_OK) return trc;
       in = out;
     }
-    long long nb = ctx->use_ref ? les::ref_blocks(L) : les::stage_blocks(L, ctx->kchunk);
+    if (ctx->axis) HIPCHK(ctx, les::launch_axis_avg(ctx->s, L, Q));
+    long long nb = ctx->use_ref ? les::ref_blocks(L) : les::stage_blocks(L, ctx->kchunk, ctx->mach);
     HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
   }
   return LES_OK;
@@ -496,10 +558,10 @@ int les_rk_step(les_ctx* ctx, double* Q, double dt, double* dt_out, double* norm
   if (stage_ckpt && ctx->prec != LES_FP64)
     return fail(ctx, LES_ERR_STATE, "les_rk_step: stage checkpoints need an FP64 context");
   les::Layout& L = ctx->L;
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+  HIPCHK(ctx, bc_fill(ctx, Q));
   const double* dtp = nullptr;
   if (!(dt > 0.0)) {
-    HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag));
+    HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag, nullptr, ctx->axis));
     dtp = ctx->scal;
   }
   int rc = step_core(ctx, Q, dtp, dt, stage_ckpt, nullptr);
@@ -518,24 +580,24 @@ int les_advance(les_ctx* ctx, double* Q, int nsteps, double* dt_out, double* nor
   if (dt_out && nsteps > LES_ADVANCE_DT_MAX)
     return fail(ctx, LES_ERR_ARG, "les_advance: dt_out holds at most %d steps (got %d)", LES_ADVANCE_DT_MAX, nsteps);
   les::Layout& L = ctx->L;
-  const long long nb = les::stage_blocks(L, ctx->kchunk);
+  const long long nb = les::stage_blocks(L, ctx->kchunk, ctx->mach);
   // the first step's dt by a pass of its own; each later one was reduced by
   // the last stage of the step before (the state it reads is that stage's
   // output, untouched since)
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+  HIPCHK(ctx, bc_fill(ctx, Q));
   HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag,
-                              dt_out ? ctx->dthist : nullptr));
+                              dt_out ? ctx->dthist : nullptr, ctx->axis));
   for (int n = 0; n < nsteps; ++n) {
     double* dtp = ctx->scal + ((n & 1) ? 12 : 0);
     double* dnext = ctx->scal + ((n & 1) ? 0 : 12);
     const bool more = n + 1 < nsteps;
-    if (n > 0) HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+    if (n > 0) HIPCHK(ctx, bc_fill(ctx, Q));
     int rc = step_core(ctx, Q, dtp, 0.0, nullptr, (more && !ctx->use_ref) ? ctx->cpart : nullptr);
     if (rc != LES_OK) return rc;
     if (!more) break;
     double* rec = dt_out ? ctx->dthist + n + 1 : nullptr;
     if (ctx->use_ref)
-      HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, dnext, ctx->flag, rec));
+      HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, dnext, ctx->flag, rec, ctx->axis));
     else
       HIPCHK(ctx, les::launch_cfl_final(ctx->s, ctx->cpart, nb, ctx->P.cfl, dnext, rec, ctx->flag));
   }
@@ -549,6 +611,9 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
   if (!stage_ckpt || !Qbar) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: stage_ckpt and Qbar are required");
   if (!(dt > 0.0)) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: dt must be > 0 (the step's fixed dt)");
   if (ctx->prec != LES_FP64) return fail(ctx, LES_ERR_STATE, "les_adjoint_step: needs an FP64 context");
+  if (ctx->P.sgs == 2 || ctx->P.CI43 != 0.0 || ctx->axis)
+    return fail(ctx, LES_ERR_STATE, "les_adjoint_step: the adjoint covers the static Smagorinsky model without "
+                                    "the isotropic SGS stress (sgs <= 1, CI = 0) on blocks without the axis");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
   les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
@@ -559,8 +624,8 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
 int les_set_face(les_ctx* ctx, int face, int type, const double* Q_outside, double p_exit) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_set_face: null context");
   if (face < 0 || face > 5) return fail(ctx, LES_ERR_ARG, "les_set_face: face %d outside [0, 6)", face);
-  if (ctx->bc[face / 2] != LES_BC_DIRICHLET)
-    return fail(ctx, LES_ERR_ARG, "les_set_face: face %d is on a periodic direction", face);
+  if (ctx->bc[face / 2] != LES_BC_DIRICHLET && !(face == 3 && ctx->bc[1] == LES_BC_AXIS))
+    return fail(ctx, LES_ERR_ARG, "les_set_face: face %d is not on a Dirichlet side", face);
   if (type != LES_FACE_FROZEN && type != LES_FACE_CHARACTERISTIC && type != LES_FACE_EXIT &&
       type != LES_FACE_FARFIELD)
     return fail(ctx, LES_ERR_ARG, "les_set_face: unknown face type %d", type);
@@ -592,6 +657,9 @@ int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qb
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual_adjoint: null context");
   if (!Q || !Rbar || !Qbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Q, Rbar and Qbar are required");
   if (Qbar == Q || Qbar == Rbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Qbar must not alias Q or Rbar");
+  if (ctx->P.sgs == 2 || ctx->P.CI43 != 0.0 || ctx->axis)
+    return fail(ctx, LES_ERR_STATE, "les_residual_adjoint: the adjoint covers the static Smagorinsky model "
+                                    "without the isotropic SGS stress (sgs <= 1, CI = 0) on blocks without the axis");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
   HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
@@ -640,6 +708,18 @@ int les_debug_stage_time(les_ctx* ctx, double* total_ms, long long* launches) {
   ctx->t_ms = 0.0;
   ctx->t_cnt = 0;
   return rc;
+}
+
+int les_debug_dynamic_coefficients(les_ctx* ctx, double* Q, double* out) {
+  if (!ctx) return LES_ERR_ARG;
+  if (!Q || !out) return fail(ctx, LES_ERR_ARG, "les_debug_dynamic_coefficients: null pointer");
+  if (ctx->P.sgs != 2) return fail(ctx, LES_ERR_STATE, "les_debug_dynamic_coefficients: sgs is not 2");
+  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
+  HIPCHK(ctx, dyn_update(ctx, Q, nullptr));
+  HIPCHK(ctx, hipMemcpyAsync(out, ctx->dyn, 2 * les::dyn_ncol(ctx->L) * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx->s));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->s));
+  return LES_OK;
 }
 
 // Plain device copy of nbytes (a multiple of 16, both pointers 16-byte

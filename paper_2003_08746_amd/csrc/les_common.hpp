@@ -48,10 +48,20 @@ struct Phys {
   double Cs2;  // Cs^2
   double k2, k4, alpha;
   double cfl, nu_fac;  // nu_fac = max(4/3, gamma/Pr)
-  int sgs;
+  int sgs;         // 0 none, 1 static Smagorinsky, 2 dynamic coefficients per column
   int alpha_half;  // alpha == 1/2: Lam_d = lam_d + sqrt(lam_d)(sqrt(lam_e) + sqrt(lam_f))
   double gamma_R;  // gamma * R (c^2 = gamma R T)
+  double CI43;     // (4/3) CI: sigma_kk / 3 = CI43 rho D^2 S_ij S_ij (0 = no isotropic SGS stress)
+  double Cp;
 };
+
+// Per-column dynamic coefficients (sgs == 2): C at dyn[c], D_T at
+// dyn[ncol + c], c = (j + 2)(ni + 4) + (i + 2) for nodes with i, j in
+// [-2, n+1] (ghost columns included).
+__host__ __device__ inline long long dyn_col(const Layout& L, int i, int j) {
+  return (long long)(j + 2) * (L.ni + 4) + (i + 2);
+}
+__host__ __device__ inline long long dyn_ncol(const Layout& L) { return (long long)(L.nj + 4) * (L.ni + 4); }
 
 // Runge-Kutta coefficients of the five-stage scheme.
 __host__ __device__ inline double rk_alpha(int l) {

@@ -113,7 +113,7 @@ __device__ bool face_ghost(const Layout& L, const Faces& F, const int bc[3], con
   const int nn[3] = {L.ni, L.nj, L.nk};
   int nd = 0, d = 0;
   for (int e = 0; e < 3; ++e)
-    if (bc[e] == 1 && (id[e] < 0 || id[e] >= nn[e])) {
+    if ((bc[e] == 1 && (id[e] < 0 || id[e] >= nn[e])) || (bc[e] == 3 && id[e] >= nn[e])) {
       ++nd;
       d = e;
     }
@@ -134,6 +134,27 @@ __device__ bool face_ghost(const Layout& L, const Faces& F, const int bc[3], con
   face_value<double>(type, F.gamma, F.p_exit[2 * d + hi], nv, qr, qo, out);
   for (int c = 0; c < 5; ++c) q[c * L.fe + dst] = (T)out[c];
   return true;
+}
+
+// Source of ghost node id: dir = true for a node outside a Dirichlet side
+// (frozen or a face rule; bc 3 is Dirichlet at j-hi); otherwise w = the node
+// whose value it copies: periodic indices wrapped (period n, or n - 1 when
+// superposed), and across the polar axis (bc 3 at j-lo) the node
+// diametrically opposite, (i, -j, k + (nk - 1)/2), with i and k wrapped into
+// the interior (so the source is never a node the fill writes).
+__device__ inline void ghost_source(const int nn[3], const int bc[3], const int id[3], int w[3], bool& dir) {
+  dir = false;
+  for (int d = 0; d < 3; ++d) {
+    const bool g = id[d] < 0 || id[d] >= nn[d];
+    if (g && (bc[d] == 1 || (bc[d] == 3 && id[d] >= nn[d]))) dir = true;
+    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d]
+         : (g && bc[d] == 2) ? (id[d] + nn[d] - 1) % (nn[d] - 1) : id[d];
+  }
+  if (bc[1] == 3 && id[1] < 0 && !dir) {
+    const int p = nn[2] - 1;
+    w[1] = -id[1];
+    w[2] = (w[2] + p / 2) % p;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -178,14 +199,9 @@ __global__ void k_ghost_fill(Layout L, int bc0, int bc1, int bc2, double* q, con
   const int id[3] = {i, j, k};
   const int nn[3] = {L.ni, L.nj, L.nk};
   const int bc[3] = {bc0, bc1, bc2};
-  bool dir = false;
+  bool dir;
   int w[3];
-  for (int d = 0; d < 3; ++d) {
-    bool g = id[d] < 0 || id[d] >= nn[d];
-    if (g && bc[d] == 1) dir = true;
-    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d]
-         : (g && bc[d] == 2) ? (id[d] + nn[d] - 1) % (nn[d] - 1) : id[d];
-  }
+  ghost_source(nn, bc, id, w, dir);
   const long long dst = L.at(i, j, k);
   if (dir) {
     if (F.any && nf == 5 && face_ghost(L, F, bc, id, w, dst, q)) return;
@@ -233,14 +249,9 @@ __global__ void k_ghost_fill_f32(Layout L, int bc0, int bc1, int bc2, float* __r
   const int id[3] = {i, j, k};
   const int nn[3] = {L.ni, L.nj, L.nk};
   const int bc[3] = {bc0, bc1, bc2};
-  bool dir = false;
+  bool dir;
   int w[3];
-  for (int d = 0; d < 3; ++d) {
-    bool g = id[d] < 0 || id[d] >= nn[d];
-    if (g && bc[d] == 1) dir = true;
-    w[d] = (g && bc[d] == 0) ? (id[d] + nn[d]) % nn[d]
-         : (g && bc[d] == 2) ? (id[d] + nn[d] - 1) % (nn[d] - 1) : id[d];
-  }
+  ghost_source(nn, bc, id, w, dir);
   const long long dst = L.at(i, j, k);
   if (dir) {
     if (F.any && face_ghost(L, F, bc, id, w, dst, q)) return;
@@ -249,6 +260,25 @@ __global__ void k_ghost_fill_f32(Layout L, int bc0, int bc1, int bc2, float* __r
   }
   const long long src = L.at(w[0], w[1], w[2]);
   for (int f = 0; f < 5; ++f) q[f * L.fe + dst] = q[f * L.fe + src];
+}
+
+// ---------------------------------------------------------------------------
+// Centerline of the O-grid (Sec. 3): every axis node (i, 0, k) takes, per
+// conserved variable, the mean of the ring (i, 1, k'), k' = 0 .. nk - 2 (the
+// distinct azimuths; zero-order extrapolation from the adjacent ring, then
+// the azimuthal average).  One thread per (i, variable), summing in
+// ascending k in FP64.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_axis_avg(Layout L, T* __restrict__ q) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 5 * L.ni) return;
+  const int f = t / L.ni, i = t % L.ni;
+  T* a = q + f * L.fe;
+  double sum = 0.0;
+  for (int k = 0; k < L.nk - 1; ++k) sum += (double)a[L.at(i, 1, k)];
+  const T mean = (T)(sum / (double)(L.nk - 1));
+  for (int k = 0; k < L.nk; ++k) a[L.at(i, 0, k)] = mean;
 }
 
 // ---------------------------------------------------------------------------
@@ -264,13 +294,15 @@ __global__ void k_ghost_fill_f32(Layout L, int bc0, int bc1, int bc2, float* __r
 constexpr long long CFL_PARTS = 65536;
 
 __global__ void __launch_bounds__(256) k_cfl_partial(Layout L, Phys P, const double* __restrict__ M,
-                                                     const double* __restrict__ Q, int kc, double* __restrict__ part) {
+                                                     const double* __restrict__ Q, int kc, int jlo,
+                                                     double* __restrict__ part) {
   __shared__ double red[4];
   const int i = blockIdx.x * 64 + threadIdx.x - LEAD;
   const int j = blockIdx.y * 4 + threadIdx.y;
   const int k0 = blockIdx.z * kc, k1 = min(L.nk, k0 + kc);
   double loc = INFINITY;
-  for (int k = k0; k < k1 && i >= 0 && i < L.ni && j < L.nj; ++k) {
+  // (rows j < jlo are skipped: the polar axis, whose nodes the residual does not advance)
+  for (int k = k0; k < k1 && i >= 0 && i < L.ni && j >= jlo && j < L.nj; ++k) {
     long long n = L.at(i, j, k);
     double m9[9];
 #pragma unroll
@@ -320,7 +352,22 @@ struct RefArgs {
   Phys P;
   const double* M;
   const double* Q;
+  const double* dyn;  // per-column dynamic SGS coefficients (P.sgs == 2)
+  int axis;           // j = 0 is the polar axis
 };
+
+// j index of a node given by its element offset
+__device__ inline int ref_j(const Layout& L, long long n) {
+  const long long t = n - L.at(-2, -2, -2);
+  return (int)((t % L.sk) / L.sj) - 2;
+}
+
+// dynamic-coefficient column (dyn_col) of a node given by its element offset
+__device__ inline long long ref_col(const Layout& L, long long n) {
+  const long long t = n - L.at(-2, -2, -2);
+  const long long r = t % L.sk;
+  return (r / L.sj) * (L.ni + 4) + (r % L.sj);
+}
 
 __device__ inline void ref_prim(const RefArgs& A, long long n, double& rho, double& u, double& v, double& w,
                                 double& p, double& tem) {
@@ -334,6 +381,10 @@ __device__ inline long long dstride(const Layout& L, int d) { return d == 0 ? 1L
 // Node flux H_d = inviscid - viscous (Eq. 15) at node n.
 __device__ void ref_node_flux(const RefArgs& A, int d, long long n, double H[5]) {
   const Layout& L = A.L;
+  if (A.axis && ref_j(L, n) == 0) {  // on the axis: the limit (xi/J = eta/J = 0)
+    for (int q = 0; q < 5; ++q) H[q] = 0.0;
+    return;
+  }
   const Phys& P = A.P;
   const long long fe = L.fe;
   double rho, u, v, w, p, tem;
@@ -361,35 +412,46 @@ __device__ void ref_node_flux(const RefArgs& A, int d, long long n, double H[5])
     for (int b = 0; b < 3; ++b) S[a][b] = 0.5 * (g[a][b] + g[b][a]);
   double skk = S[0][0] + S[1][1] + S[2][2];
   double mu = sutherland(tem, P);
-  double mus = 0.0;
+  double mus = 0.0, kaps = 0.0, pis = 0.0;
   if (P.sgs) {
     double ss = 0.0;
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) ss += S[a][b] * S[a][b];
     double delta2 = cbrt(1.0 / J);
     delta2 *= delta2;
-    mus = rho * P.Cs2 * delta2 * sqrt(2.0 * ss);
+    const double rd = rho * delta2 * sqrt(2.0 * ss);
+    if (P.sgs == 1) {
+      mus = P.Cs2 * rd;
+      kaps = mus * P.Cp_over_Prsgs;
+    } else {
+      const long long c = ref_col(L, n);
+      mus = A.dyn[c] * rd;
+      kaps = P.Cp * A.dyn[dyn_ncol(L) + c] * rd;
+    }
+    pis = P.CI43 * rho * delta2 * ss;  // sigma_kk / 3
   }
   const double mt2 = 2.0 * (mu + mus);
   double tau[3][3];
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) tau[a][b] = mt2 * (S[a][b] - (a == b ? skk / 3.0 : 0.0));
-  const double kap = mu * P.Cp_over_Pr + mus * P.Cp_over_Prsgs;
+  const double kap = mu * P.Cp_over_Pr + kaps;
   const double uu[3] = {u, v, w};
   double th[3];
   for (int x = 0; x < 3; ++x) th[x] = uu[0] * tau[0][x] + uu[1] * tau[1][x] + uu[2] * tau[2][x] + kap * g[3][x];
   const double mx = m[3 * d], my = m[3 * d + 1], mz = m[3 * d + 2];
   const double U = mx * u + my * v + mz * w;
+  const double pe = p + pis;  // the isotropic SGS stress enters like a pressure
   H[0] = rho * U;
-  H[1] = rho * u * U + mx * p - (mx * tau[0][0] + my * tau[0][1] + mz * tau[0][2]);
-  H[2] = rho * v * U + my * p - (mx * tau[1][0] + my * tau[1][1] + mz * tau[1][2]);
-  H[3] = rho * w * U + mz * p - (mx * tau[2][0] + my * tau[2][1] + mz * tau[2][2]);
-  H[4] = (A.Q[4 * fe + n] + p) * U - (mx * th[0] + my * th[1] + mz * th[2]);
+  H[1] = rho * u * U + mx * pe - (mx * tau[0][0] + my * tau[0][1] + mz * tau[0][2]);
+  H[2] = rho * v * U + my * pe - (mx * tau[1][0] + my * tau[1][1] + mz * tau[1][2]);
+  H[3] = rho * w * U + mz * pe - (mx * tau[2][0] + my * tau[2][1] + mz * tau[2][2]);
+  H[4] = (A.Q[4 * fe + n] + pe) * U - (mx * th[0] + my * th[1] + mz * th[2]);
 }
 
 // Lambda_d (anisotropic spectral radius) and pressure at node n.
 __device__ double ref_Lambda(const RefArgs& A, int d, long long n) {
   const long long fe = A.L.fe;
+  if (A.axis && ref_j(A.L, n) == 0) return 0.0;  // lam_eta = 0 on the axis
   double rho, u, v, w, p, tem;
   ref_prim(A, n, rho, u, v, w, p, tem);
   double c = sqrt(A.P.gamma * p / rho);
@@ -416,16 +478,23 @@ __device__ void ref_face_diss(const RefArgs& A, int d, long long a, double D[5])
   const double e2 = A.P.k2 * tmax(nua, nub);
   const double e4 = tmax(0.0, A.P.k4 - e2);
   const double Lf = 0.5 * (ref_Lambda(A, d, a) + ref_Lambda(A, d, a + s));
+  // the face between the axis and j = 1: cross-axis value by linear extrapolation
+  const bool axf = A.axis && d == 1 && ref_j(A.L, a) == 0;
   for (int q = 0; q < 5; ++q) {
     const double* Qq = A.Q + q * fe;
     double d1 = Qq[a + s] - Qq[a];
-    double d3 = Qq[a + 2 * s] - 3.0 * Qq[a + s] + 3.0 * Qq[a] - Qq[a - s];
+    double d3 = axf ? Qq[a + 2 * s] - 2.0 * Qq[a + s] + Qq[a]
+                    : Qq[a + 2 * s] - 3.0 * Qq[a + s] + 3.0 * Qq[a] - Qq[a - s];
     D[q] = Lf * (e2 * d1 - e4 * d3);
   }
 }
 
 __device__ void ref_residual(const RefArgs& A, int i, int j, int k, const double* f, int i_f, double R[5]) {
   const long long n = A.L.at(i, j, k);
+  if (A.axis && j == 0) {  // the axis follows the centerline condition
+    for (int q = 0; q < 5; ++q) R[q] = 0.0;
+    return;
+  }
   double acc[5] = {0, 0, 0, 0, 0};
   for (int d = 0; d < 3; ++d) {
     const long long s = dstride(A.L, d);
@@ -725,11 +794,21 @@ long long cfl_blocks(const Layout& L) {
 }
 
 hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
-                      double* dt_out, int* flag, double* also) {
+                      double* dt_out, int* flag, double* also, int axis) {
   const int kc = cfl_kc(L);
   dim3 g(nblk(L.ni + LEAD, 64), nblk(L.nj, 4), nblk(L.nk, kc)), b(64, 4);
-  k_cfl_partial<<<g, b, 0, s>>>(L, P, M, Q, kc, part);
+  k_cfl_partial<<<g, b, 0, s>>>(L, P, M, Q, kc, axis ? 1 : 0, part);
   k_cfl_final<<<1, 1024, 0, s>>>(part, cfl_blocks(L), P.cfl, dt_out, also, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_axis_avg(hipStream_t s, const Layout& L, double* q) {
+  k_axis_avg<double><<<nblk(5LL * L.ni, 256), 256, 0, s>>>(L, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_axis_avg_f32(hipStream_t s, const Layout& L, float* q) {
+  k_axis_avg<float><<<nblk(5LL * L.ni, 256), 256, 0, s>>>(L, q);
   return hipGetLastError();
 }
 
@@ -740,18 +819,18 @@ hipError_t launch_cfl_final(hipStream_t s, const double* part, long long np, dou
 }
 
 hipError_t launch_residual_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q,
-                               const double* f, int i_f, double* R, double* part) {
+                               const double* f, int i_f, double* R, double* part, const double* dyn, int axis) {
   dim3 g(nblk(L.ni, 64), nblk(L.nj, 4), L.nk), b(64, 4);
-  RefArgs A{L, P, M, Q};
+  RefArgs A{L, P, M, Q, dyn, axis};
   k_residual_ref<<<g, b, 0, s>>>(A, f, i_f, R, part);
   return hipGetLastError();
 }
 
 hipError_t launch_stage_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Qin,
                             const double* Q0, double* Qout, const double* dtp, double dt, double alpha,
-                            const double* f, int i_f, double* part) {
+                            const double* f, int i_f, double* part, const double* dyn, int axis) {
   dim3 g(nblk(L.ni, 64), nblk(L.nj, 4), L.nk), b(64, 4);
-  RefArgs A{L, P, M, Qin};
+  RefArgs A{L, P, M, Qin, dyn, axis};
   k_stage_ref<<<g, b, 0, s>>>(A, Q0, Qout, dtp, dt, alpha, f, i_f, part);
   return hipGetLastError();
 }

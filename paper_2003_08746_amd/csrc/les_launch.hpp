@@ -23,17 +23,21 @@ hipError_t launch_stream_copy(hipStream_t s, const void* src, void* dst, long lo
 long long ref_blocks(const Layout& L);
 // partials written by the CFL kernel
 long long cfl_blocks(const Layout& L);
-// dt of the interior of Q into *dt_out (and *also when not null)
+// dt of the interior of Q into *dt_out (and *also when not null); axis != 0:
+// the polar axis (j = 0) is left out
 hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q, double* part,
-                      double* dt_out, int* flag, double* also = nullptr);
+                      double* dt_out, int* flag, double* also = nullptr, int axis = 0);
+// centerline condition on the axis nodes (j = 0) of a state
+hipError_t launch_axis_avg(hipStream_t s, const Layout& L, double* q);
+hipError_t launch_axis_avg_f32(hipStream_t s, const Layout& L, float* q);
 // dt = cfl * min of np per-block CFL bounds (e.g. the stage kernel's)
 hipError_t launch_cfl_final(hipStream_t s, const double* part, long long np, double cfl, double* dt_out,
                             double* also, int* flag);
 hipError_t launch_residual_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Q,
-                               const double* f, int i_f, double* R, double* part);
+                               const double* f, int i_f, double* R, double* part, const double* dyn, int axis);
 hipError_t launch_stage_ref(hipStream_t s, const Layout& L, const Phys& P, const double* M, const double* Qin,
                             const double* Q0, double* Qout, const double* dtp, double dt, double alpha,
-                            const double* f, int i_f, double* part);
+                            const double* f, int i_f, double* part, const double* dyn, int axis);
 hipError_t launch_norm_final(hipStream_t s, const double* part, long long np, double count, double* norms, int* flag);
 hipError_t launch_probe(hipStream_t s, const Layout& L, const Phys& P, const double* Q, int i_p, double p_inf,
                         double weight, double* Jacc, double* Qbar, double* part);

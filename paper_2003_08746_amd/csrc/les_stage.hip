@@ -10,7 +10,7 @@
 //
 // Decomposition.  A block of 32 x 16 threads owns the nodes of a 32 x 16
 // patch of one k-plane: the 30 x 14 output tile and a one-node halo ring.
-// Blocks are persistent (one per CU): block v marches a contiguous range of
+// Blocks are persistent (one per CU of the device): block v marches a contiguous range of
 // (tile, k) planes in chunk-major order (k chunks as long as one block's
 // range, tiles within a chunk, planes within a tile), so the blocks that
 // run together on one XCD start on neighbouring tiles at the same plane and
@@ -100,6 +100,8 @@ struct KArgs {
   Phys P;
   const double* M;
   const double* f;
+  const double* dyn;    // per-column dynamic SGS coefficients (P.sgs == 2)
+  int axis;             // j = 0 is the polar axis
   int i_f;
   int ntx, nty;         // tiles in i, j
   long long total;      // tile-planes = ntx * nty * nk
@@ -109,6 +111,7 @@ struct KArgs {
   long long nseg;       // segments in round-robin mode
   int nblocks;          // blocks with work
   int per_xcd;          // blocks per XCD in the remapped order
+  int nxcd;             // XCDs of the device
 };
 
 // The FP32 path has the LDS for two Q planes (written at B of alternate
@@ -217,7 +220,7 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <class T, class QI, bool NORM, bool CFL>
+template <class T, class QI, bool NORM, bool CFL, bool EXT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) k_stage(KArgs a, const QI* __restrict__ Qin, const double* Q0, double* Qout,
                                               float* Qsh, const double* __restrict__ dtp, double dt_host,
                                               double alpha, double* __restrict__ part, double* __restrict__ cpart) {
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 
   // XCD-aware order: consecutive virtual blocks land on one XCD.
   const int hb = blockIdx.x;
-  const int v = (hb & 7) * a.per_xcd + (hb >> 3);
+  const int v = (hb % a.nxcd) * a.per_xcd + hb / a.nxcd;
   if (v >= a.nblocks) return;
   // contiguous mode: tile-planes [w_begin, w_end) of the chunk-major order;
   // round-robin mode: segments v, v + nblocks, v + 2 nblocks, ...
@@ -445,22 +448,33 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
         const T u = s.u[ey][ex], vv = s.v[ey][ex], w = s.w[ey][ex];
         const T tn = s.tem[ey][ex];
         const T mu = sutherland_fast(tn, P);
-        T mus = T(0);
+        T mus = T(0), kaps = T(0), pis = T(0);
         if (P.sgs) {
           const T ss = s11 * s11 + s22 * s22 + s33 * s33 + T(2) * (s12 * s12 + s13 * s13 + s23 * s23);
           T d2 = (T)icbrt(Jn);  // (1/J)^(1/3)
           d2 *= d2;
-          mus = rho * T(P.Cs2) * d2 * sqrt_nn(T(2) * ss);
+          const T rd = rho * d2 * sqrt_nn(T(2) * ss);
+          if (!EXT || P.sgs == 1) {
+            mus = T(P.Cs2) * rd;
+            kaps = mus * T(P.Cp_over_Prsgs);
+          } else {  // dynamic coefficients of this column
+            const long long cc = dyn_col(kq->L, i, j);
+            mus = T(kq->dyn[cc]) * rd;
+            kaps = T(P.Cp) * T(kq->dyn[dyn_ncol(kq->L) + cc]) * rd;
+          }
+          // isotropic SGS stress: sigma_kk / 3, added to the pressure of the fluxes
+          if (EXT && P.CI43 != 0.0) pis = T(P.CI43) * rho * d2 * ss;
         }
         const T mt2 = T(2) * (mu + mus);
         const T t11 = mt2 * (s11 - skk3), t22 = mt2 * (s22 - skk3), t33 = mt2 * (s33 - skk3);
         const T t12 = mt2 * s12, t13 = mt2 * s13, t23 = mt2 * s23;
-        const T kap = mu * T(P.Cp_over_Pr) + mus * T(P.Cp_over_Prsgs);
+        const T kap = mu * T(P.Cp_over_Pr) + kaps;
         const T th0 = u * t11 + vv * t12 + w * t13 + kap * g[3][0];
         const T th1 = u * t12 + vv * t22 + w * t23 + kap * g[3][1];
         const T th2 = u * t13 + vv * t23 + w * t33 + kap * g[3][2];
         __builtin_amdgcn_sched_barrier(0);
         const T p = s.p[ey][ex];
+        const T pe = EXT ? p + pis : p;  // pressure of the fluxes
         const T c2 = T(P.gamma_R) * tn;  // c^2 = gamma p / rho = gamma R T
         // spectral radii of the three directions and their square roots
         T lam[3], U[3], sl[3];
@@ -480,10 +494,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
           const T mx = mt[3 * e], my = mt[3 * e + 1], mz = mt[3 * e + 2];
           const T Ue = U[e];
           H[0] = rho * Ue;
-          H[1] = sq[1][ey][ex] * Ue + mx * p - (mx * t11 + my * t12 + mz * t13);
-          H[2] = sq[2][ey][ex] * Ue + my * p - (mx * t12 + my * t22 + mz * t23);
-          H[3] = sq[3][ey][ex] * Ue + mz * p - (mx * t13 + my * t23 + mz * t33);
-          H[4] = (sq[4][ey][ex] + p) * Ue - (mx * th0 + my * th1 + mz * th2);
+          H[1] = sq[1][ey][ex] * Ue + mx * pe - (mx * t11 + my * t12 + mz * t13);
+          H[2] = sq[2][ey][ex] * Ue + my * pe - (mx * t12 + my * t22 + mz * t23);
+          H[3] = sq[3][ey][ex] * Ue + mz * pe - (mx * t13 + my * t23 + mz * t33);
+          H[4] = (sq[4][ey][ex] + pe) * Ue - (mx * th0 + my * th1 + mz * th2);
         };
         __builtin_amdgcn_sched_barrier(0);
         if (nx_t) {
@@ -499,9 +513,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
         if (ny_t) {
           T H[5];
           node_flux(1, H);
+          // on the polar axis eta/J = 0: the eta node flux and radius take
+          // their limit 0 (J is infinite there)
+          const bool on_axis = EXT && kq->axis && j == 0;
 #pragma unroll
-          for (int q = 0; q < 5; ++q) s.hy[q][ty][tx - 1] = H[q];
-          s.ly[ty][tx - 1] = aniso_n(1, 2, 0);
+          for (int q = 0; q < 5; ++q) s.hy[q][ty][tx - 1] = on_axis ? T(0) : H[q];
+          s.ly[ty][tx - 1] = on_axis ? T(0) : aniso_n(1, 2, 0);
           const T pa = s.p[ey + 1][ex], pb = s.p[ey - 1][ex];
           s.ny[ty][tx - 1] = fabs(pa - T(2) * p + pb) * rcp_nr(pa + T(2) * p + pb);
         }
@@ -553,6 +570,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
             q_a[c] = sq[c][ey - 2][ex]; q_b[c] = sq[c][ey - 1][ex];
             q_d[c] = sq[c][ey + 1][ex]; q_e[c] = sq[c][ey + 2][ex];
           }
+          // the face between the axis and j = 1 takes the cross-axis value by
+          // linear extrapolation: no five-point stencil across the axis
+          if (EXT && kq->axis && j == 1) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) q_a[c] = T(2) * q_b[c] - q_c[c];
+          }
           face_diss(P, s.ly[ty][cx], s.ly[ty + 1][cx], s.ny[ty][cx], s.ny[ty + 1][cx], q_b, q_c, q_d, q_e, D1);
           face_diss(P, s.ly[ty - 1][cx], s.ly[ty][cx], s.ny[ty - 1][cx], s.ny[ty][cx], q_a, q_b, q_c, q_d, D0);
 #pragma unroll
@@ -582,10 +605,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
             const int k = t - 1;
             const unsigned n = nt - sk;
             double qnv[5];
+            const bool on_axis = EXT && kq->axis && j == 0;  // advanced by the centerline condition
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
               double R = J_prev * (double)(racc[c] + fz[c]);
               if (kq->f && i == kq->i_f) R -= kq->f[((long long)c * kq->L.nk + k) * kq->L.nj + j];
+              if (on_axis) R = 0.0;
               const double qn = q0v[c] - adt * R;
               qnv[c] = qn;
               if (Qout) sto(Qout + c * fe, n, qn);
@@ -596,7 +621,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
                 nm[c] = (a > nm[c] || a != a) ? a : nm[c];  // NaN wins so that it is reported
               }
             }
-            if (CFL) cmin = min_nan(cmin, cfl_local(qnv[0], qnv[1], qnv[2], qnv[3], qnv[4], J_prev, cm, kq->P));
+            if (CFL && !on_axis) cmin = min_nan(cmin, cfl_local(qnv[0], qnv[1], qnv[2], qnv[3], qnv[4], J_prev, cm, kq->P));
           }
 #pragma unroll
           for (int c = 0; c < 5; ++c) racc[c] = r[c] - fz[c];
@@ -657,19 +682,20 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 
 // Stage kernel configuration for a layout.
 struct Config {
-  int ntx, nty, nblocks, grid, per_xcd, kc, rr;
+  int ntx, nty, nblocks, grid, per_xcd, kc, rr, nxcd;
   long long total, per_block, nseg;
 };
 
-long long auto_per_block(const Layout& L) {
+long long auto_per_block(const Layout& L, const Machine& m) {
   const long long tiles = (long long)((L.ni + TX - 1) / TX) * ((L.nj + TY - 1) / TY);
   const long long total = tiles * L.nk;
   // one persistent block per resident slot (BPC per CU), at least 8 planes each
-  long long pb = (total + 256 * BPC - 1) / (256 * BPC);
+  const long long slots = (long long)m.cus * BPC;
+  long long pb = (total + slots - 1) / slots;
   return pb < 8 ? 8 : pb;
 }
 
-Config config(const Layout& L, long long per_block) {
+Config config(const Layout& L, long long per_block, const Machine& m) {
   Config c;
   c.ntx = (L.ni + TX - 1) / TX;
   c.nty = (L.nj + TY - 1) / TY;
@@ -702,8 +728,11 @@ Config config(const Layout& L, long long per_block) {
       }
     }
   }
-  c.per_xcd = (c.nblocks + 7) / 8;
-  c.grid = c.per_xcd * 8;
+  // hardware block b runs on XCD b mod xcds: virtual block (b mod xcds)
+  // per_xcd + b / xcds, so consecutive virtual blocks share an XCD
+  c.nxcd = m.xcds;
+  c.per_xcd = (c.nblocks + c.nxcd - 1) / c.nxcd;
+  c.grid = c.per_xcd * c.nxcd;
   return c;
 }
 
@@ -711,27 +740,40 @@ template <class T, class QI>
 hipError_t launch(hipStream_t st, const StageArgs& sa, const QI* Qin, const double* Q0, double* Qout, float* Qsh,
                   const double* dtp, double dt, double alpha, double* part, double* cpart) {
   if (part && cpart) return hipErrorInvalidValue;  // norms belong to stage 1, the CFL bound to stage 5
-  Config c = config(sa.L, sa.kchunk);
-  KArgs a{sa.L,        sa.P,   sa.M,   sa.f,      sa.i_f,    c.ntx,    c.nty,
-          c.total,     c.per_block, c.kc, c.rr, c.nseg, c.nblocks, c.per_xcd};
-  if (part)
-    k_stage<T, QI, true, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
-  else if (cpart)
-    k_stage<T, QI, false, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
-  else
-    k_stage<T, QI, false, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  Config c = config(sa.L, sa.kchunk, sa.mach);
+  KArgs a{sa.L,        sa.P,   sa.M,   sa.f,   sa.dyn,  sa.axis,  sa.i_f,    c.ntx,    c.nty,
+          c.total,     c.per_block, c.kc, c.rr, c.nseg, c.nblocks, c.per_xcd, c.nxcd};
+  // the dynamic closure, the isotropic SGS stress and the polar axis run in
+  // their own instantiations, so the default path keeps its register budget
+  const bool x = sa.P.sgs == 2 || sa.P.CI43 != 0.0 || sa.axis;
+  if (x && sa.P.sgs == 2 && !sa.dyn) return hipErrorInvalidValue;
+  if (x) {
+    if (part)
+      k_stage<T, QI, true, false, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+    else if (cpart)
+      k_stage<T, QI, false, true, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+    else
+      k_stage<T, QI, false, false, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  } else {
+    if (part)
+      k_stage<T, QI, true, false, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+    else if (cpart)
+      k_stage<T, QI, false, true, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+    else
+      k_stage<T, QI, false, false, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-int stage_kchunk(const Layout& L) {
+int stage_kchunk(const Layout& L, const Machine& m) {
   const char* env = getenv("LES_SEG");
   if (env && atoi(env) > 0) return atoi(env);
-  return (int)auto_per_block(L);
+  return (int)auto_per_block(L, m);
 }
 
-long long stage_blocks(const Layout& L, int kchunk) { return config(L, kchunk).nblocks; }
+long long stage_blocks(const Layout& L, int kchunk, const Machine& m) { return config(L, kchunk, m).nblocks; }
 
 hipError_t launch_stage_fp64(hipStream_t s, const StageArgs& a, const double* Qin, const double* Q0, double* Qout,
                              const double* dtp, double dt, double alpha, double* part, double* cpart) {

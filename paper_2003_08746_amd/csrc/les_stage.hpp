@@ -4,6 +4,14 @@
 
 namespace les {
 
+// The device's compute-unit and XCD (accelerator complex die) counts: the
+// persistent stage kernel runs one block per CU and maps consecutive blocks
+// to one XCD (each XCD has its own L2).
+struct Machine {
+  int cus = 256;
+  int xcds = 8;
+};
+
 struct StageArgs {
   Layout L;
   Phys P;
@@ -11,14 +19,17 @@ struct StageArgs {
   const double* f;  // source [5][nk][nj] or null
   int i_f;
   int kchunk;       // k planes per block (from stage_kchunk, fixed per context)
+  const double* dyn = nullptr;  // dynamic SGS coefficients per column (P.sgs == 2)
+  int axis = 0;                 // j = 0 is the polar axis of an O-grid
+  Machine mach;
 };
 
 // k planes per block of the fused kernel for this layout (LES_SEG in
 // the environment overrides the automatic choice; read once per context).
-int stage_kchunk(const Layout& L);
+int stage_kchunk(const Layout& L, const Machine& m);
 
 // Number of per-block norm partials written by one fused stage launch.
-long long stage_blocks(const Layout& L, int kchunk);
+long long stage_blocks(const Layout& L, int kchunk, const Machine& m);
 
 // One FP64 stage: Qout = Q0 - alpha dt R(Qin) on the interior (Qin's ghosts
 // already filled).  dtp (device) overrides dt when non-null.  part: norm

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "liblesmi.so")
 
 LES_OK, LES_ERR_ARG, LES_ERR_HIP, LES_ERR_NOMEM, LES_ERR_NONFINITE, LES_ERR_STATE = 0, -1, -2, -3, -4, -5
 LES_FP64, LES_MIXED = 0, 1
-LES_BC_PERIODIC, LES_BC_DIRICHLET, LES_BC_PERIODIC_SUPERPOSED = 0, 1, 2
+LES_BC_PERIODIC, LES_BC_DIRICHLET, LES_BC_PERIODIC_SUPERPOSED, LES_BC_AXIS = 0, 1, 2, 3
 LES_FACE_FROZEN, LES_FACE_CHARACTERISTIC, LES_FACE_EXIT, LES_FACE_FARFIELD = 0, 1, 2, 3
 
 EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",
@@ -52,7 +52,7 @@ class LesFlowParams(ctypes.Structure):
                 ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("S_suth", ctypes.c_double),
                 ("R_gas", ctypes.c_double), ("sgs", ctypes.c_int), ("Cs", ctypes.c_double),
                 ("k2", ctypes.c_double), ("k4", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("cfl", ctypes.c_double), ("prec", ctypes.c_int)]
+                ("cfl", ctypes.c_double), ("prec", ctypes.c_int), ("CI", ctypes.c_double)]
 
 
 _lib = None
@@ -112,6 +112,8 @@ def lib():
     L.les_debug_stage_timing.argtypes = [_vp, ctypes.c_int]
     L.les_debug_stage_time.restype = ctypes.c_int
     L.les_debug_stage_time.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.les_debug_dynamic_coefficients.restype = ctypes.c_int
+    L.les_debug_dynamic_coefficients.argtypes = [_vp, _vp, _vp]
     L.les_debug_stream_copy.restype = ctypes.c_int
     L.les_debug_stream_copy.argtypes = [_vp, _vp, ctypes.c_longlong, _vp]
     _lib = L
@@ -139,6 +141,7 @@ def flow_params_struct(p: dict, prec: int = LES_FP64) -> LesFlowParams:
     s = LesFlowParams()
     for k in ["gamma", "Pr", "Pr_sgs", "mu_ref", "T_ref", "S_suth", "R_gas", "Cs", "k2", "k4", "alpha", "cfl"]:
         setattr(s, k, float(p[k]))
+    s.CI = float(p.get("CI", 0.0))
     s.sgs = int(p["sgs"])
     s.prec = int(prec)
     return s
@@ -336,6 +339,16 @@ class Solver:
 
     def rk_step(self, Q, dt=0.0, want_dt=False, want_norms=False, ckpt=None):
         return les_rk_step(self.ctx, Q.data_ptr(), dt, want_dt, want_norms, _ptr(ckpt))
+
+    def dynamic_coefficients(self, Q):
+        """(C, D_T) per padded column, (nj+4, ni+4) numpy arrays, of the
+        dynamic SGS closure at Q (instrumentation entry point)."""
+        t = self.torch
+        out = t.empty(2 * (self.nj + 4) * (self.ni + 4), dtype=t.float64, device=self.device)
+        _check(lib().les_debug_dynamic_coefficients(self.ctx, Q.data_ptr(), out.data_ptr()), self.ctx,
+               "les_debug_dynamic_coefficients")
+        a = out.cpu().numpy().reshape(2, self.nj + 4, self.ni + 4)
+        return a[0].copy(), a[1].copy()
 
     def advance(self, Q, nsteps, want_dt=False, want_norms=False):
         """nsteps CFL steps in one call (les_advance); returns (dts, norms)."""
