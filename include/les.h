@@ -100,6 +100,16 @@ typedef struct {
   const double *xyz;
 } les_grid;
 
+/* Metrics and Jacobian given by the caller (Sec. 4: each process reads or
+ * computes them for its block).  m: device, dense padded layout
+ * [10][nk+4][nj+4][ni+4]: xi_x/J, xi_y/J, xi_z/J, eta_x/J, ..., zeta_z/J, J,
+ * valid on all nodes with indices in [-1, n]; read during les_create only.
+ * A NULL les_metrics pointer, or m = NULL, lets les_create compute them from
+ * the grid coordinates. */
+typedef struct {
+  const double *m;
+} les_metrics;
+
 /* Flow and scheme parameters (nondimensional).  Sec. 3, Eq. 2-11:
  *   gamma, R_gas (p = rho R T), Pr (kappa = mu Cp/Pr), Pr_sgs
  *   (kappa_sgs = mu_sgs Cp/Pr_sgs), Sutherland mu = mu_ref (T/T_ref)^1.5
@@ -139,32 +149,35 @@ typedef struct {
 } les_flow_params;
 
 /* Create a context for one block (Alg. 2: read mesh, compute Jacobian and
- * metrics, create ghost points).  The metrics are computed on the device from
- * grid->xyz by the conservative (Thomas-Lombard) central-difference form,
- * which preserves a uniform flow exactly up to rounding; in a periodic
- * direction the ghost-layer metrics are copies of the wrapped interior ones.
- * metrics_dense (device, dense padded layout [10][..]: xi_x/J, xi_y/J, xi_z/J,
- * eta_x/J, ..., zeta_z/J, J) may be given instead (grid->xyz is then
- * ignored and may be NULL); it must be valid on all nodes with indices in
- * [-1, n].  hip_stream: a hipStream_t (NULL = default stream).
- * Returns LES_ERR_ARG for a null out/grid/params, n < 5, bad bc (LES_BC_AXIS
+ * metrics, create ghost points).  Without caller metrics they are computed on
+ * the device from grid->xyz by the conservative (Thomas-Lombard)
+ * central-difference form, which preserves a uniform flow exactly up to
+ * rounding; in a periodic direction the ghost-layer metrics are copies of the
+ * wrapped interior ones.  With metrics->m given, those are copied and
+ * grid->xyz is ignored (it may be NULL).  hip_stream: a hipStream_t (NULL =
+ * default stream).
+ * Returns LES_ERR_ARG for a null out/grid/params, no coordinates and no
+ * metrics, n < 5, bad bc (LES_BC_AXIS
  * elsewhere than j, or without a superposed k of odd nk, or with sgs = 2),
  * gamma <= 1,
  * R_gas <= 0, Pr <= 0, negative k2/k4/mu_ref/CI, sgs outside 0..2, unknown
  * prec.  sgs = 2 allocates the dynamic closure's work arrays (50 fields of
  * field_elems doubles) here. */
-int les_create(les_ctx **out, const les_grid *grid, const double *metrics_dense,
+int les_create(les_ctx **out, const les_grid *grid, const les_metrics *metrics,
                const les_flow_params *params, void *hip_stream);
 
 void les_destroy(les_ctx *ctx);
 
 /* Library layout of state arrays (see top of file).  strides[0] = 1,
  * strides[1] = stride_j, strides[2] = stride_k; *origin = element offset of
- * interior node (0, 0, 0) within a field; *field_elems = field pitch. */
-int les_layout(const les_ctx *ctx, long long strides[3], long long *origin, long long *field_elems);
+ * interior node (0, 0, 0) within a field; *field_elems = field pitch;
+ * *ghost = ghost layers per side (2: the five-point stencils of the
+ * fourth-difference dissipation, Sec. 4).  Any output may be NULL. */
+int les_layout(const les_ctx *ctx, long long strides[3], long long *origin, long long *field_elems, int *ghost);
 
 /* Same layout without a context (for allocating before les_create). */
-int les_layout_for(int ni, int nj, int nk, long long strides[3], long long *origin, long long *field_elems);
+int les_layout_for(int ni, int nj, int nk, long long strides[3], long long *origin, long long *field_elems,
+                   int *ghost);
 
 /* Copy the library's metrics (library layout) to a caller array
  * (device, dense padded layout [10][nk+4][nj+4][ni+4]); nodes outside
@@ -329,6 +342,23 @@ int les_set_face(les_ctx *ctx, int face, int type, const double *Q_outside, doub
  *    repeated runs give identical results. */
 #define LES_STATS_NF 12
 int les_stats_accumulate(les_ctx *ctx, const double *Q, double *acc);
+
+/* Mean-flow and RMS profiles of Sec. 6 from the sums of les_stats_accumulate,
+ * and the potential core (Sec. 6: where the mean axial velocity is at least
+ * a fraction, 95 % in the paper, of the inlet jet velocity):
+ *   <phi> = acc / samples (samples = calls times nk),
+ *   prof = (<rho>, <u>, <v>, <w>, <p>, u_rms, v_rms, w_rms, p_rms, <u'v'>),
+ *   a_rms = sqrt(max(0, <a a> - <a>^2)), <u'v'> = <u v> - <u><v>;
+ *   core[j][i] = 1 where <u> >= core_frac * u_jet, else 0 (u is the
+ *   i-direction velocity, the jet axis).
+ * acc: device, dense [LES_STATS_NF][nj][ni] (read only).
+ * prof: device, dense [LES_PROF_NF][nj][ni], written.
+ * core: device, unsigned char [nj][ni], or NULL (u_jet, core_frac unused).
+ * Returns LES_ERR_ARG for null acc/prof, samples <= 0, or (with core) u_jet
+ * <= 0 or core_frac outside (0, 1]. */
+#define LES_PROF_NF 10
+int les_stats_profiles(les_ctx *ctx, const double *acc, double samples, double u_jet, double core_frac,
+                       double *prof, unsigned char *core);
 
 const char *les_last_error(const les_ctx *ctx);
 const char *les_last_create_error(void);

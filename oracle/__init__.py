@@ -80,6 +80,9 @@ def _load():
     lib.orc_fill_ghosts_faces.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
     lib.orc_stats.restype = None
     lib.orc_stats.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp]
+    lib.orc_stats_profiles.restype = None
+    lib.orc_stats_profiles.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _dp, ctypes.c_void_p]
     lib.orc_dynamic_coefficients.restype = None
     lib.orc_dynamic_coefficients.argtypes = [ctypes.POINTER(OrcDims), ctypes.POINTER(OrcParams), _dp, _dp, _dp, _dp]
     lib.orc_residual_nofill.restype = None
@@ -300,3 +303,20 @@ def stats(case, Q, acc=None, prm=None) -> np.ndarray:
     assert acc.flags.c_contiguous
     lib.orc_stats(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(Q)), _ptr(acc))
     return acc
+
+
+PROF_FIELDS = ("rho", "u", "v", "w", "p", "u_rms", "v_rms", "w_rms", "p_rms", "uv")
+
+
+def stats_profiles(acc, samples, u_jet=1.0, core_frac=0.95):
+    """Sec. 6 profiles from the sums of stats(): (prof, core) with prof of
+    shape (10, nj, ni) in PROF_FIELDS order and core the potential-core mask
+    (nj, ni) as uint8 (<u> >= core_frac u_jet)."""
+    lib = _load()
+    acc = _c(acc)
+    nj, ni = acc.shape[1:]
+    prof = np.zeros((len(PROF_FIELDS), nj, ni))
+    core = np.zeros((nj, ni), dtype=np.uint8)
+    lib.orc_stats_profiles(ni, nj, _ptr(acc), float(samples), float(u_jet), float(core_frac), _ptr(prof),
+                           core.ctypes.data)
+    return prof, core

@@ -1208,8 +1208,6 @@ double orc_objective(const orc_dims* d, const orc_params* P, const double* m, do
   return J;
 }
 
-// Test hook for the scalar rules R11 and the RK driver on y' = lambda y
-// (complex lambda), used to check the amplification polynomial.
 // Running flow statistics (the time- and azimuth-averaged mean-flow and RMS
 // profiles of Sec. 6; the averaged periodic direction is k):
 //   acc[s][j][i] += sum over k = 0..nk-1 of phi_s(i, j, k),
@@ -1231,6 +1229,37 @@ void orc_stats(const orc_dims* d, const orc_params* P, const double* Q, double* 
       }
 }
 
+// Profiles of Sec. 6 from those sums after `samples` terms per entry: the
+// Reynolds means <phi> = acc / samples of rho, u, v, w, p, the RMS
+// fluctuations a_rms = sqrt(<a a> - <a>^2) of u, v, w, p (0 where rounding
+// makes the difference negative) and the covariance <u'v'> = <u v> - <u><v>:
+// prof = dense [10][nj][ni].  The potential core (Sec. 6) is where the mean
+// axial velocity <u> reaches core_frac times the jet velocity u_jet:
+// core[j][i] = 1 there, else 0 (core may be null).
+void orc_stats_profiles(int ni, int nj, const double* acc, double samples, double u_jet, double core_frac,
+                        double* prof, unsigned char* core) {
+  const size_t plane = (size_t)ni * nj;
+  for (size_t n = 0; n < plane; ++n) {
+    double mean[12];
+    for (int s = 0; s < 12; ++s) mean[s] = acc[s * plane + n] / samples;
+    const double rho = mean[0], u = mean[1], v = mean[2], w = mean[3], p = mean[4];
+    const double uu = mean[5], vv = mean[6], ww = mean[7], uv = mean[8], pp = mean[11];
+    prof[0 * plane + n] = rho;
+    prof[1 * plane + n] = u;
+    prof[2 * plane + n] = v;
+    prof[3 * plane + n] = w;
+    prof[4 * plane + n] = p;
+    prof[5 * plane + n] = std::sqrt(std::max(0.0, uu - u * u));
+    prof[6 * plane + n] = std::sqrt(std::max(0.0, vv - v * v));
+    prof[7 * plane + n] = std::sqrt(std::max(0.0, ww - w * w));
+    prof[8 * plane + n] = std::sqrt(std::max(0.0, pp - p * p));
+    prof[9 * plane + n] = uv - u * v;
+    if (core) core[n] = u >= core_frac * u_jet ? 1 : 0;
+  }
+}
+
+// Test hook for the scalar rules R11 and the RK driver on y' = lambda y
+// (complex lambda), used to check the amplification polynomial.
 void orc_rk_scalar(double lr, double li, double dt, double* yr, double* yi) {
   double y0r = *yr, y0i = *yi, cr = y0r, ci = y0i;
   for (int l = 0; l < 5; ++l) {

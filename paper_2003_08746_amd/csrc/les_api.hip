@@ -193,6 +193,11 @@ static int timing_end(les_ctx* c) {
 
 // Adjoint work arrays are allocated on first use and kept by the context.
 static int ensure_adj_work(les_ctx* c) {
+  // the adjoint passes index the nodes of the padded box with 32-bit
+  // integers (their work arrays limit the block far below that anyway)
+  const long long box = (long long)(c->L.ni + 4) * (c->L.nj + 4) * (c->L.nk + 4);
+  if (box >= (1LL << 31))
+    return fail(c, LES_ERR_STATE, "adjoint: block too large (%lld padded nodes, limit 2^31)", box);
   const size_t need = les::adjoint_work_elems(c->L);
   if ((long long)need <= c->adj_n) return LES_OK;
   (void)hipFree(c->adj);
@@ -210,7 +215,8 @@ const char* les_last_create_error(void) { return g_create_err; }
 
 const char* les_last_error(const les_ctx* ctx) { return ctx ? ctx->err : g_create_err; }
 
-int les_layout_for(int ni, int nj, int nk, long long strides[3], long long* origin, long long* field_elems) {
+int les_layout_for(int ni, int nj, int nk, long long strides[3], long long* origin, long long* field_elems,
+                   int* ghost) {
   if (ni < 5 || nj < 5 || nk < 5) return fail(nullptr, LES_ERR_ARG, "les_layout_for: sizes must be >= 5");
   les::Layout L = les::make_layout(ni, nj, nk);
   if (strides) {
@@ -220,10 +226,11 @@ int les_layout_for(int ni, int nj, int nk, long long strides[3], long long* orig
   }
   if (origin) *origin = L.o;
   if (field_elems) *field_elems = L.fe;
+  if (ghost) *ghost = les::GH;
   return LES_OK;
 }
 
-int les_layout(const les_ctx* ctx, long long strides[3], long long* origin, long long* field_elems) {
+int les_layout(const les_ctx* ctx, long long strides[3], long long* origin, long long* field_elems, int* ghost) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_layout: null context");
   if (strides) {
     strides[0] = 1;
@@ -232,11 +239,13 @@ int les_layout(const les_ctx* ctx, long long strides[3], long long* origin, long
   }
   if (origin) *origin = ctx->L.o;
   if (field_elems) *field_elems = ctx->L.fe;
+  if (ghost) *ghost = les::GH;
   return LES_OK;
 }
 
-int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense, const les_flow_params* prm,
+int les_create(les_ctx** out, const les_grid* grid, const les_metrics* metrics, const les_flow_params* prm,
                void* hip_stream) {
+  const double* metrics_dense = metrics ? metrics->m : nullptr;
   if (!out) return fail(nullptr, LES_ERR_ARG, "les_create: out is NULL");
   *out = nullptr;
   if (!grid || !prm) return fail(nullptr, LES_ERR_ARG, "les_create: grid or params is NULL");
@@ -244,10 +253,12 @@ int les_create(les_ctx** out, const les_grid* grid, const double* metrics_dense,
     return fail(nullptr, LES_ERR_ARG, "les_create: every interior size must be >= 5 (got %d x %d x %d)", grid->ni,
                 grid->nj, grid->nk);
   {
-    // the stage kernels address a field with 32-bit byte offsets
+    // the stage kernel takes 32-bit per-thread offsets from a 64-bit base
+    // per segment of k planes: a segment of a few planes must fit them
     les::Layout Lc = les::make_layout(grid->ni, grid->nj, grid->nk);
-    if (Lc.fe >= (1LL << 29))
-      return fail(nullptr, LES_ERR_ARG, "les_create: block too large (%lld elements per field, limit 2^29)", Lc.fe);
+    if (les::stage_kmax(Lc) < 1)
+      return fail(nullptr, LES_ERR_ARG,
+                  "les_create: k plane too large (%lld elements with padding; 7 planes must stay below 2^29)", Lc.sk);
   }
   for (int d = 0; d < 3; ++d)
     if (grid->bc[d] != LES_BC_PERIODIC && grid->bc[d] != LES_BC_DIRICHLET && grid->bc[d] != LES_BC_PERIODIC_SUPERPOSED &&
@@ -616,7 +627,7 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
                                     "the isotropic SGS stress (sgs <= 1, CI = 0) on blocks without the axis");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
-  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx), ctx->mach.xcds};
   HIPCHK(ctx, les::run_adjoint_step(ctx->s, a, stage_ckpt, dt, Qbar, ctx->i_f >= 0 ? fbar : nullptr, ctx->adj));
   return LES_OK;
 }
@@ -653,6 +664,18 @@ int les_stats_accumulate(les_ctx* ctx, const double* Q, double* acc) {
   return LES_OK;
 }
 
+int les_stats_profiles(les_ctx* ctx, const double* acc, double samples, double u_jet, double core_frac,
+                       double* prof, unsigned char* core) {
+  if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_stats_profiles: null context");
+  if (!acc || !prof) return fail(ctx, LES_ERR_ARG, "les_stats_profiles: acc and prof are required");
+  if (!(samples > 0.0) || !isfinite(samples))
+    return fail(ctx, LES_ERR_ARG, "les_stats_profiles: samples must be positive (got %g)", samples);
+  if (core && (!(u_jet > 0.0) || !isfinite(u_jet) || !(core_frac > 0.0 && core_frac <= 1.0)))
+    return fail(ctx, LES_ERR_ARG, "les_stats_profiles: the core needs u_jet > 0 and 0 < core_frac <= 1");
+  HIPCHK(ctx, les::launch_stats_profiles(ctx->s, ctx->L, acc, samples, core ? core_frac * u_jet : 0.0, prof, core));
+  return LES_OK;
+}
+
 int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qbar) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual_adjoint: null context");
   if (!Q || !Rbar || !Qbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Q, Rbar and Qbar are required");
@@ -663,7 +686,7 @@ int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qb
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
   HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
-  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx), ctx->mach.xcds};
   HIPCHK(ctx, les::run_residual_vjp(ctx->s, a, Q, Rbar, Qbar, ctx->adj));
   return LES_OK;
 }

@@ -703,7 +703,39 @@ __global__ void __launch_bounds__(256) k_stats(Layout L, Phys P, const double* _
   }
 }
 
+// Mean-flow and RMS profiles from the running sums: one thread per (i, j).
+// prof = (<rho>, <u>, <v>, <w>, <p>, u_rms, v_rms, w_rms, p_rms, <u'v'>) with
+// <phi> = acc / samples and rms = sqrt(max(0, <phi phi> - <phi>^2)); core
+// (if not null) marks <u> >= core_u.
+// The means are IEEE quotients, so a core decision on <u> is the one an FP64
+// host computation of acc / samples takes.
+__global__ void __launch_bounds__(256) k_stats_profiles(int nij, const double* __restrict__ acc, double samples,
+                                                        double core_u, double* __restrict__ prof,
+                                                        unsigned char* __restrict__ core) {
+  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (n >= nij) return;
+  double m[STATS_NF];
+#pragma unroll
+  for (int f = 0; f < STATS_NF; ++f) m[f] = acc[f * (long long)nij + n] / samples;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) prof[f * (long long)nij + n] = m[f];
+  // second moments uu, vv, ww of fields 5..7, pp of field 11
+  prof[5 * (long long)nij + n] = sqrt(fmax(0.0, m[5] - m[1] * m[1]));
+  prof[6 * (long long)nij + n] = sqrt(fmax(0.0, m[6] - m[2] * m[2]));
+  prof[7 * (long long)nij + n] = sqrt(fmax(0.0, m[7] - m[3] * m[3]));
+  prof[8 * (long long)nij + n] = sqrt(fmax(0.0, m[11] - m[4] * m[4]));
+  prof[9 * (long long)nij + n] = m[8] - m[1] * m[2];
+  if (core) core[n] = m[1] >= core_u ? 1 : 0;
+}
+
 static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_stats_profiles(hipStream_t s, const Layout& L, const double* acc, double samples, double core_u,
+                                 double* prof, unsigned char* core) {
+  const long long nij = (long long)L.ni * L.nj;
+  k_stats_profiles<<<nblk(nij, 256), 256, 0, s>>>((int)nij, acc, samples, core_u, prof, core);
+  return hipGetLastError();
+}
 
 hipError_t launch_metrics(hipStream_t s, const Layout& L, const int bc[3], const double* xyz, double* M) {
   Dense D{L.ni, L.nj, L.nk};

@@ -315,6 +315,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
       ke = (int)min((long long)(k0 + kcc), (long long)kb + (w_end - wq));
       wq += ke - kb;
     }
+    // segment base: plane kb - 2, the first the segment reads.  Per-thread
+    // element offsets are taken from there, so they stay below 2^29 for any
+    // block whose planes are small enough that kc + 6 of them are (the
+    // schedule bounds kc accordingly); field and segment bases are 64-bit.
+    const int kr = kb - 2;
+    const long long sb = (long long)kr * L.sk;
+    const QI* const Qs = Qin + sb;
     const int tix = tile % a.ntx, tiy = tile / a.ntx;
     const int i0 = tix * TX, j0 = tiy * TY;
     const int i = i0 - 1 + tx, j = j0 - 1 + ty;
@@ -325,8 +332,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
     const bool out_ok = !xh && !yh && i < L.ni && j < L.nj;
     const int hi = i0 - 2 + hx2, hj = j0 - 2 + hy2;
     const bool h_ok = tid < NH2 && hi <= L.ni + 1 && hj <= L.nj + 1;
-    // element offsets of nodes (i, j, 0) and (hi, hj, 0); every node of the
-    // padded box lies below 2^29 elements per field (checked at creation)
+    // element offsets of nodes (i, j, kr) and (hi, hj, kr) from the segment
+    // base
     const unsigned col = (unsigned)((long long)i + (long long)j * L.sj + L.o);
     const unsigned hcol = (unsigned)((long long)hi + (long long)hj * L.sj + L.o);
     // own-column loads use the node clamped into the padded box, so that they
@@ -366,15 +373,15 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
     const long long lane_el = (long long)fsel * fe + L.o + icp + (long long)jcp * L.sj;
     const long long fstep2 = 2 * fe * (long long)sizeof(double);
     dma_rows<10>((const char*)(kp->M + lane_el + (long long)(kb - 1) * L.sk), fstep2, &mbw[wave][0][0][0], lane);
-    load_q<T>(Qin, fe, qcol + (unsigned)(kb - 2) * sk, qm1);
-    load_q<T>(Qin, fe, qcol + (unsigned)(kb - 1) * sk, qw);
-    if (kPrefetchQ) load_q<T>(Qin, fe, qcol + (unsigned)kb * sk, qa);
+    load_q<T>(Qs, fe, qcol, qm1);
+    load_q<T>(Qs, fe, qcol + sk, qw);
+    if (kPrefetchQ) load_q<T>(Qs, fe, qcol + 2 * sk, qa);
     prims(kp->P, qm1, um1, pm1);
     prims(kp->P, qw, up1, pp1);  // plane kb-1, written at the first B
-    if (kPrefetchRing && h_ok) load_q<T>(Qin, fe, hcol + (unsigned)(kb - 1) * sk, hq);
+    if (kPrefetchRing && h_ok) load_q<T>(Qs, fe, hcol + sk, hq);
 
     for (int t = kb - 1; t <= ke; ++t) {
-      const unsigned nt = col + (unsigned)t * sk;
+      const unsigned nt = col + (unsigned)(t - kr) * sk;
       CKArgs* kq4 = ka;
       asm volatile("" : "+s"(kq4));
       const KArgs* kq = (const KArgs*)kq4;
@@ -394,10 +401,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
         s.p[ey][ex] = pp1;
         s.u[ey][ex] = up1[0]; s.v[ey][ex] = up1[1]; s.w[ey][ex] = up1[2]; s.tem[ey][ex] = up1[3];
       }
-      if (!kPrefetchQ) load_q<T>(Qin, fe, qcol + (unsigned)(t + 1) * sk, qa);  // plane t+1 of the own column
+      if (!kPrefetchQ) load_q<T>(Qs, fe, qcol + (unsigned)(t + 1 - kr) * sk, qa);  // plane t+1 of the own column
       if (h_ok) {
         T hu[4], hp;
-        if (!kPrefetchRing) load_q<T>(Qin, fe, hcol + (unsigned)t * sk, hq);
+        if (!kPrefetchRing) load_q<T>(Qs, fe, hcol + (unsigned)(t - kr) * sk, hq);
         prims(P, hq, hu, hp);
 #pragma unroll
         for (int c = 0; c < 5; ++c) sq[c][hy2][hx2] = hq[c];
@@ -422,7 +429,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
       wait_lgkm_all();  // the wave's metric reads are done before its copies overwrite them
       // issue the next plane's loads now so that they land during C and E:
       // helper ring (FP32 path), then the wave's metric rows (five copies)
-      if (kPrefetchRing && h_ok && t < ke) load_q<T>(Qin, fe, hcol + (unsigned)(t + 1) * sk, hq);
+      if (kPrefetchRing && h_ok && t < ke) load_q<T>(Qs, fe, hcol + (unsigned)(t + 1 - kr) * sk, hq);
       if (node_t) {
         const T Jt = (T)Jn;
         T g[4][3];
@@ -541,7 +548,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
       // stores nothing to LDS); read at C of the next plane
       if (t < ke)
         dma_rows<10>((const char*)(kq->M + lane_el + (long long)(t + 1) * L.sk), fstep2, &mbw[wave][0][0][0], lane);
-      if (kPrefetchQ && t < ke) load_q<T>(Qin, fe, qcol + (unsigned)(t + 2) * sk, qn);  // consumed at C of t+1
+      if (kPrefetchQ && t < ke) load_q<T>(Qs, fe, qcol + (unsigned)(t + 2 - kr) * sk, qn);  // consumed at C of t+1
 
       // ---- E: residual (tile nodes) ----
       if (out_ok) {
@@ -589,7 +596,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
         if (CFL) {
           const unsigned n = (out_ok && t > kb) ? nt - sk : qcol;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) cm[c] = ldo(kq->M + c * fe, n);
+          for (int c = 0; c < 9; ++c) cm[c] = ldo(kq->M + sb + c * fe, n);
         }
         if (t >= kb) {
           // zeta face t - 1/2 between plane t-1 and plane t
@@ -613,8 +620,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
               if (on_axis) R = 0.0;
               const double qn = q0v[c] - adt * R;
               qnv[c] = qn;
-              if (Qout) sto(Qout + c * fe, n, qn);
-              if (Qsh) sto(Qsh + c * fe, n, (float)qn);
+              if (Qout) sto(Qout + sb + c * fe, n, qn);
+              if (Qsh) sto(Qsh + sb + c * fe, n, (float)qn);
               if (NORM) {
                 n2[c] += R * R;
                 const double a = fabs(R);
@@ -680,6 +687,18 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
   }
 }
 
+}  // namespace
+
+// The most planes one segment may march: its per-thread element offsets,
+// taken from plane kb - 2, reach kc + 6 planes and must stay below 2^29
+// (32-bit byte offsets of doubles).  0 when even one plane is too large.
+int stage_kmax(const Layout& L) {
+  const long long k = (1LL << 29) / L.sk - 6;
+  return k < 1 ? 0 : (k > (1 << 30) ? (1 << 30) : (int)k);
+}
+
+namespace {
+
 // Stage kernel configuration for a layout.
 struct Config {
   int ntx, nty, nblocks, grid, per_xcd, kc, rr, nxcd;
@@ -703,19 +722,22 @@ Config config(const Layout& L, long long per_block, const Machine& m) {
   c.per_block = per_block < 1 ? 1 : per_block;
   c.rr = c.per_block > L.nk;
   c.nseg = 0;
+  const int kmax = stage_kmax(L);
   if (!c.rr) {
-    c.kc = (int)c.per_block;
+    c.kc = (int)(c.per_block < kmax ? c.per_block : kmax);
     c.nblocks = (int)((c.total + c.per_block - 1) / c.per_block);
   } else {
-    // the number of k chunks (at most 16, chunks of at least 32 planes when
-    // nk allows) that best fills whole rounds of the blocks there are
-    // slots for; fewer chunks on ties (fewer segment start-ups)
+    // the number of k chunks (from the fewest whose chunks fit the 32-bit
+    // offsets, at most 16 more, chunks of at least 32 planes when nk allows)
+    // that best fills whole rounds of the blocks there are slots for; fewer
+    // chunks on ties (fewer segment start-ups)
     const long long ntiles = (long long)c.ntx * c.nty;
     const long long slots = (c.total + c.per_block - 1) / c.per_block;
+    const int n0 = (L.nk + kmax - 1) / kmax;
     double best = -1.0;
-    for (int n = 1; n <= 16; ++n) {
+    for (int n = n0; n <= n0 + 15; ++n) {
       const int kc = (L.nk + n - 1) / n;
-      if (n > 1 && kc < 32) break;
+      if (n > n0 && kc < 32) break;
       const long long nseg = ntiles * ((L.nk + kc - 1) / kc);
       const long long nb = nseg < slots ? nseg : slots;
       const long long rounds = (nseg + nb - 1) / nb;

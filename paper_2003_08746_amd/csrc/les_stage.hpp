@@ -28,6 +28,11 @@ struct StageArgs {
 // the environment overrides the automatic choice; read once per context).
 int stage_kchunk(const Layout& L, const Machine& m);
 
+// Largest number of k planes per segment of the stage kernel's schedule for
+// this layout (0: a single k plane is too large for the kernel's 32-bit
+// per-thread offsets, which les_create refuses).
+int stage_kmax(const Layout& L);
+
 // Number of per-block norm partials written by one fused stage launch.
 long long stage_blocks(const Layout& L, int kchunk, const Machine& m);
 

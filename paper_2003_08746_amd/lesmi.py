@@ -28,12 +28,15 @@ LES_FACE_FROZEN, LES_FACE_CHARACTERISTIC, LES_FACE_EXIT, LES_FACE_FARFIELD = 0, 
 
 EXPORTED = ["les_create", "les_destroy", "les_layout", "les_layout_for", "les_get_metrics", "les_residual",
             "les_cfl_dt", "les_set_forcing", "les_rk_step", "les_advance", "les_adjoint_step", "les_residual_adjoint",
-            "les_probe_objective", "les_set_face", "les_stats_accumulate", "les_residual_noalloc",
-            "les_last_error", "les_last_create_error"]
+            "les_probe_objective", "les_set_face", "les_stats_accumulate", "les_stats_profiles",
+            "les_residual_noalloc", "les_last_error", "les_last_create_error"]
 
 # fields of les_stats_accumulate, in its order (sums over k of each)
 LES_STATS_NF = 12
 STATS_FIELDS = ("rho", "u", "v", "w", "p", "uu", "vv", "ww", "uv", "uw", "vw", "pp")
+# fields of les_stats_profiles, in its order
+LES_PROF_NF = 10
+PROF_FIELDS = ("rho", "u", "v", "w", "p", "u_rms", "v_rms", "w_rms", "p_rms", "uv")
 
 
 class LesError(RuntimeError):
@@ -45,6 +48,10 @@ class LesError(RuntimeError):
 class LesGrid(ctypes.Structure):
     _fields_ = [("ni", ctypes.c_int), ("nj", ctypes.c_int), ("nk", ctypes.c_int), ("bc", ctypes.c_int * 3),
                 ("xyz", ctypes.c_void_p)]
+
+
+class LesMetrics(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_void_p)]
 
 
 class LesFlowParams(ctypes.Structure):
@@ -71,13 +78,15 @@ def lib():
                            "(there is no CPU fallback)")
     L = ctypes.CDLL(LIB_PATH)
     L.les_create.restype = ctypes.c_int
-    L.les_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(LesGrid), _vp, ctypes.POINTER(LesFlowParams), _vp]
+    L.les_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(LesGrid), ctypes.POINTER(LesMetrics),
+                             ctypes.POINTER(LesFlowParams), _vp]
     L.les_destroy.restype = None
     L.les_destroy.argtypes = [_vp]
     L.les_layout.restype = ctypes.c_int
-    L.les_layout.argtypes = [_vp, _llp, _llp, _llp]
+    L.les_layout.argtypes = [_vp, _llp, _llp, _llp, ctypes.POINTER(ctypes.c_int)]
     L.les_layout_for.restype = ctypes.c_int
-    L.les_layout_for.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _llp, _llp, _llp]
+    L.les_layout_for.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _llp, _llp, _llp,
+                                 ctypes.POINTER(ctypes.c_int)]
     L.les_get_metrics.restype = ctypes.c_int
     L.les_get_metrics.argtypes = [_vp, _vp]
     L.les_residual.restype = ctypes.c_int
@@ -102,6 +111,8 @@ def lib():
     L.les_set_face.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double]
     L.les_stats_accumulate.restype = ctypes.c_int
     L.les_stats_accumulate.argtypes = [_vp, _vp, _vp]
+    L.les_stats_profiles.restype = ctypes.c_int
+    L.les_stats_profiles.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp]
     L.les_last_error.restype = ctypes.c_char_p
     L.les_last_error.argtypes = [_vp]
     L.les_last_create_error.restype = ctypes.c_char_p
@@ -150,10 +161,16 @@ def flow_params_struct(p: dict, prec: int = LES_FP64) -> LesFlowParams:
 # ---------------------------------------------------------------------------
 # C names
 # ---------------------------------------------------------------------------
-def les_create(grid: LesGrid, metrics_dense_ptr, params: LesFlowParams, stream_ptr) -> int:
+def les_create(grid: LesGrid, metrics_ptr, params: LesFlowParams, stream_ptr) -> int:
+    """metrics_ptr: device pointer of caller metrics (dense padded [10][..])
+    or None to compute them from grid.xyz."""
     ctx = _vp()
-    rc = lib().les_create(ctypes.byref(ctx), ctypes.byref(grid), metrics_dense_ptr, ctypes.byref(params),
-                          stream_ptr)
+    m = None
+    if metrics_ptr is not None:
+        m = LesMetrics()
+        m.m = metrics_ptr
+    rc = lib().les_create(ctypes.byref(ctx), ctypes.byref(grid), None if m is None else ctypes.byref(m),
+                          ctypes.byref(params), stream_ptr)
     _check(rc, None, "les_create")
     return ctx.value
 
@@ -163,19 +180,24 @@ def les_destroy(ctx) -> None:
 
 
 def les_layout(ctx):
+    """(strides, origin, field_elems, ghost)"""
     st = (ctypes.c_longlong * 3)()
     o = ctypes.c_longlong()
     fe = ctypes.c_longlong()
-    _check(lib().les_layout(ctx, st, ctypes.byref(o), ctypes.byref(fe)), ctx, "les_layout")
-    return tuple(st), o.value, fe.value
+    gh = ctypes.c_int()
+    _check(lib().les_layout(ctx, st, ctypes.byref(o), ctypes.byref(fe), ctypes.byref(gh)), ctx, "les_layout")
+    return tuple(st), o.value, fe.value, gh.value
 
 
 def les_layout_for(ni, nj, nk):
+    """(strides, origin, field_elems, ghost)"""
     st = (ctypes.c_longlong * 3)()
     o = ctypes.c_longlong()
     fe = ctypes.c_longlong()
-    _check(lib().les_layout_for(ni, nj, nk, st, ctypes.byref(o), ctypes.byref(fe)), None, "les_layout_for")
-    return tuple(st), o.value, fe.value
+    gh = ctypes.c_int()
+    _check(lib().les_layout_for(ni, nj, nk, st, ctypes.byref(o), ctypes.byref(fe), ctypes.byref(gh)), None,
+           "les_layout_for")
+    return tuple(st), o.value, fe.value, gh.value
 
 
 def les_get_metrics(ctx, dense_out_ptr):
@@ -240,6 +262,11 @@ def les_stats_accumulate(ctx, Q_ptr, acc_ptr):
     _check(lib().les_stats_accumulate(ctx, Q_ptr, acc_ptr), ctx, "les_stats_accumulate")
 
 
+def les_stats_profiles(ctx, acc_ptr, samples, u_jet, core_frac, prof_ptr, core_ptr):
+    _check(lib().les_stats_profiles(ctx, acc_ptr, float(samples), float(u_jet), float(core_frac), prof_ptr,
+                                    core_ptr), ctx, "les_stats_profiles")
+
+
 def les_debug_use_reference(ctx, on: bool):
     _check(lib().les_debug_use_reference(ctx, 1 if on else 0), ctx, "les_debug_use_reference")
 
@@ -266,7 +293,9 @@ class Solver:
     """One block on one GPU.  ``case`` is a dict from ``inputs`` (ni, nj, nk,
     bc, xyz (dense padded numpy or torch), params)."""
 
-    def __init__(self, case: dict, prec: int = LES_FP64, device: str = "cuda", stream=None, xyz=None):
+    def __init__(self, case: dict, prec: int = LES_FP64, device: str = "cuda", stream=None, xyz=None, metrics=None):
+        """metrics: optional caller metrics, a device float64 tensor in the
+        dense padded layout (10, nk+4, nj+4, ni+4); then xyz is not read."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -275,19 +304,25 @@ class Solver:
         self.params = dict(case["params"])
         self.prec = prec
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        if xyz is None:
-            xyz = case["xyz"]
-        xyz_t = xyz if isinstance(xyz, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(xyz))
-        xyz_t = xyz_t.to(self.device, torch.float64).contiguous()
         g = LesGrid()
         g.ni, g.nj, g.nk = self.ni, self.nj, self.nk
         for d in range(3):
             g.bc[d] = self.bc[d]
-        g.xyz = xyz_t.data_ptr()
+        xyz_t = None
+        if metrics is None:
+            if xyz is None:
+                xyz = case["xyz"]
+            xyz_t = xyz if isinstance(xyz, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(xyz))
+            xyz_t = xyz_t.to(self.device, torch.float64).contiguous()
+            g.xyz = xyz_t.data_ptr()
+        else:
+            assert metrics.dtype == torch.float64 and metrics.is_contiguous() and metrics.is_cuda
+            assert metrics.shape == (10, self.nk + 4, self.nj + 4, self.ni + 4)
         with torch.cuda.stream(self.stream):
-            self.ctx = les_create(g, None, flow_params_struct(self.params, prec), int(self.stream.cuda_stream))
+            self.ctx = les_create(g, None if metrics is None else metrics.data_ptr(),
+                                  flow_params_struct(self.params, prec), int(self.stream.cuda_stream))
         del xyz_t
-        self.strides, self.origin, self.fe = les_layout(self.ctx)
+        self.strides, self.origin, self.fe, self.ghost = les_layout(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -307,9 +342,9 @@ class Solver:
 
     def view(self, state, nf=5):
         """Dense padded view (nf, nk+4, nj+4, ni+4) of a library-layout array."""
-        sj, sk = self.strides[1], self.strides[2]
-        start = self.origin - 2 - 2 * sj - 2 * sk
-        return state.as_strided((nf, self.nk + 4, self.nj + 4, self.ni + 4), (self.fe, sk, sj, 1),
+        sj, sk, g = self.strides[1], self.strides[2], self.ghost
+        start = self.origin - g - g * sj - g * sk
+        return state.as_strided((nf, self.nk + 2 * g, self.nj + 2 * g, self.ni + 2 * g), (self.fe, sk, sj, 1),
                                 state.storage_offset() + start)
 
     def upload(self, dense, nf=5):
@@ -383,27 +418,22 @@ class Solver:
         les_stats_accumulate(self.ctx, Q.data_ptr(), acc.data_ptr())
         return acc
 
+    def stats_profiles(self, acc, samples, u_jet=None, core_frac=0.95):
+        """Mean-flow and RMS profiles (les_stats_profiles) from the sums in
+        acc; samples = number of accumulations times nk.  Returns a dict of
+        (nj, ni) device tensors keyed by PROF_FIELDS, plus "core" (a bool
+        (nj, ni) tensor: the potential core, <u> >= core_frac u_jet) when
+        u_jet is given."""
+        t = self.torch
+        assert acc.shape == (LES_STATS_NF, self.nj, self.ni) and acc.dtype == t.float64 and acc.is_contiguous()
+        prof = t.empty((LES_PROF_NF, self.nj, self.ni), dtype=t.float64, device=self.device)
+        core = None if u_jet is None else t.empty((self.nj, self.ni), dtype=t.uint8, device=self.device)
+        les_stats_profiles(self.ctx, acc.data_ptr(), samples, 0.0 if u_jet is None else u_jet, core_frac,
+                           prof.data_ptr(), _ptr(core))
+        out = {name: prof[f] for f, name in enumerate(PROF_FIELDS)}
+        if core is not None:
+            out["core"] = core.bool()
+        return out
+
     def use_reference(self, on=True):
         les_debug_use_reference(self.ctx, on)
-
-
-def stats_profiles(acc, samples):
-    """Reynolds means and RMS fluctuations from les_stats_accumulate sums;
-    samples = number of calls times nk.  Returns a dict of (nj, ni) tensors:
-    the means of STATS_FIELDS[:5] and u_rms, v_rms, w_rms, p_rms, uv (the
-    covariance <u'v'>)."""
-    import torch
-    m = {name: acc[s] / samples for s, name in enumerate(STATS_FIELDS)}
-    out = {name: m[name] for name in STATS_FIELDS[:5]}
-    for a in ("u", "v", "w", "p"):
-        out[a + "_rms"] = torch.sqrt(torch.clamp(m[a + a] - m[a] * m[a], min=0.0))
-    out["uv"] = m["uv"] - m["u"] * m["v"]
-    return out
-
-
-def potential_core(profiles, u_jet, frac=0.95):
-    """The jet's potential core as Sec. 6 defines it: the nodes whose
-    time-averaged axial velocity is at least frac (95 %) of the inlet jet
-    velocity u_jet.  profiles: the dict of stats_profiles (its "u" entry,
-    (nj, ni)); returns a boolean (nj, ni) tensor."""
-    return profiles["u"] >= frac * u_jet

@@ -46,7 +46,8 @@ def test_every_export_is_declared():
 
 
 def test_layout_for():
-    st, o, fe = lesmi.les_layout_for(256, 128, 128)
+    st, o, fe, gh = lesmi.les_layout_for(256, 128, 128)
+    assert gh == 2  # two ghost layers per side
     assert st[0] == 1 and st[1] % 16 == 0 and st[1] >= 9 + 256 + 2
     assert st[2] == st[1] * (128 + 4)
     # interior i = 0 sits 9 elements into a row, so node i = -1 (the first
@@ -70,8 +71,10 @@ def test_create_rejects_bad_arguments():
     p = lesmi.flow_params_struct(__import__("paper_2003_08746_amd.inputs", fromlist=["x"]).flow_params())
     assert L.les_create(None, ctypes.byref(g), None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
     assert L.les_create(ctypes.byref(ctx), None, None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
-    # no coordinates and no metrics
+    # no coordinates and no metrics (also with an empty les_metrics)
     assert L.les_create(ctypes.byref(ctx), ctypes.byref(g), None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
+    m = lesmi.LesMetrics()
+    assert L.les_create(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(m), ctypes.byref(p), None) == lesmi.LES_ERR_ARG
     g.xyz = 1234  # never dereferenced: the checks below fail first
     g.ni = 4
     assert L.les_create(ctypes.byref(ctx), ctypes.byref(g), None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
@@ -95,6 +98,7 @@ def test_null_context_calls():
     assert L.les_adjoint_step(None, None, 1.0, None, None) == lesmi.LES_ERR_ARG
     assert L.les_set_forcing(None, None, 0) == lesmi.LES_ERR_ARG
     assert L.les_stats_accumulate(None, None, None) == lesmi.LES_ERR_ARG
+    assert L.les_stats_profiles(None, None, 1.0, 1.0, 0.95, None, None) == lesmi.LES_ERR_ARG
     assert L.les_set_face(None, 0, 1, None, 0.0) == lesmi.LES_ERR_ARG
     assert L.les_debug_stream_copy(None, None, 16, None) == lesmi.LES_ERR_ARG
     assert L.les_debug_stream_copy(16, 32, 24, None) == lesmi.LES_ERR_ARG  # not a multiple of 16 (no launch)
@@ -102,19 +106,24 @@ def test_null_context_calls():
 
 
 def test_create_size_limit():
-    """The stage kernels address a field with 32-bit byte offsets: a padded
-    field of 2^29 elements or more is refused before anything is allocated.
-    800 x 800 x 812 pads to 99.7 % of the limit (it passes the size check and
-    fails on the missing coordinates instead); 800 x 800 x 815 pads to 100.1 %."""
+    """The stage kernel takes 32-bit element offsets from a 64-bit base per
+    segment of k planes, and a segment spans at least seven planes: a block
+    whose padded k plane times 7 reaches 2^29 elements is refused before
+    anything is allocated, whatever nk is.  9000 x 9000 is over that limit;
+    8200 x 8200 is under it, as is an 800 x 800 x 815 block whose fields
+    exceed 2^29 elements (both fail on the missing coordinates instead)."""
     L = lesmi.lib()
     ctx = ctypes.c_void_p()
     p = lesmi.flow_params_struct(__import__("paper_2003_08746_amd.inputs", fromlist=["x"]).flow_params())
     g = lesmi.LesGrid()
-    g.ni, g.nj, g.nk = 800, 800, 815
+    g.ni, g.nj, g.nk = 9000, 9000, 5
+    assert 7 * lesmi.les_layout_for(9000, 9000, 5)[0][2] >= (1 << 29)
     assert L.les_create(ctypes.byref(ctx), ctypes.byref(g), None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
     assert b"too large" in L.les_last_create_error()
-    g.nk = 812
-    assert L.les_create(ctypes.byref(ctx), ctypes.byref(g), None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
-    assert b"too large" not in L.les_last_create_error()
-    assert lesmi.les_layout_for(800, 800, 812)[2] < (1 << 29) <= lesmi.les_layout_for(800, 800, 815)[2]
+    for n in ((8200, 8200, 5), (800, 800, 815)):
+        g.ni, g.nj, g.nk = n
+        assert L.les_create(ctypes.byref(ctx), ctypes.byref(g), None, ctypes.byref(p), None) == lesmi.LES_ERR_ARG
+        assert b"too large" not in L.les_last_create_error()
+    assert 7 * lesmi.les_layout_for(8200, 8200, 5)[0][2] < (1 << 29)
+    assert lesmi.les_layout_for(800, 800, 815)[2] >= (1 << 29)
     assert ctx.value is None

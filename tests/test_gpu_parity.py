@@ -95,6 +95,29 @@ def test_residual_parity(orc, lesmi, name):
     s.close()
 
 
+def test_caller_metrics(orc, lesmi):
+    """les_create with les_metrics: the oracle's metrics handed over (no
+    coordinates) give the same residual as the metrics the library computes,
+    to the metrics parity bound; the library's own metrics handed back give
+    the identical residual."""
+    import torch
+    case = CASES["wavy70x37x21_alpha07"]
+    s = lesmi.Solver(case)
+    R0 = s.download(s.residual(s.upload(case["Q"])))
+    mine = torch.from_numpy(s.metrics_dense()).cuda()
+    s.close()
+    s2 = lesmi.Solver(case, metrics=mine)
+    R2 = s2.download(s2.residual(s2.upload(case["Q"])))
+    s2.close()
+    assert np.array_equal(I.interior(R2), I.interior(R0))
+    mo = torch.from_numpy(orc.metrics(case)).cuda()
+    s3 = lesmi.Solver(case, metrics=mo)
+    R3 = s3.download(s3.residual(s3.upload(case["Q"])))
+    s3.close()
+    Ro = orc.residual(case, orc.metrics(case), case["Q"])
+    assert (_rel(R3, Ro) <= TOL).all(), _rel(R3, Ro)
+
+
 def test_residual_with_source(orc, lesmi):
     import torch
     case = CASES["jet150x40x20"]

@@ -91,9 +91,55 @@ def test_stats_profiles_uniform_flow(lesmi):
     acc = None
     for _ in range(3):
         acc = s.stats_accumulate(s.upload(Q), acc)
-    prof = lesmi.stats_profiles(acc, 3 * n[2])
+    prof = s.stats_profiles(acc, 3 * n[2])
     for name, val in (("rho", rho), ("u", u), ("v", v), ("w", w), ("p", p)):
         assert torch.allclose(prof[name], torch.full_like(prof[name], val), rtol=1e-13, atol=0), name
     for name in ("u_rms", "v_rms", "w_rms", "p_rms"):
         assert float(prof[name].max()) <= 1e-7, name  # sqrt of a rounding-level difference
+    assert float(prof["uv"].abs().max()) <= 1e-14
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["jet61x29x23", "jet256x128x128"])
+def test_stats_profiles_match_oracle(orc, lesmi, name):
+    """les_stats_profiles against the oracle's profiles from the same sums
+    (the oracle's, uploaded): the means are IEEE quotients on both sides, so
+    they and the potential-core mask agree bit for bit; an RMS is
+    sqrt(<a a> - <a>^2), whose rounding (FMA or not) moves it by at most
+    sqrt(4 eps <a a>); the covariance by a few ulp of <u v> and <u><v>."""
+    import torch
+    case = _cases()[name]()
+    print(f"[gpu] stats profiles {name}", flush=True)
+    s = lesmi.Solver(case)
+    Q1, _, _, _ = orc.rk_step(case, orc.metrics(case), case["Q"])
+    acc = orc.stats(case, case["Q"])
+    acc = orc.stats(case, Q1, acc)
+    samples = 2 * case["nk"]
+    u_jet = 1.4  # U_j = M_j c_inf
+    cores = {}
+    for frac in (0.95, 0.5):
+        prof_o, core_o = orc.stats_profiles(acc, samples, u_jet, frac)
+        got = s.stats_profiles(torch.from_numpy(acc).cuda(), samples, u_jet, frac)
+        torch.cuda.synchronize()
+        g = np.stack([got[f].cpu().numpy() for f in lesmi.PROF_FIELDS])
+        assert np.array_equal(g[:5], prof_o[:5])
+        assert np.array_equal(got["core"].cpu().numpy().astype(np.uint8), core_o)
+        eps = np.finfo(np.float64).eps
+        m = acc / samples
+        for f, sq in ((5, 5), (6, 6), (7, 7), (8, 11)):
+            bound = np.sqrt(4 * eps * np.abs(m[sq])) + 4 * eps * prof_o[f]
+            assert (np.abs(g[f] - prof_o[f]) <= bound).all(), lesmi.PROF_FIELDS[f]
+        bound = 4 * eps * (np.abs(m[8]) + np.abs(m[1] * m[2]))
+        assert (np.abs(g[9] - prof_o[9]) <= bound).all()
+        cores[frac] = core_o
+    # the core is a real region of the jet, neither empty nor everything, and
+    # the 95 % core lies inside the 50 % one
+    assert 0 < cores[0.95].sum() < cores[0.5].sum() < cores[0.5].size
+    assert (cores[0.95] <= cores[0.5]).all()
+    with pytest.raises(lesmi.LesError) as e:
+        s.stats_profiles(torch.from_numpy(acc).cuda(), 0.0)
+    assert e.value.code == lesmi.LES_ERR_ARG
+    with pytest.raises(lesmi.LesError) as e:
+        s.stats_profiles(torch.from_numpy(acc).cuda(), samples, u_jet, 1.5)
+    assert e.value.code == lesmi.LES_ERR_ARG
     s.close()

@@ -481,9 +481,10 @@ def test_paper_constants():
 # ---------------------------------------------------------------------------
 # Running statistics (mean-flow and RMS profiles of Sec. 6): closed forms
 # ---------------------------------------------------------------------------
-def _harmonic_state(ni, nj, nk, gamma):
+def _harmonic_state(ni, nj, nk, gamma, v_sin=False):
     """Primitives that vary along k by whole harmonics of the period nk (and
-    along i, j through the means), and the conserved state Q of Eq. 2."""
+    along i, j through the means), and the conserved state Q of Eq. 2.  The
+    fluctuation of v is B cos(th), or B sin(th) in phase with u's (v_sin)."""
     i = np.arange(-2, ni + 2)[None, None, :]
     j = np.arange(-2, nj + 2)[None, :, None]
     k = np.arange(-2, nk + 2)[:, None, None]
@@ -492,7 +493,7 @@ def _harmonic_state(ni, nj, nk, gamma):
     A, B, C, eps = 0.05, 0.03, 0.02, 0.1
     rho = 1.2 * (1.0 + eps * np.cos(2.0 * th)) + 0 * i * j
     u = U0 + A * np.sin(th) + 0 * j
-    v = V0 + B * np.cos(th) + 0 * i
+    v = V0 + B * (np.sin(th) if v_sin else np.cos(th)) + 0 * i
     w = 0.0 * (i + j + k)
     p = p0 + C * np.sin(th + 0.3)
     e = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
@@ -528,6 +529,37 @@ def test_stats_closed_forms(orc, nk):
     # a second call adds the same sums (time accumulation)
     acc2 = orc.stats(case, Q, acc.copy())
     np.testing.assert_allclose(acc2, 2 * acc, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("nk,v_sin", [(3, False), (16, False), (16, True)])
+def test_stats_profiles_closed_forms(orc, nk, v_sin):
+    """Sec. 6 profiles of the harmonic state, accumulated at two time levels:
+    means U0, V0, p0 (rho: 1.2, the cos(2 th) term averages out), RMS
+    A/sqrt(2), B/sqrt(2), 0, C/sqrt(2), and covariance <u'v'> = A B <sin cos>
+    = 0, or A B <sin^2> = A B / 2 when v's fluctuation is in phase (a u_rms
+    taken from <u u> without subtracting <u>^2, or a covariance from the
+    wrong pair, fails).  The potential core (<u> >= 0.95 u_jet) is i >= 4
+    for a threshold between U0 at i = 3 and i = 4."""
+    ni, nj = 6, 5
+    case = I.periodic_case(ni, nj, nk, I.wavy_grid(ni, nj, nk), np.zeros((5, nk + 4, nj + 4, ni + 4)))
+    Q, mm = _harmonic_state(ni, nj, nk, case["params"]["gamma"], v_sin=v_sin)
+    acc = orc.stats(case, Q)
+    acc = orc.stats(case, Q, acc)
+    u_jet = 0.335 / 0.95
+    prof, core = orc.stats_profiles(acc, 2 * nk, u_jet, 0.95)
+    A, B, C = mm["A"], mm["B"], mm["C"]
+    want = {
+        "rho": np.full((nj, ni), 1.2), "u": np.broadcast_to(mm["U0"][None, :], (nj, ni)),
+        "v": np.broadcast_to(mm["V0"][:, None], (nj, ni)), "w": np.zeros((nj, ni)), "p": mm["p0"],
+        "u_rms": np.full((nj, ni), A / np.sqrt(2)), "v_rms": np.full((nj, ni), B / np.sqrt(2)),
+        "w_rms": np.zeros((nj, ni)), "p_rms": np.full((nj, ni), C / np.sqrt(2)),
+        "uv": np.full((nj, ni), A * B / 2 if v_sin else 0.0),
+    }
+    for f, name in enumerate(orc.PROF_FIELDS):
+        # an RMS is the square root of a difference of O(1) means: its error is
+        # eps / rms, about 1e-14 here
+        np.testing.assert_allclose(prof[f], want[name], rtol=1e-12, atol=1e-12, err_msg=name)
+    assert np.array_equal(core, np.broadcast_to((np.arange(ni) >= 4)[None, :], (nj, ni)).astype(np.uint8))
 
 
 # ---------------------------------------------------------------------------
