@@ -283,6 +283,47 @@ def time_restart(case):
             "write_GBps": round(nbytes / tw / 1e9, 2), "read_GBps": round(nbytes / tr / 1e9, 2), "bitwise": same}
 
 
+def time_mesh_i(steps=3, warmup=1):
+    """The paper's largest mesh, mesh I of Tab. 2 (1700 x 1700 x 361 =
+    1.04e9 points), as one jet block on one GPU in FP64 (about 212 GB of
+    device memory: the generator's arrays are released before each
+    allocation)."""
+    import torch
+    from paper_2003_08746_amd import inputs, lesmi
+    ni, nj, nk = 1700, 1700, 361
+    torch.cuda.empty_cache()
+    case = inputs.jet_case_device(ni, nj, nk, seed=0)
+    torch.cuda.empty_cache()
+    s = lesmi.Solver(case)
+    case["xyz"] = None
+    torch.cuda.empty_cache()
+    Q = s.upload(case["Q"])
+    del case
+    torch.cuda.empty_cache()
+    try:
+        s.advance(Q, warmup)
+        s.cfl_dt(Q)
+        lesmi.les_debug_stage_timing(s.ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(Q, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stage_ms, launches = lesmi.les_debug_stage_time(s.ctx)
+        lesmi.les_debug_stage_timing(s.ctx, False)
+        s.rk_step(Q, 0.0, want_norms=True)  # raises on a non-finite state
+    finally:
+        s.close()
+        del Q
+        torch.cuda.empty_cache()
+    npts = ni * nj * nk
+    launch_s = stage_ms / launches / 1e3
+    return dict(workload=f"mesh I of Tab. 2 as one jet block {ni}x{nj}x{nk}, FP64", points=npts, steps=steps,
+                value=round(npts * 5 * steps / wall / 1e6, 2), unit="Mpoint-RK-stages/s",
+                ms_per_step=round(wall * 1e3 / steps, 2), avg_stage_launch_us=round(launch_s * 1e6, 1),
+                stage_frac_of_hbm_peak=round(BYTES_FP64 * npts / launch_s / 1e9 / HBM_PEAK_GBS, 4))
+
+
 def time_shard(case, steps, warmup, label):
     """FP64 and mixed legs of one jet shard: throughput, stage-kernel launch
     time and algorithmic bandwidth, mixed speedup and the mixed path's
@@ -355,7 +396,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip every leg but the headline (mixed, small shard, adjoint, faces, statistics, "
-                         "restart, copy)")
+                         "restart, copy, mesh I)")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -442,7 +483,8 @@ def main():
                         ("faces", lambda: time_faces(small, args.small_steps, 5)),
                         ("stats", lambda: time_stats(small)),
                         ("restart", lambda: time_restart(small)),
-                        ("copy", time_copy)):
+                        ("copy", time_copy),
+                        ("mesh_i", time_mesh_i)):
             print(f"[bench] extra: {key}", file=sys.stderr, flush=True)
             try:
                 extra[key] = fn()

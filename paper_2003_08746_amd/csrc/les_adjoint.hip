@@ -157,21 +157,7 @@ struct AdjK {
   int lo[3], hi[3];    // pass-2 box: ghost layers of periodic axes and of active faces included
   Faces F;             // boundary faces
   int general;         // a superposed axis or an active face: pass 3 visits every interior node
-  int nxcd;            // XCDs of the device
-  unsigned xper;       // blocks per XCD of the launch (set per launch)
 };
-
-// Thread index of a one-dimensional pass in an XCD-aware block order: the
-// hardware hands block b to XCD b mod nxcd, so block b takes the slot
-// (b mod nxcd) xper + b / nxcd.  Each XCD then walks one contiguous slab of
-// nodes in order, and the neighbours a node gathers (one row or one plane
-// away) were mostly brought into that XCD's L2 by the blocks just before
-// it.  The grid holds nxcd xper blocks; slots past the work exit through
-// each pass's bound check.
-__device__ __forceinline__ unsigned adj_tid(const AdjK& A) {
-  const unsigned b = blockIdx.x;
-  return ((b % (unsigned)A.nxcd) * A.xper + b / (unsigned)A.nxcd) * blockDim.x + threadIdx.x;
-}
 
 AdjK make_adjk(const AdjArgs& a) {
   AdjK A;
@@ -183,8 +169,6 @@ AdjK make_adjk(const AdjArgs& a) {
   A.bc2 = a.bc2;
   A.F = a.F;
   A.general = 0;
-  A.nxcd = a.nxcd > 0 ? a.nxcd : 1;
-  A.xper = 0;
   const int bc[3] = {a.bc0, a.bc1, a.bc2}, nn[3] = {a.L.ni, a.L.nj, a.L.nk};
   for (int d = 0; d < 3; ++d) {
     A.per[d] = bc[d] == 0 ? nn[d] : (bc[d] == 2 ? nn[d] - 1 : 0);
@@ -207,7 +191,7 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
   const double* __restrict__ M = A.M;
   // (every box of nodes here has fewer than 2^29 nodes: 32-bit index math)
   const unsigned ext_i = L.ni + 2, ext_j = L.nj + 2;
-  const unsigned t = adj_tid(A);
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ext_i * ext_j * (unsigned)(L.nk + 2)) return;
   const int i = (int)(t % ext_i) - 1;
   const int j = (int)((t / ext_i) % ext_j) - 1;
@@ -387,7 +371,7 @@ __global__ void __launch_bounds__(256) k_adj_face(AdjK A, const double* __restri
   const long long fe = L.fe;
   const unsigned ni = L.ni, nj = L.nj, nk = L.nk;
   const unsigned F0 = (ni + 1) * nj * nk, F1 = ni * (nj + 1) * nk, F2 = ni * nj * (nk + 1);
-  unsigned t = adj_tid(A);
+  unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= F0 + F1 + F2) return;
   int d, ai, aj, ak;
   if (t < F0) {
@@ -445,7 +429,7 @@ __global__ void __launch_bounds__(256) k_adj_dnode(AdjK A, const double* __restr
   const long long fe = L.fe;
   const double* __restrict__ M = A.M;
   const unsigned ext_i = L.ni + 2, ext_j = L.nj + 2;
-  const unsigned t = adj_tid(A);
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ext_i * ext_j * (unsigned)(L.nk + 2)) return;
   const int i = (int)(t % ext_i) - 1;
   const int j = (int)((t / ext_i) % ext_j) - 1;
@@ -559,7 +543,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
   const Phys& P = A.P;
   const long long fe = L.fe;
   const unsigned ri = A.hi[0] - A.lo[0] + 1, rj = A.hi[1] - A.lo[1] + 1, rk = A.hi[2] - A.lo[2] + 1;
-  const unsigned t = adj_tid(A);
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ri * rj * rk) return;
   const int i = (int)(t % ri) + A.lo[0];
   const int j = (int)((t / ri) % rj) + A.lo[1];
@@ -676,7 +660,7 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restri
   }
   const unsigned ni = nn[0], nj = nn[1];
   const unsigned S2 = bs[2] * nj * ni, S1 = cs[2] * bs[1] * ni, S0 = cs[2] * cs[1] * bs[0];
-  unsigned t = adj_tid(A);
+  unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= S2 + S1 + S0) return;
   int i, j, k;
   if (t < S2) {
@@ -731,7 +715,7 @@ __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* 
                                                           const double* __restrict__ acc, double* __restrict__ fbar,
                                                           int i_f, double fw, double* __restrict__ qfin) {
   const Layout& L = A.L;
-  const unsigned t = adj_tid(A);
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
   if (t >= nij * (unsigned)L.nk) return;
   const int i = (int)(t % ni), j = (int)((t % nij) / ni), k = (int)(t / nij);
@@ -851,22 +835,14 @@ hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const dou
     }
     nBand = bs[2] * nn[1] * nn[0] + cs[2] * bs[1] * nn[0] + cs[2] * cs[1] * bs[0];
   }
-  // XCD-aware grid of a pass over n items (see adj_tid)
-  auto K = [&](long long n) {
-    AdjK k = A;
-    k.xper = (nb(n, 256) + k.nxcd - 1) / k.nxcd;
-    return k;
-  };
-  auto G = [](const AdjK& k) { return k.xper * (unsigned)k.nxcd; };
-  const AdjK kB1 = K(nB1), kFace = K(nFace), kB = K(nB), kIn = K(nIn), kBand = K(nBand);
-  k_adj_flux<<<G(kB1), 256, 0, s>>>(kB1, Q, qb, coef, Wk);
-  k_adj_face<<<G(kFace), 256, 0, s>>>(kFace, Q, qb, coef, Wk);
-  k_adj_dnode<<<G(kB1), 256, 0, s>>>(kB1, Q, Wk);
-  k_adj_gather<<<G(kB), 256, 0, s>>>(kB, Q, Wk, qout, acc, qb, fbar, i_f, fw, qfin);
+  k_adj_flux<<<nb(nB1, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
+  k_adj_face<<<nb(nFace, 256), 256, 0, s>>>(A, Q, qb, coef, Wk);
+  k_adj_dnode<<<nb(nB1, 256), 256, 0, s>>>(A, Q, Wk);
+  k_adj_gather<<<nb(nB, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, qb, fbar, i_f, fw, qfin);
   if (A.general)
-    k_adj_fold_general<<<G(kIn), 256, 0, s>>>(kIn, Q, Wk, qout, acc, fbar, i_f, fw, qfin);
+    k_adj_fold_general<<<nb(nIn, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, fbar, i_f, fw, qfin);
   else if (nBand > 0)
-    k_adj_fold<<<G(kBand), 256, 0, s>>>(kBand, Wk, qout, acc, fbar, i_f, fw, qfin);
+    k_adj_fold<<<nb(nBand, 256), 256, 0, s>>>(A, Wk, qout, acc, fbar, i_f, fw, qfin);
   return hipGetLastError();
 }
 

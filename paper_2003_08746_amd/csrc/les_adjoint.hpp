@@ -12,7 +12,6 @@ struct AdjArgs {
   int bc0, bc1, bc2;  // 0 periodic, 1 Dirichlet, 2 periodic with superposed first and last nodes
   int i_f;
   Faces F;            // boundary faces of the Dirichlet directions
-  int nxcd;           // XCDs of the device (blocks are handed out round robin over them)
 };
 
 // Device work elements (doubles) needed by run_adjoint_step.

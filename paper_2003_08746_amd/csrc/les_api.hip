@@ -627,7 +627,7 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
                                     "the isotropic SGS stress (sgs <= 1, CI = 0) on blocks without the axis");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
-  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx), ctx->mach.xcds};
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
   HIPCHK(ctx, les::run_adjoint_step(ctx->s, a, stage_ckpt, dt, Qbar, ctx->i_f >= 0 ? fbar : nullptr, ctx->adj));
   return LES_OK;
 }
@@ -686,7 +686,7 @@ int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qb
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
   HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
-  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx), ctx->mach.xcds};
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
   HIPCHK(ctx, les::run_residual_vjp(ctx->s, a, Q, Rbar, Qbar, ctx->adj));
   return LES_OK;
 }
