@@ -270,7 +270,11 @@ int les_advance(les_ctx *ctx, double *Q, int nsteps, double *dt_out, double *nor
  * stage_ckpt: device, as written by les_rk_step with the same dt.
  * Qbar: device, library layout, FP64, in: dJ/dQ^{n+1} (interior), out: dJ/dQ^n
  *    (interior; ghost layers are used as scratch).
- * fbar: device, dense [5][nk][nj], accumulated, or NULL. */
+ * fbar: device, dense [5][nk][nj], accumulated, or NULL.
+ * The first adjoint call allocates the work arrays (84 fields of field_elems
+ * doubles; LES_ERR_NOMEM if they do not fit).  LES_ERR_STATE for the
+ * dynamic closure, the isotropic SGS stress or the axis, and for a block of
+ * 2^30 padded nodes or more. */
 int les_adjoint_step(les_ctx *ctx, const double *stage_ckpt, double dt, double *Qbar, double *fbar);
 
 /* Adjoint (vector-Jacobian product) of the residual at Q:

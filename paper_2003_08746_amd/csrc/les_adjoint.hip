@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
   const Phys& P = A.P;
   const long long fe = L.fe;
   const double* __restrict__ M = A.M;
-  // (every box of nodes here has fewer than 2^29 nodes: 32-bit index math)
+  // (the adjoint entry points refuse blocks of 2^30 padded nodes or more: 32-bit index math)
   const unsigned ext_i = L.ni + 2, ext_j = L.nj + 2;
   const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ext_i * ext_j * (unsigned)(L.nk + 2)) return;

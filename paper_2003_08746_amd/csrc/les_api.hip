@@ -193,11 +193,11 @@ static int timing_end(les_ctx* c) {
 
 // Adjoint work arrays are allocated on first use and kept by the context.
 static int ensure_adj_work(les_ctx* c) {
-  // the adjoint passes index the nodes of the padded box with 32-bit
-  // integers (their work arrays limit the block far below that anyway)
+  // the adjoint passes index nodes and faces (about three per node) with
+  // 32-bit integers (their work arrays limit the block far below that anyway)
   const long long box = (long long)(c->L.ni + 4) * (c->L.nj + 4) * (c->L.nk + 4);
-  if (box >= (1LL << 31))
-    return fail(c, LES_ERR_STATE, "adjoint: block too large (%lld padded nodes, limit 2^31)", box);
+  if (box >= (1LL << 30))
+    return fail(c, LES_ERR_STATE, "adjoint: block too large (%lld padded nodes, limit 2^30)", box);
   const size_t need = les::adjoint_work_elems(c->L);
   if ((long long)need <= c->adj_n) return LES_OK;
   (void)hipFree(c->adj);
