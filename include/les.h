@@ -250,7 +250,9 @@ int les_rk_step(les_ctx *ctx, double *Q, double dt, double *dt_out, double *norm
  * nsteps >= 1 (LES_ERR_ARG otherwise).
  * dt_out: host double[nsteps] or NULL: the time step of every step (then
  *    nsteps <= LES_ADVANCE_DT_MAX, else LES_ERR_ARG).
- * norms: host double[10] or NULL: norms of R(Q^n) of the last step.
+ * norms: host double[10] or NULL: norms of R(Q^n) of the last step (only
+ *    the last step reduces them; a non-finite state of an earlier step shows
+ *    in the next step's dt reduction).
  * A non-finite dt or norm found on the way is reported as LES_ERR_NONFINITE
  * when dt_out or norms is given (the call then synchronises). */
 #define LES_ADVANCE_DT_MAX 4096

@@ -507,7 +507,12 @@ int les_set_forcing(les_ctx* ctx, const double* f, int i_f) {
 // stages (time step read from dtp on the device when not null, else dt),
 // norm reduction of R(Q^n).  cpart (or null): the last stage also reduces
 // the per-block CFL bounds of Q^{n+1} into it (fused kernel only).
-static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, double* stage_ckpt, double* cpart) {
+// One Runge-Kutta step of Q.  with_norms: stage 1 reduces the residual norms
+// of R(Q^n) (and their non-finite flag); les_advance leaves them out of every
+// step but its last, whose non-finite states the next step's dt reduction
+// reports instead.
+static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, double* stage_ckpt, double* cpart,
+                     bool with_norms = true) {
   les::Layout& L = ctx->L;
   const size_t fe = (size_t)L.fe;
   const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
@@ -523,12 +528,14 @@ static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, doub
       if (trc != LES_OK) return trc;
       HIPCHK(ctx, les::launch_stage_mixed(ctx->s, a, l == 0 ? Q : nullptr, in32, Q, l == 4 ? Q : nullptr,
                                           l == 4 ? nullptr : ctx->Sf[l & 1], dtp, dt, les::rk_alpha(l),
-                                          l == 0 ? ctx->part : nullptr, l == 4 ? cpart : nullptr));
+                                          (l == 0 && with_norms) ? ctx->part : nullptr, l == 4 ? cpart : nullptr));
       trc = timing_end(ctx);
       if (trc != LES_OK) return trc;
     }
     if (ctx->axis) HIPCHK(ctx, les::launch_axis_avg(ctx->s, L, Q));
-    HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::stage_blocks(L, ctx->kchunk, ctx->mach), cnt, ctx->scal + 1, ctx->flag));
+    if (with_norms)
+      HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, les::stage_blocks(L, ctx->kchunk, ctx->mach), cnt,
+                                         ctx->scal + 1, ctx->flag));
   } else {
     if (stage_ckpt) HIPCHK(ctx, hipMemcpyAsync(stage_ckpt, Q, 5 * fe * sizeof(double), hipMemcpyDeviceToDevice, ctx->s));
     const double* in = stage_ckpt ? stage_ckpt : Q;
@@ -536,9 +543,9 @@ static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, doub
       double* out = l == 4 ? Q : (stage_ckpt ? stage_ckpt + (size_t)(l + 1) * 5 * fe : ctx->S[l & 1]);
       if (l > 0 && ctx->axis) HIPCHK(ctx, les::launch_axis_avg(ctx->s, L, (double*)in));
       if (l > 0 || stage_ckpt) HIPCHK(ctx, les::launch_ghost_fill(ctx->s, L, ctx->bc, (double*)in, Q, 5, faces_of(ctx)));
-      // the residual norms of R(Q^n) are always reduced on the device (fused
-      // into stage 1); only their copy to the host is optional
-      double* part = l == 0 ? ctx->part : nullptr;
+      // the residual norms of R(Q^n) are reduced on the device (fused into
+      // stage 1) whenever with_norms; only their copy to the host is optional
+      double* part = (l == 0 && with_norms) ? ctx->part : nullptr;
       HIPCHK(ctx, dyn_update(ctx, in, nullptr));
       int trc = timing_begin(ctx);
       if (trc != LES_OK) return trc;
@@ -556,7 +563,7 @@ static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, doub
     }
     if (ctx->axis) HIPCHK(ctx, les::launch_axis_avg(ctx->s, L, Q));
     long long nb = ctx->use_ref ? les::ref_blocks(L) : les::stage_blocks(L, ctx->kchunk, ctx->mach);
-    HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
+    if (with_norms) HIPCHK(ctx, les::launch_norm_final(ctx->s, ctx->part, nb, cnt, ctx->scal + 1, ctx->flag));
   }
   return LES_OK;
 }
@@ -603,7 +610,7 @@ int les_advance(les_ctx* ctx, double* Q, int nsteps, double* dt_out, double* nor
     double* dnext = ctx->scal + ((n & 1) ? 0 : 12);
     const bool more = n + 1 < nsteps;
     if (n > 0) HIPCHK(ctx, bc_fill(ctx, Q));
-    int rc = step_core(ctx, Q, dtp, 0.0, nullptr, (more && !ctx->use_ref) ? ctx->cpart : nullptr);
+    int rc = step_core(ctx, Q, dtp, 0.0, nullptr, (more && !ctx->use_ref) ? ctx->cpart : nullptr, !more);
     if (rc != LES_OK) return rc;
     if (!more) break;
     double* rec = dt_out ? ctx->dthist + n + 1 : nullptr;

@@ -81,6 +81,26 @@ def test_advance_parity(orc, lesmi, name):
     s.close()
 
 
+def test_advance_reports_blowup(lesmi):
+    """An unstable time step (CFL 20 instead of 0.5): the state leaves the
+    physical range within a few steps, and les_advance reports it
+    (LES_ERR_NONFINITE) through the dt reduction of the following steps,
+    since only its last step reduces residual norms."""
+    case, _ = SMALL["tgv32"]
+    case = dict(case)
+    case["params"] = dict(case["params"], cfl=20.0)
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    with pytest.raises(lesmi.LesError) as e:
+        s.advance(Q, 200, want_dt=True)
+    assert e.value.code == lesmi.LES_ERR_NONFINITE
+    # the context stays usable
+    Q = s.upload(case["Q"])
+    dts, _ = s.advance(Q, 1, want_dt=True)
+    assert dts[0] > 0
+    s.close()
+
+
 def test_advance_arguments(lesmi):
     case, _ = SMALL["tgv32"]
     s = lesmi.Solver(case)
