@@ -118,6 +118,40 @@ def test_caller_metrics(orc, lesmi):
     assert (_rel(R3, Ro) <= TOL).all(), _rel(R3, Ro)
 
 
+DEGENERATE = {
+    "sgs0": dict(sgs=0),                          # the paper's runs: no SGS model
+    "euler": dict(sgs=0, mu_ref=0.0),             # no viscosity at all
+    "k2_0": dict(k2=0.0),                         # fourth differences only
+    "k4_0": dict(k4=0.0),                         # second differences only
+    "no_dissipation": dict(k2=0.0, k4=0.0),
+    "alpha1": dict(alpha=1.0),                    # Lambda_d = lam_d + lam_e + lam_f
+}
+
+
+@pytest.mark.parametrize("name", list(DEGENERATE))
+def test_degenerate_parameters(orc, lesmi, name):
+    """Parameter values where terms of the method vanish or its general
+    branches reduce: the residual and two CFL steps against the oracle at
+    the FP64 bar, on the ragged jet block."""
+    base = CASES["jet150x40x20"]
+    case = dict(base)
+    case["params"] = dict(base["params"], **DEGENERATE[name])
+    print(f"[gpu] degenerate {name}", flush=True)
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    m = orc.metrics(case)
+    Rg = s.download(s.residual(Q))
+    Ro = orc.residual(case, m, case["Q"])
+    assert (_rel(Rg, Ro) <= TOL).all(), _rel(Rg, Ro)
+    Qo = case["Q"]
+    for n in range(2):
+        dt, _ = s.rk_step(Q, 0.0, want_dt=True)
+        Qo, dto, _, _ = orc.rk_step(case, m, Qo)
+        assert abs(dt - dto) <= 1e-14 * dto, (n, dt, dto)
+    assert (_rel(s.download(Q), Qo) <= TOL).all(), _rel(s.download(Q), Qo)
+    s.close()
+
+
 def test_residual_with_source(orc, lesmi):
     import torch
     case = CASES["jet150x40x20"]
