@@ -157,12 +157,14 @@ typedef struct {
  * grid->xyz is ignored (it may be NULL).  hip_stream: a hipStream_t (NULL =
  * default stream).
  * Returns LES_ERR_ARG for a null out/grid/params, no coordinates and no
- * metrics, n < 5, bad bc (LES_BC_AXIS
- * elsewhere than j, or without a superposed k of odd nk, or with sgs = 2),
- * gamma <= 1,
+ * metrics, n < 5, a padded k plane so large that seven of them reach 2^29
+ * elements (the stage kernel's 32-bit offsets from its per-segment base;
+ * about 7.7e7 nodes per plane), bad bc (LES_BC_AXIS elsewhere than j, or
+ * without a superposed k of odd nk, or with sgs = 2), gamma <= 1,
  * R_gas <= 0, Pr <= 0, negative k2/k4/mu_ref/CI, sgs outside 0..2, unknown
- * prec.  sgs = 2 allocates the dynamic closure's work arrays (50 fields of
- * field_elems doubles) here. */
+ * prec; LES_ERR_NOMEM when the block's arrays (20 FP64 fields of
+ * field_elems doubles, 10 more FP32 ones when mixed) do not fit.  sgs = 2
+ * allocates the dynamic closure's work arrays (50 fields) here too. */
 int les_create(les_ctx **out, const les_grid *grid, const les_metrics *metrics,
                const les_flow_params *params, void *hip_stream);
 
