@@ -144,7 +144,7 @@ def _dims_of(case):
             d.p_exit[f] = float(fc.get("p_exit", [0.0] * 6)[f])
         out = fc.get("outside")
         if out is not None:
-            out = _c(out)
+            out = _pad(case, out, 5)
             assert out.shape == (5, case["nk"] + 4, case["nj"] + 4, case["ni"] + 4)
             d._outside_ref = out  # keep alive while d is used
             d.outside = out.ctypes.data
@@ -155,11 +155,30 @@ def _c(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _pad(case, a, nf=None):
+    """a as a contiguous float64 array of shape (nf, nk+4, nj+4, ni+4) for
+    the block of case (any nf when None): the C code trusts the shapes, so
+    a mismatch is refused here instead of read out of bounds."""
+    a = _c(a)
+    want = (case["nk"] + 4, case["nj"] + 4, case["ni"] + 4)
+    if a.ndim != 4 or a.shape[1:] != want or (nf is not None and a.shape[0] != nf):
+        raise ValueError(f"oracle: array of shape {a.shape} for a block wanting ({nf}, {want[0]}, {want[1]}, {want[2]})")
+    return a
+
+
+def _forc(case, f):
+    """A forcing plane array (5, nk, nj), contiguous float64, shape checked."""
+    f = _c(f)
+    if f.shape != (5, case["nk"], case["nj"]):
+        raise ValueError(f"oracle: forcing of shape {f.shape}, want (5, {case['nk']}, {case['nj']})")
+    return f
+
+
 def metrics(case) -> np.ndarray:
     """Metrics (10, nk+4, nj+4, ni+4) from the coordinates case['xyz'];
     defined on nodes with all indices in [-1, n], NaN elsewhere."""
     lib = _load()
-    xyz = _c(case["xyz"])
+    xyz = _pad(case, case["xyz"], 3)
     m = np.empty((10,) + xyz.shape[1:], dtype=np.float64)
     lib.orc_metrics(ctypes.byref(_dims_of(case)), _ptr(xyz), _ptr(m))
     return m
@@ -167,7 +186,7 @@ def metrics(case) -> np.ndarray:
 
 def fill_ghosts(case, a: np.ndarray) -> np.ndarray:
     lib = _load()
-    a = _c(a).copy()
+    a = _pad(case, a).copy()
     lib.orc_fill_ghosts(ctypes.byref(_dims_of(case)), _ptr(a), a.shape[0])
     return a
 
@@ -177,8 +196,8 @@ def fill_ghosts_faces(case, m, Q, prm=None) -> np.ndarray:
     ghosts and the boundary faces of case["faces"]."""
     lib = _load()
     prm = case["params"] if prm is None else prm
-    q = _c(Q).copy()
-    lib.orc_fill_ghosts_faces(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(q))
+    q = _pad(case, Q, 5).copy()
+    lib.orc_fill_ghosts_faces(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, m, 10)), _ptr(q))
     return q
 
 
@@ -186,10 +205,10 @@ def residual(case, m, Q, prm=None, f=None, i_f=-1) -> np.ndarray:
     """R(Q) on the padded box (zeros in the ghost layers)."""
     lib = _load()
     prm = case["params"] if prm is None else prm
-    Q = _c(Q)
+    Q = _pad(case, Q, 5)
     R = np.zeros_like(Q)
-    fa = None if f is None else _c(f)
-    lib.orc_residual(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q), _ptr(fa),
+    fa = None if f is None else _forc(case, f)
+    lib.orc_residual(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, m, 10)), _ptr(Q), _ptr(fa),
                      int(i_f), _ptr(R))
     return R
 
@@ -198,9 +217,9 @@ def residual_nofill(case, m, Q, prm=None) -> np.ndarray:
     """R(Q) with Q's ghost layers and axis nodes taken as given (no fill)."""
     lib = _load()
     prm = case["params"] if prm is None else prm
-    Q = _c(Q)
+    Q = _pad(case, Q, 5)
     R = np.zeros_like(Q)
-    lib.orc_residual_nofill(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q), _ptr(R))
+    lib.orc_residual_nofill(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, m, 10)), _ptr(Q), _ptr(R))
     return R
 
 
@@ -208,12 +227,12 @@ def residual_tangent(case, m, Q, dQ, prm=None, f=None, df=None, i_f=-1):
     """(R, dR) with dR the exact directional derivative of R along (dQ, df)."""
     lib = _load()
     prm = case["params"] if prm is None else prm
-    Q = _c(Q)
+    Q = _pad(case, Q, 5)
     R = np.zeros_like(Q)
     dR = np.zeros_like(Q)
-    lib.orc_residual_tangent(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q),
-                             _ptr(None if dQ is None else _c(dQ)), _ptr(None if f is None else _c(f)),
-                             _ptr(None if df is None else _c(df)), int(i_f), _ptr(R), _ptr(dR))
+    lib.orc_residual_tangent(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, m, 10)), _ptr(Q),
+                             _ptr(None if dQ is None else _pad(case, dQ, 5)), _ptr(None if f is None else _forc(case, f)),
+                             _ptr(None if df is None else _forc(case, df)), int(i_f), _ptr(R), _ptr(dR))
     return R, dR
 
 
@@ -224,37 +243,37 @@ def dynamic_coefficients(case, m, Q, prm=None):
     prm = case["params"] if prm is None else prm
     C = np.zeros((case["nj"] + 4, case["ni"] + 4))
     D = np.zeros_like(C)
-    lib.orc_dynamic_coefficients(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)),
-                                 _ptr(_c(Q)), _ptr(C), _ptr(D))
+    lib.orc_dynamic_coefficients(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, m, 10)),
+                                 _ptr(_pad(case, Q, 5)), _ptr(C), _ptr(D))
     return C, D
 
 
 def cfl_dt(case, m, Q, prm=None) -> float:
     lib = _load()
     prm = case["params"] if prm is None else prm
-    return lib.orc_cfl_dt(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(_c(Q)))
+    return lib.orc_cfl_dt(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, m, 10)), _ptr(_pad(case, Q, 5)))
 
 
 def rk_step(case, m, Q, dt=0.0, prm=None, f=None, i_f=-1, want_stages=False):
     """One RK step from Q (not modified).  Returns (Q_next, dt, norms[10], stages|None)."""
     lib = _load()
     prm = case["params"] if prm is None else prm
-    Qn = _c(Q).copy()
+    Qn = _pad(case, Q, 5).copy()
     norms = np.zeros(10, dtype=np.float64)
     stages = np.zeros((5,) + Qn.shape, dtype=np.float64) if want_stages else None
-    dt_used = lib.orc_rk_step(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Qn),
-                              float(dt), _ptr(None if f is None else _c(f)), int(i_f), _ptr(norms), _ptr(stages))
+    dt_used = lib.orc_rk_step(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, m, 10)), _ptr(Qn),
+                              float(dt), _ptr(None if f is None else _forc(case, f)), int(i_f), _ptr(norms), _ptr(stages))
     return Qn, dt_used, norms, stages
 
 
 def rk_step_tangent(case, m, Q, dQ, dt, f=None, df=None, i_f=-1):
     """One RK step at fixed dt with its exact tangent: returns (Q_next, dQ_next)."""
     lib = _load()
-    Qn = _c(Q).copy()
-    dQn = _c(dQ).copy()
-    lib.orc_rk_step_tangent(ctypes.byref(_dims_of(case)), ctypes.byref(params(case["params"])), _ptr(_c(m)),
-                            _ptr(Qn), _ptr(dQn), float(dt), _ptr(None if f is None else _c(f)),
-                            _ptr(None if df is None else _c(df)), int(i_f))
+    Qn = _pad(case, Q, 5).copy()
+    dQn = _pad(case, dQ, 5).copy()
+    lib.orc_rk_step_tangent(ctypes.byref(_dims_of(case)), ctypes.byref(params(case["params"])), _ptr(_pad(case, m, 10)),
+                            _ptr(Qn), _ptr(dQn), float(dt), _ptr(None if f is None else _forc(case, f)),
+                            _ptr(None if df is None else _forc(case, df)), int(i_f))
     return Qn, dQn
 
 
@@ -263,20 +282,20 @@ def objective_rollout(case, m, Q0, f, df, i_f, i_p, p_inf, nsteps, dt, dQ0=None)
     derivative along (dQ0, df) computed with dual numbers."""
     lib = _load()
     prm = case["params"]
-    Q = _c(Q0).copy()
+    Q = _pad(case, Q0, 5).copy()
     dJ = ctypes.c_double(0.0)
-    J = lib.orc_objective_rollout(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(m)), _ptr(Q),
-                                  _ptr(None if dQ0 is None else _c(dQ0)), _ptr(_c(f)),
-                                  _ptr(None if df is None else _c(df)), int(i_f), int(i_p), float(p_inf),
+    J = lib.orc_objective_rollout(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, m, 10)), _ptr(Q),
+                                  _ptr(None if dQ0 is None else _pad(case, dQ0, 5)), _ptr(_forc(case, f)),
+                                  _ptr(None if df is None else _forc(case, df)), int(i_f), int(i_p), float(p_inf),
                                   int(nsteps), float(dt), ctypes.byref(dJ))
     return J, dJ.value
 
 
 def objective(case, m, Q0, f, i_f, i_p, p_inf, nsteps, dt):
     lib = _load()
-    Q = _c(Q0).copy()
-    return lib.orc_objective(ctypes.byref(_dims_of(case)), ctypes.byref(params(case["params"])), _ptr(_c(m)),
-                             _ptr(Q), _ptr(_c(f)), int(i_f), int(i_p), float(p_inf), int(nsteps), float(dt))
+    Q = _pad(case, Q0, 5).copy()
+    return lib.orc_objective(ctypes.byref(_dims_of(case)), ctypes.byref(params(case["params"])), _ptr(_pad(case, m, 10)),
+                             _ptr(Q), _ptr(_forc(case, f)), int(i_f), int(i_p), float(p_inf), int(nsteps), float(dt))
 
 
 def rk_scalar(lam: complex, dt: float, y0: complex = 1.0) -> complex:
@@ -301,7 +320,7 @@ def stats(case, Q, acc=None, prm=None) -> np.ndarray:
         acc = np.zeros((len(STATS_FIELDS), case["nj"], case["ni"]))
     assert acc.shape == (len(STATS_FIELDS), case["nj"], case["ni"]) and acc.dtype == np.float64
     assert acc.flags.c_contiguous
-    lib.orc_stats(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_c(Q)), _ptr(acc))
+    lib.orc_stats(ctypes.byref(_dims_of(case)), ctypes.byref(params(prm)), _ptr(_pad(case, Q, 5)), _ptr(acc))
     return acc
 
 

@@ -435,11 +435,15 @@ def test_isentropic_vortex_second_order(orc):
 # Dual-number tangent of the oracle against central finite differences, and
 # the source term R12.
 # ---------------------------------------------------------------------------
-def test_tangent_matches_finite_differences(orc):
+@pytest.mark.parametrize("CI", [0.0, 0.05])
+def test_tangent_matches_finite_differences(orc, CI):
+    """The oracle's dual-number tangent of the residual against central
+    differences, with and without the isotropic SGS stress."""
     n = (12, 10, 8)
     xyz = I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3)
     Q = I.smooth_state(*n, seed=7, amp=0.1)
     case = _case(*n, xyz, Q, mu_ref=5e-3, sgs=1)
+    case["params"]["CI"] = CI
     m = orc.metrics(case)
     rng = np.random.default_rng(11)
     dQ = rng.standard_normal(Q.shape) * np.abs(Q).mean(axis=(1, 2, 3))[:, None, None, None]
@@ -1171,3 +1175,21 @@ def test_axis_mms_second_order(orc):
     errs = np.array(errs)
     orders = np.log2(errs[:-1] / errs[1:])
     assert (orders[-1] > 1.7).all() and (orders[0] > 1.2).all(), (errs, orders)
+
+
+def test_oracle_refuses_mismatched_shapes(orc):
+    """The oracle's C code trusts array shapes; its wrapper refuses arrays
+    that do not fit the block (a coordinate array of another block once
+    corrupted the heap of a test run)."""
+    n = (6, 5, 7)
+    case = I.periodic_case(*n, I.wavy_grid(5, 6, 7), I.smooth_state(*n, seed=1))
+    with pytest.raises(ValueError):
+        orc.metrics(case)
+    case = I.periodic_case(*n, I.wavy_grid(*n), I.smooth_state(*n, seed=1))
+    m = orc.metrics(case)
+    with pytest.raises(ValueError):
+        orc.residual(case, m, case["Q"][:, 1:])
+    with pytest.raises(ValueError):
+        orc.residual(case, m[:9], case["Q"])
+    with pytest.raises(ValueError):
+        orc.residual(case, m, case["Q"], f=np.zeros((5, n[1], n[2])), i_f=1)
