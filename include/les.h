@@ -125,7 +125,8 @@ typedef struct {
  *   CI >= 0 (sgs >= 1): Yoshizawa's isotropic SGS stress (Eq. 11)
  *   sigma_kk = 2 CI rho Delta^2 |S|^2, added as sigma_kk/3 to the pressure of
  *   the momentum and energy fluxes (Eq. 1); CI = 0 leaves it out.
- *   The adjoint entry points need sgs <= 1 and CI = 0 (LES_ERR_STATE).
+ *   The adjoint entry points need sgs <= 1 (LES_ERR_STATE); they differentiate
+ *   the isotropic SGS stress with the rest of the residual.
  * Turkel-Vatsa dissipation constants k2, k4 and anisotropy exponent alpha:
  *   D = Lam_face (eps2 dQ - eps4 d3Q), eps2 = k2 max(nu_a, nu_b),
  *   eps4 = max(0, k4 - eps2), nu = |p+ - 2p + p-| / (p+ + 2p + p-),
@@ -277,8 +278,8 @@ int les_advance(les_ctx *ctx, double *Q, int nsteps, double *dt_out, double *nor
  * fbar: device, dense [5][nk][nj], accumulated, or NULL.
  * The first adjoint call allocates the work arrays (84 fields of field_elems
  * doubles; LES_ERR_NOMEM if they do not fit).  LES_ERR_STATE for the
- * dynamic closure, the isotropic SGS stress or the axis, and for a block of
- * 2^30 padded nodes or more. */
+ * dynamic closure or the axis, and for a block of 2^30 padded nodes or
+ * more. */
 int les_adjoint_step(les_ctx *ctx, const double *stage_ckpt, double dt, double *Qbar, double *fbar);
 
 /* Adjoint (vector-Jacobian product) of the residual at Q:

@@ -237,13 +237,20 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
   const double th = q.T * P.inv_Tref;
   const double ithS = rcp_nr(th + P.S);
   const double mu = P.mu_ref * P.one_plus_S * th * sqrt_pos(th) * ithS;
-  double mus = 0.0, Smag = 0.0, cd2 = 0.0;
+  double mus = 0.0, Smag = 0.0, cd2 = 0.0, ss = 0.0, cid2 = 0.0, pis = 0.0;
   if (P.sgs) {
-    Smag = sqrt_nn(2.0 * (S11 * S11 + S22 * S22 + S33 * S33 + 2.0 * (S12 * S12 + S13 * S13 + S23 * S23)));
+    ss = S11 * S11 + S22 * S22 + S33 * S33 + 2.0 * (S12 * S12 + S13 * S13 + S23 * S23);
+    Smag = sqrt_nn(2.0 * ss);
     double d2 = icbrt(J);  // (1/J)^(1/3)
     cd2 = P.Cs2 * d2 * d2;
     mus = q.rho * cd2 * Smag;
+    // isotropic SGS stress: sigma_kk / 3 = CI43 rho D^2 S:S, added to the
+    // pressure of the momentum and energy fluxes (not to the sensor or the
+    // spectral radii)
+    cid2 = P.CI43 * d2 * d2;
+    pis = q.rho * cid2 * ss;
   }
+  const double pe = q.p + pis;
   const double mt = mu + mus;
   const double mt2 = 2.0 * mt;
   const double tau[3][3] = {{mt2 * (S11 - skk3), mt2 * S12, mt2 * S13},
@@ -289,12 +296,14 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
     // H4 = (e + p) U - m . Theta
     qd[3] += Hb[4] * U;
     pb += Hb[4] * U;
-    Ub += Hb[4] * (Qv[4] + q.p);
+    Ub += Hb[4] * (Qv[4] + pe);
     for (int x = 0; x < 3; ++x) thb[x] -= Hb[4] * mm[x];
     ub[0] += Ub * mx;
     ub[1] += Ub * my;
     ub[2] += Ub * mz;
   }
+  // so far pb is the adjoint of the flux pressure p + sigma_kk / 3
+  const double peb = pb;
   // ---- Theta_x = u_a tau_ax + kappa dT/dx ----
   double kapb = 0.0;
   double gb[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -328,6 +337,17 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
       Sb13 += 4.0 * S13 * sb;
       Sb23 += 4.0 * S23 * sb;
     }
+  }
+  if (cid2 != 0.0) {
+    // sigma_kk / 3 = CI43 rho D^2 S:S -> rho and S
+    rb += peb * cid2 * ss;
+    const double ssb = peb * q.rho * cid2;
+    Sb11 += 2.0 * S11 * ssb;
+    Sb22 += 2.0 * S22 * ssb;
+    Sb33 += 2.0 * S33 * ssb;
+    Sb12 += 4.0 * S12 * ssb;
+    Sb13 += 4.0 * S13 * ssb;
+    Sb23 += 4.0 * S23 * ssb;
   }
   // Sutherland: dmu/dT = mu (3/(2 th) - 1/(th + S)) / T_ref
   Tb += mub * mu * (1.5 * rcp_nr(th) - ithS) * P.inv_Tref;

@@ -78,7 +78,13 @@ def _cases():
     n = (5, 6, 7)
     xyz = I.wavy_grid(*n, L=(1.0, 1.2, 1.4), amp=0.2)
     c4 = I.periodic_case(*n, xyz, I.smooth_state(*n, seed=13, amp=0.1), mu_ref=3e-3, sgs=1)
-    return {"jet61x29x23": c1, "wavy47x33x19_alpha07": c2, "tgv32": c3, "wavy5x6x7": c4}
+    # the isotropic SGS stress (sigma_kk / 3 added to the flux pressure)
+    c5 = _with_pressure_noise(I.jet_case(61, 29, 23, seed=3, CI=0.05), 31)
+    n = (47, 33, 19)
+    c6 = I.periodic_case(*n, I.wavy_grid(*n, L=(2.0, 1.5, 1.0), amp=0.3), I.smooth_state(*n, seed=5, amp=0.1),
+                         mu_ref=3e-3, sgs=1, CI=0.05)
+    return {"jet61x29x23": c1, "wavy47x33x19_alpha07": c2, "tgv32": c3, "wavy5x6x7": c4,
+            "jet61x29x23_ci": c5, "wavy47x33x19_ci": c6}
 
 
 CASES = _cases()
@@ -102,7 +108,7 @@ def test_residual_adjoint_dot_product(orc, lesmi, name):
     s.close()
 
 
-@pytest.mark.parametrize("name,i_f", [("jet61x29x23", 7), ("wavy5x6x7", 2)])
+@pytest.mark.parametrize("name,i_f", [("jet61x29x23", 7), ("wavy5x6x7", 2), ("jet61x29x23_ci", 7)])
 def test_rk_step_adjoint_dot_product(orc, lesmi, name, i_f):
     """One RK step with forcing on plane i_f: <w, dQ^{n+1}> against
     <Qbar, v> + <fbar, df>.  On the 5 x 6 x 7 periodic box the forcing plane
