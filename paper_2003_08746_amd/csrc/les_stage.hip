@@ -220,7 +220,11 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <class T, class QI, bool NORM, bool CFL, bool EXT>
+// Optional paths of the stage kernel (template bit mask EXT)
+constexpr int kExtSgs = 1;   // dynamic closure coefficients, isotropic SGS stress
+constexpr int kExtAxis = 2;  // the O-grid's polar axis at j = 0
+
+template <class T, class QI, bool NORM, bool CFL, int EXT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) k_stage(KArgs a, const QI* __restrict__ Qin, const double* Q0, double* Qout,
                                               float* Qsh, const double* __restrict__ dtp, double dt_host,
                                               double alpha, double* __restrict__ part, double* __restrict__ cpart) {
@@ -415,6 +419,16 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
       lds_barrier();
 
       // ---- C: node work at plane t ----
+      // the face between the axis and j = 1 takes the cross-axis value by
+      // linear extrapolation (no five-point stencil across the axis): the
+      // halo row below the axis holds 2 Q(0) - Q(1) for the dissipation of
+      // phase E (its pressure, velocity and temperature keep the cross-axis
+      // values for the sensor and the gradients; the row's own fluxes serve
+      // only the axis, whose residual is not formed)
+      if ((EXT & kExtAxis) && j == -1 && load_ok && kq->axis) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sq[c][ey][ex] = T(2) * sq[c][ey + 1][ex] - sq[c][ey + 2][ex];
+      }
       prims(P, qa, up1, pp1);  // plane t+1 of the own column
       // Q^(0) rows of the plane finished in this iteration (t-1), needed in E
       if (t > kb)
@@ -461,7 +475,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
           T d2 = (T)icbrt(Jn);  // (1/J)^(1/3)
           d2 *= d2;
           const T rd = rho * d2 * sqrt_nn(T(2) * ss);
-          if (!EXT || P.sgs == 1) {
+          if (!(EXT & kExtSgs) || P.sgs == 1) {
             mus = T(P.Cs2) * rd;
             kaps = mus * T(P.Cp_over_Prsgs);
           } else {  // dynamic coefficients of this column
@@ -470,7 +484,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
             kaps = T(P.Cp) * T(kq->dyn[dyn_ncol(kq->L) + cc]) * rd;
           }
           // isotropic SGS stress: sigma_kk / 3, added to the pressure of the fluxes
-          if (EXT && P.CI43 != 0.0) pis = T(P.CI43) * rho * d2 * ss;
+          if ((EXT & kExtSgs) && P.CI43 != 0.0) pis = T(P.CI43) * rho * d2 * ss;
         }
         const T mt2 = T(2) * (mu + mus);
         const T t11 = mt2 * (s11 - skk3), t22 = mt2 * (s22 - skk3), t33 = mt2 * (s33 - skk3);
@@ -481,7 +495,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
         const T th2 = u * t13 + vv * t23 + w * t33 + kap * g[3][2];
         __builtin_amdgcn_sched_barrier(0);
         const T p = s.p[ey][ex];
-        const T pe = EXT ? p + pis : p;  // pressure of the fluxes
+        const T pe = (EXT & kExtSgs) ? p + pis : p;  // pressure of the fluxes
         const T c2 = T(P.gamma_R) * tn;  // c^2 = gamma p / rho = gamma R T
         // spectral radii of the three directions and their square roots
         T lam[3], U[3], sl[3];
@@ -522,7 +536,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
           node_flux(1, H);
           // on the polar axis eta/J = 0: the eta node flux and radius take
           // their limit 0 (J is infinite there)
-          const bool on_axis = EXT && kq->axis && j == 0;
+          const bool on_axis = (EXT & kExtAxis) && kq->axis && j == 0;
 #pragma unroll
           for (int q = 0; q < 5; ++q) s.hy[q][ty][tx - 1] = on_axis ? T(0) : H[q];
           s.ly[ty][tx - 1] = on_axis ? T(0) : aniso_n(1, 2, 0);
@@ -577,12 +591,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
             q_a[c] = sq[c][ey - 2][ex]; q_b[c] = sq[c][ey - 1][ex];
             q_d[c] = sq[c][ey + 1][ex]; q_e[c] = sq[c][ey + 2][ex];
           }
-          // the face between the axis and j = 1 takes the cross-axis value by
-          // linear extrapolation: no five-point stencil across the axis
-          if (EXT && kq->axis && j == 1) {
-#pragma unroll
-            for (int c = 0; c < 5; ++c) q_a[c] = T(2) * q_b[c] - q_c[c];
-          }
           face_diss(P, s.ly[ty][cx], s.ly[ty + 1][cx], s.ny[ty][cx], s.ny[ty + 1][cx], q_b, q_c, q_d, q_e, D1);
           face_diss(P, s.ly[ty - 1][cx], s.ly[ty][cx], s.ny[ty - 1][cx], s.ny[ty][cx], q_a, q_b, q_c, q_d, D0);
 #pragma unroll
@@ -612,7 +620,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
             const int k = t - 1;
             const unsigned n = nt - sk;
             double qnv[5];
-            const bool on_axis = EXT && kq->axis && j == 0;  // advanced by the centerline condition
+            const bool on_axis = (EXT & kExtAxis) && kq->axis && j == 0;  // advanced by the centerline condition
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
               double R = J_prev * (double)(racc[c] + fz[c]);
@@ -758,6 +766,18 @@ Config config(const Layout& L, long long per_block, const Machine& m) {
   return c;
 }
 
+template <class T, class QI, int EXT>
+hipError_t launch_x(hipStream_t st, const Config& c, const KArgs& a, const QI* Qin, const double* Q0, double* Qout,
+                    float* Qsh, const double* dtp, double dt, double alpha, double* part, double* cpart) {
+  if (part)
+    k_stage<T, QI, true, false, EXT><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  else if (cpart)
+    k_stage<T, QI, false, true, EXT><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  else
+    k_stage<T, QI, false, false, EXT><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  return hipGetLastError();
+}
+
 template <class T, class QI>
 hipError_t launch(hipStream_t st, const StageArgs& sa, const QI* Qin, const double* Q0, double* Qout, float* Qsh,
                   const double* dtp, double dt, double alpha, double* part, double* cpart) {
@@ -765,26 +785,18 @@ hipError_t launch(hipStream_t st, const StageArgs& sa, const QI* Qin, const doub
   Config c = config(sa.L, sa.kchunk, sa.mach);
   KArgs a{sa.L,        sa.P,   sa.M,   sa.f,   sa.dyn,  sa.axis,  sa.i_f,    c.ntx,    c.nty,
           c.total,     c.per_block, c.kc, c.rr, c.nseg, c.nblocks, c.per_xcd, c.nxcd};
-  // the dynamic closure, the isotropic SGS stress and the polar axis run in
-  // their own instantiations, so the default path keeps its register budget
-  const bool x = sa.P.sgs == 2 || sa.P.CI43 != 0.0 || sa.axis;
-  if (x && sa.P.sgs == 2 && !sa.dyn) return hipErrorInvalidValue;
-  if (x) {
-    if (part)
-      k_stage<T, QI, true, false, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
-    else if (cpart)
-      k_stage<T, QI, false, true, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
-    else
-      k_stage<T, QI, false, false, true><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
-  } else {
-    if (part)
-      k_stage<T, QI, true, false, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
-    else if (cpart)
-      k_stage<T, QI, false, true, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
-    else
-      k_stage<T, QI, false, false, false><<<c.grid, NT, 0, st>>>(a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+  // the optional SGS models (dynamic closure, isotropic SGS stress) and the
+  // polar axis run in instantiations of their own, so that each path keeps
+  // only the registers it needs
+  const int x = ((sa.P.sgs == 2 || sa.P.CI43 != 0.0) ? kExtSgs : 0) | (sa.axis ? kExtAxis : 0);
+  if ((x & kExtSgs) && sa.P.sgs == 2 && !sa.dyn) return hipErrorInvalidValue;
+  switch (x) {
+    case 0: return launch_x<T, QI, 0>(st, c, a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+    case kExtSgs: return launch_x<T, QI, kExtSgs>(st, c, a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+    case kExtAxis: return launch_x<T, QI, kExtAxis>(st, c, a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
+    default:
+      return launch_x<T, QI, kExtSgs | kExtAxis>(st, c, a, Qin, Q0, Qout, Qsh, dtp, dt, alpha, part, cpart);
   }
-  return hipGetLastError();
 }
 
 }  // namespace
