@@ -91,7 +91,8 @@ typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT =
  *                       axis and j = 1 takes the cross-axis value by linear
  *                       extrapolation (no five-point stencil across the
  *                       axis).  The CFL bound skips the axis.  Not with
- *                       sgs = 2 or the adjoint entry points.
+ *                       sgs = 2.  The adjoint entry points differentiate the
+ *                       centerline condition and the cross-axis ghosts.
  * xyz: device, dense padded layout [3][nk+4][nj+4][ni+4], coordinates on every
  * node including ghosts and edges (read during les_create only). */
 typedef struct {
@@ -278,8 +279,11 @@ int les_advance(les_ctx *ctx, double *Q, int nsteps, double *dt_out, double *nor
  * fbar: device, dense [5][nk][nj], accumulated, or NULL.
  * The first adjoint call allocates the work arrays (84 fields of field_elems
  * doubles; LES_ERR_NOMEM if they do not fit).  LES_ERR_STATE for the
- * dynamic closure or the axis, and for a block of 2^30 padded nodes or
- * more. */
+ * dynamic closure, and for a block of 2^30 padded nodes or more.  With
+ * LES_BC_AXIS the centerline condition on every stage input and on the
+ * result is part of the step (the axis entries of Qbar come out 0), and a
+ * forcing plane's axis row (i_f, 0, k) receives no fbar: the centerline
+ * condition overwrites it after each stage. */
 int les_adjoint_step(les_ctx *ctx, const double *stage_ckpt, double dt, double *Qbar, double *fbar);
 
 /* Adjoint (vector-Jacobian product) of the residual at Q:
@@ -334,6 +338,10 @@ int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, do
  * p_exit: imposed pressure (> 0) of an exit face; ignored otherwise.
  * LES_ERR_ARG for a bad face, type or pressure, or a face that is not on a
  * Dirichlet side (face 3, j-hi, is one with LES_BC_AXIS).
+ * With LES_BC_AXIS the i-side faces fill their ghosts for j >= 0 only (those
+ * below the axis are edges of two boundary directions and stay frozen), and
+ * on the axis node, where the metric row of xi vanishes, n is the normalised
+ * azimuthal mean of the unit normals of the ring j = 1 at that face.
  * The adjoint entry points differentiate the face rules (the outside state
  * and p_exit are constants). */
 int les_set_face(les_ctx *ctx, int face, int type, const double *Q_outside, double p_exit);

@@ -397,11 +397,35 @@ void fill_faces(const Box& b, S* a) {
         w[d] = hi ? b.n(d) - 1 : 0;  // boundary node r
         const size_t r = b.at(w[0], w[1], w[2]), g = b.at(i, j, k);
         // outward unit normal from grad(xi_d) = J (xi_d/J)_x,y,z at r
-        const double J = b.m[9 * b.N + r];
         double nrm[3], nn = 0.0;
-        for (int x = 0; x < 3; ++x) {
-          nrm[x] = J * b.m[(size_t)(3 * d + x) * b.N + r];
-          nn += nrm[x] * nrm[x];
+        if (b.axis && w[1] == 0 && d != 1) {
+          // R20: at a node on the polar axis every azimuth meets and the
+          // metric row vanishes; the normal is the mean over the ring j = 1
+          // (k' = 0 .. nk - 2) of its unit normals, normalised
+          double sum[3] = {0.0, 0.0, 0.0};
+          for (int kk = 0; kk < b.nk - 1; ++kk) {
+            int rw[3] = {w[0], 1, kk};
+            rw[d] = hi ? b.n(d) - 1 : 0;
+            const size_t rr = b.at(rw[0], rw[1], rw[2]);
+            const double Jr = b.m[9 * b.N + rr];
+            double u[3], un = 0.0;
+            for (int x = 0; x < 3; ++x) {
+              u[x] = Jr * b.m[(size_t)(3 * d + x) * b.N + rr];
+              un += u[x] * u[x];
+            }
+            un = std::sqrt(un);
+            for (int x = 0; x < 3; ++x) sum[x] += u[x] / un;
+          }
+          for (int x = 0; x < 3; ++x) {
+            nrm[x] = sum[x];
+            nn += nrm[x] * nrm[x];
+          }
+        } else {
+          const double J = b.m[9 * b.N + r];
+          for (int x = 0; x < 3; ++x) {
+            nrm[x] = J * b.m[(size_t)(3 * d + x) * b.N + r];
+            nn += nrm[x] * nrm[x];
+          }
         }
         nn = std::sqrt(nn);
         for (int x = 0; x < 3; ++x) nrm[x] = (hi ? 1.0 : -1.0) * nrm[x] / nn;

@@ -92,10 +92,11 @@ __device__ __forceinline__ bool face_ok(const Layout& L, int d, int i, int j, in
   return true;
 }
 
-// W = coef * J * qbar on the interior, zero elsewhere.
+// W = coef * J * qbar on the interior, zero elsewhere and on the polar axis
+// (whose nodes the residual does not advance; J is infinite there).
 __device__ __forceinline__ void Wat(const Layout& L, const double* __restrict__ M, const double* __restrict__ qb,
-                                    double coef, int i, int j, int k, double W[5]) {
-  if (!interior(L, i, j, k)) {
+                                    double coef, int i, int j, int k, double W[5], bool axis) {
+  if (!interior(L, i, j, k) || (axis && j == 0)) {
     for (int c = 0; c < 5; ++c) W[c] = 0.0;
     return;
   }
@@ -156,7 +157,8 @@ struct AdjK {
   int per[3];          // period of each axis: n (periodic), n - 1 (superposed), 0 (Dirichlet)
   int lo[3], hi[3];    // pass-2 box: ghost layers of periodic axes and of active faces included
   Faces F;             // boundary faces
-  int general;         // a superposed axis or an active face: pass 3 visits every interior node
+  int general;         // a superposed axis, the polar axis or an active face: pass 3 visits every interior node
+  int axis;            // j = 0 is the polar axis (bc1 == 3)
 };
 
 AdjK make_adjk(const AdjArgs& a) {
@@ -169,13 +171,19 @@ AdjK make_adjk(const AdjArgs& a) {
   A.bc2 = a.bc2;
   A.F = a.F;
   A.general = 0;
+  A.axis = a.axis;
   const int bc[3] = {a.bc0, a.bc1, a.bc2}, nn[3] = {a.L.ni, a.L.nj, a.L.nk};
   for (int d = 0; d < 3; ++d) {
+    // bc 3 (polar axis, j only): its lo side is the axis, whose cross-axis
+    // ghosts are images of interior nodes; its hi side is Dirichlet
+    const bool per_like_lo = bc[d] == 0 || bc[d] == 2 || bc[d] == 3;
+    const bool per_like_hi = bc[d] == 0 || bc[d] == 2;
     A.per[d] = bc[d] == 0 ? nn[d] : (bc[d] == 2 ? nn[d] - 1 : 0);
-    const bool flo = bc[d] == 1 && a.F.type[2 * d] != 0, fhi = bc[d] == 1 && a.F.type[2 * d + 1] != 0;
-    A.lo[d] = (bc[d] != 1 || flo) ? -2 : 0;
-    A.hi[d] = (bc[d] != 1 || fhi) ? nn[d] + 1 : nn[d] - 1;
-    if (bc[d] == 2 || flo || fhi) A.general = 1;
+    const bool flo = bc[d] == 1 && a.F.type[2 * d] != 0;
+    const bool fhi = (bc[d] == 1 || bc[d] == 3) && a.F.type[2 * d + 1] != 0;
+    A.lo[d] = (per_like_lo || flo) ? -2 : 0;
+    A.hi[d] = (per_like_hi || fhi) ? nn[d] + 1 : nn[d] - 1;
+    if (bc[d] == 2 || bc[d] == 3 || flo || fhi) A.general = 1;
   }
   return A;
 }
@@ -222,6 +230,18 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
     }
     for (int qq = 0; qq < 4; ++qq)
       for (int x = 0; x < 3; ++x) g[qq][x] = J * (m[x] * dd[0][qq] + m[3 + x] * dd[1][qq] + m[6 + x] * dd[2][qq]);
+  }
+  if (A.axis && j <= 0) {
+    // polar axis: its residual is not formed (W = 0 around it along xi and
+    // zeta) and its eta node flux and spectral radius are the constant 0;
+    // the row below it (a ghost across the axis, where J < 0) serves only
+    // the axis residual.  Nothing but the pressure sensors (kept above)
+    // depends on them here
+    for (int d = 0; d < 3; ++d) Wk[(W_LAM + d) * fe + n] = 0.0;
+    for (int c = 0; c < 12; ++c) Wk[(W_A + c) * fe + n] = 0.0;
+    for (int c = W_PRHO; c <= W_PT; ++c) Wk[c * fe + n] = 0.0;
+    for (int a = 0; a < 4; ++a) Wk[(W_QD1 + a) * fe + n] = 0.0;
+    return;
   }
   {
     // for the dissipation adjoint: Lambda_d at the node
@@ -270,8 +290,8 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
   for (int d = 0; d < 3; ++d) {
     const int di = d == 0, dj = d == 1, dk = d == 2;
     double Wm[5], Wp[5];
-    Wat(L, M, qb, coef, i - di, j - dj, k - dk, Wm);
-    Wat(L, M, qb, coef, i + di, j + dj, k + dk, Wp);
+    Wat(L, M, qb, coef, i - di, j - dj, k - dk, Wm, A.axis);
+    Wat(L, M, qb, coef, i + di, j + dj, k + dk, Wp, A.axis);
     double Hb[5];
     bool any = false;
     for (int c = 0; c < 5; ++c) {
@@ -409,6 +429,7 @@ __global__ void __launch_bounds__(256) k_adj_face(AdjK A, const double* __restri
   const int di = d == 0, dj = d == 1, dk = d == 2;
   const long long s = dstr(L, d);
   const long long an = L.at(ai, aj, ak), bn = an + s;
+  const bool axis_face = A.axis && d == 1 && aj == 0;
   const double La = Wk[(W_LAM + d) * fe + an], Lb = Wk[(W_LAM + d) * fe + bn];
   const double na = fabs(Wk[(W_NU + d) * fe + an]), nb = fabs(Wk[(W_NU + d) * fe + bn]);
   const double e2 = P.k2 * (na >= nb ? na : nb);
@@ -417,15 +438,18 @@ __global__ void __launch_bounds__(256) k_adj_face(AdjK A, const double* __restri
   const double e4 = e4_active ? e4raw : 0.0;
   const double Lf = 0.5 * (La + Lb);
   double Wa[5], Wb[5];
-  Wat(L, A.M, qb, coef, ai, aj, ak, Wa);
-  Wat(L, A.M, qb, coef, ai + di, aj + dj, ak + dk, Wb);
+  Wat(L, A.M, qb, coef, ai, aj, ak, Wa, A.axis);
+  Wat(L, A.M, qb, coef, ai + di, aj + dj, ak + dk, Wb, A.axis);
   double Lfb = 0.0, e2b = 0.0, e4b = 0.0;
   for (int c = 0; c < 5; ++c) {
     const double Db = Wb[c] - Wa[c];
     Wk[(W_DB + 5 * d + c) * fe + an] = Db;
     const double* Qc = Q + c * fe;
     const double d1 = Qc[bn] - Qc[an];
-    const double d3 = Qc[bn + s] - 3.0 * Qc[bn] + 3.0 * Qc[an] - Qc[an - s];
+    // the face between the axis and j = 1 takes the cross-axis value by
+    // linear extrapolation, Q(-1) = 2 Q(0) - Q(1): d3 = Q(2) - 2 Q(1) + Q(0)
+    const double qam = axis_face ? 2.0 * Qc[an] - Qc[bn] : Qc[an - s];
+    const double d3 = Qc[bn + s] - 3.0 * Qc[bn] + 3.0 * Qc[an] - qam;
     Lfb += Db * (e2 * d1 - e4 * d3);
     e2b += Db * Lf * d1;
     e4b -= Db * Lf * d3;
@@ -459,6 +483,10 @@ __global__ void __launch_bounds__(256) k_adj_dnode(AdjK A, const double* __restr
   double rb = 0, ub[3] = {0, 0, 0}, pb = 0;
   double lamb[3] = {0, 0, 0};
   bool any = false;
+  // on the polar axis the spectral radii are constants (0 along eta; the
+  // others serve only faces between axis nodes, whose adjoint is 0): only
+  // the pressure sensors depend on the state there
+  const bool on_axis = A.axis && j == 0;
   Prim q;
   Radii r0;
   for (int d = 0; d < 3; ++d) {
@@ -468,19 +496,21 @@ __global__ void __launch_bounds__(256) k_adj_dnode(AdjK A, const double* __restr
     const bool f_hi = face_ok(L, d, i, j, k);                 // face (n, n+e): node is a
     double cpw = 0.0;
     if (f_lo || f_hi) {
-      if (!any) {
+      if (!any && !on_axis) {
         q = prim_at(Q, fe, n, P);
         r0 = radii_at(M, fe, n, q, P);
         any = true;
       }
-      const double Lamb = (f_lo ? Wk[(W_LH + d) * fe + n - s] : 0.0) + (f_hi ? Wk[(W_LH + d) * fe + n] : 0.0);
       const double nub = (f_lo ? Wk[(W_NUB + d) * fe + n - s] : 0.0) + (f_hi ? Wk[(W_NUA + d) * fe + n] : 0.0);
-      // Lambda_d(n) -> lam_d, lam_e, lam_f
-      double dd0, de0, df0;
-      aniso_d(r0.lam[d], r0.lam[(d + 1) % 3], r0.lam[(d + 2) % 3], P, dd0, de0, df0);
-      lamb[d] += Lamb * dd0;
-      lamb[(d + 1) % 3] += Lamb * de0;
-      lamb[(d + 2) % 3] += Lamb * df0;
+      if (!on_axis) {
+        const double Lamb = (f_lo ? Wk[(W_LH + d) * fe + n - s] : 0.0) + (f_hi ? Wk[(W_LH + d) * fe + n] : 0.0);
+        // Lambda_d(n) -> lam_d, lam_e, lam_f
+        double dd0, de0, df0;
+        aniso_d(r0.lam[d], r0.lam[(d + 1) % 3], r0.lam[(d + 2) % 3], P, dd0, de0, df0);
+        lamb[d] += Lamb * dd0;
+        lamb[(d + 1) % 3] += Lamb * de0;
+        lamb[(d + 2) % 3] += Lamb * df0;
+      }
       // nu_d(n) = |Delta2| / Sigma with p(n-e), p(n), p(n+e): from the
       // pre-pass, Delta2 / Sigma (signed) and 1 / Sigma
       const double ns = Wk[(W_NU + d) * fe + n], iSg = Wk[(W_IS + d) * fe + n];
@@ -489,6 +519,10 @@ __global__ void __launch_bounds__(256) k_adj_dnode(AdjK A, const double* __restr
       cpw = nub * (sd - sv);  // weight of p(n - e) and p(n + e)
     }
     Wk[(W_CP + d) * fe + n] = cpw;
+  }
+  if (on_axis) {
+    Wk[W_PP * fe + n] += pb;
+    return;
   }
   if (!any) return;
   // lam_e = |U_e| + c |m_e|
@@ -526,12 +560,15 @@ __device__ __forceinline__ bool in_b1(const Layout& L, int i, int j, int k) {
 // (x at an active boundary face of a Dirichlet axis)?
 __device__ __forceinline__ bool has_images(const AdjK& A, int i, int j, int k) {
   const int id[3] = {i, j, k}, nn[3] = {A.L.ni, A.L.nj, A.L.nk}, bc[3] = {A.bc0, A.bc1, A.bc2};
+  // rings j = 1, 2 are the images of the ghosts across the polar axis
+  if (A.axis && (j == 1 || j == 2)) return true;
   for (int d = 0; d < 3; ++d) {
     const int p = A.per[d];
     if (p) {
       if ((id[d] + p >= nn[d] && id[d] + p <= nn[d] + 1) || (id[d] - p <= -1 && id[d] - p >= -2)) return true;
-    } else if (bc[d] == 1) {
-      if ((id[d] == 0 && A.F.type[2 * d] != 0) || (id[d] == nn[d] - 1 && A.F.type[2 * d + 1] != 0)) return true;
+    } else if (bc[d] == 1 || bc[d] == 3) {
+      if ((id[d] == 0 && bc[d] == 1 && A.F.type[2 * d] != 0) || (id[d] == nn[d] - 1 && A.F.type[2 * d + 1] != 0))
+        return true;
     }
   }
   return false;
@@ -631,7 +668,14 @@ __global__ void __launch_bounds__(256) k_adj_gather(AdjK A, const double* __rest
       if (!face_ok(L, d, ai, aj, ak)) continue;
       const long long an = n + off[r] * s;
       const double A2 = Wk[(W_A2 + d) * fe + an], A4 = Wk[(W_A4 + d) * fe + an];
-      const double w = r == 0 ? (A2 + 3.0 * A4) : (r == 1 ? -(A2 + 3.0 * A4) : (r == 2 ? -A4 : A4));
+      double w = r == 0 ? (A2 + 3.0 * A4) : (r == 1 ? -(A2 + 3.0 * A4) : (r == 2 ? -A4 : A4));
+      if (A.axis && d == 1 && aj == 0) {
+        // the face between the axis and j = 1: d3 = Q(2) - 2 Q(1) + Q(0)
+        // (the cross-axis value linearly extrapolated), so the axis node
+        // takes -(A2 + A4), node j = 1 takes A2 + 2 A4 and the ghost below
+        // the axis nothing
+        w = r == 0 ? (A2 + 2.0 * A4) : (r == 1 ? -(A2 + A4) : (r == 2 ? -A4 : 0.0));
+      }
       if (w == 0.0) continue;
       // Dbar of the face, stored by the face pass
       for (int c = 0; c < 5; ++c) out[c] += w * Wk[(W_DB + 5 * d + c) * fe + an];
@@ -756,8 +800,8 @@ __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* 
         cand[d][nc[d]] = id[d] - p;
         kind[d][nc[d]++] = 0;
       }
-    } else if (bc[d] == 1) {
-      if (id[d] == 0 && A.F.type[2 * d] != 0) {
+    } else if (bc[d] == 1 || bc[d] == 3) {
+      if (id[d] == 0 && bc[d] == 1 && A.F.type[2 * d] != 0) {
         cand[d][nc[d]] = -1;
         kind[d][nc[d]++] = 1;
         cand[d][nc[d]] = -2;
@@ -794,7 +838,11 @@ __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* 
         const int d = kd[0] ? 0 : (kd[1] ? 1 : 2), hi = kd[d] == 2;
         const int type = A.F.type[2 * d + hi];
         double nv[3], qo[5] = {0, 0, 0, 0, 0};
-        face_normal(L, A.F.M, d, hi, n0, nv);
+        {
+          int r[3] = {i, j, k};
+          r[d] = hi ? nn[d] - 1 : 0;
+          face_normal(L, A.F, d, hi, r[0], r[1], r[2], nv);
+        }
         if (A.F.outside)
           for (int c = 0; c < 5; ++c) qo[c] = A.F.outside[c * fe + g];
         for (int c = 0; c < 5; ++c) {  // column c of the face rule's Jacobian
@@ -806,6 +854,22 @@ __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* 
           s[c] += dot;
         }
       }
+  if (A.axis && (j == 1 || j == 2)) {
+    // ghosts (i', -j, k') across the polar axis copy node (w(i'), j,
+    // (w(k') + (nk - 1)/2) mod (nk - 1)), w wrapping a ghost index (i' a
+    // periodic image of i; ghosts of a Dirichlet i side below the axis are
+    // edges and keep their values)
+    const int p = L.nk - 1, half = p / 2;
+    for (int a = 0; a < nc[0]; ++a) {
+      if (kind[0][a] != 0) continue;
+      for (int kk = -2; kk <= L.nk + 1; ++kk) {
+        const int w2 = (kk >= 0 && kk < L.nk) ? kk : (kk + p) % p;
+        if ((w2 + half) % p != k) continue;
+        const long long g = L.at(cand[0][a], -j, kk);
+        for (int c = 0; c < 5; ++c) s[c] += G[c * fe + g];
+      }
+    }
+  }
   for (int c = 0; c < 5; ++c) qout[c * fe + n0] = s[c];
   finish_node(L, n0, j, k, s, acc, fbar, i == i_f, fw, qfin);
 }
@@ -828,6 +892,36 @@ __global__ void __launch_bounds__(256) k_adj_init(Layout L, const double* __rest
     acc[c * L.fe + n] = 0.0;
     if (fbar && i == i_f) fbar[((long long)c * L.nk + k) * L.nj + j] += w * q;
   }
+}
+
+// Reverse of the centerline condition, one thread per (i, variable): the
+// forward writes the mean of the ring (i, 1, k'), k' = 0 .. nk - 2, to every
+// axis node (i, 0, k), k = 0 .. nk - 1; so every ring node receives the sum
+// of the axis adjoints over k (ascending) divided by nk - 1, and the axis
+// adjoints are cleared.
+__global__ void __launch_bounds__(256) k_axis_avg_adj(Layout L, double* __restrict__ q) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 5 * L.ni) return;
+  const int f = t / L.ni, i = t % L.ni;
+  double* a = q + f * L.fe;
+  double sum = 0.0;
+  for (int k = 0; k < L.nk; ++k) {
+    const long long n = L.at(i, 0, k);
+    sum += a[n];
+    a[n] = 0.0;
+  }
+  const double share = sum / (double)(L.nk - 1);
+  for (int k = 0; k < L.nk - 1; ++k) a[L.at(i, 1, k)] += share;
+}
+
+// fbar[c][k][j] += w q_c on the source plane i_f (interior nodes).
+__global__ void __launch_bounds__(256) k_adj_source(Layout L, const double* __restrict__ q, double* __restrict__ fbar,
+                                                    int i_f, double w) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.nj * L.nk) return;
+  const int j = t % L.nj, k = t / L.nj;
+  const long long n = L.at(i_f, j, k);
+  for (int c = 0; c < 5; ++c) fbar[((long long)c * L.nk + k) * L.nj + j] += w * q[c * L.fe + n];
 }
 
 inline unsigned nb(long long n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -870,10 +964,18 @@ hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const dou
 
 size_t adjoint_work_elems(const Layout& L) { return (size_t)W_NF * (size_t)L.fe; }
 
+hipError_t launch_axis_avg_adjoint(hipStream_t s, const Layout& L, double* qbar) {
+  k_axis_avg_adj<<<nb(5LL * L.ni, 256), 256, 0, s>>>(L, qbar);
+  return hipGetLastError();
+}
+
 hipError_t run_residual_vjp(hipStream_t s, const AdjArgs& a, const double* Q, const double* Rbar, double* Qbar,
                             double* work) {
   const AdjK A = make_adjk(a);
-  return residual_vjp(s, A, Q, Rbar, 1.0, work, Qbar);
+  hipError_t e = residual_vjp(s, A, Q, Rbar, 1.0, work, Qbar);
+  // the residual reads the state after the centerline condition
+  if (e == hipSuccess && A.axis) e = launch_axis_avg_adjoint(s, a.L, Qbar);
+  return e;
 }
 
 hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt, double dt, double* Qbar,
@@ -885,10 +987,18 @@ hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt,
   double* qcur = work + (long long)W_Q1 * fe;
   double* qnext = work + (long long)(W_Q1 + 5) * fe;
   double* acc = work + (long long)W_ACC * fe;
-  // qcur = Qbar, acc = 0, fbar += alpha_5 dt Qbar (interior)
+  // With the polar axis every stage input and the step's result pass
+  // through the centerline condition C (linear): Q^{n+1} = C(Z_5) and the
+  // stage input of stage l > 1 is C(Z_l) for the raw stage output Z_l, so
+  // the reverse applies C^T to Qbar first, to each stage's result before it
+  // is used, and to the final sum (the step's input was C(Q^n)).  The
+  // source-plane update then takes the transformed adjoint, in a pass of its
+  // own.
   const bool want_f = fbar && a.i_f >= 0;
-  k_adj_init<<<nb(nIn, 256), 256, 0, s>>>(L, Qbar, qcur, acc, want_f ? fbar : nullptr, a.i_f, rk_alpha(4) * dt);
   hipError_t e = hipSuccess;
+  if (A.axis && (e = launch_axis_avg_adjoint(s, L, Qbar)) != hipSuccess) return e;
+  // qcur = Qbar, acc = 0, fbar += alpha_5 dt Qbar (interior)
+  k_adj_init<<<nb(nIn, 256), 256, 0, s>>>(L, Qbar, qcur, acc, want_f ? fbar : nullptr, a.i_f, rk_alpha(4) * dt);
   for (int l = 4; l >= 0; --l) {
     const double al = rk_alpha(l) * dt;
     // qbar_{l-1} = (dR/dQ|Q^(l-1))^T (-alpha_l dt qbar_l), acc += qbar_l,
@@ -896,9 +1006,16 @@ hipError_t run_adjoint_step(hipStream_t s, const AdjArgs& a, const double* ckpt,
     // qbar_0
     const double* Ql = ckpt + (long long)l * 5 * fe;
     const bool f_next = want_f && l > 0;
-    e = residual_vjp(s, A, Ql, qcur, -al, work, qnext, acc, f_next ? fbar : nullptr, a.i_f,
-                     f_next ? rk_alpha(l - 1) * dt : 0.0, l == 0 ? Qbar : nullptr);
+    const bool f_here = f_next && !A.axis;
+    e = residual_vjp(s, A, Ql, qcur, -al, work, qnext, acc, f_here ? fbar : nullptr, a.i_f,
+                     f_here ? rk_alpha(l - 1) * dt : 0.0, l == 0 ? Qbar : nullptr);
     if (e != hipSuccess) return e;
+    if (A.axis) {
+      e = launch_axis_avg_adjoint(s, L, l == 0 ? Qbar : qnext);
+      if (e != hipSuccess) return e;
+      if (f_next) k_adj_source<<<nb((long long)L.nj * L.nk, 256), 256, 0, s>>>(L, qnext, fbar, a.i_f,
+                                                                                rk_alpha(l - 1) * dt);
+    }
     double* tmp = qcur;
     qcur = qnext;
     qnext = tmp;

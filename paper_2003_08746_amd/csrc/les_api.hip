@@ -99,6 +99,7 @@ static les::Faces faces_of(const les_ctx* c) {
   F.outside = c->outside;
   F.M = c->M;
   F.gamma = c->P.gamma;
+  F.axis = c->axis;
   return F;
 }
 
@@ -629,12 +630,12 @@ int les_adjoint_step(les_ctx* ctx, const double* stage_ckpt, double dt, double* 
   if (!stage_ckpt || !Qbar) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: stage_ckpt and Qbar are required");
   if (!(dt > 0.0)) return fail(ctx, LES_ERR_ARG, "les_adjoint_step: dt must be > 0 (the step's fixed dt)");
   if (ctx->prec != LES_FP64) return fail(ctx, LES_ERR_STATE, "les_adjoint_step: needs an FP64 context");
-  if (ctx->P.sgs == 2 || ctx->axis)
+  if (ctx->P.sgs == 2)
     return fail(ctx, LES_ERR_STATE, "les_adjoint_step: the adjoint covers the static Smagorinsky model "
-                                    "(sgs <= 1, with or without the isotropic SGS stress) on blocks without the axis");
+                                    "(sgs <= 1, with or without the isotropic SGS stress)");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
-  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx), ctx->axis};
   HIPCHK(ctx, les::run_adjoint_step(ctx->s, a, stage_ckpt, dt, Qbar, ctx->i_f >= 0 ? fbar : nullptr, ctx->adj));
   return LES_OK;
 }
@@ -687,13 +688,13 @@ int les_residual_adjoint(les_ctx* ctx, double* Q, const double* Rbar, double* Qb
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_residual_adjoint: null context");
   if (!Q || !Rbar || !Qbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Q, Rbar and Qbar are required");
   if (Qbar == Q || Qbar == Rbar) return fail(ctx, LES_ERR_ARG, "les_residual_adjoint: Qbar must not alias Q or Rbar");
-  if (ctx->P.sgs == 2 || ctx->axis)
+  if (ctx->P.sgs == 2)
     return fail(ctx, LES_ERR_STATE, "les_residual_adjoint: the adjoint covers the static Smagorinsky model "
-                                    "(sgs <= 1, with or without the isotropic SGS stress) on blocks without the axis");
+                                    "(sgs <= 1, with or without the isotropic SGS stress)");
   int rc = ensure_adj_work(ctx);
   if (rc != LES_OK) return rc;
-  HIPCHK(ctx, les::launch_ghost_fill(ctx->s, ctx->L, ctx->bc, Q, Q, 5, faces_of(ctx)));
-  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx)};
+  HIPCHK(ctx, bc_fill(ctx, Q));
+  les::AdjArgs a{ctx->L, ctx->P, ctx->M, ctx->bc[0], ctx->bc[1], ctx->bc[2], ctx->i_f, faces_of(ctx), ctx->axis};
   HIPCHK(ctx, les::run_residual_vjp(ctx->s, a, Q, Rbar, Qbar, ctx->adj));
   return LES_OK;
 }

@@ -16,6 +16,7 @@ struct Faces {
   const double* M;        // metrics [10][fe] (face normals)
   double gamma;
   int any;                // some face is not frozen
+  int axis;               // j = 0 is the polar axis (face normals there, see face_normal)
 };
 
 // A value with one derivative (forward mode), enough for the face rule.
@@ -141,8 +142,30 @@ __device__ void face_value(int type, double gamma, double pe, const double nv[3]
 }
 
 // Outward unit normal of face (d, hi) at node rn from grad(xi_d) = J (xi_d/J).
-__device__ inline void face_normal(const Layout& L, const double* __restrict__ M, int d, int hi, long long rn,
+__device__ inline void face_normal(const Layout& L, const Faces& F, int d, int hi, int i, int j, int k,
                                    double nv[3]) {
+  const double* __restrict__ M = F.M;
+  if (F.axis && j == 0 && d != 1) {
+    // on the polar axis every azimuth meets and the metric row of d
+    // vanishes: the normal is the azimuthal mean of the unit normals of the
+    // ring j = 1 (k' = 0 .. nk - 2, ascending), normalised
+    double sm[3] = {0.0, 0.0, 0.0};
+    for (int kk = 0; kk < L.nk - 1; ++kk) {
+      const long long rr = L.at(i, 1, kk);
+      const double J = M[9 * L.fe + rr];
+      double u[3], nrm = 0.0;
+      for (int x = 0; x < 3; ++x) {
+        u[x] = J * M[(3 * d + x) * L.fe + rr];
+        nrm += u[x] * u[x];
+      }
+      const double inv = 1.0 / sqrt(nrm);
+      for (int x = 0; x < 3; ++x) sm[x] += u[x] * inv;
+    }
+    const double sg = (hi ? 1.0 : -1.0) / sqrt(sm[0] * sm[0] + sm[1] * sm[1] + sm[2] * sm[2]);
+    for (int x = 0; x < 3; ++x) nv[x] = sm[x] * sg;
+    return;
+  }
+  const long long rn = L.at(i, j, k);
   const double J = M[9 * L.fe + rn];
   double nrm = 0.0;
   for (int x = 0; x < 3; ++x) {

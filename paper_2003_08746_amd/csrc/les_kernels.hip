@@ -111,6 +111,9 @@ template <class T>
 __device__ bool face_ghost(const Layout& L, const Faces& F, const int bc[3], const int id[3], const int w[3],
                            long long dst, T* q) {
   const int nn[3] = {L.ni, L.nj, L.nk};
+  // below the polar axis a ghost of a Dirichlet i side is an edge of two
+  // boundary directions: it keeps its given value
+  if (bc[1] == 3 && id[1] < 0) return false;
   int nd = 0, d = 0;
   for (int e = 0; e < 3; ++e)
     if ((bc[e] == 1 && (id[e] < 0 || id[e] >= nn[e])) || (bc[e] == 3 && id[e] >= nn[e])) {
@@ -125,7 +128,7 @@ __device__ bool face_ghost(const Layout& L, const Faces& F, const int bc[3], con
   r[d] = hi ? nn[d] - 1 : 0;
   const long long rn = L.at(r[0], r[1], r[2]);
   double nv[3];
-  face_normal(L, F.M, d, hi, rn, nv);
+  face_normal(L, F, d, hi, r[0], r[1], r[2], nv);
   double qr[5], qo[5] = {0, 0, 0, 0, 0}, out[5];
   for (int c = 0; c < 5; ++c) {
     qr[c] = (double)q[c * L.fe + rn];

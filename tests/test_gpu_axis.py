@@ -164,9 +164,154 @@ def test_axis_arguments(lesmi):
     with pytest.raises(lesmi.LesError) as e:
         lesmi.Solver(dict(case, params=dict(case["params"], sgs=2)))
     assert e.value.code == lesmi.LES_ERR_ARG
+
+
+# ---------------------------------------------------------------------------
+# Boundary faces around the O-grid, and the adjoint with the axis
+# ---------------------------------------------------------------------------
+G = I.GAMMA
+
+
+def _faces_case(bc_i, seed=1):
+    """The 40 x 24 x 61 O-grid with a far-field face at j-hi and, with bc_i =
+    1, an entrance (i-lo) and an exit (i-hi): the paper's domain in small.
+    The outside state is the unperturbed round jet."""
+    case = I.ogrid_case(40, 24, 61, seed=seed)
+    case["bc"] = (bc_i, 3, 2)
+    Q0 = I.ogrid_case(40, 24, 61, seed=seed, pert=0.0)["Q"]
+    if bc_i == 1:
+        case["faces"] = dict(types=[1, 2, 0, 3, 0, 0], p_exit=[0.0, 1.0 / G, 0, 0, 0, 0], outside=Q0)
+    else:
+        case["faces"] = dict(types=[0, 0, 0, 3, 0, 0], p_exit=[0.0] * 6, outside=Q0)
+    return case
+
+
+def _solver_with_faces(lesmi, case):
     s = lesmi.Solver(case)
-    Q = s.upload(case["Q"])
-    with pytest.raises(lesmi.LesError) as e:
-        s.residual_adjoint(Q, s.upload(case["Q"]))
-    assert e.value.code == lesmi.LES_ERR_STATE
+    fc = case["faces"]
+    Q0d = s.upload(fc["outside"])
+    for f, t in enumerate(fc["types"]):
+        if t == 1:
+            s.set_face(f, lesmi.LES_FACE_CHARACTERISTIC, Q0d)
+        elif t == 2:
+            s.set_face(f, lesmi.LES_FACE_EXIT, p_exit=fc["p_exit"][f])
+        elif t == 3:
+            s.set_face(f, lesmi.LES_FACE_FARFIELD, Q0d)
+    return s
+
+
+def test_axis_with_entrance_exit_and_farfield(orc, lesmi):
+    """Entrance and exit faces on the axial sides of the O-grid: the ghosts of
+    those sides below the axis are edges of two boundary directions and keep
+    their values, as in the oracle."""
+    case = _faces_case(1)
+    s = _solver_with_faces(lesmi, case)
+    Qd = s.upload(case["Q"])
+    Rg = s.download(s.residual(Qd))
+    dts, _ = s.advance(Qd, 2, want_dt=True)
+    Qg = s.download(Qd)
     s.close()
+    m = orc.metrics(case)
+    Ro = orc.residual(case, m, case["Q"])
+    assert (_rel(Rg, Ro) <= TOL).all(), _rel(Rg, Ro)
+    Qo = case["Q"]
+    for n in range(2):
+        Qo, dto, _, _ = orc.rk_step(case, m, Qo)
+        assert abs(dts[n] - dto) <= 1e-14 * dto
+    assert (_rel(Qg, Qo) <= TOL).all(), _rel(Qg, Qo)
+
+
+def _noisy(case, seed):
+    """Seeded 1e-4 noise on the pressure and the momenta (interior and
+    ghosts), so that no pressure second difference and no velocity component
+    sits on a kink of |.| where the two linearisations could take different
+    branches."""
+    rng = np.random.default_rng(seed)
+    out = dict(case)
+    Q = case["Q"].copy()
+    Q[4] += 1e-4 * (1.0 / G) / (G - 1.0) * rng.uniform(-1, 1, size=Q[4].shape)
+    Q[1:4] += 1e-4 * np.abs(Q[1:4]).max() * rng.uniform(-1, 1, size=Q[1:4].shape)
+    out["Q"] = Q
+    return out
+
+
+def _adj_cases():
+    return {"ogrid40x24x61": _noisy(CASES["ogrid40x24x61"], 41),
+            "ogrid24x16x361_ci": _noisy(CASES["ogrid24x16x361"], 43),
+            "ogrid40x24x61_farfield": _noisy(_faces_case(0), 47),
+            "ogrid40x24x61_faces": _noisy(_faces_case(1), 53)}
+
+
+ADJ = _adj_cases()
+
+
+def _interior_rand(case, seed, scale_by_field=True):
+    rng = np.random.default_rng(seed)
+    a = np.zeros_like(case["Q"])
+    sl = (slice(None), slice(2, -2), slice(2, -2), slice(2, -2))
+    a[sl] = rng.standard_normal(a[sl].shape)
+    if scale_by_field:
+        a *= np.abs(I.interior(case["Q"])).reshape(5, -1).max(1)[:, None, None, None]
+    return a
+
+
+def _dot(a, b):
+    return float((I.interior(a) * I.interior(b)).sum())
+
+
+def _make(lesmi, case):
+    return _solver_with_faces(lesmi, case) if "faces" in case else lesmi.Solver(case)
+
+
+@pytest.mark.parametrize("name", list(ADJ))
+def test_axis_residual_adjoint_dot_product(orc, lesmi, name):
+    """<w, (dR/dQ) v> from the oracle's dual-number tangent against
+    <(dR/dQ)^T w, v> from the GPU adjoint, with the centerline condition,
+    the cross-axis ghosts, the axis limits of the eta flux and radius and the
+    extrapolated fourth difference all inside dR/dQ."""
+    case = ADJ[name]
+    print(f"[gpu] axis residual adjoint {name}", flush=True)
+    m = orc.metrics(case)
+    v = _interior_rand(case, 1)
+    w = _interior_rand(case, 2, scale_by_field=False)
+    _, dR = orc.residual_tangent(case, m, case["Q"], v)
+    lhs = _dot(w, dR)
+    s = _make(lesmi, case)
+    Q = s.upload(case["Q"])
+    Qbar = s.download(s.residual_adjoint(Q, s.upload(w)))
+    s.close()
+    rhs = _dot(Qbar, v)
+    scale = float(np.abs(I.interior(w) * I.interior(dR)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+    # nothing depends on the axis values the centerline condition overwrites
+    assert np.abs(I.interior(Qbar)[:, :, 0, :]).max() == 0.0
+
+
+@pytest.mark.parametrize("name,i_f", [("ogrid40x24x61", 7), ("ogrid24x16x361_ci", 5), ("ogrid40x24x61_faces", 9)])
+def test_axis_rk_step_adjoint_dot_product(orc, lesmi, name, i_f):
+    """One RK step with forcing on plane i_f, through the centerline condition
+    of every stage input and of the result."""
+    import torch
+    case = ADJ[name]
+    print(f"[gpu] axis rk-step adjoint {name}", flush=True)
+    m = orc.metrics(case)
+    rng = np.random.default_rng(7)
+    f = 1e-3 * rng.uniform(-1, 1, size=(5, case["nk"], case["nj"]))
+    df = rng.standard_normal(f.shape)
+    v = _interior_rand(case, 8)
+    w = _interior_rand(case, 9, scale_by_field=False)
+    dt = 0.8 * orc.cfl_dt(case, m, case["Q"])
+    _, dQ1 = orc.rk_step_tangent(case, m, case["Q"], v, dt, f=f, df=df, i_f=i_f)
+    lhs = _dot(w, dQ1)
+    s = _make(lesmi, case)
+    s.set_forcing(torch.from_numpy(f).cuda(), i_f)
+    Q = s.upload(case["Q"])
+    ck = torch.empty(25 * s.fe, dtype=torch.float64, device="cuda")
+    s.rk_step(Q, dt, ckpt=ck)
+    Qbar = s.upload(w)
+    fbar = torch.zeros(f.shape, dtype=torch.float64, device="cuda")
+    s.adjoint_step(ck, dt, Qbar, fbar)
+    rhs = _dot(s.download(Qbar), v) + float((fbar.cpu().numpy() * df).sum())
+    s.close()
+    scale = float(np.abs(I.interior(w) * I.interior(dQ1)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)

@@ -1100,6 +1100,39 @@ def test_axis_uniform_flow_preserved(orc):
     assert rel.max() <= 1e-13, rel
 
 
+def test_axis_face_normal_on_axis_row(orc):
+    """R20: on the polar axis the metric row of an axial face vanishes, and
+    the face rule takes the azimuthal mean of the ring's unit normals.  On the
+    O-grid (axial coordinate x = Lx i / ni) every ring normal is -x at i-lo
+    and +x at i-hi, so with a state that is uniform near the axis the axis
+    row's entrance and exit ghosts equal those of the ring j = 1 exactly, and
+    a uniform stream equal to the outside state is preserved with every face
+    active (entrance, exit, far field)."""
+    c = I.ogrid_case(12, 10, 25, seed=1)
+    c["bc"] = (1, 3, 2)
+    sh = c["Q"].shape[1:]
+    Q = I.uniform_state(sh, vel=(1.1, 0.0, 0.0))
+    outside = I.uniform_state(sh, vel=(1.3, 0.05, 0.0))
+    outside[4] *= 1.1  # a different pressure outside
+    g = I.GAMMA
+    c["faces"] = dict(types=[1, 2, 0, 3, 0, 0], p_exit=[0.0, 0.9 / g, 0, 0, 0, 0], outside=outside)
+    c["Q"] = Q
+    m = orc.metrics(c)
+    q = orc.fill_ghosts_faces(c, m, Q)
+    assert np.isfinite(q).all()
+    for i in (0, 1, -2, -1):  # ghost layers of both axial faces
+        a, b = q[:, 2:-2, 2, i], q[:, 2:-2, 3, i]  # axis row j = 0 and ring j = 1
+        # (equal up to the rounding of the normalised normals)
+        assert np.allclose(a, b, rtol=1e-14, atol=0), (i, np.abs(a - b).max())
+    # the entrance ghosts differ from the interior (the rule is active)
+    assert np.abs(q[:, 2:-2, 3, 1] - Q[:, 2:-2, 3, 2]).max() > 1e-3
+    # a uniform stream equal to the outside state, exit at its pressure
+    c["faces"] = dict(types=[1, 2, 0, 3, 0, 0], p_exit=[0.0, 1.0 / g, 0, 0, 0, 0], outside=Q)
+    R = I.interior(orc.residual(c, m, Q))
+    scale = float(np.nanmax(np.where(np.isfinite(m[9]), np.abs(m[9]), 0)[2:-2, 3:-2, 2:-2]))
+    assert np.abs(R).max() <= 1e-12 * scale, (np.abs(R).max(), scale)
+
+
 def test_axis_centerline_average(orc):
     """After a step every axis node holds, for each conserved variable, the
     mean over the nk - 1 distinct azimuths of the ring j = 1 (so that mean is
