@@ -201,6 +201,50 @@ def time_faces(case, steps, warmup):
             "faces": "i-lo characteristic entrance, i-hi exit, j-lo/j-hi far field, k periodic"}
 
 
+def time_variant(case, steps, warmup, what, setup=None, base=None):
+    """One FP64 les_advance leg of a model or domain variant: throughput,
+    step time, mean stage-kernel launch, and (with base, a dict of the same
+    block's default-model leg) its ratio to that leg."""
+    from paper_2003_08746_amd import lesmi
+    r = time_gpu(case, lesmi.LES_FP64, steps, warmup, setup)
+    npts = case["ni"] * case["nj"] * case["nk"]
+    out = {"workload": what, "points": npts, "value": round(npts * 5 * steps / r["wall_s"] / 1e6, 2),
+           "unit": "Mpoint-RK-stages/s", "ms_per_step": round(r["wall_s"] * 1e3 / steps, 4),
+           "avg_stage_launch_us": round(r["stage_ms"] / r["launches"] * 1e3, 2)}
+    if base and "value" in base:
+        out["vs_default_model"] = round(out["value"] / base["value"], 3)
+    return out
+
+
+def time_sgs_variants(case, steps, warmup, base):
+    """The 256 x 128 x 128 shard with the optional SGS models: the dynamic
+    closure (five streaming kernels before every residual, the stage kernel's
+    EXT instantiation) and Yoshizawa's isotropic SGS stress with the static
+    model."""
+    dyn = dict(case)
+    dyn["params"] = dict(case["params"], sgs=2)
+    ci = dict(case)
+    ci["params"] = dict(case["params"], sgs=1, CI=0.05)
+    return {"dynamic": time_variant(dyn, steps, warmup, "jet shard 256x128x128, dynamic closure", base=base),
+            "sigma_kk": time_variant(ci, steps, warmup, "jet shard 256x128x128, Smagorinsky + sigma_kk (CI 0.05)",
+                                     base=base)}
+
+
+def time_ogrid(steps=20, warmup=2):
+    """Mesh B of Tab. 2 as an O-grid block (256 axial x 128 radial x 361
+    azimuthal points, 11.8M): the polar axis with its centerline condition,
+    the superposed azimuthal seam, a far-field face at the outer radius,
+    periodic axial direction."""
+    from paper_2003_08746_amd import inputs, lesmi
+    case = inputs.ogrid_case(256, 128, 361, seed=0)
+
+    def setup(s, Q):
+        s.set_face(3, lesmi.LES_FACE_FARFIELD, Q)
+
+    return time_variant(case, steps, warmup, "mesh B of Tab. 2 as an O-grid 256x128x361 (axis, far field), FP64",
+                        setup=setup)
+
+
 def time_stats(case, calls=50):
     """Running flow statistics (les_stats_accumulate) on the benchmark shard:
     mean time per call from HIP events on the solver's stream, against its
@@ -395,8 +439,8 @@ def main():
     ap.add_argument("--small-steps", type=int, default=100, help="steps of the 256 x 128 x 128 shard legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip every leg but the headline (mixed, small shard, adjoint, faces, statistics, "
-                         "restart, copy, mesh I)")
+                    help="skip every leg but the headline (mixed, small shard, adjoint, faces, SGS variants, "
+                         "O-grid, statistics, restart, copy, mesh I)")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -479,8 +523,11 @@ def main():
                 extra["jet256x128x128"]["fp64"]["traffic_GBps"] = round(t_small / ls / 1e9, 1)
         except Exception as e:  # the leg reports its own error; the headline stands
             extra["jet256x128x128"] = {"error": str(e)[:200]}
+        base = extra.get("jet256x128x128", {}).get("fp64")
         for key, fn in (("adjoint", time_adjoint),
                         ("faces", lambda: time_faces(small, args.small_steps, 5)),
+                        ("sgs_variants", lambda: time_sgs_variants(small, 20, 2, base)),
+                        ("ogrid", time_ogrid),
                         ("stats", lambda: time_stats(small)),
                         ("restart", lambda: time_restart(small)),
                         ("copy", time_copy),
