@@ -13,18 +13,26 @@
 // ^ the test filter (weights 1/4, 1/2, 1/4 along each index), u~ and T~ the
 // test-filtered Favre velocity and temperature, D = (1/J)^(1/3).
 //
-// Five launches per evaluation, all streaming one node per thread:
-//   k_dyn_raw     the 23 grid-level fields (rho, rho u, rho T, rho u u,
-//                 rho u T on the whole padded box; the 9 strain and
-//                 temperature-gradient products on [-1, n]^3);
-//   k_dyn_filter  three separable passes of the test filter (i, j, k);
-//   k_dyn_node    the four contractions at every interior node;
-//   k_dyn_coef    per padded column: the sums over interior k (ascending,
-//                 one thread per column, so the order is fixed) and the
-//                 clipped ratios; ghost columns take the wrapped (periodic)
-//                 or nearest interior (Dirichlet) column.
-// This is an optional model: the streaming passes cost about 1 KB of HBM
-// traffic per point and evaluation (23 fields, three filter passes).
+// Three launches per evaluation:
+//   k_dyn_plane   per (i, j) tile and segment of k planes, marching in k:
+//                 the 23 grid-level fields of each plane (rho, rho u,
+//                 rho T, rho u u, rho u T on the whole padded box; the 9
+//                 strain and temperature-gradient products on [-1, n]^3)
+//                 computed into LDS and filtered along i and j there, then
+//                 along k in registers; written on [-1, n]^3;
+//   k_dyn_node    per interior column and segment of k: the test-filtered
+//                 Favre velocity and temperature gradients and the four
+//                 contractions at each node, summed over the segment's k
+//                 in ascending order;
+//   k_dyn_coef    per padded column: the segment sums added in ascending
+//                 order (a fixed order) and the clipped ratios; ghost
+//                 columns take the wrapped (periodic) or nearest interior
+//                 (Dirichlet) column.
+// The filter is separable and applied along i, then j, then k, each a
+// three-point sum evaluated left to right.  This is an optional model: its
+// passes move about 0.45 KB of HBM traffic per point and evaluation (the 23
+// filtered fields written once and read once).
+
 #include "les_dynamic.hpp"
 
 namespace les {
@@ -34,18 +42,6 @@ namespace {
 constexpr int NRAW = 23;
 // symmetric index pairs (a <= b) in the order of the raw fields
 __constant__ int kPair[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-
-__device__ inline bool in_box(const Layout& L, int i, int j, int k) {
-  return i >= -2 && j >= -2 && k >= -2 && i <= L.ni + 1 && j <= L.nj + 1 && k <= L.nk + 1;
-}
-
-// node index (i, j, k) in [-2, n+1]^3 of a linear thread index over the padded box
-__device__ inline void padded_node(const Layout& L, long long t, int& i, int& j, int& k) {
-  const int pi = L.ni + 4, pj = L.nj + 4;
-  i = (int)(t % pi) - 2;
-  j = (int)((t / pi) % pj) - 2;
-  k = (int)(t / ((long long)pi * pj)) - 2;
-}
 
 // primitives (u, v, w, T) of a state node, in FP64
 template <class QI>
@@ -78,25 +74,22 @@ __device__ inline void dyn_chain(const double* M, long long fe, long long n, con
   for (int x = 0; x < 3; ++x) g[x] = J * (M[x * fe + n] * d[0] + M[(3 + x) * fe + n] * d[1] + M[(6 + x) * fe + n] * d[2]);
 }
 
+// Raw fields of node (i, j, k) of the padded box (F[14..22] = 0 off
+// [-1, n]^3), each stored to F[q * fs] as it is formed.
 template <class QI>
-__global__ void __launch_bounds__(256) k_dyn_raw(Layout L, Phys P, const double* __restrict__ M,
-                                                 const QI* __restrict__ Q, double* __restrict__ W) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long tot = (long long)(L.ni + 4) * (L.nj + 4) * (L.nk + 4);
-  if (t >= tot) return;
-  int i, j, k;
-  padded_node(L, t, i, j, k);
+__device__ inline void dyn_raw(const Layout& L, const Phys& P, const double* __restrict__ M, const QI* __restrict__ Q,
+                               int i, int j, int k, double* F, int fs) {
   const long long fe = L.fe, n = L.at(i, j, k);
   double rho, u[3], T;
   dyn_prims(Q, fe, n, P, rho, u, T);
-  double F[NRAW];
   F[0] = rho;
-  for (int a = 0; a < 3; ++a) F[1 + a] = rho * u[a];
-  F[4] = rho * T;
-  for (int q = 0; q < 6; ++q) F[5 + q] = rho * u[kPair[q][0]] * u[kPair[q][1]];
-  for (int a = 0; a < 3; ++a) F[11 + a] = rho * u[a] * T;
-  for (int q = 14; q < NRAW; ++q) F[q] = 0.0;
-  if (i >= -1 && j >= -1 && k >= -1 && i <= L.ni && j <= L.nj && k <= L.nk) {
+  for (int a = 0; a < 3; ++a) F[(1 + a) * fs] = rho * u[a];
+  F[4 * fs] = rho * T;
+  for (int q = 0; q < 6; ++q) F[(5 + q) * fs] = rho * u[kPair[q][0]] * u[kPair[q][1]];
+  for (int a = 0; a < 3; ++a) F[(11 + a) * fs] = rho * u[a] * T;
+  if (!(i >= -1 && j >= -1 && k >= -1 && i <= L.ni && j <= L.nj && k <= L.nk)) {
+    for (int q = 14; q < NRAW; ++q) F[q * fs] = 0.0;
+  } else {
     // node gradients of u, v, w, T (central differences, chain rule)
     double dd[4][3];
     const long long st[3] = {1, L.sj, L.sk};
@@ -113,48 +106,82 @@ __global__ void __launch_bounds__(256) k_dyn_raw(Layout L, Phys P, const double*
     dyn_strain(du, Sd, mag);
     const double D = cbrt(1.0 / M[9 * fe + n]);
     const double w = D * D * rho * mag;
-    for (int q = 0; q < 6; ++q) F[14 + q] = w * Sd[kPair[q][0]][kPair[q][1]];
-    for (int a = 0; a < 3; ++a) F[20 + a] = w * dT[a];
-  }
-  for (int q = 0; q < NRAW; ++q) W[q * fe + n] = F[q];
-}
-
-// out = test filter of in along direction d at nodes whose d index is in
-// [-1, n] (every other index over the padded box)
-__global__ void __launch_bounds__(256) k_dyn_filter(Layout L, int d, const double* __restrict__ in,
-                                                    double* __restrict__ out) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long tot = (long long)(L.ni + 4) * (L.nj + 4) * (L.nk + 4);
-  if (t >= tot) return;
-  int i, j, k;
-  padded_node(L, t, i, j, k);
-  const int id[3] = {i, j, k}, nn[3] = {L.ni, L.nj, L.nk};
-  if (id[d] < -1 || id[d] > nn[d]) return;
-  const long long n = L.at(i, j, k), s = d == 0 ? 1 : (d == 1 ? L.sj : L.sk);
-  for (int q = 0; q < NRAW; ++q) {
-    const double* a = in + q * L.fe;
-    out[q * L.fe + n] = 0.25 * a[n - s] + 0.5 * a[n] + 0.25 * a[n + s];
+    for (int q = 0; q < 6; ++q) F[(14 + q) * fs] = w * Sd[kPair[q][0]][kPair[q][1]];
+    for (int a = 0; a < 3; ++a) F[(20 + a) * fs] = w * dT[a];
   }
 }
 
-// X[0..3][n] = L^d:M, M:M, K.N, N.N at interior nodes from the filtered
-// fields F (valid on [-1, n]^3 for rho^, (rho u)^, (rho T)^; on the
-// interior for the rest)
-__global__ void __launch_bounds__(256) k_dyn_node(Layout L, const double* __restrict__ M,
-                                                  const double* __restrict__ F, double* __restrict__ X) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long tot = (long long)L.ni * L.nj * L.nk;
-  if (t >= tot) return;
-  const int i = (int)(t % L.ni), j = (int)((t / L.ni) % L.nj), k = (int)(t / ((long long)L.ni * L.nj));
+// Tile of k_dyn_plane: DPX x DPY threads hold the raw fields of the output
+// tile (DPX - 2) x (DPY - 2) and its one-node ring; a block marches DPK
+// output planes in k.
+constexpr int DPX = 32, DPY = 8, DPK = 16;
+constexpr int DPTI = DPX - 2, DPTJ = DPY - 2;
+
+__host__ __device__ inline long long dyn_plane_tiles(const Layout& L) {
+  return (long long)((L.ni + 2 + DPTI - 1) / DPTI) * ((L.nj + 2 + DPTJ - 1) / DPTJ);
+}
+inline long long dyn_plane_blocks(const Layout& L) { return dyn_plane_tiles(L) * ((L.nk + 2 + DPK - 1) / DPK); }
+
+// V[q] = the test filter of raw field q (along i, then j, then k) at every
+// node of [-1, n]^3.  Each block owns a tile and a segment of DPK output
+// planes; per plane of its march it computes the raw fields of the tile and
+// ring into LDS and filters them along i and j there, and it filters along k
+// in registers: out(k) = (0.25 G(k-1) + 0.5 G(k)) + 0.25 G(k+1), carried as
+// the pending sum of the two earlier planes and a quarter of the last.
+template <class QI>
+__global__ void __launch_bounds__(DPX * DPY) k_dyn_plane(Layout L, Phys P, const double* __restrict__ M,
+                                                         const QI* __restrict__ Q, double* __restrict__ V) {
+  __shared__ double sF[NRAW][DPY][DPX];
+  const int tiles_i = (L.ni + 2 + DPTI - 1) / DPTI;
+  const long long tiles = dyn_plane_tiles(L);
+  const long long b = blockIdx.x;
+  const long long tb = b % tiles;
+  const int ka = -1 + (int)(b / tiles) * DPK;    // first output plane
+  const int kb = ka + DPK < L.nk + 1 ? ka + DPK : L.nk + 1;  // one past the last
+  const int tx = threadIdx.x % DPX, ty = threadIdx.x / DPX;
+  const int i0 = -1 + (int)(tb % tiles_i) * DPTI, j0 = -1 + (int)(tb / tiles_i) * DPTJ;
+  const int i = i0 - 1 + tx, j = j0 - 1 + ty;
+  const bool out_node = tx >= 1 && tx < DPX - 1 && ty >= 1 && ty < DPY - 1 && i <= L.ni && j <= L.nj;
+  double pend[NRAW], quarter[NRAW];
+  for (int q = 0; q < NRAW; ++q) pend[q] = quarter[q] = 0.0;
+  for (int k = ka - 1; k <= kb; ++k) {
+    __syncthreads();  // the previous plane's filter has read sF
+    if (i <= L.ni + 1 && j <= L.nj + 1) {
+      dyn_raw(L, P, M, Q, i, j, k, &sF[0][ty][tx], DPY * DPX);
+    } else {
+      for (int q = 0; q < NRAW; ++q) sF[q][ty][tx] = 0.0;
+    }
+    __syncthreads();
+    // along i (rows ty - 1, ty, ty + 1), then along j, then along k
+    if (out_node) {
+      const long long n = L.at(i, j, k - 1);
+      for (int q = 0; q < NRAW; ++q) {
+        double gi[3];
+        for (int r = 0; r < 3; ++r)
+          gi[r] = 0.25 * sF[q][ty - 1 + r][tx - 1] + 0.5 * sF[q][ty - 1 + r][tx] + 0.25 * sF[q][ty - 1 + r][tx + 1];
+        const double g = 0.25 * gi[0] + 0.5 * gi[1] + 0.25 * gi[2];
+        if (k - 1 >= ka) V[q * L.fe + n] = pend[q] + 0.25 * g;
+        pend[q] = quarter[q] + 0.5 * g;
+        quarter[q] = 0.25 * g;
+      }
+    }
+  }
+}
+
+// x[0..3] = L^d:M, M:M, K.N, N.N at interior node (i, j, k) from the
+// filtered fields V (rho^, (rho u)^, (rho T)^ are also read at the six
+// axis neighbours)
+__device__ inline void dyn_contract(const Layout& L, const double* __restrict__ M, const double* __restrict__ V,
+                                    int i, int j, int k, double x[4]) {
   const long long fe = L.fe, n = L.at(i, j, k);
   const long long st[3] = {1, L.sj, L.sk};
   // test-filtered velocity and temperature at the axis neighbours
   double dd[4][3];
   for (int e = 0; e < 3; ++e) {
     const long long p1 = n + st[e], p0 = n - st[e];
-    const double r1 = F[p1], r0 = F[p0];
-    for (int a = 0; a < 3; ++a) dd[a][e] = 0.5 * (F[(1 + a) * fe + p1] / r1 - F[(1 + a) * fe + p0] / r0);
-    dd[3][e] = 0.5 * (F[4 * fe + p1] / r1 - F[4 * fe + p0] / r0);
+    const double r1 = V[p1], r0 = V[p0];
+    for (int a = 0; a < 3; ++a) dd[a][e] = 0.5 * (V[(1 + a) * fe + p1] / r1 - V[(1 + a) * fe + p0] / r0);
+    dd[3][e] = 0.5 * (V[4 * fe + p1] / r1 - V[4 * fe + p0] / r0);
   }
   double du[3][3], dT[3], Sd[3][3], mag;
   for (int a = 0; a < 3; ++a) dyn_chain(M, fe, n, dd[a], du[a]);
@@ -163,7 +190,7 @@ __global__ void __launch_bounds__(256) k_dyn_node(Layout L, const double* __rest
   const double D = cbrt(1.0 / M[9 * fe + n]);
   const double Dt2 = 4.0 * D * D;  // (2 D)^2
   double fv[NRAW];
-  for (int q = 0; q < NRAW; ++q) fv[q] = F[q * fe + n];
+  for (int q = 0; q < NRAW; ++q) fv[q] = V[q * fe + n];
   double Lm[3][3], Mm[3][3];
   for (int q = 0; q < 6; ++q) {
     const int a = kPair[q][0], c = kPair[q][1];
@@ -184,10 +211,34 @@ __global__ void __launch_bounds__(256) k_dyn_node(Layout L, const double* __rest
     kn += K * N;
     nn += N * N;
   }
-  X[n] = lm;
-  X[fe + n] = mm;
-  X[2 * fe + n] = kn;
-  X[3 * fe + n] = nn;
+  x[0] = lm;
+  x[1] = mm;
+  x[2] = kn;
+  x[3] = nn;
+}
+
+// Column segments of the k sums: DNK planes per thread.
+constexpr int DNK = 16;
+inline int dyn_nseg(const Layout& L) { return (L.nk + DNK - 1) / DNK; }
+
+// Xp[q][seg][j][i] = sum over k of segment seg (ascending) of contraction q
+// at the interior nodes of column (i, j).
+__global__ void __launch_bounds__(256) k_dyn_node(Layout L, int nseg, const double* __restrict__ M,
+                                                  const double* __restrict__ V, double* __restrict__ Xp) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ncoli = (long long)L.ni * L.nj;
+  if (t >= ncoli * nseg) return;
+  const long long col = t % ncoli;
+  const int seg = (int)(t / ncoli);
+  const int i = (int)(col % L.ni), j = (int)(col / L.ni);
+  const int k1 = (seg + 1) * DNK < L.nk ? (seg + 1) * DNK : L.nk;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = seg * DNK; k < k1; ++k) {
+    double x[4];
+    dyn_contract(L, M, V, i, j, k, x);
+    for (int q = 0; q < 4; ++q) s[q] += x[q];
+  }
+  for (int q = 0; q < 4; ++q) Xp[((long long)q * nseg + seg) * ncoli + col] = s[q];
 }
 
 __device__ inline int dyn_src(int x, int n, int bc) {
@@ -197,18 +248,19 @@ __device__ inline int dyn_src(int x, int n, int bc) {
   return ((x % p) + p) % p;
 }
 
-__global__ void __launch_bounds__(256) k_dyn_coef(Layout L, int bc0, int bc1, const double* __restrict__ X,
+// per padded column: the segment sums of its source column added in
+// ascending segment order, then the clipped ratios
+__global__ void __launch_bounds__(256) k_dyn_coef(Layout L, int bc0, int bc1, int nseg, const double* __restrict__ Xp,
                                                   double* __restrict__ dyn) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long ncol = dyn_ncol(L);
   if (c >= ncol) return;
   const int i = (int)(c % (L.ni + 4)) - 2, j = (int)(c / (L.ni + 4)) - 2;
   const int is = dyn_src(i, L.ni, bc0), js = dyn_src(j, L.nj, bc1);
+  const long long ncoli = (long long)L.ni * L.nj, col = (long long)js * L.ni + is;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = 0; k < L.nk; ++k) {
-    const long long n = L.at(is, js, k);
-    for (int q = 0; q < 4; ++q) s[q] += X[q * L.fe + n];
-  }
+  for (int g = 0; g < nseg; ++g)
+    for (int q = 0; q < 4; ++q) s[q] += Xp[((long long)q * nseg + g) * ncoli + col];
   dyn[c] = s[1] > 0.0 ? fmax(0.0, s[0] / s[1]) : 0.0;
   dyn[ncol + c] = s[3] > 0.0 ? fmax(0.0, s[2] / s[3]) : 0.0;
 }
@@ -218,23 +270,18 @@ inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 template <class QI>
 hipError_t run(hipStream_t s, const Layout& L, const int bc[3], const Phys& P, const double* M, const QI* Q,
                double* work, double* dyn) {
-  const long long fe = L.fe;
-  double* W = work;
-  double* V = work + NRAW * fe;
-  double* X = work + 2 * NRAW * fe;
-  const long long tot = (long long)(L.ni + 4) * (L.nj + 4) * (L.nk + 4);
-  k_dyn_raw<QI><<<nblk(tot, 256), 256, 0, s>>>(L, P, M, Q, W);
-  k_dyn_filter<<<nblk(tot, 256), 256, 0, s>>>(L, 0, W, V);
-  k_dyn_filter<<<nblk(tot, 256), 256, 0, s>>>(L, 1, V, W);
-  k_dyn_filter<<<nblk(tot, 256), 256, 0, s>>>(L, 2, W, V);
-  k_dyn_node<<<nblk((long long)L.ni * L.nj * L.nk, 256), 256, 0, s>>>(L, M, V, X);
-  k_dyn_coef<<<nblk(dyn_ncol(L), 256), 256, 0, s>>>(L, bc[0], bc[1], X, dyn);
+  double* V = work;
+  double* X = work + (long long)NRAW * L.fe;
+  k_dyn_plane<QI><<<(unsigned)dyn_plane_blocks(L), DPX * DPY, 0, s>>>(L, P, M, Q, V);
+  const int nseg = dyn_nseg(L);
+  k_dyn_node<<<nblk((long long)L.ni * L.nj * nseg, 256), 256, 0, s>>>(L, nseg, M, V, X);
+  k_dyn_coef<<<nblk(dyn_ncol(L), 256), 256, 0, s>>>(L, bc[0], bc[1], nseg, X, dyn);
   return hipGetLastError();
 }
 
 }  // namespace
 
-long long dynamic_work_elems(const Layout& L) { return (2LL * NRAW + 4) * L.fe; }
+long long dynamic_work_elems(const Layout& L) { return (NRAW + 4LL) * L.fe; }
 
 hipError_t launch_dynamic(hipStream_t s, const Layout& L, const int bc[3], const Phys& P, const double* M,
                           const double* Q, double* work, double* dyn) {
