@@ -74,83 +74,108 @@ __device__ inline void dyn_chain(const double* M, long long fe, long long n, con
   for (int x = 0; x < 3; ++x) g[x] = J * (M[x * fe + n] * d[0] + M[(3 + x) * fe + n] * d[1] + M[(6 + x) * fe + n] * d[2]);
 }
 
-// Raw fields of node (i, j, k) of the padded box (F[14..22] = 0 off
-// [-1, n]^3), each stored to F[q * fs] as it is formed.
-template <class QI>
-__device__ inline void dyn_raw(const Layout& L, const Phys& P, const double* __restrict__ M, const QI* __restrict__ Q,
-                               int i, int j, int k, double* F, int fs) {
-  const long long fe = L.fe, n = L.at(i, j, k);
-  double rho, u[3], T;
-  dyn_prims(Q, fe, n, P, rho, u, T);
-  F[0] = rho;
-  for (int a = 0; a < 3; ++a) F[(1 + a) * fs] = rho * u[a];
-  F[4 * fs] = rho * T;
-  for (int q = 0; q < 6; ++q) F[(5 + q) * fs] = rho * u[kPair[q][0]] * u[kPair[q][1]];
-  for (int a = 0; a < 3; ++a) F[(11 + a) * fs] = rho * u[a] * T;
-  if (!(i >= -1 && j >= -1 && k >= -1 && i <= L.ni && j <= L.nj && k <= L.nk)) {
-    for (int q = 14; q < NRAW; ++q) F[q * fs] = 0.0;
-  } else {
-    // node gradients of u, v, w, T (central differences, chain rule)
-    double dd[4][3];
-    const long long st[3] = {1, L.sj, L.sk};
-    for (int e = 0; e < 3; ++e) {
-      double r1, u1[3], T1, r0, u0[3], T0;
-      dyn_prims(Q, fe, n + st[e], P, r1, u1, T1);
-      dyn_prims(Q, fe, n - st[e], P, r0, u0, T0);
-      for (int a = 0; a < 3; ++a) dd[a][e] = 0.5 * (u1[a] - u0[a]);
-      dd[3][e] = 0.5 * (T1 - T0);
-    }
-    double du[3][3], dT[3], Sd[3][3], mag;
-    for (int a = 0; a < 3; ++a) dyn_chain(M, fe, n, dd[a], du[a]);
-    dyn_chain(M, fe, n, dd[3], dT);
-    dyn_strain(du, Sd, mag);
-    const double D = cbrt(1.0 / M[9 * fe + n]);
-    const double w = D * D * rho * mag;
-    for (int q = 0; q < 6; ++q) F[(14 + q) * fs] = w * Sd[kPair[q][0]][kPair[q][1]];
-    for (int a = 0; a < 3; ++a) F[(20 + a) * fs] = w * dT[a];
-  }
-}
-
 // Tile of k_dyn_plane: DPX x DPY threads hold the raw fields of the output
 // tile (DPX - 2) x (DPY - 2) and its one-node ring; a block marches DPK
-// output planes in k.
+// output planes in k.  The primitives are formed once per node and plane on
+// the thread tile and one more ring (PPX x PPY) and shared through LDS.
 constexpr int DPX = 32, DPY = 8, DPK = 16;
 constexpr int DPTI = DPX - 2, DPTJ = DPY - 2;
+constexpr int PPX = DPX + 2, PPY = DPY + 2;
 
 __host__ __device__ inline long long dyn_plane_tiles(const Layout& L) {
   return (long long)((L.ni + 2 + DPTI - 1) / DPTI) * ((L.nj + 2 + DPTJ - 1) / DPTJ);
 }
 inline long long dyn_plane_blocks(const Layout& L) { return dyn_plane_tiles(L) * ((L.nk + 2 + DPK - 1) / DPK); }
 
+// the primitives (rho, u, v, w, T) of node (i, j, k), zero off the padded box
+template <class QI>
+__device__ inline void dyn_prims_at(const Layout& L, const Phys& P, const QI* __restrict__ Q, int i, int j, int k,
+                                    double pr[5]) {
+  for (int c = 0; c < 5; ++c) pr[c] = 0.0;
+  if (i >= -2 && j >= -2 && k >= -2 && i <= L.ni + 1 && j <= L.nj + 1 && k <= L.nk + 1)
+    dyn_prims(Q, L.fe, L.at(i, j, k), P, pr[0], &pr[1], pr[4]);
+}
+
 // V[q] = the test filter of raw field q (along i, then j, then k) at every
 // node of [-1, n]^3.  Each block owns a tile and a segment of DPK output
-// planes; per plane of its march it computes the raw fields of the tile and
-// ring into LDS and filters them along i and j there, and it filters along k
-// in registers: out(k) = (0.25 G(k-1) + 0.5 G(k)) + 0.25 G(k+1), carried as
-// the pending sum of the two earlier planes and a quarter of the last.
+// planes.  Per plane k of its march: the primitives of plane k + 1 into LDS,
+// the raw fields of plane k into LDS (in-plane neighbours' primitives from
+// LDS, those of planes k -+ 1 of the thread's own column from registers and
+// LDS), the filter along i and j from LDS, and the filter along k in
+// registers: out(k) = (0.25 G(k-1) + 0.5 G(k)) + 0.25 G(k+1), carried as the
+// pending sum of the two earlier planes and a quarter of the last.
 template <class QI>
 __global__ void __launch_bounds__(DPX * DPY) k_dyn_plane(Layout L, Phys P, const double* __restrict__ M,
                                                          const QI* __restrict__ Q, double* __restrict__ V) {
   __shared__ double sF[NRAW][DPY][DPX];
+  __shared__ double sP[2][5][PPY][PPX];
+  const long long fe = L.fe;
   const int tiles_i = (L.ni + 2 + DPTI - 1) / DPTI;
   const long long tiles = dyn_plane_tiles(L);
   const long long b = blockIdx.x;
   const long long tb = b % tiles;
-  const int ka = -1 + (int)(b / tiles) * DPK;    // first output plane
+  const int ka = -1 + (int)(b / tiles) * DPK;                // first output plane
   const int kb = ka + DPK < L.nk + 1 ? ka + DPK : L.nk + 1;  // one past the last
   const int tx = threadIdx.x % DPX, ty = threadIdx.x / DPX;
   const int i0 = -1 + (int)(tb % tiles_i) * DPTI, j0 = -1 + (int)(tb / tiles_i) * DPTJ;
-  const int i = i0 - 1 + tx, j = j0 - 1 + ty;
+  const int i = i0 - 1 + tx, j = j0 - 1 + ty;  // this thread's node; the LDS tiles start at (i0 - 2, j0 - 2)
+  const bool in_box = i <= L.ni + 1 && j <= L.nj + 1;
+  const bool grad_ij = i >= -1 && j >= -1 && i <= L.ni && j <= L.nj;
   const bool out_node = tx >= 1 && tx < DPX - 1 && ty >= 1 && ty < DPY - 1 && i <= L.ni && j <= L.nj;
+
+  // primitives of plane kp on the LDS tile, into buffer kp & 1
+  auto prims_plane = [&](int kp) {
+    for (int t = threadIdx.x; t < PPX * PPY; t += DPX * DPY) {
+      const int x = t % PPX, y = t / PPX;
+      double pr[5];
+      dyn_prims_at(L, P, Q, i0 - 2 + x, j0 - 2 + y, kp, pr);
+      for (int c = 0; c < 5; ++c) sP[kp & 1][c][y][x] = pr[c];
+    }
+  };
+  double pm[5];  // primitives of plane k - 1 at this node
+  dyn_prims_at(L, P, Q, i, j, ka - 2, pm);
+  prims_plane(ka - 1);
   double pend[NRAW], quarter[NRAW];
   for (int q = 0; q < NRAW; ++q) pend[q] = quarter[q] = 0.0;
   for (int k = ka - 1; k <= kb; ++k) {
-    __syncthreads();  // the previous plane's filter has read sF
-    if (i <= L.ni + 1 && j <= L.nj + 1) {
-      dyn_raw(L, P, M, Q, i, j, k, &sF[0][ty][tx], DPY * DPX);
+    // (the previous plane's readers of buffer (k + 1) & 1 and of sF passed
+    // the barrier before its filter)
+    prims_plane(k + 1);
+    __syncthreads();
+    const int bc = k & 1, bn = (k + 1) & 1;
+    double pc[5];
+    for (int c = 0; c < 5; ++c) pc[c] = sP[bc][c][ty + 1][tx + 1];
+    if (in_box) {
+      const double rho = pc[0], u[3] = {pc[1], pc[2], pc[3]}, T = pc[4];
+      sF[0][ty][tx] = rho;
+      for (int a = 0; a < 3; ++a) sF[1 + a][ty][tx] = rho * u[a];
+      sF[4][ty][tx] = rho * T;
+      for (int q = 0; q < 6; ++q) sF[5 + q][ty][tx] = rho * u[kPair[q][0]] * u[kPair[q][1]];
+      for (int a = 0; a < 3; ++a) sF[11 + a][ty][tx] = rho * u[a] * T;
+      if (grad_ij && k >= -1 && k <= L.nk) {
+        // node gradients of u, v, w, T (central differences, chain rule)
+        double dd[4][3];
+        for (int a = 0; a < 4; ++a) {
+          dd[a][0] = 0.5 * (sP[bc][1 + a][ty + 1][tx + 2] - sP[bc][1 + a][ty + 1][tx]);
+          dd[a][1] = 0.5 * (sP[bc][1 + a][ty + 2][tx + 1] - sP[bc][1 + a][ty][tx + 1]);
+          dd[a][2] = 0.5 * (sP[bn][1 + a][ty + 1][tx + 1] - pm[1 + a]);
+        }
+        const long long n = L.at(i, j, k);
+        double du[3][3], dT[3], Sd[3][3], mag;
+        for (int a = 0; a < 3; ++a) dyn_chain(M, fe, n, dd[a], du[a]);
+        dyn_chain(M, fe, n, dd[3], dT);
+        dyn_strain(du, Sd, mag);
+        const double D = cbrt(1.0 / M[9 * fe + n]);
+        const double w = D * D * rho * mag;
+        for (int q = 0; q < 6; ++q) sF[14 + q][ty][tx] = w * Sd[kPair[q][0]][kPair[q][1]];
+        for (int a = 0; a < 3; ++a) sF[20 + a][ty][tx] = w * dT[a];
+      } else {
+        for (int q = 14; q < NRAW; ++q) sF[q][ty][tx] = 0.0;
+      }
     } else {
       for (int q = 0; q < NRAW; ++q) sF[q][ty][tx] = 0.0;
     }
+    for (int c = 0; c < 5; ++c) pm[c] = pc[c];
     __syncthreads();
     // along i (rows ty - 1, ty, ty + 1), then along j, then along k
     if (out_node) {
@@ -160,7 +185,7 @@ __global__ void __launch_bounds__(DPX * DPY) k_dyn_plane(Layout L, Phys P, const
         for (int r = 0; r < 3; ++r)
           gi[r] = 0.25 * sF[q][ty - 1 + r][tx - 1] + 0.5 * sF[q][ty - 1 + r][tx] + 0.25 * sF[q][ty - 1 + r][tx + 1];
         const double g = 0.25 * gi[0] + 0.5 * gi[1] + 0.25 * gi[2];
-        if (k - 1 >= ka) V[q * L.fe + n] = pend[q] + 0.25 * g;
+        if (k - 1 >= ka) V[q * fe + n] = pend[q] + 0.25 * g;
         pend[q] = quarter[q] + 0.5 * g;
         quarter[q] = 0.25 * g;
       }
