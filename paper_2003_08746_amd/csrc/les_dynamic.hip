@@ -96,12 +96,26 @@ __device__ inline void dyn_prims_at(const Layout& L, const Phys& P, const QI* __
     dyn_prims(Q, L.fe, L.at(i, j, k), P, pr[0], &pr[1], pr[4]);
 }
 
+// A double from the neighbouring lane of the wave (DPP wave shifts by one
+// lane): lane l reads lane l - 1 (shr) or l + 1 (shl); the end lanes read 0.
+__device__ inline double lane_prev(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double lane_next(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // V[q] = the test filter of raw field q (along i, then j, then k) at every
 // node of [-1, n]^3.  Each block owns a tile and a segment of DPK output
 // planes.  Per plane k of its march: the primitives of plane k + 1 into LDS,
-// the raw fields of plane k into LDS (in-plane neighbours' primitives from
-// LDS, those of planes k -+ 1 of the thread's own column from registers and
-// LDS), the filter along i and j from LDS, and the filter along k in
+// the raw fields of plane k in registers (in-plane neighbours' primitives
+// from LDS, those of planes k -+ 1 of the thread's own column from registers
+// and LDS), the filter along i across lanes into LDS, along j from LDS, and
+// along k in
 // registers: out(k) = (0.25 G(k-1) + 0.5 G(k)) + 0.25 G(k+1), carried as the
 // pending sum of the two earlier planes and a quarter of the last.
 template <class QI>
@@ -145,13 +159,15 @@ __global__ void __launch_bounds__(DPX * DPY) k_dyn_plane(Layout L, Phys P, const
     const int bc = k & 1, bn = (k + 1) & 1;
     double pc[5];
     for (int c = 0; c < 5; ++c) pc[c] = sP[bc][c][ty + 1][tx + 1];
+    double F[NRAW];
+    for (int q = 0; q < NRAW; ++q) F[q] = 0.0;
     if (in_box) {
       const double rho = pc[0], u[3] = {pc[1], pc[2], pc[3]}, T = pc[4];
-      sF[0][ty][tx] = rho;
-      for (int a = 0; a < 3; ++a) sF[1 + a][ty][tx] = rho * u[a];
-      sF[4][ty][tx] = rho * T;
-      for (int q = 0; q < 6; ++q) sF[5 + q][ty][tx] = rho * u[kPair[q][0]] * u[kPair[q][1]];
-      for (int a = 0; a < 3; ++a) sF[11 + a][ty][tx] = rho * u[a] * T;
+      F[0] = rho;
+      for (int a = 0; a < 3; ++a) F[1 + a] = rho * u[a];
+      F[4] = rho * T;
+      for (int q = 0; q < 6; ++q) F[5 + q] = rho * u[kPair[q][0]] * u[kPair[q][1]];
+      for (int a = 0; a < 3; ++a) F[11 + a] = rho * u[a] * T;
       if (grad_ij && k >= -1 && k <= L.nk) {
         // node gradients of u, v, w, T (central differences, chain rule)
         double dd[4][3];
@@ -167,24 +183,21 @@ __global__ void __launch_bounds__(DPX * DPY) k_dyn_plane(Layout L, Phys P, const
         dyn_strain(du, Sd, mag);
         const double D = cbrt(1.0 / M[9 * fe + n]);
         const double w = D * D * rho * mag;
-        for (int q = 0; q < 6; ++q) sF[14 + q][ty][tx] = w * Sd[kPair[q][0]][kPair[q][1]];
-        for (int a = 0; a < 3; ++a) sF[20 + a][ty][tx] = w * dT[a];
-      } else {
-        for (int q = 14; q < NRAW; ++q) sF[q][ty][tx] = 0.0;
+        for (int q = 0; q < 6; ++q) F[14 + q] = w * Sd[kPair[q][0]][kPair[q][1]];
+        for (int a = 0; a < 3; ++a) F[20 + a] = w * dT[a];
       }
-    } else {
-      for (int q = 0; q < NRAW; ++q) sF[q][ty][tx] = 0.0;
     }
     for (int c = 0; c < 5; ++c) pm[c] = pc[c];
+    // along i: the row's neighbours are the adjacent lanes (a row of the
+    // tile is 32 consecutive lanes of one wave; only interior columns are
+    // used below)
+    for (int q = 0; q < NRAW; ++q) sF[q][ty][tx] = 0.25 * lane_prev(F[q]) + 0.5 * F[q] + 0.25 * lane_next(F[q]);
     __syncthreads();
-    // along i (rows ty - 1, ty, ty + 1), then along j, then along k
+    // along j, then along k
     if (out_node) {
       const long long n = L.at(i, j, k - 1);
       for (int q = 0; q < NRAW; ++q) {
-        double gi[3];
-        for (int r = 0; r < 3; ++r)
-          gi[r] = 0.25 * sF[q][ty - 1 + r][tx - 1] + 0.5 * sF[q][ty - 1 + r][tx] + 0.25 * sF[q][ty - 1 + r][tx + 1];
-        const double g = 0.25 * gi[0] + 0.5 * gi[1] + 0.25 * gi[2];
+        const double g = 0.25 * sF[q][ty - 1][tx] + 0.5 * sF[q][ty][tx] + 0.25 * sF[q][ty + 1][tx];
         if (k - 1 >= ka) V[q * fe + n] = pend[q] + 0.25 * g;
         pend[q] = quarter[q] + 0.5 * g;
         quarter[q] = 0.25 * g;
