@@ -110,6 +110,27 @@ def test_dynamic_coefficients(orc, lesmi, name):
     assert compared >= (0 if name.startswith("tgv") else 2)
 
 
+def test_dynamic_coefficients_jet_shard(orc, lesmi):
+    """The coefficients on the 256 x 128 x 128 jet shard of the benchmark's
+    dynamic-closure leg (every tile and k segment of the three kernels full,
+    the last of each ragged), weighted as above, to 1e-10."""
+    case = I.jet_case(256, 128, 128, seed=0, sgs=2)
+    print("[gpu] dynamic coefficients jet256x128x128", flush=True)
+    s = lesmi.Solver(case)
+    C, D = s.dynamic_coefficients(s.upload(case["Q"]))
+    s.close()
+    m = orc.metrics(case)
+    Co, Do = orc.dynamic_coefficients(case, m, case["Q"])
+    wC, wD, _ = _column_weights(orc, case, m)
+    for lab, x, xo, w in (("C", C, Co, wC), ("D_T", D, Do, wD)):
+        a, ao = x[2:-2, 2:-2] * w, xo[2:-2, 2:-2] * w
+        assert ao.max() > 0.0, lab
+        err = np.abs(a - ao).max() / ao.max()
+        assert err <= 1e-10, (lab, err)
+    # the ghost columns: wrapped along periodic i, nearest interior column along Dirichlet j
+    assert np.array_equal(C[2:-2, :2], C[2:-2, -4:-2]) and np.array_equal(C[:2, 2:-2], np.repeat(C[2:3, 2:-2], 2, 0))
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_sgs_residual_parity(orc, lesmi, name):
     case = CASES[name]
