@@ -78,7 +78,7 @@ __device__ inline void dyn_chain(const double* M, long long fe, long long n, con
 // tile (DPX - 2) x (DPY - 2) and its one-node ring; a block marches DPK
 // output planes in k.  The primitives are formed once per node and plane on
 // the thread tile and one more ring (PPX x PPY) and shared through LDS.
-constexpr int DPX = 32, DPY = 8, DPK = 16;
+constexpr int DPX = 32, DPY = 16, DPK = 16;
 constexpr int DPTI = DPX - 2, DPTJ = DPY - 2;
 constexpr int PPX = DPX + 2, PPY = DPY + 2;
 
