@@ -155,6 +155,60 @@ def test_axis_with_farfield_face(orc, lesmi):
     assert (_rel(Qg, Qo) <= TOL).all(), _rel(Qg, Qo)
 
 
+def test_axis_mesh_b_residual_and_dt(orc, lesmi):
+    """Mesh B of Tab. 2 as an O-grid block, 256 x 128 x 361 (11.8M points),
+    in the configuration the benchmark times (axis, superposed azimuthal
+    seam, far-field face at the outer radius).
+
+    The library's metrics match the oracle's to 1e-13 of each row's maximum,
+    and the CFL step to 1e-14.  The residual is compared with the oracle's
+    metrics handed to les_create, because at this resolution the ring next
+    to the axis (J up to 1e7) makes the residual sensitive to the last bits
+    of its inputs: there a metric term moved by one unit in the last place of
+    its row's maximum moves R by ~1e-11 of its maximum, and a state moved by
+    one unit in the last place moves the oracle's own R_rho_v by ~1.3e-12.
+    So the bound per field is 1e-12 of the field's maximum, or four times the
+    change that such a last-place perturbation of the state causes in the
+    oracle's own residual where that is larger."""
+    import torch
+    case = I.ogrid_case(256, 128, 361, seed=0)
+    case["faces"] = dict(types=[0, 0, 0, 3, 0, 0], p_exit=[0.0] * 6, outside=case["Q"])
+    print("[gpu] axis mesh B 256x128x361 metrics, residual and dt", flush=True)
+    m = orc.metrics(case)
+    s = lesmi.Solver(case)
+    Qd = s.upload(case["Q"])
+    s.set_face(3, lesmi.LES_FACE_FARFIELD, Qd)
+    dt = s.cfl_dt(Qd)
+    mg = s.metrics_dense()
+    s.close()
+    sl = (slice(None), slice(2, -2), slice(2, -2), slice(2, -2))
+    a, b = mg[sl], m[sl]
+    np.testing.assert_array_equal(~np.isfinite(a[9]), ~np.isfinite(b[9]))
+    fin = np.isfinite(b)
+    mag = np.array([np.abs(b[c][fin[c]]).max() for c in range(10)])
+    den = np.array([mag[3 * (c // 3):3 * (c // 3) + 3].max() for c in range(9)] + [mag[9]])
+    err = np.array([np.abs(a[c][fin[c]] - b[c][fin[c]]).max() for c in range(10)]) / den
+    assert (err <= 1e-13).all(), err
+    dto = orc.cfl_dt(case, m, case["Q"])
+    assert abs(dt - dto) <= 1e-14 * dto, (dt, dto)
+
+    s = lesmi.Solver(case, metrics=torch.from_numpy(m).cuda())
+    Qd = s.upload(case["Q"])
+    s.set_face(3, lesmi.LES_FACE_FARFIELD, Qd)
+    Rg = I.interior(s.download(s.residual(Qd)))
+    s.close()
+    Ro = I.interior(orc.residual(case, m, case["Q"]))
+    rng = np.random.default_rng(17)
+    Qp = case["Q"] * (1.0 + 2.0 ** -52 * rng.uniform(-1, 1, size=case["Q"].shape))
+    Rp = I.interior(orc.residual(case, m, Qp))
+    scale = np.abs(Ro).reshape(5, -1).max(1)
+    floor = np.abs(Rp - Ro).reshape(5, -1).max(1) / scale
+    bound = np.maximum(TOL, 4.0 * floor)
+    err = np.abs(Rg - Ro).reshape(5, -1).max(1) / scale
+    assert (err <= bound).all(), (err, bound)
+    assert (bound <= 1e-11).all(), bound  # the floor itself stays near rounding
+
+
 def test_axis_arguments(lesmi):
     case = dict(CASES["ogrid40x24x61"])
     for bc in ((3, 0, 2), (0, 3, 0), (0, 0, 3)):

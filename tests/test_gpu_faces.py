@@ -77,6 +77,24 @@ def test_face_ghosts_and_residual(orc, lesmi):
     s.close()
 
 
+def test_face_jet_shard_residual(orc, lesmi):
+    """The 256 x 128 x 128 jet shard with the faces the benchmark's faces leg
+    times (entrance at i-lo, exit at i-hi, far field on both j sides): the
+    whole residual per field to 1e-12 and the CFL step to 1e-14."""
+    case, Q0 = _case(256, 128, 128, seed=0)
+    print("[gpu] faces: residual 256x128x128", flush=True)
+    s = _solver(lesmi, case, Q0)
+    Q = s.upload(case["Q"])
+    dt = s.cfl_dt(Q)
+    Rg = s.download(s.residual(Q))
+    s.close()
+    m = orc.metrics(case)
+    Ro = orc.residual(case, m, case["Q"])
+    assert (_rel(Rg, Ro) <= TOL).all(), _rel(Rg, Ro)
+    dto = orc.cfl_dt(case, m, case["Q"])
+    assert abs(dt - dto) <= 1e-14 * dto, (dt, dto)
+
+
 def test_face_rk_steps_fp64(orc, lesmi):
     case, Q0 = _case()
     print("[gpu] faces: 2 RK steps FP64", flush=True)
