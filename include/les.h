@@ -72,7 +72,8 @@ typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT =
  *                       metrics and the ghosts wrap with period n - 1; node
  *                       n - 1 is updated like every interior node, so it stays
  *                       equal to node 0 when it starts equal (it counts in the
- *                       norms and the statistics).  A ghost takes the node
+ *                       norms; the statistics along k count it once, with
+ *                       node 0).  A ghost takes the node
  *                       reached by wrapping its ghost coordinates only.
  *   LES_BC_AXIS      -- (j only) the O-grid's centerline (Sec. 3): node j = 0
  *                       lies on the polar axis, j-hi is a Dirichlet side; k
@@ -348,11 +349,13 @@ int les_set_face(les_ctx *ctx, int face, int type, const double *Q_outside, doub
 
 /* Running flow statistics for the time- and azimuth-averaged mean-flow and
  * RMS profiles of Sec. 6 (the periodic k direction is the averaged one):
- *   acc[s][j][i] += sum over k = 0..nk-1 of phi_s(i, j, k),
+ *   acc[s][j][i] += sum over k = 0..nk_s-1 of phi_s(i, j, k),
  *   phi = (rho, u, v, w, p, u u, v v, w w, u v, u w, v w, p p),
  * with the primitives of Eq. 2: u_a = (rho u_a) / rho and
- * p = (gamma - 1)(e - rho |u|^2 / 2).  After N calls the Reynolds means are
- * acc / (N nk); e.g. u_rms = sqrt(<u u> - <u>^2).
+ * p = (gamma - 1)(e - rho |u|^2 / 2); nk_s = nk, or nk - 1 when k is
+ * LES_BC_PERIODIC_SUPERPOSED (node nk - 1 is node 0's place, counted once).
+ * After N calls the Reynolds means are acc / (N nk_s); e.g.
+ * u_rms = sqrt(<u u> - <u>^2).
  * Q: device, library layout, FP64 (interior read only).
  * acc: device, dense [LES_STATS_NF][nj][ni], FP64, caller-owned; zero it
  *    before the first call.  The sums over k are taken in a fixed order, so
@@ -363,7 +366,8 @@ int les_stats_accumulate(les_ctx *ctx, const double *Q, double *acc);
 /* Mean-flow and RMS profiles of Sec. 6 from the sums of les_stats_accumulate,
  * and the potential core (Sec. 6: where the mean axial velocity is at least
  * a fraction, 95 % in the paper, of the inlet jet velocity):
- *   <phi> = acc / samples (samples = calls times nk),
+ *   <phi> = acc / samples (samples = calls times nk_s of
+ *   les_stats_accumulate),
  *   prof = (<rho>, <u>, <v>, <w>, <p>, u_rms, v_rms, w_rms, p_rms, <u'v'>),
  *   a_rms = sqrt(max(0, <a a> - <a>^2)), <u'v'> = <u v> - <u><v>;
  *   core[j][i] = 1 where <u> >= core_frac * u_jet, else 0 (u is the

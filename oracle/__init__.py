@@ -313,7 +313,8 @@ STATS_FIELDS = ("rho", "u", "v", "w", "p", "uu", "vv", "ww", "uv", "uw", "vw", "
 def stats(case, Q, acc=None, prm=None) -> np.ndarray:
     """Running statistics (Sec. 6 mean-flow and RMS profiles, averaged over
     time and the periodic direction k): acc[s][j][i] += sum_k phi_s, phi in
-    STATS_FIELDS order.  Returns acc (a new zero array when acc is None)."""
+    STATS_FIELDS order, over the distinct k planes (nk - 1 of them along a
+    superposed k direction).  Returns acc (a new zero array when acc is None)."""
     lib = _load()
     prm = case["params"] if prm is None else prm
     if acc is None:

@@ -1234,16 +1234,19 @@ double orc_objective(const orc_dims* d, const orc_params* P, const double* m, do
 
 // Running flow statistics (the time- and azimuth-averaged mean-flow and RMS
 // profiles of Sec. 6; the averaged periodic direction is k):
-//   acc[s][j][i] += sum over k = 0..nk-1 of phi_s(i, j, k),
+//   acc[s][j][i] += sum over the distinct azimuths k = 0..nk_s-1 of phi_s(i, j, k),
 //   phi = (rho, u, v, w, p, uu, vv, ww, uv, uw, vw, pp),
 // with the primitives of Eq. 2: u_a = (rho u_a) / rho,
 // p = (gamma - 1)(e - rho (u^2 + v^2 + w^2) / 2).  acc: dense [12][nj][ni].
+// nk_s = nk, or nk - 1 when k is superposed periodic (Sec. 3: the first and
+// last points are the same place, which the average counts once).
 void orc_stats(const orc_dims* d, const orc_params* P, const double* Q, double* acc) {
   Box b(*d);
   const size_t plane = (size_t)b.ni * b.nj;
+  const int nks = b.bc[2] == 2 ? b.nk - 1 : b.nk;
   for (int j = 0; j < b.nj; ++j)
     for (int i = 0; i < b.ni; ++i)
-      for (int k = 0; k < b.nk; ++k) {
+      for (int k = 0; k < nks; ++k) {
         const size_t n = b.at(i, j, k);
         const double rho = Q[n];
         const double u = Q[b.N + n] / rho, v = Q[2 * b.N + n] / rho, w = Q[3 * b.N + n] / rho;

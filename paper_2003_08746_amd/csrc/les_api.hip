@@ -668,7 +668,9 @@ int les_set_face(les_ctx* ctx, int face, int type, const double* Q_outside, doub
 int les_stats_accumulate(les_ctx* ctx, const double* Q, double* acc) {
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_stats_accumulate: null context");
   if (!Q || !acc) return fail(ctx, LES_ERR_ARG, "les_stats_accumulate: Q and acc are required");
-  HIPCHK(ctx, les::launch_stats(ctx->s, ctx->L, ctx->P, Q, acc));
+  // a superposed k direction repeats plane 0 as plane nk - 1: counted once
+  const int nks = ctx->bc[2] == 2 ? ctx->L.nk - 1 : ctx->L.nk;
+  HIPCHK(ctx, les::launch_stats(ctx->s, ctx->L, ctx->P, nks, Q, acc));
   return LES_OK;
 }
 

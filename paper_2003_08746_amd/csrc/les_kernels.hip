@@ -655,21 +655,22 @@ namespace les {
 // ---------------------------------------------------------------------------
 // Running flow statistics (Sec. 6: time- and azimuth-averaged mean-flow and
 // RMS profiles; the periodic k direction is the averaged one):
-//   acc[s][j][i] += sum over k of phi_s(i, j, k),
-//   phi = (rho, u, v, w, p, uu, vv, ww, uv, uw, vw, pp).
+//   acc[s][j][i] += sum over k = 0..nks-1 of phi_s(i, j, k),
+//   phi = (rho, u, v, w, p, uu, vv, ww, uv, uw, vw, pp),
+// nks = the distinct k planes (nk, or nk - 1 along a superposed direction).
 // A block of 64 x 4 threads covers 64 nodes of one row j; thread (x, y) sums
 // the y-th of four contiguous k ranges in ascending k, and the four partial
 // sums are added in a fixed order, so repeated runs give identical sums.
 // ---------------------------------------------------------------------------
 constexpr int STATS_NF = 12;
 
-__global__ void __launch_bounds__(256) k_stats(Layout L, Phys P, const double* __restrict__ Q,
+__global__ void __launch_bounds__(256) k_stats(Layout L, Phys P, int nks, const double* __restrict__ Q,
                                                double* __restrict__ acc) {
   __shared__ double red[3][STATS_NF][64];
   const int x = threadIdx.x, y = threadIdx.y;
   const int i = blockIdx.x * 64 + x, j = blockIdx.y;
-  const int kper = (L.nk + 3) / 4;
-  const int k0 = y * kper, k1 = min(L.nk, k0 + kper);
+  const int kper = (nks + 3) / 4;
+  const int k0 = y * kper, k1 = min(nks, k0 + kper);
   double s[STATS_NF];
 #pragma unroll
   for (int f = 0; f < STATS_NF; ++f) s[f] = 0.0;
@@ -809,9 +810,9 @@ hipError_t launch_stream_copy(hipStream_t s, const void* src, void* dst, long lo
   return hipGetLastError();
 }
 
-hipError_t launch_stats(hipStream_t s, const Layout& L, const Phys& P, const double* Q, double* acc) {
+hipError_t launch_stats(hipStream_t s, const Layout& L, const Phys& P, int nks, const double* Q, double* acc) {
   dim3 g(nblk(L.ni, 64), L.nj), b(64, 4);
-  k_stats<<<g, b, 0, s>>>(L, P, Q, acc);
+  k_stats<<<g, b, 0, s>>>(L, P, nks, Q, acc);
   return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ hipError_t launch_ghost_fill(hipStream_t s, const Layout& L, const int bc[3], do
 hipError_t launch_ghost_fill_f32(hipStream_t s, const Layout& L, const int bc[3], float* q, const double* frozen,
                                  const Faces& F);
 // acc[12][nj][ni] += sums over k of the primitives and their second moments
-hipError_t launch_stats(hipStream_t s, const Layout& L, const Phys& P, const double* Q, double* acc);
+hipError_t launch_stats(hipStream_t s, const Layout& L, const Phys& P, int nks, const double* Q, double* acc);
 hipError_t launch_stats_profiles(hipStream_t s, const Layout& L, const double* acc, double samples, double core_u,
                                  double* prof, unsigned char* core);
 // p[0 .. n) = 0 on stream s.

@@ -418,9 +418,15 @@ class Solver:
         les_stats_accumulate(self.ctx, Q.data_ptr(), acc.data_ptr())
         return acc
 
+    @property
+    def stats_planes(self) -> int:
+        """k planes one les_stats_accumulate call sums: nk, or nk - 1 along a
+        superposed k direction (its last plane repeats the first)."""
+        return self.nk - 1 if self.bc[2] == LES_BC_PERIODIC_SUPERPOSED else self.nk
+
     def stats_profiles(self, acc, samples, u_jet=None, core_frac=0.95):
         """Mean-flow and RMS profiles (les_stats_profiles) from the sums in
-        acc; samples = number of accumulations times nk.  Returns a dict of
+        acc; samples = number of accumulations times stats_planes.  Returns a dict of
         (nj, ni) device tensors keyed by PROF_FIELDS, plus "core" (a bool
         (nj, ni) tensor: the potential core, <u> >= core_frac u_jet) when
         u_jet is given."""

@@ -100,6 +100,29 @@ def test_superposed_equals_periodic_on_gpu(lesmi):
     b.close()
 
 
+def test_superposed_statistics(orc, lesmi):
+    """Running statistics along a superposed k direction count the repeated
+    plane once: the GPU sums of the superposed block equal the GPU sums of the
+    periodic block of one plane fewer (the same terms in the same order), and
+    the oracle's to the summation bound of the plain statistics test."""
+    base, axis = _cases()["wavy47x33x19_k"]
+    case = I.superposed_case(base, axis)
+    print("[gpu] superposed statistics", flush=True)
+    a, b = lesmi.Solver(base), lesmi.Solver(case)
+    assert a.stats_planes == base["nk"] and b.stats_planes == base["nk"] == case["nk"] - 1
+    acc_a = a.stats_accumulate(a.upload(base["Q"])).cpu().numpy()
+    acc_b = b.stats_accumulate(b.upload(case["Q"])).cpu().numpy()
+    a.close()
+    b.close()
+    np.testing.assert_array_equal(acc_b, acc_a)
+    want = orc.stats(case, case["Q"])
+    n = b.stats_planes
+    eps = np.finfo(np.float64).eps
+    for k in range(want.shape[0]):
+        tol = (n * n + 8 * n) * eps * np.abs(want[k]).max()
+        assert np.abs(acc_b[k] - want[k]).max() <= tol, (k, np.abs(acc_b[k] - want[k]).max(), tol)
+
+
 def _interior_rand(case, seed, scale_by_field=True):
     rng = np.random.default_rng(seed)
     a = np.zeros_like(case["Q"])
