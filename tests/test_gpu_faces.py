@@ -111,6 +111,32 @@ def test_face_rk_steps_fp64(orc, lesmi):
     s.close()
 
 
+@pytest.mark.parametrize("sgs,CI", [(2, 0.0), (1, 0.05)])
+def test_face_sgs_variants(orc, lesmi, sgs, CI):
+    """The SGS variants with boundary faces: the dynamic closure's test
+    filter and column sums read the face ghosts (ghost columns of the
+    Dirichlet sides take the nearest interior column), and sigma_kk enters the
+    flux pressure next to them; residual and two CFL steps in FP64."""
+    case, Q0 = _case(40, 20, 12, seed=5)
+    case["params"] = dict(case["params"], sgs=sgs, CI=CI)
+    print(f"[gpu] faces: SGS variant sgs={sgs} CI={CI}", flush=True)
+    m = orc.metrics(case)
+    s = _solver(lesmi, case, Q0)
+    Q = s.upload(case["Q"])
+    Rg = s.download(s.residual(Q))
+    Ro = orc.residual(case, m, case["Q"])
+    assert (_rel(Rg, Ro) <= TOL).all(), _rel(Rg, Ro)
+    Q = s.upload(case["Q"])
+    dts, _ = s.advance(Q, 2, want_dt=True)
+    Qg = s.download(Q)
+    s.close()
+    Qo = case["Q"]
+    for n in range(2):
+        Qo, dto, _, _ = orc.rk_step(case, m, Qo)
+        assert abs(dts[n] - dto) <= 1e-14 * dto
+    assert (_rel(Qg, Qo) <= TOL).all(), _rel(Qg, Qo)
+
+
 def test_face_rk_steps_mixed(orc, lesmi):
     case, Q0 = _case()
     print("[gpu] faces: 2 RK steps mixed", flush=True)
