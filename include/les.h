@@ -91,9 +91,13 @@ typedef enum { LES_FACE_FROZEN = 0, LES_FACE_CHARACTERISTIC = 1, LES_FACE_EXIT =
  *                       and the fourth difference of the face between the
  *                       axis and j = 1 takes the cross-axis value by linear
  *                       extrapolation (no five-point stencil across the
- *                       axis).  The CFL bound skips the axis.  Not with
- *                       sgs = 2.  The adjoint entry points differentiate the
- *                       centerline condition and the cross-axis ghosts.
+ *                       axis).  The CFL bound skips the axis.  With sgs = 2
+ *                       the axis nodes (zero volume) carry no strain products
+ *                       and no contractions, the axis column takes the ring
+ *                       j = 1's coefficients and ghost column (i, -m) ring
+ *                       column (i, m).  The adjoint entry points
+ *                       differentiate the centerline condition and the
+ *                       cross-axis ghosts.
  * xyz: device, dense padded layout [3][nk+4][nj+4][ni+4], coordinates on every
  * node including ghosts and edges (read during les_create only). */
 typedef struct {
@@ -120,8 +124,9 @@ typedef struct {
  *   mu_sgs = rho (Cs Delta)^2 sqrt(2 S_ij S_ij), Delta = (1/J)^(1/3);
  *   sgs = 2: dynamic closure (Germano's identity with a test filter of width
  *   2 Delta, weights 1/4, 1/2, 1/4 per index, in the Favre form of Moin,
- *   Squires, Cabot and Lee; Lilly's least squares summed over the periodic k
- *   direction, clipped at 0): mu_sgs = C rho Delta^2 |S| and kappa_sgs =
+ *   Squires, Cabot and Lee; Lilly's least squares summed over the distinct
+ *   planes of the periodic k direction (nk - 1 along a superposed one),
+ *   clipped at 0): mu_sgs = C rho Delta^2 |S| and kappa_sgs =
  *   Cp D_T rho Delta^2 |S| with one C, D_T per (i, j) column, re-evaluated
  *   with every residual (Pr_sgs and Cs are then unused).
  *   CI >= 0 (sgs >= 1): Yoshizawa's isotropic SGS stress (Eq. 11)
@@ -163,11 +168,11 @@ typedef struct {
  * metrics, n < 5, a padded k plane so large that seven of them reach 2^29
  * elements (the stage kernel's 32-bit offsets from its per-segment base;
  * about 7.7e7 nodes per plane), bad bc (LES_BC_AXIS elsewhere than j, or
- * without a superposed k of odd nk, or with sgs = 2), gamma <= 1,
+ * without a superposed k of odd nk), gamma <= 1,
  * R_gas <= 0, Pr <= 0, negative k2/k4/mu_ref/CI, sgs outside 0..2, unknown
  * prec; LES_ERR_NOMEM when the block's arrays (20 FP64 fields of
  * field_elems doubles, 10 more FP32 ones when mixed) do not fit.  sgs = 2
- * allocates the dynamic closure's work arrays (50 fields) here too. */
+ * allocates the dynamic closure's work arrays (27 fields) here too. */
 int les_create(les_ctx **out, const les_grid *grid, const les_metrics *metrics,
                const les_flow_params *params, void *hip_stream);
 

@@ -60,7 +60,8 @@
 //       the compressible (Favre) form of Moin, Squires, Cabot and Lee (1991),
 //       by Lilly's least squares averaged over the periodic k direction:
 //         C(i,j) = max(0, <L^d : M> / <M : M>),  D_T(i,j) = max(0, <K . N> / <N . N>),
-//       with <.> the sum over interior k and, at one node (^ = test filter,
+//       with <.> the sum over the distinct interior k (nk - 1 of them along a
+//       superposed direction, R15) and, at one node (^ = test filter,
 //       the index-space tensor product of the weights (1/4, 1/2, 1/4)):
 //         L_ij = (rho u_i u_j)^ - (rho u_i)^ (rho u_j)^ / rho^,
 //         M_ij = 2 (D^2 rho |S| S^d_ij)^ - 2 (2D)^2 rho^ |S~| S~^d_ij,
@@ -90,8 +91,18 @@
 //       the cross-axis value by linear extrapolation, Q(-1) = 2 Q(0) - Q(1),
 //       i.e. d3 = Q(2) - 2 Q(1) + Q(0), so no five-point stencil reaches
 //       across the axis (the pressure sensor, a three-point stencil, keeps
-//       its cross-axis neighbour).  The CFL bound skips the axis nodes.  The
-//       dynamic closure (R17) is not defined there (sgs = 2 refused).
+//       its cross-axis neighbour).  The CFL bound skips the axis nodes.
+//   R20 the face normal of an entrance, exit or far-field face at an axis
+//       node (where the metric row of that direction vanishes): the
+//       normalised azimuthal mean of the unit normals of the ring j = 1.
+//   R21 the dynamic closure (R17) with the polar axis: an axis node's control
+//       volume vanishes (1/J = 0, so D = 0) and its strain is 0/0, so its
+//       grid-level products D^2 rho |S| S^d and D^2 rho |S| grad T are 0, the
+//       contractions are summed over the off-axis rings only, the axis
+//       column takes the ring j = 1's coefficients, and ghost column (i, -m)
+//       across the axis takes column (i, m) (its azimuthal sums run over the
+//       same points).  (Only the axis nodes' own residual, which is not
+//       formed, reads the axis column.)
 //   R15 superposed periodic direction (Sec. 3: the first and last azimuthal
 //       points coincide): bc = 2, period n - 1; node n - 1 is node 0 again
 //       (it takes node 0's metrics), ghosts wrap with period n - 1.  A ghost
@@ -649,6 +660,9 @@ void dynamic_coefficients(const Box& b, const orc_params& P, const double* m, co
   for (int k = -1; k <= b.nk; ++k)
     for (int j = -1; j <= b.nj; ++j)
       for (int i = -1; i <= b.ni; ++i) {
+        // R21: on the polar axis the node's control volume vanishes (1/J = 0,
+        // so D = 0) and its strain is 0/0: the products are 0 there
+        if (b.axis && j == 0) continue;
         const size_t n = b.at(i, j, k);
         S du[3][3], dT[3], Sd[3][3], mag;
         for (int a = 0; a < 3; ++a) gradient(&u[(size_t)a * N], i, j, k, du[a]);
@@ -679,13 +693,16 @@ void dynamic_coefficients(const Box& b, const orc_params& P, const double* m, co
         for (int a = 0; a < 3; ++a) ut[(size_t)a * N + n] = filt(1 + a, i, j, k) / rh;
         Tt[n] = filt(4, i, j, k) / rh;
       }
-  // per-column sums over interior k (ascending) of L^d:M, M:M, K.N, N.N
+  // per-column sums over the distinct interior k (ascending; a superposed k
+  // direction's last plane is its first one's place) of L^d:M, M:M, K.N,
+  // N.N; none on the polar axis (R21)
   const size_t cols = (size_t)b.pj * b.pi;
+  const int nks = b.bc[2] == 2 ? b.nk - 1 : b.nk;
   std::vector<S> nC(cols, S(0.0)), dC(cols, S(0.0)), nD(cols, S(0.0)), dD(cols, S(0.0));
-  for (int j = 0; j < b.nj; ++j)
+  for (int j = b.axis ? 1 : 0; j < b.nj; ++j)
     for (int i = 0; i < b.ni; ++i) {
       const size_t col = (size_t)(j + G) * b.pi + (size_t)(i + G);
-      for (int k = 0; k < b.nk; ++k) {
+      for (int k = 0; k < nks; ++k) {
         const size_t n = b.at(i, j, k);
         S fv[NF];
         for (int f = 0; f < NF; ++f) fv[f] = filt(f, i, j, k);
@@ -724,10 +741,18 @@ void dynamic_coefficients(const Box& b, const orc_params& P, const double* m, co
   Dc.assign(cols, S(0.0));
   for (int j = -G; j < b.nj + G; ++j)
     for (int i = -G; i < b.ni + G; ++i) {
-      // ghost columns: wrapped (periodic) or nearest interior (Dirichlet) column
+      // ghost columns: wrapped (periodic) or nearest interior (Dirichlet)
+      // column; across the polar axis column (i, -m) is the ring column
+      // (i, m) (its azimuthal sums run over the same points), and the axis
+      // column takes the ring j = 1's coefficients (R21)
       int ii = i, jj = j;
       if (i < 0 || i >= b.ni) ii = b.bc[0] == 1 ? std::min(std::max(i, 0), b.ni - 1) : wrap(i, b.ni, b.bc[0]);
-      if (j < 0 || j >= b.nj) jj = b.bc[1] == 1 ? std::min(std::max(j, 0), b.nj - 1) : wrap(j, b.nj, b.bc[1]);
+      if (b.axis) {
+        jj = j < 0 ? -j : std::min(j, b.nj - 1);
+        if (jj == 0) jj = 1;
+      } else if (j < 0 || j >= b.nj) {
+        jj = b.bc[1] == 1 ? std::min(std::max(j, 0), b.nj - 1) : wrap(j, b.nj, b.bc[1]);
+      }
       const size_t src = (size_t)(jj + G) * b.pi + (size_t)(ii + G), dst = (size_t)(j + G) * b.pi + (size_t)(i + G);
       Cc[dst] = val(dC[src]) > 0.0 ? s_max(S(0.0), nC[src] / dC[src]) : S(0.0);
       Dc[dst] = val(dD[src]) > 0.0 ? s_max(S(0.0), nD[src] / dD[src]) : S(0.0);
@@ -790,10 +815,6 @@ void residual(const Box& b, const orc_params& P, const double* m, const S* Q, co
   // tau[3*a+b] (symmetric), Theta[x] = u_i tau_ix + (kappa + kappa_sgs) dT/dx,
   // pis = sigma_kk / 3 (R18)
   std::vector<S> Cdyn, Ddyn;
-  if (P.sgs == 2 && b.axis) {
-    std::fprintf(stderr, "oracle: the dynamic closure is not defined on the axis (R19)\n");
-    std::abort();
-  }
   if (P.sgs == 2) dynamic_coefficients(b, P, m, Q, Cdyn, Ddyn);
   std::vector<S> tau(9 * N), Theta(3 * N), pis(N, S(0.0));
 #pragma omp parallel for

@@ -268,8 +268,6 @@ int les_create(les_ctx** out, const les_grid* grid, const les_metrics* metrics, 
                   grid->bc[d]);
   if (grid->bc[1] == LES_BC_AXIS && (grid->bc[2] != LES_BC_PERIODIC_SUPERPOSED || (grid->nk - 1) % 2 != 0))
     return fail(nullptr, LES_ERR_ARG, "les_create: the axis needs a superposed periodic k direction with nk - 1 even");
-  if (grid->bc[1] == LES_BC_AXIS && prm->sgs == 2)
-    return fail(nullptr, LES_ERR_ARG, "les_create: the dynamic closure is not defined on the axis");
   if (!metrics_dense && !grid->xyz) return fail(nullptr, LES_ERR_ARG, "les_create: need xyz or metrics");
   if (!(prm->gamma > 1.0) || !(prm->R_gas > 0.0) || !(prm->Pr > 0.0) || !(prm->Pr_sgs > 0.0) ||
       !(prm->mu_ref >= 0.0) || !(prm->T_ref > 0.0) || !(prm->S_suth >= 0.0) || !(prm->k2 >= 0.0) ||

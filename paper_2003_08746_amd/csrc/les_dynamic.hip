@@ -27,7 +27,11 @@
 //   k_dyn_coef    per padded column: the segment sums added in ascending
 //                 order (a fixed order) and the clipped ratios; ghost
 //                 columns take the wrapped (periodic) or nearest interior
-//                 (Dirichlet) column.
+//                 (Dirichlet) column, across the polar axis the ring column
+//                 of the same radius; the axis column takes ring 1's.
+// The sums over k run over the distinct planes (nk - 1 along a superposed
+// direction).  On the polar axis (a node of zero volume) the strain and
+// temperature-gradient products are 0 and no contractions are formed.
 // The filter is separable and applied along i, then j, then k, each a
 // three-point sum evaluated left to right.  This is an optional model: its
 // passes move about 0.45 KB of HBM traffic per point and evaluation (the 23
@@ -119,7 +123,7 @@ __device__ inline double lane_next(double v) {
 // registers: out(k) = (0.25 G(k-1) + 0.5 G(k)) + 0.25 G(k+1), carried as the
 // pending sum of the two earlier planes and a quarter of the last.
 template <class QI>
-__global__ void __launch_bounds__(DPX * DPY) k_dyn_plane(Layout L, Phys P, const double* __restrict__ M,
+__global__ void __launch_bounds__(DPX * DPY) k_dyn_plane(Layout L, Phys P, int axis, const double* __restrict__ M,
                                                          const QI* __restrict__ Q, double* __restrict__ V) {
   __shared__ double sF[NRAW][DPY][DPX];
   __shared__ double sP[2][5][PPY][PPX];
@@ -134,7 +138,9 @@ __global__ void __launch_bounds__(DPX * DPY) k_dyn_plane(Layout L, Phys P, const
   const int i0 = -1 + (int)(tb % tiles_i) * DPTI, j0 = -1 + (int)(tb / tiles_i) * DPTJ;
   const int i = i0 - 1 + tx, j = j0 - 1 + ty;  // this thread's node; the LDS tiles start at (i0 - 2, j0 - 2)
   const bool in_box = i <= L.ni + 1 && j <= L.nj + 1;
-  const bool grad_ij = i >= -1 && j >= -1 && i <= L.ni && j <= L.nj;
+  // the strain and temperature-gradient products on [-1, n]^3, except on the
+  // polar axis (a node of zero volume, D = 0, whose strain is 0/0: 0 there)
+  const bool grad_ij = i >= -1 && j >= -1 && i <= L.ni && j <= L.nj && !(axis && j == 0);
   const bool out_node = tx >= 1 && tx < DPX - 1 && ty >= 1 && ty < DPY - 1 && i <= L.ni && j <= L.nj;
 
   // primitives of plane kp on the LDS tile, into buffer kp & 1
@@ -255,13 +261,15 @@ __device__ inline void dyn_contract(const Layout& L, const double* __restrict__ 
   x[3] = nn;
 }
 
-// Column segments of the k sums: DNK planes per thread.
+// Column segments of the k sums: DNK planes per thread, over the nks
+// distinct planes (nk - 1 along a superposed k direction, whose last plane
+// is its first one's place).
 constexpr int DNK = 16;
-inline int dyn_nseg(const Layout& L) { return (L.nk + DNK - 1) / DNK; }
+inline int dyn_nseg(int nks) { return (nks + DNK - 1) / DNK; }
 
 // Xp[q][seg][j][i] = sum over k of segment seg (ascending) of contraction q
 // at the interior nodes of column (i, j).
-__global__ void __launch_bounds__(256) k_dyn_node(Layout L, int nseg, const double* __restrict__ M,
+__global__ void __launch_bounds__(256) k_dyn_node(Layout L, int nks, int nseg, int axis, const double* __restrict__ M,
                                                   const double* __restrict__ V, double* __restrict__ Xp) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long ncoli = (long long)L.ni * L.nj;
@@ -269,7 +277,8 @@ __global__ void __launch_bounds__(256) k_dyn_node(Layout L, int nseg, const doub
   const long long col = t % ncoli;
   const int seg = (int)(t / ncoli);
   const int i = (int)(col % L.ni), j = (int)(col / L.ni);
-  const int k1 = (seg + 1) * DNK < L.nk ? (seg + 1) * DNK : L.nk;
+  // (no contractions on the polar axis: its column takes the ring j = 1's)
+  const int k1 = (axis && j == 0) ? 0 : ((seg + 1) * DNK < nks ? (seg + 1) * DNK : nks);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = seg * DNK; k < k1; ++k) {
     double x[4];
@@ -280,6 +289,12 @@ __global__ void __launch_bounds__(256) k_dyn_node(Layout L, int nseg, const doub
 }
 
 __device__ inline int dyn_src(int x, int n, int bc) {
+  if (bc == 3) {
+    // polar axis (j): column -m across the axis is ring column m, the axis
+    // column takes ring 1's, the far side is Dirichlet
+    const int y = x < 0 ? -x : (x < n ? x : n - 1);
+    return y == 0 ? 1 : y;
+  }
   if (x >= 0 && x < n) return x;
   if (bc == 1) return x < 0 ? 0 : n - 1;  // Dirichlet: nearest interior column
   const int p = bc == 2 ? n - 1 : n;      // periodic (superposed: period n - 1)
@@ -310,9 +325,11 @@ hipError_t run(hipStream_t s, const Layout& L, const int bc[3], const Phys& P, c
                double* work, double* dyn) {
   double* V = work;
   double* X = work + (long long)NRAW * L.fe;
-  k_dyn_plane<QI><<<(unsigned)dyn_plane_blocks(L), DPX * DPY, 0, s>>>(L, P, M, Q, V);
-  const int nseg = dyn_nseg(L);
-  k_dyn_node<<<nblk((long long)L.ni * L.nj * nseg, 256), 256, 0, s>>>(L, nseg, M, V, X);
+  const int axis = bc[1] == 3;
+  const int nks = bc[2] == 2 ? L.nk - 1 : L.nk;
+  k_dyn_plane<QI><<<(unsigned)dyn_plane_blocks(L), DPX * DPY, 0, s>>>(L, P, axis, M, Q, V);
+  const int nseg = dyn_nseg(nks);
+  k_dyn_node<<<nblk((long long)L.ni * L.nj * nseg, 256), 256, 0, s>>>(L, nks, nseg, axis, M, V, X);
   k_dyn_coef<<<nblk(dyn_ncol(L), 256), 256, 0, s>>>(L, bc[0], bc[1], nseg, X, dyn);
   return hipGetLastError();
 }

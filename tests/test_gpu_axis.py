@@ -215,9 +215,80 @@ def test_axis_arguments(lesmi):
         with pytest.raises(lesmi.LesError) as e:
             lesmi.Solver(dict(case, bc=bc))
         assert e.value.code == lesmi.LES_ERR_ARG
-    with pytest.raises(lesmi.LesError) as e:
-        lesmi.Solver(dict(case, params=dict(case["params"], sgs=2)))
-    assert e.value.code == lesmi.LES_ERR_ARG
+
+
+# ---------------------------------------------------------------------------
+# The dynamic closure on the O-grid (R21)
+# ---------------------------------------------------------------------------
+DYN = {"ogrid40x24x61_dyn": lambda: I.ogrid_case(40, 24, 61, seed=1, sgs=2),
+       "ogrid24x16x361_dyn_ci": lambda: I.ogrid_case(24, 16, 361, seed=2, sgs=2, CI=0.02)}
+
+
+@pytest.mark.parametrize("name", list(DYN))
+def test_axis_dynamic_closure(orc, lesmi, name):
+    """The dynamic closure with the polar axis: the coefficients (weighted
+    by the SGS fluxes they produce, as for the other blocks; the axis row,
+    whose coefficients are the ring's, has zero weight), the residual and two
+    CFL steps per field to 1e-12."""
+    from tests.test_gpu_sgs import _column_weights
+    case = DYN[name]()
+    print(f"[gpu] axis dynamic closure {name}", flush=True)
+    m = orc.metrics(case)
+    s = lesmi.Solver(case)
+    C, D = s.dynamic_coefficients(s.upload(case["Q"]))
+    Co, Do = orc.dynamic_coefficients(case, m, case["Q"])
+    np.testing.assert_array_equal(C[2], C[3])  # the axis column is the ring's
+    with np.errstate(invalid="ignore", divide="ignore"):
+        wC, wD, _ = _column_weights(orc, case, m)
+    for lab, x, xo, w in (("C", C, Co, wC), ("D_T", D, Do, wD)):
+        w = np.where(np.isfinite(w), w, 0.0)
+        w[0] = 0.0  # the axis row
+        a, ao = x[2:-2, 2:-2] * w, xo[2:-2, 2:-2] * w
+        assert ao.max() > 0.0, lab
+        assert np.abs(a - ao).max() <= 1e-10 * ao.max(), (lab, np.abs(a - ao).max() / ao.max())
+    Qd = s.upload(case["Q"])
+    Rg = s.download(s.residual(Qd))
+    Ro = orc.residual(case, m, case["Q"])
+    assert (_rel(Rg, Ro) <= TOL).all(), _rel(Rg, Ro)
+    Qd = s.upload(case["Q"])
+    dts, _ = s.advance(Qd, 2, want_dt=True)
+    Qg = s.download(Qd)
+    s.close()
+    Qo = case["Q"]
+    for n in range(2):
+        Qo, dto, _, _ = orc.rk_step(case, m, Qo)
+        assert abs(dts[n] - dto) <= 1e-14 * dto
+    assert (_rel(Qg, Qo) <= TOL).all(), _rel(Qg, Qo)
+
+
+def test_axis_dynamic_mixed_and_fused(orc, lesmi):
+    """The dynamic closure on the O-grid in the FP32-mixed form (two steps
+    at the FP64 steps' dt, against the oracle, to the mixed bound) and the
+    fused kernel against the reference kernel."""
+    case = DYN["ogrid40x24x61_dyn"]()
+    m = orc.metrics(case)
+    s = lesmi.Solver(case, prec=lesmi.LES_MIXED)
+    Q = s.upload(case["Q"])
+    dts, _ = s.advance(Q, 2, want_dt=True)
+    Qg = s.download(Q)
+    s.close()
+    Qo = case["Q"]
+    for n in range(2):
+        Qo, _, _, _ = orc.rk_step(case, m, Qo, dt=dts[n])
+    d = I.interior(Qg) - I.interior(Qo)
+    sc = np.abs(I.interior(Qo)).reshape(5, -1).max(1)
+    sc[1:4] = sc[1:4].max()
+    linf = np.abs(d).reshape(5, -1).max(1) / sc
+    assert (linf <= MIXED_BOUND).all(), linf
+    out = []
+    for ref in (False, True):
+        s = lesmi.Solver(case)
+        s.use_reference(ref)
+        Q = s.upload(case["Q"])
+        s.rk_step(Q, 0.0)
+        out.append(s.download(Q))
+        s.close()
+    assert (_rel(out[0], out[1]) <= 1e-13).all(), _rel(out[0], out[1])
 
 
 # ---------------------------------------------------------------------------

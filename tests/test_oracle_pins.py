@@ -1085,11 +1085,13 @@ def test_dynamic_conservation(orc):
 # Centerline of the O-grid (R19; Sec. 3): uniform flow, the azimuthal
 # average, no five-point stencil across the axis, convergence next to it
 # ---------------------------------------------------------------------------
-def test_axis_uniform_flow_preserved(orc):
+@pytest.mark.parametrize("sgs", [1, 2])
+def test_axis_uniform_flow_preserved(orc, sgs):
     """A uniform flow (with a component across the axis) on the O-grid:
     the residual vanishes off the axis and steps leave the state unchanged
-    (the azimuthal mean of a uniform ring is the uniform state)."""
-    c = I.ogrid_case(12, 10, 25, seed=1)
+    (the azimuthal mean of a uniform ring is the uniform state); with the
+    dynamic closure (R21) too, whose coefficients are 0 for uniform flow."""
+    c = I.ogrid_case(12, 10, 25, seed=1, sgs=sgs)
     sh = c["Q"].shape[1:]
     Q = I.uniform_state(sh, vel=(1.2, 0.3, -0.2))
     c["Q"] = Q
@@ -1102,6 +1104,44 @@ def test_axis_uniform_flow_preserved(orc):
         Qn, _, _, _ = orc.rk_step(c, m, Qn)
     rel = np.abs(I.interior(Qn) - I.interior(Q)).reshape(5, -1).max(1) / np.abs(I.interior(Q)).reshape(5, -1).max(1)
     assert rel.max() <= 1e-13, rel
+
+
+def test_axis_dynamic_columns(orc):
+    """R21: with the polar axis the dynamic closure's axis column takes the
+    ring j = 1's coefficients and ghost column (i, -m) the ring column (i, m);
+    the coefficients are finite and not all zero on a perturbed round jet; a
+    state whose products on the axis row were taken from its (0/0) strain
+    would be NaN there."""
+    c = I.ogrid_case(24, 12, 41, seed=4, sgs=2)
+    m = orc.metrics(c)
+    C, D = orc.dynamic_coefficients(c, m, c["Q"])
+    assert np.isfinite(C).all() and np.isfinite(D).all()
+    assert C[3:-2, 2:-2].max() > 0.0 and D[3:-2, 2:-2].max() > 0.0
+    for x in (C, D):
+        np.testing.assert_array_equal(x[2], x[3])  # axis row j = 0 <- ring 1
+        np.testing.assert_array_equal(x[1], x[3])  # j = -1 <- ring 1
+        np.testing.assert_array_equal(x[0], x[4])  # j = -2 <- ring 2
+        np.testing.assert_array_equal(x[-2], x[-3])  # j-hi ghosts: nearest ring
+    R = orc.residual(c, m, c["Q"])
+    assert np.isfinite(I.interior(R)).all()
+
+
+def test_superposed_dynamic_equals_periodic(orc):
+    """The dynamic closure's sums over a superposed k direction run over its
+    distinct planes: the superposed block's coefficients, residual and step
+    equal the periodic block's of one plane fewer, bit for bit."""
+    c = _periodic_base()
+    c["params"] = dict(c["params"], sgs=2)
+    cs = I.superposed_case(c, 2)
+    m, ms = orc.metrics(c), orc.metrics(cs)
+    C, D = orc.dynamic_coefficients(c, m, c["Q"])
+    Cs, Ds = orc.dynamic_coefficients(cs, ms, cs["Q"])
+    np.testing.assert_array_equal(Cs, C)
+    np.testing.assert_array_equal(Ds, D)
+    assert C[2:-2, 2:-2].max() > 0.0
+    R, Rs = orc.residual(c, m, c["Q"]), orc.residual(cs, ms, cs["Q"])
+    n = c["nk"]
+    np.testing.assert_array_equal(_along(I.interior(Rs), 2, slice(0, n)), I.interior(R))
 
 
 def test_axis_face_normal_on_axis_row(orc):
