@@ -308,7 +308,9 @@ int les_residual_adjoint(les_ctx *ctx, double *Q, const double *Rbar, double *Qb
 /* Probe objective on the plane i = i_p (interior of Q):
  *   *J_accum += weight * sum_{j,k} (p - p_inf)^2          (J_accum: device)
  *   Qbar[i_p plane] += weight * 2 (p - p_inf) dp/dQ       (Qbar: device or NULL)
- * with p = (gamma - 1)(e - (m_1^2 + m_2^2 + m_3^2) / (2 rho)). */
+ * with p = (gamma - 1)(e - (m_1^2 + m_2^2 + m_3^2) / (2 rho)); k runs over the
+ * distinct planes (0..nk-2 along a superposed k direction, whose last plane
+ * repeats the first). */
 int les_probe_objective(les_ctx *ctx, const double *Q, int i_p, double p_inf, double weight, double *J_accum,
                         double *Qbar);
 

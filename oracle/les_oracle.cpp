@@ -1072,7 +1072,10 @@ S probe_pressure_sq(const Box& b, const orc_params& P, const S* Q, int i_p, doub
   const size_t N = b.N;
   const double g = P.gamma;
   S acc = 0.0;
-  for (int k = 0; k < b.nk; ++k)
+  // over the distinct k planes (a superposed direction's last plane is its
+  // first one's place)
+  const int nks = b.bc[2] == 2 ? b.nk - 1 : b.nk;
+  for (int k = 0; k < nks; ++k)
     for (int j = 0; j < b.nj; ++j) {
       size_t n = b.at(i_p, j, k);
       S rho = Q[n], u = Q[N + n] / rho, v = Q[2 * N + n] / rho, w = Q[3 * N + n] / rho;

@@ -704,7 +704,9 @@ int les_probe_objective(les_ctx* ctx, const double* Q, int i_p, double p_inf, do
   if (!ctx) return fail(nullptr, LES_ERR_ARG, "les_probe_objective: null context");
   if (!Q || !J_accum) return fail(ctx, LES_ERR_ARG, "les_probe_objective: Q and J_accum are required");
   if (i_p < 0 || i_p >= ctx->L.ni) return fail(ctx, LES_ERR_ARG, "les_probe_objective: plane %d outside [0, %d)", i_p, ctx->L.ni);
-  HIPCHK(ctx, les::launch_probe(ctx->s, ctx->L, ctx->P, Q, i_p, p_inf, weight, J_accum, Qbar, ctx->part));
+  // over the distinct k planes (a superposed direction's last plane repeats its first)
+  const int nks = ctx->bc[2] == 2 ? ctx->L.nk - 1 : ctx->L.nk;
+  HIPCHK(ctx, les::launch_probe(ctx->s, ctx->L, ctx->P, nks, Q, i_p, p_inf, weight, J_accum, Qbar, ctx->part));
   return LES_OK;
 }
 

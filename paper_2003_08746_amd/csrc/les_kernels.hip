@@ -609,11 +609,12 @@ __global__ void __launch_bounds__(256) k_norm_final(const double* __restrict__ p
 // Pass 1: every block sums its share of the plane into part[blockIdx.x]
 // (and adds the objective's Q adjoint, node by node); pass 2 adds the block
 // sums in a fixed order, so that the objective does not depend on timing.
-__global__ void __launch_bounds__(256) k_probe(Layout L, Phys P, const double* __restrict__ Q, int i_p, double p_inf,
-                                               double weight, double* __restrict__ part, double* __restrict__ Qbar) {
+__global__ void __launch_bounds__(256) k_probe(Layout L, Phys P, int nks, const double* __restrict__ Q, int i_p,
+                                               double p_inf, double weight, double* __restrict__ part,
+                                               double* __restrict__ Qbar) {
   __shared__ double red[4];
   double s = 0.0;
-  const long long cnt = (long long)L.nj * L.nk;
+  const long long cnt = (long long)L.nj * nks;
   for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < cnt; t += (long long)gridDim.x * 256) {
     int j = (int)(t % L.nj), k = (int)(t / L.nj);
     long long n = L.at(i_p, j, k);
@@ -876,11 +877,11 @@ hipError_t launch_norm_final(hipStream_t s, const double* part, long long np, do
   return hipGetLastError();
 }
 
-hipError_t launch_probe(hipStream_t s, const Layout& L, const Phys& P, const double* Q, int i_p, double p_inf,
-                        double weight, double* Jacc, double* Qbar, double* part) {
+hipError_t launch_probe(hipStream_t s, const Layout& L, const Phys& P, int nks, const double* Q, int i_p,
+                        double p_inf, double weight, double* Jacc, double* Qbar, double* part) {
   // up to 64 blocks (part holds at least that many doubles)
-  const unsigned nb = min(64u, nblk((long long)L.nj * L.nk, 256));
-  k_probe<<<nb, 256, 0, s>>>(L, P, Q, i_p, p_inf, weight, part, Qbar);
+  const unsigned nb = min(64u, nblk((long long)L.nj * nks, 256));
+  k_probe<<<nb, 256, 0, s>>>(L, P, nks, Q, i_p, p_inf, weight, part, Qbar);
   k_probe_final<<<1, 64, 0, s>>>(part, (int)nb, weight, Jacc);
   return hipGetLastError();
 }

@@ -41,7 +41,7 @@ hipError_t launch_stage_ref(hipStream_t s, const Layout& L, const Phys& P, const
                             const double* Q0, double* Qout, const double* dtp, double dt, double alpha,
                             const double* f, int i_f, double* part, const double* dyn, int axis);
 hipError_t launch_norm_final(hipStream_t s, const double* part, long long np, double count, double* norms, int* flag);
-hipError_t launch_probe(hipStream_t s, const Layout& L, const Phys& P, const double* Q, int i_p, double p_inf,
-                        double weight, double* Jacc, double* Qbar, double* part);
+hipError_t launch_probe(hipStream_t s, const Layout& L, const Phys& P, int nks, const double* Q, int i_p,
+                        double p_inf, double weight, double* Jacc, double* Qbar, double* part);
 
 }  // namespace les

@@ -123,6 +123,57 @@ def test_superposed_statistics(orc, lesmi):
         assert np.abs(acc_b[k] - want[k]).max() <= tol, (k, np.abs(acc_b[k] - want[k]).max(), tol)
 
 
+def test_superposed_dynamic_closure(orc, lesmi):
+    """The dynamic closure's column sums along a superposed k direction run
+    over its distinct planes: the superposed block's coefficients equal the
+    periodic block's of one plane fewer on the GPU, bit for bit, and its
+    residual matches the oracle's to 1e-12."""
+    base, axis = _cases()["wavy47x33x19_k"]
+    base = dict(base, params=dict(base["params"], sgs=2))
+    case = I.superposed_case(base, axis)
+    print("[gpu] superposed dynamic closure", flush=True)
+    a, b = lesmi.Solver(base), lesmi.Solver(case)
+    Ca, Da = a.dynamic_coefficients(a.upload(base["Q"]))
+    Cb, Db = b.dynamic_coefficients(b.upload(case["Q"]))
+    np.testing.assert_array_equal(Cb, Ca)
+    np.testing.assert_array_equal(Db, Da)
+    Rg = b.download(b.residual(b.upload(case["Q"])))
+    a.close()
+    b.close()
+    Ro = orc.residual(case, orc.metrics(case), case["Q"])
+    assert (_rel(Rg, Ro) <= TOL).all(), _rel(Rg, Ro)
+
+
+def test_superposed_rollout_objective(orc, lesmi):
+    """The forcing workload on a block with a superposed k direction: the
+    probe objective sums the plane's distinct azimuths, and its gradient with
+    respect to the forcing (GPU adjoint) matches the oracle's dual-number
+    directional derivative (3 steps, 2 directions)."""
+    import torch
+    from paper_2003_08746_amd.rollout import LesRollout
+    base, axis = _cases()["wavy47x33x19_k"]
+    case = I.superposed_case(base, axis)
+    print("[gpu] superposed rollout objective", flush=True)
+    i_f, i_p, p_inf, nsteps = 5, 12, 1.0 / I.GAMMA, 3
+    f = 1e-3 * np.random.default_rng(1).uniform(-1, 1, size=(5, case["nk"], case["nj"]))
+    m = orc.metrics(case)
+    dt = 0.8 * orc.cfl_dt(case, m, case["Q"])
+    s = lesmi.Solver(case)
+    Q0 = s.upload(case["Q"])
+    ft = torch.from_numpy(f).cuda().requires_grad_(True)
+    J = LesRollout.apply(ft, Q0, s, nsteps, dt, i_f, i_p, p_inf, "stages")
+    J.backward()
+    g = ft.grad.cpu().numpy()
+    s.close()
+    for seed in (2, 3):
+        d = np.random.default_rng(seed).standard_normal(f.shape)
+        d /= np.linalg.norm(d)
+        Jo, dJo = orc.objective_rollout(case, m, case["Q"], f, d, i_f, i_p, p_inf, nsteps, dt)
+        assert abs(J.item() - Jo) <= 1e-11 * abs(Jo), (J.item(), Jo)
+        gd = float((g * d).sum())
+        assert abs(gd - dJo) <= 1e-10 * abs(dJo), (seed, gd, dJo)
+
+
 def _interior_rand(case, seed, scale_by_field=True):
     rng = np.random.default_rng(seed)
     a = np.zeros_like(case["Q"])

@@ -930,6 +930,12 @@ def test_probe_objective_uniform(orc):
     for N, dt in ((1, 0.01), (4, 0.003)):
         J = orc.objective(case, m, Q, f, 3, 5, pinf, N, dt)
         assert J == pytest.approx(N * dt * n[1] * n[2] * (p - pinf) ** 2, rel=1e-12)
+    # along a superposed k direction the plane's distinct azimuths count once:
+    # the block of nk + 1 planes gives the periodic block's J
+    cs = I.superposed_case(case, 2)
+    ms = orc.metrics(cs)
+    J = orc.objective(cs, ms, cs["Q"], np.zeros((5, n[2] + 1, n[1])), 3, 5, pinf, 1, 0.01)
+    assert J == pytest.approx(0.01 * n[1] * n[2] * (p - pinf) ** 2, rel=1e-12)
 
 
 @pytest.mark.parametrize("i_p", [2, 6])
