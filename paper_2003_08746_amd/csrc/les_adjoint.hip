@@ -579,11 +579,11 @@ __device__ __forceinline__ bool has_images(const AdjK& A, int i, int j, int k) {
 // non-null, on_f) and, after the last stage, qfin = acc + q (qfin non-null).
 __device__ __forceinline__ void finish_node(const Layout& L, long long n, int j, int k, const double q[5],
                                             const double* __restrict__ acc, double* __restrict__ fbar, bool on_f,
-                                            double fw, double* __restrict__ qfin) {
+                                            double fw, double* __restrict__ qfin, int c0 = 0, int c1 = 5) {
   if (fbar && on_f)
-    for (int c = 0; c < 5; ++c) fbar[((long long)c * L.nk + k) * L.nj + j] += fw * q[c];
+    for (int c = c0; c < c1; ++c) fbar[((long long)c * L.nk + k) * L.nj + j] += fw * q[c];
   if (qfin)
-    for (int c = 0; c < 5; ++c) qfin[c * L.fe + n] = acc[c * L.fe + n] + q[c];
+    for (int c = c0; c < c1; ++c) qfin[c * L.fe + n] = acc[c * L.fe + n] + q[c];
 }
 
 // Pass 2 runs over B = R_i x R_j x R_k, R_d = [lo_d, hi_d]: the ghost layers
@@ -774,16 +774,87 @@ __global__ void __launch_bounds__(256) k_adj_fold(AdjK A, const double* __restri
 // each face ghost G = face_value(q_r) (both layers, and their periodic
 // images), the Jacobian column by column from forward-mode dual numbers.
 // Ghosts of two Dirichlet directions are frozen and carry nothing.
+// Is interior node (i, j, k) the boundary node of an active face (so that
+// its face ghosts depend on it through the face rule)?
+__device__ __forceinline__ bool at_active_face(const AdjK& A, int i, int j, int k) {
+  const int id[3] = {i, j, k}, nn[3] = {A.L.ni, A.L.nj, A.L.nk}, bc[3] = {A.bc0, A.bc1, A.bc2};
+  for (int d = 0; d < 3; ++d) {
+    if (bc[d] == 1 && id[d] == 0 && A.F.type[2 * d] != 0) return true;
+    if ((bc[d] == 1 || bc[d] == 3) && id[d] == nn[d] - 1 && A.F.type[2 * d + 1] != 0) return true;
+  }
+  return false;
+}
+
+// Boundary nodes of the active faces, listed face by face (face f = 2 d +
+// hi, the plane id[d] = 0 or n_d - 1 with the other two indices in row
+// order); a node on several active faces is listed under the first.
+__host__ __device__ inline long long face_plane(const int nn[3], int f) {
+  const int d = f / 2;
+  return (long long)nn[(d + 1) % 3] * nn[(d + 2) % 3];
+}
+inline long long face_node_slots(const AdjK& A) {
+  const int nn[3] = {A.L.ni, A.L.nj, A.L.nk};
+  long long n = 0;
+  for (int f = 0; f < 6; ++f)
+    if (A.F.type[f] != 0) n += face_plane(nn, f);
+  return n;
+}
+// node of slot x of that list, or false when the slot is a repeat
+__device__ inline bool face_node(const AdjK& A, long long x, int id[3]) {
+  const int nn[3] = {A.L.ni, A.L.nj, A.L.nk};
+  for (int f = 0; f < 6; ++f) {
+    if (A.F.type[f] == 0) continue;
+    const long long np = face_plane(nn, f);
+    if (x >= np) {
+      x -= np;
+      continue;
+    }
+    const int d = f / 2, e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+    id[d] = (f & 1) ? nn[d] - 1 : 0;
+    id[e1] = (int)(x % nn[e1]);
+    id[e2] = (int)(x / nn[e1]);
+    for (int g = 0; g < f; ++g) {  // listed under an earlier face?
+      if (A.F.type[g] == 0) continue;
+      const int dg = g / 2;
+      if (id[dg] == ((g & 1) ? nn[dg] - 1 : 0)) return false;
+    }
+    return true;
+  }
+  return false;
+}
+
+// FACES = false: the nodes with images that are not at an active face (no
+// face-rule Jacobian, so the kernel stays light), one thread per node;
+// FACES = true: the boundary nodes of the active faces, one thread per
+// (component, listed node), each taking one column of the face rule's
+// Jacobian.  Together they visit each node with images once; each
+// component's sum is formed in the same order either way.
+template <bool FACES>
 __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* __restrict__ Q,
                                                           const double* __restrict__ Wk, double* __restrict__ qout,
                                                           const double* __restrict__ acc, double* __restrict__ fbar,
-                                                          int i_f, double fw, double* __restrict__ qfin) {
+                                                          int i_f, double fw, double* __restrict__ qfin,
+                                                          long long slots) {
   const Layout& L = A.L;
-  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-  const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
-  if (t >= nij * (unsigned)L.nk) return;
-  const int i = (int)(t % ni), j = (int)((t % nij) / ni), k = (int)(t / nij);
-  if (!has_images(A, i, j, k)) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int c0 = 0, c1 = 5, i, j, k;
+  if (FACES) {
+    if (t >= 5 * slots) return;
+    c0 = (int)(t / slots);
+    c1 = c0 + 1;
+    int id3[3];
+    if (!face_node(A, t % slots, id3)) return;
+    i = id3[0];
+    j = id3[1];
+    k = id3[2];
+  } else {
+    const unsigned ni = L.ni, nij = (unsigned)L.ni * L.nj;
+    if (t >= (long long)nij * L.nk) return;
+    i = (int)(t % ni);
+    j = (int)((t % nij) / ni);
+    k = (int)(t / nij);
+    if (!has_images(A, i, j, k) || at_active_face(A, i, j, k)) return;
+  }
   const int id[3] = {i, j, k}, nn[3] = {L.ni, L.nj, L.nk}, bc[3] = {A.bc0, A.bc1, A.bc2};
   int cand[3][3], kind[3][3], nc[3];  // kind: 0 own / periodic image, 1 lo-face ghost, 2 hi-face ghost
   for (int d = 0; d < 3; ++d) {
@@ -817,10 +888,9 @@ __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* 
   const long long fe = L.fe, n0 = L.at(i, j, k);
   const double* G = Wk + (long long)W_GG * fe;
   double s[5], qr[5];
-  for (int c = 0; c < 5; ++c) {
-    s[c] = qout[c * fe + n0];
-    qr[c] = Q[c * fe + n0];
-  }
+  for (int c = c0; c < c1; ++c) s[c] = qout[c * fe + n0];
+  if (FACES)
+    for (int c = 0; c < 5; ++c) qr[c] = Q[c * fe + n0];
   for (int a = 0; a < nc[0]; ++a)
     for (int b = 0; b < nc[1]; ++b)
       for (int e = 0; e < nc[2]; ++e) {
@@ -829,12 +899,13 @@ __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* 
         const int nface = (kd[0] != 0) + (kd[1] != 0) + (kd[2] != 0);
         if (nface > 1) continue;  // edge ghost: frozen
         const long long g = L.at(cand[0][a], cand[1][b], cand[2][e]);
-        double gb[5];
-        for (int c = 0; c < 5; ++c) gb[c] = G[c * fe + g];
         if (nface == 0) {
-          for (int c = 0; c < 5; ++c) s[c] += gb[c];
+          for (int c = c0; c < c1; ++c) s[c] += G[c * fe + g];
           continue;
         }
+        if (!FACES) continue;  // (not reached: face ghosts exist at active faces only)
+        double gb[5];
+        for (int c = 0; c < 5; ++c) gb[c] = G[c * fe + g];
         const int d = kd[0] ? 0 : (kd[1] ? 1 : 2), hi = kd[d] == 2;
         const int type = A.F.type[2 * d + hi];
         double nv[3], qo[5] = {0, 0, 0, 0, 0};
@@ -845,7 +916,7 @@ __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* 
         }
         if (A.F.outside)
           for (int c = 0; c < 5; ++c) qo[c] = A.F.outside[c * fe + g];
-        for (int c = 0; c < 5; ++c) {  // column c of the face rule's Jacobian
+        for (int c = c0; c < c1; ++c) {  // column c of the face rule's Jacobian
           DualD qd[5], od[5];
           for (int m = 0; m < 5; ++m) qd[m] = DualD(qr[m], m == c ? 1.0 : 0.0);
           face_value<DualD>(type, A.F.gamma, A.F.p_exit[2 * d + hi], nv, qd, qo, od);
@@ -859,19 +930,26 @@ __global__ void __launch_bounds__(256) k_adj_fold_general(AdjK A, const double* 
     // (w(k') + (nk - 1)/2) mod (nk - 1)), w wrapping a ghost index (i' a
     // periodic image of i; ghosts of a Dirichlet i side below the axis are
     // edges and keep their values)
+    // the ghost azimuths kk in [-2, nk + 1] with ((w(kk) + half) mod p) = k,
+    // w(kk) = kk on [0, nk) and (kk + p) mod p outside, in ascending kk:
+    // -2, -1, t0, t0 + p (when t0 = 0), nk, nk + 1 with t0 = (k - half) mod p
     const int p = L.nk - 1, half = p / 2;
+    const int t0 = ((k - half) % p + p) % p;
+    const int kks[6] = {-2, -1, t0, t0 + p, L.nk, L.nk + 1};
     for (int a = 0; a < nc[0]; ++a) {
       if (kind[0][a] != 0) continue;
-      for (int kk = -2; kk <= L.nk + 1; ++kk) {
+      for (int q = 0; q < 6; ++q) {
+        const int kk = kks[q];
+        if (q == 3 && kk >= L.nk) continue;  // t0 + p lies in [0, nk) only for t0 = 0
         const int w2 = (kk >= 0 && kk < L.nk) ? kk : (kk + p) % p;
         if ((w2 + half) % p != k) continue;
         const long long g = L.at(cand[0][a], -j, kk);
-        for (int c = 0; c < 5; ++c) s[c] += G[c * fe + g];
+        for (int c = c0; c < c1; ++c) s[c] += G[c * fe + g];
       }
     }
   }
-  for (int c = 0; c < 5; ++c) qout[c * fe + n0] = s[c];
-  finish_node(L, n0, j, k, s, acc, fbar, i == i_f, fw, qfin);
+  for (int c = c0; c < c1; ++c) qout[c * fe + n0] = s[c];
+  finish_node(L, n0, j, k, s, acc, fbar, i == i_f, fw, qfin, c0, c1);
 }
 
 // Start of the Runge-Kutta reverse (interior): qcur = Qbar, acc = 0, and
@@ -894,24 +972,24 @@ __global__ void __launch_bounds__(256) k_adj_init(Layout L, const double* __rest
   }
 }
 
-// Reverse of the centerline condition, one thread per (i, variable): the
+// Reverse of the centerline condition, one wave per (i, variable): the
 // forward writes the mean of the ring (i, 1, k'), k' = 0 .. nk - 2, to every
 // axis node (i, 0, k), k = 0 .. nk - 1; so every ring node receives the sum
-// of the axis adjoints over k (ascending) divided by nk - 1, and the axis
-// adjoints are cleared.
-__global__ void __launch_bounds__(256) k_axis_avg_adj(Layout L, double* __restrict__ q) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 5 * L.ni) return;
-  const int f = t / L.ni, i = t % L.ni;
+// of the axis adjoints over k divided by nk - 1, and the axis adjoints are
+// consumed (set to 0).  Lane l sums k = l, l + 64, ... ascending, and the
+// partial sums are added by a fixed shuffle tree.
+__global__ void __launch_bounds__(64) k_axis_avg_adj(Layout L, double* __restrict__ q) {
+  const int f = blockIdx.x / L.ni, i = blockIdx.x % L.ni;
   double* a = q + f * L.fe;
   double sum = 0.0;
-  for (int k = 0; k < L.nk; ++k) {
+  for (int k = threadIdx.x; k < L.nk; k += 64) {
     const long long n = L.at(i, 0, k);
     sum += a[n];
     a[n] = 0.0;
   }
+  sum = __shfl(wave_sum(sum), 0, 64);
   const double share = sum / (double)(L.nk - 1);
-  for (int k = 0; k < L.nk - 1; ++k) a[L.at(i, 1, k)] += share;
+  for (int k = threadIdx.x; k < L.nk - 1; k += 64) a[L.at(i, 1, k)] += share;
 }
 
 // fbar[c][k][j] += w q_c on the source plane i_f (interior nodes).
@@ -954,7 +1032,12 @@ hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const dou
   k_adj_dnode<<<nb(nB1, 256), 256, 0, s>>>(A, Q, Wk);
   k_adj_gather<<<nb(nB, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, qb, fbar, i_f, fw, qfin);
   if (A.general)
-    k_adj_fold_general<<<nb(nIn, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, fbar, i_f, fw, qfin);
+  {
+    k_adj_fold_general<false><<<nb(nIn, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, fbar, i_f, fw, qfin, 0);
+    const long long slots = face_node_slots(A);
+    if (slots > 0)
+      k_adj_fold_general<true><<<nb(5 * slots, 256), 256, 0, s>>>(A, Q, Wk, qout, acc, fbar, i_f, fw, qfin, slots);
+  }
   else if (nBand > 0)
     k_adj_fold<<<nb(nBand, 256), 256, 0, s>>>(A, Wk, qout, acc, fbar, i_f, fw, qfin);
   return hipGetLastError();
@@ -965,7 +1048,7 @@ hipError_t residual_vjp(hipStream_t s, const AdjK& A, const double* Q, const dou
 size_t adjoint_work_elems(const Layout& L) { return (size_t)W_NF * (size_t)L.fe; }
 
 hipError_t launch_axis_avg_adjoint(hipStream_t s, const Layout& L, double* qbar) {
-  k_axis_avg_adj<<<nb(5LL * L.ni, 256), 256, 0, s>>>(L, qbar);
+  k_axis_avg_adj<<<(unsigned)(5LL * L.ni), 64, 0, s>>>(L, qbar);
   return hipGetLastError();
 }
 

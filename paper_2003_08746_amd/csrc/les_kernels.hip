@@ -269,19 +269,19 @@ __global__ void k_ghost_fill_f32(Layout L, int bc0, int bc1, int bc2, float* __r
 // Centerline of the O-grid (Sec. 3): every axis node (i, 0, k) takes, per
 // conserved variable, the mean of the ring (i, 1, k'), k' = 0 .. nk - 2 (the
 // distinct azimuths; zero-order extrapolation from the adjacent ring, then
-// the azimuthal average).  One thread per (i, variable), summing in
-// ascending k in FP64.
+// the azimuthal average).  One wave per (i, variable): lane l sums k' = l,
+// l + 64, ... in ascending order in FP64, the 64 partial sums are added by a
+// fixed shuffle tree, and the lanes write the axis nodes.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_axis_avg(Layout L, T* __restrict__ q) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 5 * L.ni) return;
-  const int f = t / L.ni, i = t % L.ni;
+__global__ void __launch_bounds__(64) k_axis_avg(Layout L, T* __restrict__ q) {
+  const int f = blockIdx.x / L.ni, i = blockIdx.x % L.ni;
   T* a = q + f * L.fe;
   double sum = 0.0;
-  for (int k = 0; k < L.nk - 1; ++k) sum += (double)a[L.at(i, 1, k)];
+  for (int k = threadIdx.x; k < L.nk - 1; k += 64) sum += (double)a[L.at(i, 1, k)];
+  sum = __shfl(wave_sum(sum), 0, 64);
   const T mean = (T)(sum / (double)(L.nk - 1));
-  for (int k = 0; k < L.nk; ++k) a[L.at(i, 0, k)] = mean;
+  for (int k = threadIdx.x; k < L.nk; k += 64) a[L.at(i, 0, k)] = mean;
 }
 
 // ---------------------------------------------------------------------------
@@ -840,12 +840,12 @@ hipError_t launch_cfl(hipStream_t s, const Layout& L, const Phys& P, const doubl
 }
 
 hipError_t launch_axis_avg(hipStream_t s, const Layout& L, double* q) {
-  k_axis_avg<double><<<nblk(5LL * L.ni, 256), 256, 0, s>>>(L, q);
+  k_axis_avg<double><<<(unsigned)(5LL * L.ni), 64, 0, s>>>(L, q);
   return hipGetLastError();
 }
 
 hipError_t launch_axis_avg_f32(hipStream_t s, const Layout& L, float* q) {
-  k_axis_avg<float><<<nblk(5LL * L.ni, 256), 256, 0, s>>>(L, q);
+  k_axis_avg<float><<<(unsigned)(5LL * L.ni), 64, 0, s>>>(L, q);
   return hipGetLastError();
 }
 

@@ -69,8 +69,16 @@ def test_axis_residual_and_ghosts(orc, lesmi, name):
     s.close()
     m = orc.metrics(case)
     Qo = orc.fill_ghosts_faces(case, m, case["Q"])
-    # ghost layers (the cross-axis rows included) and axis nodes as the oracle fills them
-    np.testing.assert_allclose(Qg, Qo, rtol=1e-15, atol=0)
+    # ghost layers (the cross-axis rows included) as the oracle fills them;
+    # the axis row holds ring means, summed in another fixed order than the
+    # oracle's: within the summation bound (nk - 1) eps max|ring| per field
+    off = np.ones(Qg.shape[1:], dtype=bool)
+    off[:, 2, :] = False  # padded row of j = 0
+    np.testing.assert_allclose(Qg[:, off], Qo[:, off], rtol=1e-15, atol=0)
+    ring = np.abs(Qo[:, 2:-2, 3, 2:-2]).reshape(5, -1).max(1)
+    bound = (case["nk"] - 1) * np.finfo(np.float64).eps * ring
+    err = np.abs(Qg[:, :, 2, :] - Qo[:, :, 2, :]).reshape(5, -1).max(1)
+    assert (err <= bound).all(), (err, bound)
     Ro = orc.residual(case, m, case["Q"])
     assert (_rel(R, Ro) <= TOL).all(), _rel(R, Ro)
     assert np.abs(I.interior(R)[:, :, 0, :]).max() == 0.0  # the axis is not advanced by R
@@ -94,8 +102,11 @@ def test_axis_rk_parity(orc, lesmi, name):
     assert (_rel(Qg, Qo) <= TOL).all(), _rel(Qg, Qo)
     Qi = I.interior(Qg)
     nk = case["nk"]
-    np.testing.assert_allclose(Qi[:, :, 0, :], np.broadcast_to(Qi[:, :nk - 1, 1, :].mean(axis=1)[:, None, :],
-                                                                 Qi[:, :, 0, :].shape), rtol=1e-14, atol=0)
+    # every axis node is the mean of its ring, within the summation bound
+    ring = Qi[:, :nk - 1, 1, :]
+    bound = (nk - 1) * np.finfo(np.float64).eps * np.abs(ring).max(axis=1)[:, None, :]
+    err = np.abs(Qi[:, :, 0, :] - ring.mean(axis=1)[:, None, :])
+    assert (err <= bound).all(), float((err / np.maximum(bound, 1e-300)).max())
 
 
 def test_axis_mixed(orc, lesmi):
