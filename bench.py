@@ -245,6 +245,43 @@ def time_ogrid(steps=20, warmup=2):
                         setup=setup)
 
 
+def time_ogrid_adjoint(ni=128, nj=64, nk=121, reps=3):
+    """One RK step with stage checkpoints and its adjoint (les_adjoint_step)
+    on an O-grid block with the polar axis, the superposed azimuthal seam
+    and a far-field face at the outer radius (the paper's domain; the
+    adjoint then runs the centerline transpose and the face rule's
+    Jacobian): forward and backward times from HIP events on the solver's
+    stream, the last of reps repetitions."""
+    import numpy as np
+    import torch
+    from paper_2003_08746_amd import inputs, lesmi
+    case = inputs.ogrid_case(ni, nj, nk, seed=0)
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    s.set_face(3, lesmi.LES_FACE_FARFIELD, Q)
+    dt = 0.5 * s.cfl_dt(Q)
+    ck = torch.empty(25 * s.fe, dtype=torch.float64, device="cuda")
+    w = np.zeros_like(case["Q"])
+    w[:, 2:-2, 2:-2, 2:-2] = 1e-3
+    Qbar0 = s.upload(w)
+    res = {}
+    for _ in range(reps):
+        Qd = Q.clone()
+        Qbar = Qbar0.clone()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        s.rk_step(Qd, dt, ckpt=ck)
+        e1.record(s.stream)
+        s.adjoint_step(ck, dt, Qbar)
+        e2.record(s.stream)
+        torch.cuda.synchronize()
+        res = dict(forward_ms=round(e0.elapsed_time(e1), 4), backward_ms=round(e1.elapsed_time(e2), 4))
+    s.close()
+    res["adjoint_over_forward"] = round(res["backward_ms"] / res["forward_ms"], 3)
+    return {"workload": f"O-grid {ni}x{nj}x{nk} (axis, superposed seam, far field), FP64, one RK step", **res}
+
+
 def time_stats(case, calls=50):
     """Running flow statistics (les_stats_accumulate) on the benchmark shard:
     mean time per call from HIP events on the solver's stream, against its
@@ -440,7 +477,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip every leg but the headline (mixed, small shard, adjoint, faces, SGS variants, "
-                         "O-grid, statistics, restart, copy, mesh I)")
+                         "O-grid and its adjoint, statistics, restart, copy, mesh I)")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -528,6 +565,7 @@ def main():
                         ("faces", lambda: time_faces(small, args.small_steps, 5)),
                         ("sgs_variants", lambda: time_sgs_variants(small, 20, 2, base)),
                         ("ogrid", time_ogrid),
+                        ("ogrid_adjoint", time_ogrid_adjoint),
                         ("stats", lambda: time_stats(small)),
                         ("restart", lambda: time_restart(small)),
                         ("copy", time_copy),
