@@ -144,11 +144,6 @@ __device__ __forceinline__ double aniso_d(double ld, double le, double lf, const
 
 __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-// Pressure sensor of direction d at node n (p at n-e, n, n+e).
-__device__ __forceinline__ double sensor(double pm, double p0, double pp) {
-  return fabs(pp - 2.0 * p0 + pm) * rcp_nr(pp + 2.0 * p0 + pm);
-}
-
 struct AdjK {
   Layout L;
   Phys P;
@@ -205,7 +200,6 @@ __global__ void __launch_bounds__(256) k_adj_flux(AdjK A, const double* __restri
   const int j = (int)((t / ext_i) % ext_j) - 1;
   const int k = (int)(t / (ext_i * ext_j)) - 1;
   const long long n = L.at(i, j, k);
-  const int id[3] = {i, j, k};
 
   const Prim q = prim_at(Q, fe, n, P);
   double m[9];
