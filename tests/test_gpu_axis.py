@@ -357,6 +357,33 @@ def test_axis_with_entrance_exit_and_farfield(orc, lesmi):
     assert (_rel(Qg, Qo) <= TOL).all(), _rel(Qg, Qo)
 
 
+def test_axis_whole_cylinder_mixed(orc, lesmi):
+    """The whole cylinder (entrance, exit, far field, axis) in the FP32-mixed
+    form: two steps at the steps' own CFL dt against the FP64 oracle, to the
+    mixed bound (momenta against their common scale)."""
+    case = _faces_case(1)
+    s = lesmi.Solver(case, prec=lesmi.LES_MIXED)
+    fc = case["faces"]
+    Q0d = s.upload(fc["outside"])
+    s.set_face(0, lesmi.LES_FACE_CHARACTERISTIC, Q0d)
+    s.set_face(1, lesmi.LES_FACE_EXIT, p_exit=fc["p_exit"][1])
+    s.set_face(3, lesmi.LES_FACE_FARFIELD, Q0d)
+    Qd = s.upload(case["Q"])
+    dts, _ = s.advance(Qd, 2, want_dt=True)
+    Qg = s.download(Qd)
+    s.close()
+    m = orc.metrics(case)
+    Qo = case["Q"]
+    for n in range(2):
+        Qo, _, _, _ = orc.rk_step(case, m, Qo, dt=dts[n])
+    d = I.interior(Qg) - I.interior(Qo)
+    sc = np.abs(I.interior(Qo)).reshape(5, -1).max(1)
+    sc[1:4] = sc[1:4].max()
+    linf = np.abs(d).reshape(5, -1).max(1) / sc
+    print(f"[gpu] whole cylinder mixed: Linf {linf}", flush=True)
+    assert (linf <= MIXED_BOUND).all(), linf
+
+
 def _noisy(case, seed):
     """Seeded 1e-4 noise on the pressure and the momenta (interior and
     ghosts), so that no pressure second difference and no velocity component

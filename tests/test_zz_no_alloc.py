@@ -53,6 +53,28 @@ def test_noalloc_matches_residual_twice(lesmi):
     assert not np.array_equal(n1, n2)
 
 
+def test_noalloc_ogrid_dynamic_closure(lesmi):
+    """The no-allocation residual on an O-grid (centerline condition and
+    cross-axis ghosts applied in place) with the dynamic closure (its
+    coefficients formed in work arrays allocated by les_create) and a
+    far-field face: bit for bit as les_residual."""
+    case = I.ogrid_case(40, 24, 61, seed=1, sgs=2)
+    print("[gpu] no-alloc residual: O-grid 40x24x61, dynamic closure, far field", flush=True)
+    import torch
+    s = lesmi.Solver(case)
+    Q = s.upload(case["Q"])
+    s.set_face(3, lesmi.LES_FACE_FARFIELD, Q)
+    R, norms = s.residual(Q, want_norms=True)
+    R2 = s.empty_state()
+    R2.fill_(7.0)
+    nd = torch.full((10,), -1.0, dtype=torch.float64, device="cuda")
+    lesmi.les_residual_noalloc(s.ctx, Q.data_ptr(), R2.data_ptr(), nd.data_ptr())
+    torch.cuda.synchronize()
+    assert torch.equal(s.view(R2), s.view(R)), float((s.view(R2) - s.view(R)).abs().max())
+    assert np.array_equal(nd.cpu().numpy(), np.asarray(norms))
+    s.close()
+
+
 def test_noalloc_refuses_too_many_blocks(lesmi, monkeypatch):
     import torch
     case = I.jet_case(256, 128, 128, seed=0)
