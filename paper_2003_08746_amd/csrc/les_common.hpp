@@ -172,28 +172,31 @@ __device__ __forceinline__ T sutherland_fast(T tem, const Phys& P) {
   return T(P.mu_ref * P.one_plus_S) * th * sqrt_pos(th) * rcp_nr(th + T(P.S));
 }
 
-// Local CFL bound of one node (FP64, IEEE operations): the inverse of
+// Local CFL bound of one node (FP64, with the short reciprocal and square
+// root): the inverse of
 //   sum_d (|U_d| + c |grad d|) + 2 max(4/3, gamma/Pr) (mu/rho) sum_d |grad d|^2
 // with the physical metrics grad d = J (d_x/J, d_y/J, d_z/J) (m9 = the nine
 // metric terms over J, row by row) and the molecular viscosity of Eq. 6;
 // dt = cfl * min over the interior.  NaN for a state with non-positive
-// density or pressure, so that the minimum reports it.
+// density or pressure, so that the minimum reports it (the short sequences
+// may return anything there; the test below overrides it).
 __device__ inline double cfl_local(double q0, double q1, double q2, double q3, double q4, double J,
                                    const double m9[9], const Phys& P) {
   double u, v, w, p, tem;
-  prim_from_q(q0, q1, q2, q3, q4, P, u, v, w, p, tem);
-  const double c = sqrt(P.gamma * p / q0);
-  const double nuv = P.nu_fac * sutherland(tem, P) / q0;
+  prim_from_q_fast(q0, q1, q2, q3, q4, P, u, v, w, p, tem);
+  const double ir = rcp_nr(q0);
+  const double c = sqrt_pos(P.gamma * p * ir);
+  const double nuv = P.nu_fac * sutherland_fast(tem, P) * ir;
   double lam = 0.0, g2 = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double gx = J * m9[3 * d], gy = J * m9[3 * d + 1], gz = J * m9[3 * d + 2];
     const double U = gx * u + gy * v + gz * w;
     const double gg = gx * gx + gy * gy + gz * gz;
-    lam += fabs(U) + c * sqrt(gg);
+    lam += fabs(U) + c * sqrt_pos(gg);
     g2 += gg;
   }
-  double l = 1.0 / (lam + 2.0 * nuv * g2);
+  double l = rcp_nr(lam + 2.0 * nuv * g2);
   if (!(l > 0.0) || !(q0 > 0.0) || !(p > 0.0)) l = __builtin_nan("");
   return l;
 }
