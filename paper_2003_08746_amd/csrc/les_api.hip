@@ -510,8 +510,14 @@ int les_set_forcing(les_ctx* ctx, const double* f, int i_f) {
 // of R(Q^n) (and their non-finite flag); les_advance leaves them out of every
 // step but its last, whose non-finite states the next step's dt reduction
 // reports instead.
+//
+// Mixed precision: stage l writes its FP32 state to Sf[(l + par) & 1] and
+// stage l + 1 reads it.  shadow_out: the last stage also writes the FP32
+// copy of Q^{n+1} (to Sf[par]); shadow_in: stage 1 reads that copy (written
+// by the step before, with the other par) for its stencil instead of
+// converting the FP64 Q^n as it loads it -- the same FP32 values.
 static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, double* stage_ckpt, double* cpart,
-                     bool with_norms = true) {
+                     bool with_norms = true, int par = 0, bool shadow_in = false, bool shadow_out = false) {
   les::Layout& L = ctx->L;
   const size_t fe = (size_t)L.fe;
   const double* f = ctx->i_f >= 0 ? ctx->f : nullptr;
@@ -519,15 +525,16 @@ static int step_core(les_ctx* ctx, double* Q, const double* dtp, double dt, doub
   if (ctx->prec == LES_MIXED) {
     les::StageArgs a{L, ctx->P, ctx->M, f, ctx->i_f, ctx->kchunk, ctx->dyn, ctx->axis, ctx->mach};
     for (int l = 0; l < 5; ++l) {
-      const float* in32 = l == 0 ? nullptr : ctx->Sf[(l - 1) & 1];
+      const float* in32 = (l == 0 && !shadow_in) ? nullptr : ctx->Sf[(l + 1 + par) & 1];
+      float* out32 = (l < 4 || shadow_out) ? ctx->Sf[(l + par) & 1] : nullptr;
       if (l > 0 && ctx->axis) HIPCHK(ctx, les::launch_axis_avg_f32(ctx->s, L, (float*)in32));
-      if (l > 0) HIPCHK(ctx, les::launch_ghost_fill_f32(ctx->s, L, ctx->bc, (float*)in32, Q, faces_of(ctx)));
-      HIPCHK(ctx, dyn_update(ctx, l == 0 ? Q : nullptr, in32));
+      if (in32) HIPCHK(ctx, les::launch_ghost_fill_f32(ctx->s, L, ctx->bc, (float*)in32, Q, faces_of(ctx)));
+      HIPCHK(ctx, dyn_update(ctx, in32 ? nullptr : Q, in32));
       int trc = timing_begin(ctx);
       if (trc != LES_OK) return trc;
-      HIPCHK(ctx, les::launch_stage_mixed(ctx->s, a, l == 0 ? Q : nullptr, in32, Q, l == 4 ? Q : nullptr,
-                                          l == 4 ? nullptr : ctx->Sf[l & 1], dtp, dt, les::rk_alpha(l),
-                                          (l == 0 && with_norms) ? ctx->part : nullptr, l == 4 ? cpart : nullptr));
+      HIPCHK(ctx, les::launch_stage_mixed(ctx->s, a, in32 ? nullptr : Q, in32, Q, l == 4 ? Q : nullptr, out32, dtp,
+                                          dt, les::rk_alpha(l), (l == 0 && with_norms) ? ctx->part : nullptr,
+                                          l == 4 ? cpart : nullptr));
       trc = timing_end(ctx);
       if (trc != LES_OK) return trc;
     }
@@ -604,12 +611,18 @@ int les_advance(les_ctx* ctx, double* Q, int nsteps, double* dt_out, double* nor
   HIPCHK(ctx, bc_fill(ctx, Q));
   HIPCHK(ctx, les::launch_cfl(ctx->s, L, ctx->P, ctx->M, Q, ctx->part, ctx->scal, ctx->flag,
                               dt_out ? ctx->dthist : nullptr, ctx->axis));
+  // Mixed precision: each step after the first takes the FP32 copy of its
+  // Q^n from the step before, where its ghost layers are plain copies or
+  // frozen values (no face rules, polar axis or dynamic closure, which would
+  // then work on FP32 values): the same stencil values, one FP64 read less.
+  const bool shadow = ctx->prec == LES_MIXED && !ctx->axis && ctx->P.sgs != 2 && !faces_of(ctx).any;
   for (int n = 0; n < nsteps; ++n) {
     double* dtp = ctx->scal + ((n & 1) ? 12 : 0);
     double* dnext = ctx->scal + ((n & 1) ? 0 : 12);
     const bool more = n + 1 < nsteps;
     if (n > 0) HIPCHK(ctx, bc_fill(ctx, Q));
-    int rc = step_core(ctx, Q, dtp, 0.0, nullptr, (more && !ctx->use_ref) ? ctx->cpart : nullptr, !more);
+    int rc = step_core(ctx, Q, dtp, 0.0, nullptr, (more && !ctx->use_ref) ? ctx->cpart : nullptr, !more, n & 1,
+                       shadow && n > 0, shadow && more);
     if (rc != LES_OK) return rc;
     if (!more) break;
     double* rec = dt_out ? ctx->dthist + n + 1 : nullptr;

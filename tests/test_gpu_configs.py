@@ -119,16 +119,22 @@ def test_advance_arguments(lesmi):
 
 
 def test_advance_mixed_matches_rk_steps(lesmi):
-    """Mixed precision: les_advance and one les_rk_step per step agree."""
+    """Mixed precision: les_advance and one les_rk_step per step agree bit
+    for bit.  On this block (periodic and frozen ghosts) every step of
+    les_advance after the first takes the FP32 copy of its state that the
+    step before wrote, where les_rk_step converts the FP64 state as it
+    loads it: the same FP32 values, so the same result.  Four steps use
+    both FP32 buffer orders twice."""
     case, _ = SMALL["jet150x40x20"]
     s = lesmi.Solver(case, prec=lesmi.LES_MIXED)
     Q = s.upload(case["Q"])
-    dts, _ = s.advance(Q, 3, want_dt=True)
+    dts, _ = s.advance(Q, 4, want_dt=True)
     Q2 = s.upload(case["Q"])
-    for n in range(3):
+    for n in range(4):
         dt, _ = s.rk_step(Q2, 0.0, want_dt=True)
-        assert abs(dt - dts[n]) <= 1e-15 * dt
-    assert (_rel(s.download(Q2), s.download(Q)) <= 1e-15).all()
+        assert dt == dts[n], (n, dt, dts[n])
+    a, b = I.interior(s.download(Q)), I.interior(s.download(Q2))
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), _rel(s.download(Q), s.download(Q2))
     s.close()
 
 
