@@ -255,8 +255,8 @@ int les_rk_step(les_ctx *ctx, double *Q, double dt, double *dt_out, double *norm
  * registers (the first step's dt takes a pass of its own): no separate pass
  * over Q and the metrics per step.  In LES_MIXED the last stage of each step
  * but the final one also writes the FP32 copy of Q^{n+1} that the next step's
- * stencil reads (where the ghost layers are periodic or frozen), so Q^n is
- * not read twice; the result is still that of les_rk_step, bit for bit.
+ * stencil reads (where the ghost layers are periodic or frozen) in place of
+ * the FP64 Q^n; the result is still that of les_rk_step, bit for bit.
  * Q: device, library layout, FP64, 16-byte aligned (LES_ERR_ARG otherwise),
  *    in/out as for les_rk_step; the caller must not touch it until the call's
  *    work on the stream is done.
